@@ -1,0 +1,227 @@
+"""Plain FP64 CPU oracle of the LW-ACM time step (arXiv:1111.2142).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the CPU-baseline leg of ``bench.py``; the product library never
+imports, links or calls it.  It shares no code with the HIP library.
+
+The arithmetic lives in ``lwacm_oracle.c`` (population form of Eq. ACM2.0,
+odd parts from their definition Eq. feqo, forcing Eq. force, halfway
+bounce-back Eqs. ACM2.0cbb-ACM2.0cccbb2 and moving walls Eq. ACM2.0ccccbb,
+reverse mode by the chain rule).  This module only marshals numpy arrays and
+strings the per-step calls together:
+
+* ``run``        -- n forward steps (two arrays toggled);
+* ``diagnostics``-- mass sum(rho) and energy 1/2 sum|u|^2 over fluid nodes;
+* ``vjp``        -- reverse mode of one step;
+* ``gradient``   -- reverse sweep over n steps with a checkpoint every K
+                    steps and recomputation in between.
+
+Arrays: ``rho`` has shape (nz, ny, nx) (nz = 1 for D2Q9), ``u`` has shape
+(D, nz, ny, nx); float64, C order (x fastest).
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Callable, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liblwacm_oracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIBPATH)
+    common = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+              _u8p, _dp, ctypes.c_int, _dp, ctypes.c_double]
+    lib.oracle_step.argtypes = common + [_dp, _dp, _dp, _dp]
+    lib.oracle_step.restype = ctypes.c_int
+    lib.oracle_vjp.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.oracle_vjp.restype = ctypes.c_int
+    lib.oracle_diagnostics.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       _u8p, _dp, _dp, _dp, _dp]
+    lib.oracle_diagnostics.restype = ctypes.c_int
+    lib.oracle_lattice_info.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int), _dp,
+                                        ctypes.POINTER(ctypes.c_int)]
+    lib.oracle_lattice_info.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray], p=_dp):
+    if a is None:
+        return ctypes.cast(None, p)
+    return a.ctypes.data_as(p)
+
+
+def num_threads() -> int:
+    """Threads the oracle's parallel loops use (OMP_NUM_THREADS)."""
+    return int(_load().oracle_num_threads())
+
+
+def lattice_info(q: int):
+    """(D, velocities (q,3) int, weights (q,), opposite (q,)) of the oracle's lattice."""
+    lib = _load()
+    d = ctypes.c_int()
+    v = (ctypes.c_int * (3 * q))()
+    w = (ctypes.c_double * q)()
+    opp = (ctypes.c_int * q)()
+    if lib.oracle_lattice_info(q, ctypes.byref(d), v, w, opp) != 0:
+        raise ValueError(f"unknown lattice Q={q}")
+    return (d.value, np.array(v[:], dtype=np.int64).reshape(q, 3), np.array(w[:]),
+            np.array(opp[:], dtype=np.int64))
+
+
+@dataclass
+class Problem:
+    """What the paper's statement of a run fixes: lattice, grid, omega, walls, force."""
+    q: int                     # 9 (D2Q9) or 19 (D3Q19)
+    nx: int
+    ny: int
+    nz: int = 1
+    omega: float = 1.0
+    mask: Optional[np.ndarray] = None     # uint8 (nz,ny,nx); 0 fluid, m>=1 wall id
+    wall_u: Optional[np.ndarray] = None   # (n_ids, 3) wall velocities by id
+    g: Optional[Tuple[float, ...]] = None  # body acceleration
+    rho0: float = 1.0          # mean fluid density at t=0, used by moving walls
+
+    @property
+    def d(self) -> int:
+        return 2 if self.q == 9 else 3
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def _args(self):
+        mask = None
+        if self.mask is not None:
+            mask = np.ascontiguousarray(self.mask, dtype=np.uint8)
+            assert mask.shape == self.shape
+        wall = None
+        n_ids = 0
+        if self.wall_u is not None:
+            wall = np.ascontiguousarray(self.wall_u, dtype=np.float64).reshape(-1, 3)
+            n_ids = wall.shape[0]
+            wall = wall.reshape(-1)
+        g = None
+        if self.g is not None:
+            g = np.zeros(3)
+            g[:len(self.g)] = self.g
+        self._keep = (mask, wall, g)
+        return [self.q, self.nx, self.ny, self.nz, float(self.omega), _ptr(mask, _u8p),
+                _ptr(wall), n_ids, _ptr(g), float(self.rho0)]
+
+
+def _f64(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def step(p: Problem, rho, u):
+    """One step of Eq. ACM2.0 (with forcing and walls); returns new (rho, u)."""
+    lib = _load()
+    rho = _f64(rho, p.shape)
+    u = _f64(u, (p.d,) + p.shape)
+    r1 = np.empty_like(rho)
+    u1 = np.empty_like(u)
+    rc = lib.oracle_step(*p._args(), _ptr(rho), _ptr(u), _ptr(r1), _ptr(u1))
+    if rc != 0:
+        raise RuntimeError(f"oracle_step failed ({rc})")
+    return r1, u1
+
+
+def run(p: Problem, rho, u, nsteps: int, callback: Optional[Callable] = None):
+    """n forward steps; ``callback(t, rho, u)`` after each step if given."""
+    lib = _load()
+    a_r = _f64(rho, p.shape).copy()
+    a_u = _f64(u, (p.d,) + p.shape).copy()
+    b_r = np.empty_like(a_r)
+    b_u = np.empty_like(a_u)
+    args = p._args()
+    for t in range(nsteps):
+        rc = lib.oracle_step(*args, _ptr(a_r), _ptr(a_u), _ptr(b_r), _ptr(b_u))
+        if rc != 0:
+            raise RuntimeError(f"oracle_step failed ({rc})")
+        a_r, b_r = b_r, a_r
+        a_u, b_u = b_u, a_u
+        if callback is not None:
+            callback(t + 1, a_r, a_u)
+    return a_r, a_u
+
+
+def diagnostics(p: Problem, rho, u):
+    """(mass, energy) = (sum rho, 1/2 sum |u|^2) over fluid nodes."""
+    lib = _load()
+    rho = _f64(rho, p.shape)
+    u = _f64(u, (p.d,) + p.shape)
+    m = ctypes.c_double()
+    e = ctypes.c_double()
+    mask = None if p.mask is None else np.ascontiguousarray(p.mask, dtype=np.uint8)
+    lib.oracle_diagnostics(p.q, p.nx, p.ny, p.nz, _ptr(mask, _u8p), _ptr(rho), _ptr(u),
+                           ctypes.byref(m), ctypes.byref(e))
+    return m.value, e.value
+
+
+def vjp(p: Problem, rho, u, lam_rho1, lam_u1):
+    """Reverse mode of one step entered with state (rho, u).
+
+    Returns (lam_rho0, lam_u0, dL_domega) for output cotangents (lam_rho1, lam_u1).
+    """
+    lib = _load()
+    rho = _f64(rho, p.shape)
+    u = _f64(u, (p.d,) + p.shape)
+    lr1 = _f64(lam_rho1, p.shape)
+    lu1 = _f64(lam_u1, (p.d,) + p.shape)
+    lr0 = np.empty_like(rho)
+    lu0 = np.empty_like(u)
+    dw = ctypes.c_double()
+    rc = lib.oracle_vjp(*p._args(), _ptr(rho), _ptr(u), _ptr(lr1), _ptr(lu1), _ptr(lr0),
+                        _ptr(lu0), ctypes.byref(dw))
+    if rc != 0:
+        raise RuntimeError(f"oracle_vjp failed ({rc})")
+    return lr0, lu0, dw.value
+
+
+def gradient(p: Problem, rho0, u0, nsteps: int, final_cotangent: Callable, K: int = 100):
+    """Gradient of a final-state loss through ``nsteps`` steps.
+
+    ``final_cotangent(rho_T, u_T) -> (lam_rho_T, lam_u_T)`` gives dL/d(state_T).
+    The reverse sweep keeps a checkpoint every K steps and recomputes the
+    states of one segment at a time.  Returns (dL/drho0, dL/du0, dL/domega,
+    (rho_T, u_T)).
+    """
+    rho = _f64(rho0, p.shape).copy()
+    u = _f64(u0, (p.d,) + p.shape).copy()
+    checkpoints = {}
+    for t0 in range(0, nsteps, K):
+        checkpoints[t0] = (rho.copy(), u.copy())
+        rho, u = run(p, rho, u, min(K, nsteps - t0))
+    lam_r, lam_u = final_cotangent(rho, u)
+    lam_r = _f64(lam_r, p.shape)
+    lam_u = _f64(lam_u, (p.d,) + p.shape)
+    dw_total = 0.0
+    for t0 in sorted(checkpoints, reverse=True):
+        nseg = min(K, nsteps - t0)
+        states = [checkpoints[t0]]
+        for _ in range(nseg - 1):
+            states.append(step(p, *states[-1]))
+        for s in reversed(states):
+            lam_r, lam_u, dw = vjp(p, s[0], s[1], lam_r, lam_u)
+            dw_total += dw
+    return lam_r, lam_u, dw_total, (rho, u)

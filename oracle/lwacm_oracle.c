@@ -1,0 +1,440 @@
+/*
+ * lwacm_oracle.c -- plain FP64 CPU oracle of the LW-ACM time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this file's library.  It shares no
+ * code, header, table or constant with the HIP library: lattices, equilibria
+ * and the update are written out again here, directly from the paper, in the
+ * paper's own (population) form and in double precision, with no fusion,
+ * blocking or algebraic simplification.
+ *
+ * What it computes (Asinari, Ohwada, Chiavazzo, Di Rienzo, "Link-wise
+ * artificial compressibility method", arXiv:1111.2142):
+ *   - lattices D2Q9 and D3Q19 with their weights (Appendix A, Eqs.
+ *     d2q9_equilibrium_compact, weight_factors, weight_factors_3d);
+ *   - the equilibrium f^(e) (Eq. d2q9_equilibrium_compact, "formally
+ *     identical" for D3Q19) and its odd part f^(e,o), taken literally as
+ *     half the difference of f^(e) at +u and -u (Eq. feqo);
+ *   - the link-wise update, Eq. ACM2.0: every population at x is the
+ *     upstream equilibrium plus (2 - 2/omega) times the odd-part difference
+ *     between x and the upstream node;
+ *   - the forcing step, Eq. force: the odd part evaluated at (rho(x,t), g) is
+ *     added to every population;
+ *   - halfway bounce-back for a solid upstream node, Eqs. ACM2.0cbb to
+ *     ACM2.0cccbb2, with the moving-wall correction of Eqs. ACM2.0movebb
+ *     and ACM2.0ccccbb, (2/omega - 1) * 2 f^(e,o)(rho0, u_w);
+ *   - new moments rho = sum f_i, rho u = sum v_i f_i (Section 2.1);
+ *   - diagnostics: mass sum(rho) and kinetic energy 1/2 sum |u|^2 over
+ *     fluid nodes (the energy of Section 3.1.1, in lattice units);
+ *   - the vector-Jacobian product of one step (reverse mode), obtained by
+ *     the chain rule through the same population form.  The paper has no
+ *     adjoint; the oracle's reading is "exact derivative of the step above",
+ *     pinned by central finite differences in the tests.
+ *
+ * Layout: structure of arrays, node index ((z*ny)+y)*nx+x, every axis
+ * periodic; walls are solid mask nodes (mask != 0), mask value m >= 1 selects
+ * wall velocity wall_u[3*m .. 3*m+2] (all zero when wall_u is NULL).
+ * Solid nodes are never updated: their state is copied through.
+ * The state is (rho, u) in double precision; u has D components (SoA).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MAXQ 19
+
+typedef struct {
+    int q;          /* number of links */
+    int d;          /* dimension */
+    int v[MAXQ][3]; /* link velocities */
+    double w[MAXQ]; /* weights */
+    int opp[MAXQ];  /* BB(i): the link opposite to i */
+} lattice_t;
+
+/* D2Q9 in the order of Appendix A: rest, the four axis links, the four
+ * diagonals, with weights 4/9, 1/9, 1/36 (Eq. weight_factors). */
+static const int D2Q9_V[9][2] = {
+    {0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1}, {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+
+/* D3Q19: rest, six axis links, twelve face diagonals (Appendix A names only
+ * the groups; the order inside a group is this oracle's own choice).
+ * Weights 1/3, 1/18, 1/36 (Eq. weight_factors_3d). */
+static const int D3Q19_V[19][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+static int make_lattice(int q, lattice_t *L)
+{
+    memset(L, 0, sizeof(*L));
+    if (q == 9) {
+        L->q = 9;
+        L->d = 2;
+        for (int i = 0; i < 9; ++i) {
+            L->v[i][0] = D2Q9_V[i][0];
+            L->v[i][1] = D2Q9_V[i][1];
+            L->v[i][2] = 0;
+            L->w[i] = (i == 0) ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+        }
+    } else if (q == 19) {
+        L->q = 19;
+        L->d = 3;
+        for (int i = 0; i < 19; ++i) {
+            for (int k = 0; k < 3; ++k) L->v[i][k] = D3Q19_V[i][k];
+            L->w[i] = (i == 0) ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+        }
+    } else {
+        return -1;
+    }
+    /* BB(i): found by search for the link with velocity -v_i. */
+    for (int i = 0; i < L->q; ++i) {
+        L->opp[i] = -1;
+        for (int j = 0; j < L->q; ++j)
+            if (L->v[j][0] == -L->v[i][0] && L->v[j][1] == -L->v[i][1] &&
+                L->v[j][2] == -L->v[i][2])
+                L->opp[i] = j;
+        if (L->opp[i] < 0) return -1;
+    }
+    return 0;
+}
+
+/* ---- equilibrium and odd part, Eqs. d2q9_equilibrium_compact and feqo ---- */
+
+static double vdot(const lattice_t *L, int i, const double u[3])
+{
+    return L->v[i][0] * u[0] + L->v[i][1] * u[1] + L->v[i][2] * u[2];
+}
+
+static double feq(const lattice_t *L, int i, double rho, const double u[3])
+{
+    double c = vdot(L, i, u);
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return L->w[i] * rho * (1.0 + 3.0 * c + 4.5 * c * c - 1.5 * uu);
+}
+
+static double feo(const lattice_t *L, int i, double rho, const double u[3])
+{
+    double mu[3] = {-u[0], -u[1], -u[2]};
+    return 0.5 * (feq(L, i, rho, u) - feq(L, i, rho, mu));
+}
+
+/* Partial derivatives of f^(e) with respect to rho and to u (componentwise),
+ * differentiated term by term from Eq. d2q9_equilibrium_compact. */
+static void dfeq(const lattice_t *L, int i, double rho, const double u[3], double *d_rho,
+                 double d_u[3])
+{
+    double c = vdot(L, i, u);
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    *d_rho = L->w[i] * (1.0 + 3.0 * c + 4.5 * c * c - 1.5 * uu);
+    for (int k = 0; k < 3; ++k)
+        d_u[k] = L->w[i] * rho * (3.0 * L->v[i][k] + 9.0 * c * L->v[i][k] - 3.0 * u[k]);
+}
+
+/* Derivatives of f^(e,o)(rho,u) = 1/2 [f^(e)(rho,u) - f^(e)(rho,-u)] by the
+ * chain rule through the definition (the -u argument flips the sign of the
+ * u-derivative of the second term). */
+static void dfeo(const lattice_t *L, int i, double rho, const double u[3], double *d_rho,
+                 double d_u[3])
+{
+    double mu[3] = {-u[0], -u[1], -u[2]};
+    double ap, am, bp[3], bm[3];
+    dfeq(L, i, rho, u, &ap, bp);
+    dfeq(L, i, rho, mu, &am, bm);
+    *d_rho = 0.5 * (ap - am);
+    for (int k = 0; k < 3; ++k) d_u[k] = 0.5 * (bp[k] + bm[k]);
+}
+
+/* ---- grid helpers ---- */
+
+static long node_index(int nx, int ny, int x, int y, int z)
+{
+    return ((long)z * ny + y) * nx + x;
+}
+
+static int wrap(int a, int n)
+{
+    a %= n;
+    return a < 0 ? a + n : a;
+}
+
+/* Upstream neighbour x - v_i with periodic wrap in every axis. */
+static long upstream(const lattice_t *L, int nx, int ny, int nz, int x, int y, int z, int i)
+{
+    return node_index(nx, ny, wrap(x - L->v[i][0], nx), wrap(y - L->v[i][1], ny),
+                      wrap(z - L->v[i][2], nz));
+}
+
+static void load_u(const lattice_t *L, long n, long idx, const double *u, double out[3])
+{
+    out[0] = out[1] = out[2] = 0.0;
+    for (int k = 0; k < L->d; ++k) out[k] = u[k * n + idx];
+}
+
+static void wall_velocity(const double *wall_u, int n_ids, int m, double out[3])
+{
+    out[0] = out[1] = out[2] = 0.0;
+    if (wall_u && m >= 0 && m < n_ids)
+        for (int k = 0; k < 3; ++k) out[k] = wall_u[3 * m + k];
+}
+
+/* Populations f_i(x, t+1), i = 0..q-1, of one fluid node x (Eq. ACM2.0 with
+ * the forcing of Eq. force and the bounce-back / moving-wall rules). */
+static void node_populations(const lattice_t *L, int nx, int ny, int nz, double omega,
+                             const uint8_t *mask, const double *wall_u, int n_ids,
+                             const double g[3], double rho0, const double *rho,
+                             const double *u, int x, int y, int z, double f[MAXQ])
+{
+    long n = (long)nx * ny * nz;
+    long ix = node_index(nx, ny, x, y, z);
+    double a = 2.0 * (omega - 1.0) / omega;
+    double ux[3];
+    load_u(L, n, ix, u, ux);
+    double rx = rho[ix];
+    for (int i = 0; i < L->q; ++i) {
+        long iy = upstream(L, nx, ny, nz, x, y, z, i);
+        if (!mask || mask[iy] == 0) {
+            double uy[3];
+            load_u(L, n, iy, u, uy);
+            double ry = rho[iy];
+            f[i] = feq(L, i, ry, uy) + a * (feo(L, i, rx, ux) - feo(L, i, ry, uy));
+        } else {
+            /* The upstream node is solid: the population leaving x along
+             * BB(i) = ib is reflected back halfway (Eq. ACM2.0ccbb), then
+             * post-combined (Eq. ACM2.0cccbb) and corrected for the wall
+             * motion (Eq. ACM2.0ccccbb). */
+            int ib = L->opp[i];
+            double uw[3];
+            wall_velocity(wall_u, n_ids, mask[iy], uw);
+            double fstar = feq(L, ib, rx, ux) - a * feo(L, ib, rx, ux);
+            f[i] = fstar + a * feo(L, i, rx, ux) + (2.0 / omega - 1.0) * 2.0 * feo(L, i, rho0, uw);
+        }
+        if (g) f[i] += feo(L, i, rx, g);
+    }
+}
+
+/* Number of threads the parallel loops below use (1 without OpenMP). */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+int oracle_lattice_info(int q, int *d, int *v_out, double *w_out, int *opp_out)
+{
+    lattice_t L;
+    if (make_lattice(q, &L)) return -1;
+    *d = L.d;
+    for (int i = 0; i < L.q; ++i) {
+        for (int k = 0; k < 3; ++k) v_out[3 * i + k] = L.v[i][k];
+        w_out[i] = L.w[i];
+        opp_out[i] = L.opp[i];
+    }
+    return 0;
+}
+
+/* One LW-ACM time step.  rho_out/u_out must not alias rho_in/u_in
+ * (two arrays toggled, Section 2.4). */
+int oracle_step(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
+                const double *wall_u, int n_ids, const double *g_in, double rho0,
+                const double *rho_in, const double *u_in, double *rho_out, double *u_out)
+{
+    lattice_t L;
+    if (make_lattice(q, &L)) return -1;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (L.d == 2 && nz != 1)) return -1;
+    long n = (long)nx * ny * nz;
+    double g[3] = {0, 0, 0};
+    if (g_in)
+        for (int k = 0; k < L.d; ++k) g[k] = g_in[k];
+    const double *gp = g_in ? g : NULL;
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long ix = node_index(nx, ny, x, y, z);
+                if (mask && mask[ix] != 0) {
+                    rho_out[ix] = rho_in[ix];
+                    for (int k = 0; k < L.d; ++k) u_out[k * n + ix] = u_in[k * n + ix];
+                    continue;
+                }
+                double f[MAXQ];
+                node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_in,
+                                 u_in, x, y, z, f);
+                double r = 0.0, j[3] = {0, 0, 0};
+                for (int i = 0; i < L.q; ++i) {
+                    r += f[i];
+                    for (int k = 0; k < 3; ++k) j[k] += L.v[i][k] * f[i];
+                }
+                rho_out[ix] = r;
+                for (int k = 0; k < L.d; ++k) u_out[k * n + ix] = j[k] / r;
+            }
+    return 0;
+}
+
+/* Mass sum(rho) and energy 1/2 sum |u|^2 over fluid nodes. */
+int oracle_diagnostics(int q, int nx, int ny, int nz, const uint8_t *mask, const double *rho,
+                       const double *u, double *mass, double *energy)
+{
+    lattice_t L;
+    if (make_lattice(q, &L)) return -1;
+    long n = (long)nx * ny * nz;
+    double m = 0.0, e = 0.0;
+    for (long ix = 0; ix < n; ++ix) {
+        if (mask && mask[ix] != 0) continue;
+        m += rho[ix];
+        double s = 0.0;
+        for (int k = 0; k < L.d; ++k) s += u[k * n + ix] * u[k * n + ix];
+        e += 0.5 * s;
+    }
+    *mass = m;
+    *energy = e;
+    return 0;
+}
+
+/*
+ * Reverse mode of one step.  Given the state (rho_t, u_t) entering the step
+ * and the cotangents (lam_rho1, lam_u1) of the step's outputs, return the
+ * cotangents (lam_rho0, lam_u0) of the inputs and dL/domega of this step.
+ *
+ * Pass 1, per fluid target x: the cotangent of every population,
+ *   fbar_i = dL/d rho+ + dL/d u+ . (v_i - u+) / rho+,
+ * then every term of f_i that depends on x itself (post-combine, bounce-back,
+ * forcing) is accumulated into x's own input cotangent, and d f_i / d a into
+ * a per-node array.  The forcing term enters every f_i (Eq. force), so its
+ * rho(x,t)-derivative is carried by fbar_i like the other local terms.
+ * Pass 2, per fluid source y: the terms f^(e)_i(y) - a f^(e,o)_i(y) that
+ * stream to the fluid target y + v_i.
+ * Cotangents of solid nodes are zero (their state never influences a fluid
+ * update: bounce-back reads only the fluid node's own state).
+ */
+int oracle_vjp(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
+               const double *wall_u, int n_ids, const double *g_in, double rho0,
+               const double *rho_t, const double *u_t, const double *lam_rho1,
+               const double *lam_u1, double *lam_rho0, double *lam_u0, double *dL_domega)
+{
+    lattice_t L;
+    if (make_lattice(q, &L)) return -1;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (L.d == 2 && nz != 1)) return -1;
+    long n = (long)nx * ny * nz;
+    double a = 2.0 * (omega - 1.0) / omega;
+    double g[3] = {0, 0, 0};
+    if (g_in)
+        for (int k = 0; k < L.d; ++k) g[k] = g_in[k];
+    const double *gp = g_in ? g : NULL;
+
+    double *fbar = (double *)calloc((size_t)L.q * n, sizeof(double));
+    double *da = (double *)calloc((size_t)n, sizeof(double));
+    if (!fbar || !da) {
+        free(fbar);
+        free(da);
+        return -2;
+    }
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long ix = node_index(nx, ny, x, y, z);
+                lam_rho0[ix] = 0.0;
+                for (int k = 0; k < L.d; ++k) lam_u0[k * n + ix] = 0.0;
+                if (mask && mask[ix] != 0) continue;
+                double f[MAXQ];
+                node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_t,
+                                 u_t, x, y, z, f);
+                double r = 0.0, j[3] = {0, 0, 0};
+                for (int i = 0; i < L.q; ++i) {
+                    r += f[i];
+                    for (int k = 0; k < 3; ++k) j[k] += L.v[i][k] * f[i];
+                }
+                double up[3] = {j[0] / r, j[1] / r, j[2] / r};
+                double lr = lam_rho1[ix];
+                double lu[3] = {0, 0, 0};
+                for (int k = 0; k < L.d; ++k) lu[k] = lam_u1[k * n + ix];
+
+                double ux[3];
+                load_u(&L, n, ix, u_t, ux);
+                double rx = rho_t[ix];
+                double acc_r = 0.0, acc_u[3] = {0, 0, 0}, acc_a = 0.0;
+                for (int i = 0; i < L.q; ++i) {
+                    double fb = lr;
+                    for (int k = 0; k < 3; ++k) fb += lu[k] * (L.v[i][k] - up[k]) / r;
+                    fbar[(size_t)i * n + ix] = fb;
+
+                    double dr, du[3];
+                    /* post-combine term a f^(e,o)_i(x) (present for both cases) */
+                    dfeo(&L, i, rx, ux, &dr, du);
+                    acc_r += fb * a * dr;
+                    for (int k = 0; k < 3; ++k) acc_u[k] += fb * a * du[k];
+                    acc_a += fb * feo(&L, i, rx, ux);
+
+                    long iy = upstream(&L, nx, ny, nz, x, y, z, i);
+                    if (!mask || mask[iy] == 0) {
+                        double uy[3];
+                        load_u(&L, n, iy, u_t, uy);
+                        acc_a -= fb * feo(&L, i, rho_t[iy], uy);
+                    } else {
+                        int ib = L.opp[i];
+                        double uw[3];
+                        wall_velocity(wall_u, n_ids, mask[iy], uw);
+                        double er, eu[3], orr, ou[3];
+                        dfeq(&L, ib, rx, ux, &er, eu);
+                        dfeo(&L, ib, rx, ux, &orr, ou);
+                        acc_r += fb * (er - a * orr);
+                        for (int k = 0; k < 3; ++k) acc_u[k] += fb * (eu[k] - a * ou[k]);
+                        /* d/da of [-a f^(e,o)_ib(x) + (2/omega - 1) 2 f^(e,o)_i(rho0,uw)]
+                         * with 2/omega - 1 = 1 - a */
+                        acc_a += fb * (-feo(&L, ib, rx, ux) - 2.0 * feo(&L, i, rho0, uw));
+                    }
+                    if (gp) {
+                        /* forcing term f^(e,o)_i(rho(x,t), g): linear in rho(x,t) */
+                        double gr, gu[3];
+                        dfeo(&L, i, rx, g, &gr, gu);
+                        acc_r += fb * gr;
+                    }
+                }
+                lam_rho0[ix] += acc_r;
+                for (int k = 0; k < L.d; ++k) lam_u0[k * n + ix] += acc_u[k];
+                da[ix] = acc_a;
+            }
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long iy = node_index(nx, ny, x, y, z);
+                if (mask && mask[iy] != 0) continue;
+                double uy[3];
+                load_u(&L, n, iy, u_t, uy);
+                double ry = rho_t[iy];
+                double acc_r = 0.0, acc_u[3] = {0, 0, 0};
+                for (int i = 0; i < L.q; ++i) {
+                    long ixt = node_index(nx, ny, wrap(x + L.v[i][0], nx), wrap(y + L.v[i][1], ny),
+                                          wrap(z + L.v[i][2], nz));
+                    if (mask && mask[ixt] != 0) continue;
+                    double fb = fbar[(size_t)i * n + ixt];
+                    double er, eu[3], orr, ou[3];
+                    dfeq(&L, i, ry, uy, &er, eu);
+                    dfeo(&L, i, ry, uy, &orr, ou);
+                    acc_r += fb * (er - a * orr);
+                    for (int k = 0; k < 3; ++k) acc_u[k] += fb * (eu[k] - a * ou[k]);
+                }
+                lam_rho0[iy] += acc_r;
+                for (int k = 0; k < L.d; ++k) lam_u0[k * n + iy] += acc_u[k];
+            }
+
+    double s = 0.0;
+    for (long ix = 0; ix < n; ++ix) s += da[ix];
+    *dL_domega = s * 2.0 / (omega * omega); /* a = 2 - 2/omega, da/domega = 2/omega^2 */
+    free(fbar);
+    free(da);
+    return 0;
+}
