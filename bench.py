@@ -1,0 +1,181 @@
+"""Benchmark of the LW-ACM time step on one MI355X.
+
+Workload: D3Q19 Taylor-Green vortex on a 256^3 periodic grid (u0 = 0.02,
+omega = 1.7), synthetic initial field, state resident in HBM.  A timed step
+is one full forward step (gather, link terms, post-combine, normalisation,
+store, fused FP64 mass/energy reduction).  Reported beside it: the same
+step with FP16-deviation storage, the reverse (adjoint) step and the
+checkpointed forward+reverse cost, the roofline of the forward kernel, and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS D3Q19 256^3 FP32 (vs FP16-store); adjoint/forward step time ratio"
+HBM_PEAK_GBS = 8000.0
+
+
+def _events_time(fn, n, stream):
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    fn(n)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3  # seconds
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 generic, 2 march")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forward-only", action="store_true",
+                    help="time only the FP32 forward step (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU halo-exchange design is described but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1111_2142_amd import lwacm as L
+
+    L.load_library()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    n = args.n
+    cfg = wl.TGV3D_256
+    drho, u = wl.taylor_green_3d(n, cfg.u0)
+    drho_t = torch.as_tensor(drho, dtype=torch.float32, device=dev)
+    u_t = torch.as_tensor(u, dtype=torch.float32, device=dev)
+    nodes = n ** 3
+    del drho, u
+
+    def make(storage):
+        s = L.Solver(L.LWACM_D3Q19, n, n, n, cfg.omega, storage=storage, device=dev,
+                     variant=args.variant)
+        s.set_state(drho_t, u_t)
+        return s
+
+    # ---- FP32 forward (the headline)
+    s32 = make(L.LWACM_FP32)
+    s32.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dt32_ev = _events_time(s32.step, args.steps, stream)
+    wall32 = time.perf_counter() - t0
+    ms32 = dt32_ev / args.steps * 1e3
+    mlups32 = nodes * args.steps / dt32_ev / 1e6
+    mass, energy = s32.diagnostics()
+    print(f"[bench] fp32 forward: {ms32:.4f} ms/step, {mlups32:.0f} MLUPS, mass {mass:.6f}, "
+          f"energy {energy:.6e}", file=sys.stderr, flush=True)
+
+    bytes32 = 32.0 * nodes
+    achieved = bytes32 / (ms32 * 1e-3) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": round(mlups32, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"d3q19_tgv_{n}^3", "lattice": "D3Q19", "grid": [n, n, n],
+                   "omega": cfg.omega, "u0": cfg.u0, "storage": "fp32",
+                   "diagnostics": "fused FP64 mass+energy every step"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+    if args.forward_only:
+        print(json.dumps(result), flush=True)
+        return
+
+    # ---- FP16-deviation storage
+    s32_state = None
+    s16 = make(L.LWACM_FP16_DEV)
+    s16.step(args.warmup)
+    dt16 = _events_time(s16.step, args.steps, stream)
+    ms16 = dt16 / args.steps * 1e3
+    mlups16 = nodes * args.steps / dt16 / 1e6
+    print(f"[bench] fp16 forward: {ms16:.4f} ms/step, {mlups16:.0f} MLUPS", file=sys.stderr,
+          flush=True)
+    s16.close()
+    result["fp16_store"] = {"value": round(mlups16, 1), "unit": "MLUPS",
+                            "ms_per_step": round(ms16, 5),
+                            "achieved_GBs": round(16.0 * nodes / dt16 * args.steps / 1e9, 1)}
+
+    # ---- reverse step at the same size (reads state_t and mu_t, writes mu_{t-1})
+    st = s32.save_state()
+    mu_a = torch.zeros((4, n, n, n), dtype=torch.float32, device=dev)
+    mu_b = torch.zeros_like(mu_a)
+    dw = torch.zeros(1, dtype=torch.float64, device=dev)
+    lam = torch.zeros_like(mu_a)
+    lam[1:] = u_t
+    L.lwacm_adjoint_seed(s32.ctx, st, lam, mu_a)
+    nadj = max(10, args.steps // 4)
+
+    def adj(k):
+        a, b = mu_a, mu_b
+        for _ in range(k):
+            L.lwacm_adjoint_step(s32.ctx, st, a, b, dw, False)
+            a, b = b, a
+
+    adj(3)
+    dta = _events_time(adj, nadj, stream)
+    msa = dta / nadj * 1e3
+    print(f"[bench] reverse step: {msa:.4f} ms/step", file=sys.stderr, flush=True)
+    result["adjoint"] = {"ms_per_step": round(msa, 5),
+                         "adjoint_forward_ratio": round(msa / ms32, 3),
+                         "with_recompute_ratio": round((msa + ms32) / ms32, 3),
+                         "achieved_GBs": round(48.0 * nodes / (msa * 1e-3) / 1e9, 1)}
+    s32.close()
+    del mu_a, mu_b, lam, st
+    torch.cuda.empty_cache()
+
+    # ---- FP64 CPU oracle on a bounded sample of the same workload
+    if not args.no_cpu_baseline:
+        import oracle
+        p = oracle.Problem(q=19, nx=n, ny=n, nz=n, omega=cfg.omega)
+        d0, u0 = wl.taylor_green_3d(n, cfg.u0)
+        r0 = 1.0 + d0
+        del d0
+        oracle.run(p, r0, u0, 1)   # warm-up (page-in)
+        nsteps_cpu = 2
+        t0 = time.perf_counter()
+        oracle.run(p, r0, u0, nsteps_cpu)
+        dtc = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": round(nodes * nsteps_cpu / dtc / 1e6, 3), "unit": "MLUPS",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{nsteps_cpu} steps of the full {n}^3 D3Q19 grid (FP64, OpenMP over z-y rows)"}
+        print(f"[bench] cpu oracle: {result['cpu_baseline']['value']} MLUPS on "
+              f"{oracle.num_threads()} threads", file=sys.stderr, flush=True)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * lwacm.h -- C ABI of the MI355X (gfx950) LW-ACM library.
+ *
+ * The library advances the link-wise artificial compressibility method
+ * (LW-ACM; Asinari, Ohwada, Chiavazzo, Di Rienzo, arXiv:1111.2142) on the
+ * D2Q9 and D3Q19 lattices.  Every node pulls the stored moments of its
+ * upstream link neighbours, evaluates the link equilibria and their odd
+ * parts, applies the update of Eq. ACM2.0 (Section 2.1) and sums the new
+ * moments.  No populations are stored: the state is D+1 fields per node.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grid: nx * ny * nz nodes (nz = 1 for D2Q9), node index
+ *    ((z * ny) + y) * nx + x, x fastest.  Every axis is periodic; walls are
+ *    solid nodes of the mask.
+ *  - State buffers (caller-owned device memory, lwacm_state_bytes() bytes
+ *    each): structure of arrays, field-major: field 0 is rho - 1, fields
+ *    1..D are u_x, u_y (, u_z).  Storage LWACM_FP32 holds float; storage
+ *    LWACM_FP16_DEV holds IEEE half values of (field * 2^k), with k set by
+ *    lwacm_set_fp16_scales (default 14 for both), rounded to nearest even.
+ *    Arithmetic is always FP32.
+ *  - FP32 field arguments (d_drho, d_u, d_lambda, d_mu) are device arrays
+ *    in the same SoA order: d_drho has nodes floats, d_u has D * nodes.
+ *  - Every call is asynchronous on the stream given to lwacm_init unless it
+ *    returns host values (stated per call).  Pointers are not retained
+ *    beyond the call unless stated.
+ *  - Errors: calls return LWACM_OK (0) or a negative code; no C++
+ *    exception crosses the ABI.  A failed launch returns LWACM_EDEVICE.
+ *    lwacm_strerror() names every code.
+ */
+#ifndef LWACM_H
+#define LWACM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lwacm_ctx lwacm_ctx; /* opaque; owned by the library */
+
+enum { LWACM_D2Q9 = 9, LWACM_D3Q19 = 19 };
+enum { LWACM_FP32 = 0, LWACM_FP16_DEV = 1 };
+enum {
+    LWACM_OK = 0,
+    LWACM_EINVAL = -1,      /* bad argument (null pointer, size, omega, mask value) */
+    LWACM_ENOMEM = -2,      /* the library could not allocate its scratch */
+    LWACM_EDEVICE = -3,     /* a HIP call or kernel launch failed */
+    LWACM_ENONFINITE = -4,  /* mass or kinetic energy is not finite (blow-up) */
+    LWACM_EUNSUPPORTED = -5 /* valid request this build does not implement */
+};
+
+/* Kernel selection for lwacm_set_variant. */
+enum {
+    LWACM_KERNEL_AUTO = 0,    /* fastest kernel that supports the problem */
+    LWACM_KERNEL_GENERIC = 1, /* one thread per node, neighbours from global memory */
+    LWACM_KERNEL_MARCH = 2    /* D3Q19 z-marching tile kernel */
+};
+
+/* Bytes of one state buffer: (D+1) * nodes * (4 for FP32, 2 for FP16).
+ * Returns 0 for an invalid lattice, size or storage. */
+size_t lwacm_state_bytes(int lattice, int nx, int ny, int nz, int storage);
+
+/*
+ * Create a context for one problem, as the paper states it (Sections 2.1,
+ * 2.3-2.4 and 3): lattice, grid, relaxation frequency omega (viscosity
+ * nu = (1/omega - 1/2)/3, Eq. viscosity2), walls, body acceleration.
+ *
+ *  lattice      LWACM_D2Q9 or LWACM_D3Q19 (Appendix A).
+ *  nx, ny, nz   grid size, each >= 1; nz must be 1 for D2Q9.
+ *  omega        0 < omega < 2 (the paper finds LW-ACM stable for
+ *               1 <= omega < 2; smaller values are accepted).
+ *  storage      LWACM_FP32 or LWACM_FP16_DEV.
+ *  d_state_a/b  two caller-owned device buffers of lwacm_state_bytes() bytes
+ *               (the two toggled arrays); kept until lwacm_destroy.  The
+ *               current state starts in d_state_a.
+ *  d_mask       NULL (all fluid) or nodes uint8 values kept until destroy:
+ *               0 fluid, m >= 1 a solid node whose wall moves with
+ *               h_wall_u[3m .. 3m+2].  Fluid nodes next to a solid node use
+ *               halfway bounce-back (Eqs. ACM2.0cbb-ACM2.0cccbb2) with the
+ *               moving-wall term of Eq. ACM2.0ccccbb.  Solid nodes are
+ *               never updated.  Values >= n_wall_ids (>= 2 when h_wall_u is
+ *               NULL) give LWACM_EINVAL.
+ *  h_wall_u     host table of n_wall_ids velocities (3 floats each), or NULL
+ *               (all walls at rest); copied.  n_wall_ids <= 16.
+ *  d_q          link-wall distances for interpolated bounce-back
+ *               (Eqs. ACM2.0cc, ACM2.0move): must be NULL (q = 1/2, halfway
+ *               walls); non-NULL gives LWACM_EUNSUPPORTED.
+ *  h_g          host body acceleration g[3] (Eq. force), or NULL; copied.
+ *  stream       HIP stream every call of this context is issued on.
+ *
+ * On success *out holds the context; on failure *out is NULL.  The call
+ * synchronises the stream once (mask validation).
+ */
+int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omega, int storage,
+               void *d_state_a, void *d_state_b, const uint8_t *d_mask, const float *h_wall_u,
+               int n_wall_ids, const float *d_q, const float *h_g, hipStream_t stream);
+
+/* FP16 storage scales: stored value = field * 2^k (k_rho for rho - 1, k_u for
+ * u).  0 <= k <= 24.  Takes effect at the next lwacm_set_state. */
+int lwacm_set_fp16_scales(lwacm_ctx *c, int k_rho, int k_u);
+
+/* Choose the kernel (LWACM_KERNEL_*); LWACM_EUNSUPPORTED if the kernel
+ * cannot run this problem. */
+int lwacm_set_variant(lwacm_ctx *c, int variant);
+
+/* Load the state from FP32 fields (rho - 1 and u, SoA), converting to the
+ * storage format, and set rho0 (the mean fluid density used by moving walls,
+ * Section 3.2) to the mean of 1 + d_drho over fluid nodes.  Resets the step
+ * counter.  Synchronises the stream (rho0 reduction). */
+int lwacm_set_state(lwacm_ctx *c, const float *d_drho, const float *d_u);
+
+/* Advance nsteps >= 0 time steps (Eq. ACM2.0 with forcing Eq. force and the
+ * wall rules), toggling the two state buffers.  Each step also reduces the
+ * mass sum(rho) and kinetic energy 1/2 sum|u|^2 of its output over fluid
+ * nodes in FP64 (per-block partials, fixed-order final sum: bitwise
+ * reproducible); see lwacm_diagnostics.  Asynchronous. */
+int lwacm_step(lwacm_ctx *c, int nsteps);
+
+/* Mass and energy of the state after the most recent lwacm_step (host
+ * doubles; synchronises the stream).  LWACM_ENONFINITE if either is not
+ * finite; LWACM_EINVAL if no step ran since lwacm_set_state/load_state. */
+int lwacm_diagnostics(lwacm_ctx *c, double *h_mass, double *h_energy);
+
+/* Optional device history: step k (counted from lwacm_set_state) also writes
+ * its (mass, energy) to d_hist[2 * (k % capacity)].  NULL disables. */
+int lwacm_set_diag_history(lwacm_ctx *c, double *d_hist, int capacity);
+
+/* Current state as FP32 fields: d_drho (rho - 1) and d_u (either may be
+ * NULL), and, if h_mass/h_energy are non-NULL, the FP64 mass sum(rho) and
+ * energy 1/2 sum|u|^2 over fluid nodes (then the call synchronises and may
+ * return LWACM_ENONFINITE). */
+int lwacm_moments(lwacm_ctx *c, float *d_drho, float *d_u, double *h_mass, double *h_energy);
+
+/* Copy the current state buffer (storage format) to / from caller memory of
+ * lwacm_state_bytes() bytes, for checkpoints.  load_state keeps rho0 and sets
+ * the step counter to `step`. */
+int lwacm_save_state(lwacm_ctx *c, void *d_dst);
+int lwacm_load_state(lwacm_ctx *c, const void *d_src, long long step);
+
+/* Device pointer to the current state buffer (storage format). */
+const void *lwacm_current_state(lwacm_ctx *c);
+
+/* Steps taken since lwacm_set_state (or the value given to load_state). */
+long long lwacm_step_count(lwacm_ctx *c);
+
+/*
+ * Reverse mode (not in the paper: the exact derivative of the step above).
+ *
+ * Notation: one forward step maps state_t to state_{t+1}; its outputs are
+ * rho+ = 1 + D and u+ = J / rho+ with D = sum of link terms and J the new
+ * momentum.  The reverse sweep carries mu_t = (dL/dD, dL/dJ) of step t, a
+ * (D+1)-field FP32 array in the state's SoA order.
+ *
+ * lwacm_adjoint_seed: mu_{T-1} from the loss cotangent lambda_T = (dL/d(rho-1),
+ *   dL/du) of the final state and that state (storage format):
+ *   mu_R = lambda_rho - lambda_u . u / rho, mu_J = lambda_u / rho; zero on
+ *   solid nodes.
+ * lwacm_adjoint_step: given state_t (storage format, the input of step t)
+ *   and mu_t, computes lambda_t = dL/d state_t and writes
+ *     final_t0 == 0: mu_{t-1} = (lambda_rho - lambda_u . u_t / rho_t, lambda_u / rho_t)
+ *     final_t0 != 0: lambda_t itself (the gradient with respect to the
+ *                    initial (rho - 1, u)),
+ *   and adds this step's dL/domega to *d_dL_domega (device FP64 scalar,
+ *   fixed-order reduction: bitwise reproducible).  rho0 and the walls are
+ *   constants of the problem.  d_mu_out must not alias d_mu_in.
+ * Both are asynchronous.
+ */
+int lwacm_adjoint_seed(lwacm_ctx *c, const void *d_state_T, const float *d_lambda_T, float *d_mu);
+int lwacm_adjoint_step(lwacm_ctx *c, const void *d_state_t, const float *d_mu_in, float *d_mu_out,
+                       double *d_dL_domega, int final_t0);
+
+/* Release the library's scratch.  Caller buffers are untouched. */
+void lwacm_destroy(lwacm_ctx *c);
+
+/* Static text for an error code. */
+const char *lwacm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LWACM_H */

@@ -48,6 +48,9 @@ def _load():
     lib.oracle_step.restype = ctypes.c_int
     lib.oracle_vjp.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_vjp.restype = ctypes.c_int
+    lib.oracle_step_nodes.argtypes = common + [_dp, _dp, ctypes.POINTER(ctypes.c_long),
+                                               ctypes.c_long, _dp, _dp]
+    lib.oracle_step_nodes.restype = ctypes.c_int
     lib.oracle_diagnostics.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        _u8p, _dp, _dp, _dp, _dp]
     lib.oracle_diagnostics.restype = ctypes.c_int
@@ -144,6 +147,25 @@ def step(p: Problem, rho, u):
     if rc != 0:
         raise RuntimeError(f"oracle_step failed ({rc})")
     return r1, u1
+
+
+def step_nodes(p: Problem, rho, u, idx):
+    """One step evaluated only at the flat node indices ``idx``.
+
+    Returns (rho_new[len(idx)], u_new[D, len(idx)]).
+    """
+    lib = _load()
+    rho = _f64(rho, p.shape)
+    u = _f64(u, (p.d,) + p.shape)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    r = np.empty(len(idx))
+    uu = np.empty((len(idx), p.d))
+    rc = lib.oracle_step_nodes(*p._args(), _ptr(rho), _ptr(u),
+                               idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(idx),
+                               _ptr(r), _ptr(uu))
+    if rc != 0:
+        raise RuntimeError(f"oracle_step_nodes failed ({rc})")
+    return r, np.ascontiguousarray(uu.T)
 
 
 def run(p: Problem, rho, u, nsteps: int, callback: Optional[Callable] = None):

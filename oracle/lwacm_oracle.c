@@ -280,6 +280,46 @@ int oracle_step(int q, int nx, int ny, int nz, double omega, const uint8_t *mask
     return 0;
 }
 
+/* The same update for a list of nodes only (for spot checks of large grids
+ * the full-grid loop would be too slow for).  rho_sel/u_sel receive the new
+ * state of node idx[k] at position k (u_sel: D values per node). */
+int oracle_step_nodes(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
+                      const double *wall_u, int n_ids, const double *g_in, double rho0,
+                      const double *rho_in, const double *u_in, const long *idx, long count,
+                      double *rho_sel, double *u_sel)
+{
+    lattice_t L;
+    if (make_lattice(q, &L)) return -1;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (L.d == 2 && nz != 1)) return -1;
+    long n = (long)nx * ny * nz;
+    double g[3] = {0, 0, 0};
+    if (g_in)
+        for (int k = 0; k < L.d; ++k) g[k] = g_in[k];
+    const double *gp = g_in ? g : NULL;
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < count; ++k) {
+        long ix = idx[k];
+        if (ix < 0 || ix >= n) continue;
+        if (mask && mask[ix] != 0) {
+            rho_sel[k] = rho_in[ix];
+            for (int c = 0; c < L.d; ++c) u_sel[k * L.d + c] = u_in[c * n + ix];
+            continue;
+        }
+        int x = (int)(ix % nx), y = (int)((ix / nx) % ny), z = (int)(ix / ((long)nx * ny));
+        double f[MAXQ];
+        node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_in, u_in, x,
+                         y, z, f);
+        double r = 0.0, j[3] = {0, 0, 0};
+        for (int i = 0; i < L.q; ++i) {
+            r += f[i];
+            for (int c = 0; c < 3; ++c) j[c] += L.v[i][c] * f[i];
+        }
+        rho_sel[k] = r;
+        for (int c = 0; c < L.d; ++c) u_sel[k * L.d + c] = j[c] / r;
+    }
+    return 0;
+}
+
 /* Mass sum(rho) and energy 1/2 sum |u|^2 over fluid nodes. */
 int oracle_diagnostics(int q, int nx, int ny, int nz, const uint8_t *mask, const double *rho,
                        const double *u, double *mass, double *energy)

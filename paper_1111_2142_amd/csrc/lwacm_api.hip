@@ -1,0 +1,381 @@
+// lwacm_api.hip -- the C ABI declared in include/lwacm.h: argument checks,
+// context and scratch management, buffer toggling and kernel dispatch.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "lwacm.h"
+#include "lwacm_internal.hpp"
+
+using lwacm::ProblemArgs;
+using lwacm::ReduceArgs;
+
+struct lwacm_ctx {
+    ProblemArgs p;
+    int lattice;
+    int storage;
+    int variant;  // requested LWACM_KERNEL_*
+    bool force;
+    double omega;
+    double rho0;
+    void *buf[2];
+    int cur;
+    float wall_u[lwacm::kMaxWallIds][3];
+    int n_wall_ids;
+    int k_rho, k_u;
+    hipStream_t stream;
+    double *d_partials;
+    size_t n_partial_blocks;
+    unsigned *d_counter;
+    double *d_diag;     // [2] mass deviation, energy of the last step's output
+    double *d_scratch;  // [2] for lwacm_moments
+    unsigned *d_scan;   // [2] mask scan
+    double *d_hist;
+    int hist_cap;
+    long long steps;
+    bool diag_valid;
+    unsigned long long n_fluid;
+};
+
+namespace {
+
+int dev_err(hipError_t e)
+{
+    return e == hipSuccess ? LWACM_OK : LWACM_EDEVICE;
+}
+
+void set_wall_terms(lwacm_ctx *c)
+{
+    const float a = c->p.a;
+    for (int m = 0; m < lwacm::kMaxWallIds; ++m)
+        for (int k = 0; k < 3; ++k) {
+            const double uw = (m < c->n_wall_ids) ? c->wall_u[m][k] : 0.0;
+            c->p.wall_da[m][k] = (float)(6.0 * c->rho0 * uw);
+            c->p.wall_term[m][k] = (float)((1.0 - a) * 6.0 * c->rho0 * uw);
+        }
+}
+
+void set_scales(lwacm_ctx *c)
+{
+    if (c->storage == LWACM_FP16_DEV) {
+        c->p.st_scale[0] = ldexpf(1.0f, c->k_rho);
+        c->p.st_scale[1] = ldexpf(1.0f, c->k_u);
+        c->p.ld_scale[0] = ldexpf(1.0f, -c->k_rho);
+        c->p.ld_scale[1] = ldexpf(1.0f, -c->k_u);
+    } else {
+        c->p.st_scale[0] = c->p.st_scale[1] = 1.0f;
+        c->p.ld_scale[0] = c->p.ld_scale[1] = 1.0f;
+    }
+}
+
+ReduceArgs reduce_args(lwacm_ctx *c, double *out, double *out2)
+{
+    ReduceArgs r;
+    r.partials = c->d_partials;
+    r.counter = c->d_counter;
+    r.out = out;
+    r.out2 = out2;
+    r.accumulate = 0;
+    r.out_scale = 1.0;
+    return r;
+}
+
+bool use_march(const lwacm_ctx *c)
+{
+    if (c->variant == LWACM_KERNEL_GENERIC) return false;
+    return lwacm::march_supported(c->p);
+}
+
+void free_scratch(lwacm_ctx *c)
+{
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_counter) (void)hipFree(c->d_counter);
+    if (c->d_diag) (void)hipFree(c->d_diag);
+    if (c->d_scratch) (void)hipFree(c->d_scratch);
+    if (c->d_scan) (void)hipFree(c->d_scan);
+    c->d_partials = nullptr;
+    c->d_counter = nullptr;
+    c->d_diag = c->d_scratch = nullptr;
+    c->d_scan = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lwacm_state_bytes(int lattice, int nx, int ny, int nz, int storage)
+{
+    if ((lattice != LWACM_D2Q9 && lattice != LWACM_D3Q19) || nx < 1 || ny < 1 || nz < 1) return 0;
+    if (lattice == LWACM_D2Q9 && nz != 1) return 0;
+    if (storage != LWACM_FP32 && storage != LWACM_FP16_DEV) return 0;
+    const size_t fields = (lattice == LWACM_D2Q9) ? 3 : 4;
+    return fields * (size_t)nx * (size_t)ny * (size_t)nz * (storage == LWACM_FP32 ? 4 : 2);
+}
+
+const char *lwacm_strerror(int code)
+{
+    switch (code) {
+    case LWACM_OK: return "success";
+    case LWACM_EINVAL: return "invalid argument";
+    case LWACM_ENOMEM: return "out of device memory for library scratch";
+    case LWACM_EDEVICE: return "HIP runtime or kernel launch error";
+    case LWACM_ENONFINITE: return "non-finite mass or kinetic energy (unstable run)";
+    case LWACM_EUNSUPPORTED: return "not supported by this build";
+    default: return "unknown error code";
+    }
+}
+
+int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omega, int storage,
+               void *d_state_a, void *d_state_b, const uint8_t *d_mask, const float *h_wall_u,
+               int n_wall_ids, const float *d_q, const float *h_g, hipStream_t stream)
+{
+    if (!out) return LWACM_EINVAL;
+    *out = nullptr;
+    if (lwacm_state_bytes(lattice, nx, ny, nz, storage) == 0) return LWACM_EINVAL;
+    if (!(omega > 0.0 && omega < 2.0)) return LWACM_EINVAL;
+    if (!d_state_a || !d_state_b || d_state_a == d_state_b) return LWACM_EINVAL;
+    if (h_wall_u && (n_wall_ids < 1 || n_wall_ids > lwacm::kMaxWallIds)) return LWACM_EINVAL;
+    if (d_q) return LWACM_EUNSUPPORTED;
+
+    lwacm_ctx *c = new (std::nothrow) lwacm_ctx;
+    if (!c) return LWACM_ENOMEM;
+    memset(c, 0, sizeof(*c));
+    c->lattice = lattice;
+    c->storage = storage;
+    c->variant = LWACM_KERNEL_AUTO;
+    c->omega = omega;
+    c->rho0 = 1.0;
+    c->buf[0] = d_state_a;
+    c->buf[1] = d_state_b;
+    c->stream = stream;
+    c->k_rho = c->k_u = 14;
+    ProblemArgs &p = c->p;
+    p.Q = lattice;
+    p.D = lattice == LWACM_D2Q9 ? 2 : 3;
+    p.nx = nx;
+    p.ny = ny;
+    p.nz = nz;
+    p.n = (long long)nx * ny * nz;
+    p.a = (float)(2.0 - 2.0 / omega);
+    p.A = (float)(3.0 * (2.0 / omega - 1.0));
+    p.mask = d_mask;
+    if (h_g) {
+        for (int k = 0; k < p.D; ++k) p.g[k] = h_g[k];
+        c->force = true;
+    }
+    if (h_wall_u) {
+        c->n_wall_ids = n_wall_ids;
+        for (int m = 0; m < n_wall_ids; ++m)
+            for (int k = 0; k < 3; ++k) c->wall_u[m][k] = h_wall_u[3 * m + k];
+    }
+    set_scales(c);
+    set_wall_terms(c);
+
+    size_t nb = lwacm::kGenericMaxBlocks;
+    const size_t mb = lwacm::march_num_blocks(p);
+    if (mb > nb) nb = mb;
+    c->n_partial_blocks = nb;
+    hipError_t e = hipMalloc(&c->d_partials, 2 * nb * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&c->d_counter, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMalloc(&c->d_diag, 2 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&c->d_scratch, 2 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&c->d_scan, 2 * sizeof(unsigned));
+    if (e != hipSuccess) {
+        free_scratch(c);
+        delete c;
+        return LWACM_ENOMEM;
+    }
+    e = hipMemsetAsync(c->d_counter, 0, sizeof(unsigned), stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_diag, 0, 2 * sizeof(double), stream);
+
+    c->n_fluid = (unsigned long long)p.n;
+    if (e == hipSuccess && d_mask) {
+        e = hipMemsetAsync(c->d_scan, 0, 2 * sizeof(unsigned), stream);
+        if (e == hipSuccess) e = lwacm::launch_mask_scan(p, c->d_scan, stream);
+        unsigned scan[2] = {0, 0};
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(scan, c->d_scan, sizeof(scan), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e == hipSuccess) {
+            const unsigned limit = h_wall_u ? (unsigned)n_wall_ids : 2u;
+            if (scan[0] >= limit) {
+                free_scratch(c);
+                delete c;
+                return LWACM_EINVAL;
+            }
+            c->n_fluid = scan[1];
+        }
+    }
+    if (e != hipSuccess) {
+        free_scratch(c);
+        delete c;
+        return LWACM_EDEVICE;
+    }
+    *out = c;
+    return LWACM_OK;
+}
+
+int lwacm_set_fp16_scales(lwacm_ctx *c, int k_rho, int k_u)
+{
+    if (!c || k_rho < 0 || k_rho > 24 || k_u < 0 || k_u > 24) return LWACM_EINVAL;
+    c->k_rho = k_rho;
+    c->k_u = k_u;
+    set_scales(c);
+    return LWACM_OK;
+}
+
+int lwacm_set_variant(lwacm_ctx *c, int variant)
+{
+    if (!c) return LWACM_EINVAL;
+    if (variant == LWACM_KERNEL_AUTO || variant == LWACM_KERNEL_GENERIC) {
+        c->variant = variant;
+        return LWACM_OK;
+    }
+    if (variant == LWACM_KERNEL_MARCH) {
+        if (!lwacm::march_supported(c->p)) return LWACM_EUNSUPPORTED;
+        c->variant = variant;
+        return LWACM_OK;
+    }
+    return LWACM_EINVAL;
+}
+
+int lwacm_set_state(lwacm_ctx *c, const float *d_drho, const float *d_u)
+{
+    if (!c || !d_drho || !d_u) return LWACM_EINVAL;
+    set_scales(c);
+    hipError_t e = lwacm::launch_set_state(c->p, c->storage, d_drho, d_u, c->buf[c->cur], c->stream);
+    if (e != hipSuccess) return LWACM_EDEVICE;
+    // rho0 = mean fluid density of the stored state (moving-wall term)
+    ReduceArgs r = reduce_args(c, c->d_scratch, nullptr);
+    e = lwacm::launch_moments(c->p, c->storage, c->buf[c->cur], nullptr, nullptr, r,
+                              lwacm::generic_grid(c->p.n), c->stream);
+    double h[2] = {0.0, 0.0};
+    if (e == hipSuccess) e = hipMemcpyAsync(h, c->d_scratch, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return LWACM_EDEVICE;
+    if (!isfinite(h[0]) || !isfinite(h[1])) return LWACM_ENONFINITE;
+    c->rho0 = c->n_fluid ? 1.0 + h[0] / (double)c->n_fluid : 1.0;
+    set_wall_terms(c);
+    c->steps = 0;
+    c->diag_valid = false;
+    return LWACM_OK;
+}
+
+int lwacm_step(lwacm_ctx *c, int nsteps)
+{
+    if (!c || nsteps < 0) return LWACM_EINVAL;
+    const bool march = use_march(c);
+    const unsigned gb = lwacm::generic_grid(c->p.n);
+    for (int s = 0; s < nsteps; ++s) {
+        double *hist = nullptr;
+        if (c->d_hist) hist = c->d_hist + 2 * (size_t)((c->steps + 1) % c->hist_cap);
+        ReduceArgs r = reduce_args(c, c->d_diag, hist);
+        const void *src = c->buf[c->cur];
+        void *dst = c->buf[c->cur ^ 1];
+        hipError_t e = march ? lwacm::launch_fwd_march(c->p, c->storage, c->force, src, dst, r, c->stream)
+                             : lwacm::launch_fwd_generic(c->p, c->storage, c->force, src, dst, r, gb,
+                                                         c->stream);
+        if (e != hipSuccess) return LWACM_EDEVICE;
+        c->cur ^= 1;
+        c->steps += 1;
+        c->diag_valid = true;
+    }
+    return LWACM_OK;
+}
+
+int lwacm_diagnostics(lwacm_ctx *c, double *h_mass, double *h_energy)
+{
+    if (!c || !h_mass || !h_energy) return LWACM_EINVAL;
+    if (!c->diag_valid) return LWACM_EINVAL;
+    double h[2];
+    hipError_t e = hipMemcpyAsync(h, c->d_diag, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return LWACM_EDEVICE;
+    *h_mass = (double)c->n_fluid + h[0];
+    *h_energy = h[1];
+    return (isfinite(h[0]) && isfinite(h[1])) ? LWACM_OK : LWACM_ENONFINITE;
+}
+
+int lwacm_set_diag_history(lwacm_ctx *c, double *d_hist, int capacity)
+{
+    if (!c || (d_hist && capacity < 1)) return LWACM_EINVAL;
+    c->d_hist = d_hist;
+    c->hist_cap = d_hist ? capacity : 0;
+    return LWACM_OK;
+}
+
+int lwacm_moments(lwacm_ctx *c, float *d_drho, float *d_u, double *h_mass, double *h_energy)
+{
+    if (!c) return LWACM_EINVAL;
+    ReduceArgs r = reduce_args(c, c->d_scratch, nullptr);
+    hipError_t e = lwacm::launch_moments(c->p, c->storage, c->buf[c->cur], d_drho, d_u, r,
+                                         lwacm::generic_grid(c->p.n), c->stream);
+    if (e != hipSuccess) return LWACM_EDEVICE;
+    if (!h_mass && !h_energy) return LWACM_OK;
+    double h[2];
+    e = hipMemcpyAsync(h, c->d_scratch, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return LWACM_EDEVICE;
+    if (h_mass) *h_mass = (double)c->n_fluid + h[0];
+    if (h_energy) *h_energy = h[1];
+    return (isfinite(h[0]) && isfinite(h[1])) ? LWACM_OK : LWACM_ENONFINITE;
+}
+
+int lwacm_save_state(lwacm_ctx *c, void *d_dst)
+{
+    if (!c || !d_dst) return LWACM_EINVAL;
+    const size_t bytes = lwacm_state_bytes(c->lattice, c->p.nx, c->p.ny, c->p.nz, c->storage);
+    return dev_err(hipMemcpyAsync(d_dst, c->buf[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream));
+}
+
+int lwacm_load_state(lwacm_ctx *c, const void *d_src, long long step)
+{
+    if (!c || !d_src || step < 0) return LWACM_EINVAL;
+    const size_t bytes = lwacm_state_bytes(c->lattice, c->p.nx, c->p.ny, c->p.nz, c->storage);
+    hipError_t e = hipMemcpyAsync(c->buf[c->cur], d_src, bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return LWACM_EDEVICE;
+    c->steps = step;
+    c->diag_valid = false;
+    return LWACM_OK;
+}
+
+const void *lwacm_current_state(lwacm_ctx *c)
+{
+    return c ? c->buf[c->cur] : nullptr;
+}
+
+long long lwacm_step_count(lwacm_ctx *c)
+{
+    return c ? c->steps : -1;
+}
+
+int lwacm_adjoint_seed(lwacm_ctx *c, const void *d_state_T, const float *d_lambda_T, float *d_mu)
+{
+    if (!c || !d_state_T || !d_lambda_T || !d_mu || (const void *)d_lambda_T == (const void *)d_mu)
+        return LWACM_EINVAL;
+    return dev_err(lwacm::launch_adj_seed(c->p, c->storage, d_state_T, d_lambda_T, d_mu, c->stream));
+}
+
+int lwacm_adjoint_step(lwacm_ctx *c, const void *d_state_t, const float *d_mu_in, float *d_mu_out,
+                       double *d_dL_domega, int final_t0)
+{
+    if (!c || !d_state_t || !d_mu_in || !d_mu_out || !d_dL_domega || d_mu_in == d_mu_out)
+        return LWACM_EINVAL;
+    ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
+    r.accumulate = 1;
+    r.out_scale = 2.0 / (c->omega * c->omega);  // da/domega for a = 2 - 2/omega
+    return dev_err(lwacm::launch_adj_generic(c->p, c->storage, d_state_t, d_mu_in, d_mu_out,
+                                             final_t0, r, lwacm::generic_grid(c->p.n), c->stream));
+}
+
+void lwacm_destroy(lwacm_ctx *c)
+{
+    if (!c) return;
+    free_scratch(c);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,198 @@
+// lwacm_device.hpp -- device-side building blocks of the LW-ACM kernels:
+// lattice tables, the per-link term of the update, storage conversion and a
+// deterministic FP64 grid reduction.  gfx950 only (wave64).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lwacm {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- lattices
+// Link velocities grouped by their z component (Appendix A lists the groups
+// rest / axis / diagonal; the order inside is free).  The nine links with
+// v_z = 0 come first and are exactly the D2Q9 set, so both lattices share
+// indices 0..8:
+//   0 rest, 1 (+x), 2 (-x), 3 (+y), 4 (-y), 5 (+x+y), 6 (-x-y), 7 (+x-y), 8 (-x+y),
+//   9 (+z), 10 (+x+z), 11 (-x+z), 12 (+y+z), 13 (-y+z),
+//   14 (-z), 15 (-x-z), 16 (+x-z), 17 (-y-z), 18 (+y-z).
+// Links 14..18 are the opposites of 9..13 in the same order; 1..8 pair up
+// as (1,2), (3,4), (5,6), (7,8).
+__host__ __device__ constexpr int link_cx(int i)
+{
+    constexpr int t[19] = {0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 1, -1, 0, 0, 0, -1, 1, 0, 0};
+    return t[i];
+}
+__host__ __device__ constexpr int link_cy(int i)
+{
+    constexpr int t[19] = {0, 0, 0, 1, -1, 1, -1, -1, 1, 0, 0, 0, 1, -1, 0, 0, 0, -1, 1};
+    return t[i];
+}
+__host__ __device__ constexpr int link_cz(int i)
+{
+    constexpr int t[19] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, -1, -1, -1, -1, -1};
+    return t[i];
+}
+__host__ __device__ constexpr int link_opp(int i)
+{
+    constexpr int t[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 14, 15, 16, 17, 18, 9, 10, 11, 12, 13};
+    return t[i];
+}
+
+template <int Q>
+struct Lattice;
+
+// D2Q9: weights 4/9, 1/9 (axis), 1/36 (diagonal), Eq. weight_factors.
+template <>
+struct Lattice<9> {
+    static constexpr int Q = 9;
+    static constexpr int D = 2;
+    __host__ __device__ static constexpr float w(int i)
+    {
+        return i == 0 ? 4.0f / 9.0f : (i <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f);
+    }
+};
+
+// D3Q19: weights 1/3, 1/18 (axis), 1/36 (face diagonal), Eq. weight_factors_3d.
+template <>
+struct Lattice<19> {
+    static constexpr int Q = 19;
+    static constexpr int D = 3;
+    __host__ __device__ static constexpr float w(int i)
+    {
+        return i == 0 ? 1.0f / 3.0f
+                      : ((i <= 4 || i == 9 || i == 14) ? 1.0f / 18.0f : 1.0f / 36.0f);
+    }
+};
+
+// ------------------------------------------------------ the link term
+// Pre-combined population of Eq. ACM2.0b (pre-combining step), in deviation
+// form: f*_i - w_i = w_i [drho + rho (c (A + 9/2 c) - 3/2 |u|^2)] with
+// c = v_i . u and A = 3 (2/omega - 1) = 3 (1 - a).  It follows from the
+// equilibrium of Appendix A and the odd part f^(e,o)_i = 3 w_i rho c.
+// The caller passes B = -3/2 |u|^2 and v_i . u.
+__device__ __forceinline__ float link_term_unweighted(float drho, float rho, float c, float B,
+                                                      float A)
+{
+    float t = fmaf(4.5f, c, A);
+    t = fmaf(c, t, B);
+    return fmaf(rho, t, drho);
+}
+
+// New velocity u = J / (1 + D) with D = rho - 1 of the updated node, written
+// as u = J - J * q with q = D / (1 + D).  Forming 1 + D in FP32 loses the low
+// bits of D; in this form that loss only scales the O(D) correction, so the
+// per-step error stays at one rounding of u.  The reciprocal is the hardware
+// approximation (1 ulp), which is ample for the correction term.
+__device__ __forceinline__ float normalisation_factor(float D)
+{
+    return D * __builtin_amdgcn_rcpf(1.0f + D);
+}
+
+// ------------------------------------------------------- storage formats
+template <class T>
+struct Storage;
+
+template <>
+struct Storage<float> {
+    __device__ __forceinline__ static float load(const float *p, long long i, float)
+    {
+        return p[i];
+    }
+    __device__ __forceinline__ static void store(float *p, long long i, float v, float)
+    {
+        p[i] = v;
+    }
+};
+
+// FP16 deviation storage: value * 2^k rounded to nearest even; the scale
+// arguments are 2^-k on load and 2^k on store (exact in FP32).
+template <>
+struct Storage<__half> {
+    __device__ __forceinline__ static float load(const __half *p, long long i, float inv_scale)
+    {
+        return __half2float(p[i]) * inv_scale;
+    }
+    __device__ __forceinline__ static void store(__half *p, long long i, float v, float scale)
+    {
+        p[i] = __float2half_rn(v * scale);
+    }
+};
+
+// --------------------------------------------- deterministic reductions
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+    return v;
+}
+
+// Sum NV doubles over the block into thread 0 with a fixed tree.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV])
+{
+    __shared__ double sh[NV][16];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[k][wid] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += sh[k][w];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Grid-wide sum of NV doubles per block.  Each block stores its block sum in
+// partials[NV*bid + k]; the block that finishes last (counted with an
+// agent-scope atomic) adds all partials in a fixed order, so the result does
+// not depend on scheduling.  Returns true in every thread of that last block;
+// thread 0 of it then holds the totals in `out` and has reset the counter.
+template <int NV>
+__device__ bool grid_sum_last_block(double (&v)[NV], double *partials, unsigned *counter,
+                                    unsigned nblocks, unsigned bid, double (&out)[NV])
+{
+    __shared__ unsigned s_last;
+    block_sum<NV>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            __hip_atomic_store(&partials[(size_t)NV * bid + k], v[k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        unsigned prev = atomicAdd(counter, 1u);
+        s_last = (prev == nblocks - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (unsigned b = threadIdx.x; b < nblocks; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            acc[k] += __hip_atomic_load(&partials[(size_t)NV * b + k], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    block_sum<NV>(acc);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) out[k] = acc[k];
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return true;
+}
+
+}  // namespace lwacm

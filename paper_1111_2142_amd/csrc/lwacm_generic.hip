@@ -1,0 +1,444 @@
+// lwacm_generic.hip -- one-thread-per-node LW-ACM kernels for D2Q9 and D3Q19.
+//
+// Forward step (Eq. ACM2.0 in pull form, Eqs. ACM2.0b): every fluid node x
+// gathers, for each link i, the pre-combined term of its upstream node
+// x - v_i; a solid upstream node is replaced by the node's own term for the
+// opposite link plus the moving-wall correction (halfway bounce-back,
+// Eqs. ACM2.0cbb-ACM2.0ccccbb).  The post-combine term sums to a rho_x u_x in
+// the momentum, and the forcing of Eq. force adds rho_x g.  Neighbours come
+// straight from global memory (L2 hits); this path serves every lattice,
+// size and mask and is the baseline the tile kernels are checked against.
+//
+// Reverse step: every source node y collects, for each of its links k, the
+// cotangent weight of the node that consumes its term (y + v_k, or y itself
+// through bounce-back) and applies the transposed derivative of the link term.
+#include "lwacm_device.hpp"
+#include "lwacm_internal.hpp"
+
+namespace lwacm {
+
+namespace {
+
+struct Coord {
+    int x, y, z;
+};
+
+__device__ __forceinline__ Coord decompose(long long idx, int nx, int ny)
+{
+    long long t = idx / nx;
+    Coord c;
+    c.x = (int)(idx - t * nx);
+    c.z = (int)(t / ny);
+    c.y = (int)(t - (long long)c.z * ny);
+    return c;
+}
+
+__device__ __forceinline__ int wrap_add(int a, int d, int n)
+{
+    int r = a + d;
+    return r < 0 ? r + n : (r >= n ? r - n : r);
+}
+
+__device__ __forceinline__ long long node_at(const ProblemArgs &p, int x, int y, int z)
+{
+    return ((long long)z * p.ny + y) * p.nx + x;
+}
+
+template <int D, class T>
+__device__ __forceinline__ void load_state(const T *s, long long n, long long idx,
+                                           const ProblemArgs &p, float &drho, float (&u)[3])
+{
+    drho = Storage<T>::load(s, idx, p.ld_scale[0]);
+    u[0] = Storage<T>::load(s, n + idx, p.ld_scale[1]);
+    u[1] = Storage<T>::load(s, 2 * n + idx, p.ld_scale[1]);
+    u[2] = (D == 3) ? Storage<T>::load(s, 3 * n + idx, p.ld_scale[1]) : 0.0f;
+}
+
+template <int Q>
+__device__ __forceinline__ float vdot(int i, const float (&u)[3])
+{
+    float c = 0.0f;
+    if (link_cx(i) != 0) c = (link_cx(i) > 0) ? c + u[0] : c - u[0];
+    if (link_cy(i) != 0) c = (link_cy(i) > 0) ? c + u[1] : c - u[1];
+    if (Q == 19 && link_cz(i) != 0) c = (link_cz(i) > 0) ? c + u[2] : c - u[2];
+    return c;
+}
+
+template <int Q, class T, bool MASK, bool FORCE>
+__global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, const T *__restrict__ src,
+                                                               T *__restrict__ dst, ReduceArgs r)
+{
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    const long long n = p.n;
+    double acc[2] = {0.0, 0.0};  // mass deviation sum(rho - 1), energy
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        float drx, ux[3];
+        load_state<D, T>(src, n, idx, p, drx, ux);
+        if (MASK && p.mask[idx] != 0) {
+            // solid node: never updated, copied through to the other buffer
+            Storage<T>::store(dst, idx, drx, p.st_scale[0]);
+            for (int k = 0; k < D; ++k) Storage<T>::store(dst, (k + 1) * n + idx, ux[k], p.st_scale[1]);
+            continue;
+        }
+        const Coord c = decompose(idx, p.nx, p.ny);
+        const float rx = 1.0f + drx;
+        const float Bx = -1.5f * (ux[0] * ux[0] + ux[1] * ux[1] + ux[2] * ux[2]);
+        float Dsum = 0.0f, J[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const long long up = node_at(p, wrap_add(c.x, -link_cx(i), p.nx),
+                                         wrap_add(c.y, -link_cy(i), p.ny),
+                                         wrap_add(c.z, -link_cz(i), p.nz));
+            float s;
+            uint8_t m = 0;
+            if (MASK) m = p.mask[up];
+            if (MASK && m != 0) {
+                // bounce-back: own term of the opposite link + moving wall
+                const int ib = link_opp(i);
+                s = L::w(ib) * link_term_unweighted(drx, rx, vdot<Q>(ib, ux), Bx, p.A);
+                const float uw[3] = {p.wall_term[m][0], p.wall_term[m][1], p.wall_term[m][2]};
+                s = fmaf(L::w(i), vdot<Q>(i, uw), s);
+            } else {
+                float dry, uy[3];
+                load_state<D, T>(src, n, up, p, dry, uy);
+                const float By = -1.5f * (uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2]);
+                s = L::w(i) * link_term_unweighted(dry, 1.0f + dry, vdot<Q>(i, uy), By, p.A);
+            }
+            Dsum += s;
+            if (link_cx(i) != 0) J[0] += link_cx(i) * s;
+            if (link_cy(i) != 0) J[1] += link_cy(i) * s;
+            if (link_cz(i) != 0) J[2] += link_cz(i) * s;
+        }
+        // post-combine (sum_i v_i a f^(e,o)_i(x) = a rho_x u_x) and forcing
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            J[k] = fmaf(p.a * rx, ux[k], J[k]);
+            if (FORCE) J[k] = fmaf(rx, p.g[k], J[k]);
+        }
+        // u = J / (1 + D) evaluated as J - J * (D / (1 + D)): the rounding of
+        // 1 + D then only touches the small correction term, which keeps the
+        // FP32 error from accumulating over long runs.
+        const float q = normalisation_factor(Dsum);
+        float e = 0.0f;
+        Storage<T>::store(dst, idx, Dsum, p.st_scale[0]);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float uk = fmaf(-J[k], q, J[k]);
+            Storage<T>::store(dst, (k + 1) * n + idx, uk, p.st_scale[1]);
+            e = fmaf(uk, uk, e);
+        }
+        acc[0] += (double)Dsum;
+        acc[1] += 0.5 * (double)e;
+    }
+    double tot[2];
+    if (grid_sum_last_block<2>(acc, r.partials, r.counter, gridDim.x, blockIdx.x, tot) &&
+        threadIdx.x == 0) {
+        r.out[0] = tot[0];
+        r.out[1] = tot[1];
+        if (r.out2) {
+            r.out2[0] = tot[0];
+            r.out2[1] = tot[1];
+        }
+    }
+}
+
+template <int Q, class T, bool MASK>
+__global__ __launch_bounds__(kGenericBlock) void k_adj_generic(ProblemArgs p, const T *__restrict__ state,
+                                                               const float *__restrict__ mu_in,
+                                                               float *__restrict__ mu_out,
+                                                               int final_t0, ReduceArgs r)
+{
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    const long long n = p.n;
+    double acc[1] = {0.0};  // dL/da
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        if (MASK && p.mask[idx] != 0) {
+            mu_out[idx] = 0.0f;
+            for (int k = 0; k < D; ++k) mu_out[(k + 1) * n + idx] = 0.0f;
+            continue;
+        }
+        float dry, uy[3];
+        load_state<D, T>(state, n, idx, p, dry, uy);
+        const float ry = 1.0f + dry;
+        const float By = -1.5f * (uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2]);
+        const Coord c = decompose(idx, p.nx, p.ny);
+        const float muR_y = mu_in[idx];
+        float muJ_y[3] = {mu_in[n + idx], mu_in[2 * n + idx], D == 3 ? mu_in[3 * n + idx] : 0.0f};
+        float lr = 0.0f, lu[3] = {0.0f, 0.0f, 0.0f}, da = 0.0f;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const long long t = node_at(p, wrap_add(c.x, link_cx(k), p.nx),
+                                        wrap_add(c.y, link_cy(k), p.ny),
+                                        wrap_add(c.z, link_cz(k), p.nz));
+            float m;
+            uint8_t wm = 0;
+            if (MASK) wm = p.mask[t];
+            if (MASK && wm != 0) {
+                // the term bounces back into y itself along -v_k
+                m = muR_y - vdot<Q>(k, muJ_y);
+                const float wd[3] = {p.wall_da[wm][0], p.wall_da[wm][1], p.wall_da[wm][2]};
+                da = fmaf(L::w(k) * vdot<Q>(k, wd), m, da);
+            } else {
+                float mt[3] = {mu_in[n + t], mu_in[2 * n + t], D == 3 ? mu_in[3 * n + t] : 0.0f};
+                m = mu_in[t] + vdot<Q>(k, mt);
+            }
+            const float cc = vdot<Q>(k, uy);
+            const float wm_ = L::w(k) * m;
+            // d s_k / d(rho-1) = w_k [1 + c (A + 9/2 c) - 3/2 |u|^2]
+            lr = fmaf(wm_, 1.0f + cc * fmaf(4.5f, cc, p.A) + By, lr);
+            // d s_k / d u = w_k rho [(A + 9 c) v_k - 3 u]
+            const float q = wm_ * ry * fmaf(9.0f, cc, p.A);
+            if (link_cx(k) != 0) lu[0] += link_cx(k) * q;
+            if (link_cy(k) != 0) lu[1] += link_cy(k) * q;
+            if (link_cz(k) != 0) lu[2] += link_cz(k) * q;
+#pragma unroll
+            for (int j = 0; j < D; ++j) lu[j] = fmaf(-3.0f * wm_ * ry, uy[j], lu[j]);
+            // d s_k / d a = -3 w_k rho c
+            da = fmaf(-3.0f * wm_ * ry, cc, da);
+        }
+        // post-combine a rho u and forcing rho g of the node's own momentum
+        float mJu = 0.0f;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            lr = fmaf(muJ_y[j], fmaf(p.a, uy[j], p.g[j]), lr);
+            lu[j] = fmaf(p.a * ry, muJ_y[j], lu[j]);
+            mJu = fmaf(muJ_y[j], uy[j], mJu);
+        }
+        da = fmaf(ry, mJu, da);
+        if (final_t0) {
+            mu_out[idx] = lr;
+#pragma unroll
+            for (int j = 0; j < D; ++j) mu_out[(j + 1) * n + idx] = lu[j];
+        } else {
+            // fold the normalisation u = J / rho of the previous step
+            const float inv = 1.0f / ry;
+            float lu_u = 0.0f;
+#pragma unroll
+            for (int j = 0; j < D; ++j) lu_u = fmaf(lu[j], uy[j], lu_u);
+            mu_out[idx] = lr - lu_u * inv;
+#pragma unroll
+            for (int j = 0; j < D; ++j) mu_out[(j + 1) * n + idx] = lu[j] * inv;
+        }
+        acc[0] += (double)da;
+    }
+    double tot[1];
+    if (grid_sum_last_block<1>(acc, r.partials, r.counter, gridDim.x, blockIdx.x, tot) &&
+        threadIdx.x == 0)
+        r.out[0] += tot[0] * r.out_scale;
+}
+
+template <int D, class T>
+__global__ __launch_bounds__(kGenericBlock) void k_adj_seed(ProblemArgs p, const T *__restrict__ state,
+                                                            const float *__restrict__ lam,
+                                                            float *__restrict__ mu)
+{
+    const long long n = p.n;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        if (p.mask && p.mask[idx] != 0) {
+            for (int k = 0; k <= D; ++k) mu[k * n + idx] = 0.0f;
+            continue;
+        }
+        float dr, u[3];
+        load_state<D, T>(state, n, idx, p, dr, u);
+        const float inv = 1.0f / (1.0f + dr);
+        float lu_u = 0.0f;
+        for (int j = 0; j < D; ++j) lu_u = fmaf(lam[(j + 1) * n + idx], u[j], lu_u);
+        mu[idx] = lam[idx] - lu_u * inv;
+        for (int j = 0; j < D; ++j) mu[(j + 1) * n + idx] = lam[(j + 1) * n + idx] * inv;
+    }
+}
+
+template <int D, class T>
+__global__ __launch_bounds__(kGenericBlock) void k_set_state(ProblemArgs p, const float *__restrict__ drho,
+                                                             const float *__restrict__ u,
+                                                             T *__restrict__ dst)
+{
+    const long long n = p.n;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        Storage<T>::store(dst, idx, drho[idx], p.st_scale[0]);
+        for (int k = 0; k < D; ++k)
+            Storage<T>::store(dst, (k + 1) * n + idx, u[k * n + idx], p.st_scale[1]);
+    }
+}
+
+template <int D, class T>
+__global__ __launch_bounds__(kGenericBlock) void k_moments(ProblemArgs p, const T *__restrict__ src,
+                                                           float *__restrict__ drho,
+                                                           float *__restrict__ u, ReduceArgs r)
+{
+    const long long n = p.n;
+    double acc[2] = {0.0, 0.0};
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        float dr, uu[3];
+        load_state<D, T>(src, n, idx, p, dr, uu);
+        if (drho) drho[idx] = dr;
+        if (u)
+            for (int k = 0; k < D; ++k) u[k * n + idx] = uu[k];
+        if (p.mask && p.mask[idx] != 0) continue;
+        float e = 0.0f;
+        for (int k = 0; k < D; ++k) e = fmaf(uu[k], uu[k], e);
+        acc[0] += (double)dr;
+        acc[1] += 0.5 * (double)e;
+    }
+    double tot[2];
+    if (grid_sum_last_block<2>(acc, r.partials, r.counter, gridDim.x, blockIdx.x, tot) &&
+        threadIdx.x == 0) {
+        r.out[0] = tot[0];
+        r.out[1] = tot[1];
+    }
+}
+
+// Largest mask value and number of fluid nodes (integer atomics: exact).
+__global__ __launch_bounds__(kGenericBlock) void k_mask_scan(ProblemArgs p, unsigned *out)
+{
+    __shared__ unsigned s_max, s_fluid;
+    if (threadIdx.x == 0) s_max = s_fluid = 0;
+    __syncthreads();
+    unsigned mx = 0, fluid = 0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < p.n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const unsigned m = p.mask[idx];
+        mx = m > mx ? m : mx;
+        fluid += (m == 0);
+    }
+    atomicMax(&s_max, mx);
+    atomicAdd(&s_fluid, fluid);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicMax(&out[0], s_max);
+        atomicAdd(&out[1], s_fluid);
+    }
+}
+
+unsigned grid_for(long long n)
+{
+    long long b = (n + kGenericBlock - 1) / kGenericBlock;
+    if (b < 1) b = 1;
+    return (unsigned)(b > (long long)kGenericMaxBlocks ? kGenericMaxBlocks : b);
+}
+
+template <int Q, class T>
+hipError_t fwd_dispatch(const ProblemArgs &p, bool force, const void *src, void *dst,
+                        const ReduceArgs &r, unsigned nb, hipStream_t s)
+{
+    const T *a = static_cast<const T *>(src);
+    T *b = static_cast<T *>(dst);
+    if (p.mask) {
+        if (force)
+            k_fwd_generic<Q, T, true, true><<<nb, kGenericBlock, 0, s>>>(p, a, b, r);
+        else
+            k_fwd_generic<Q, T, true, false><<<nb, kGenericBlock, 0, s>>>(p, a, b, r);
+    } else {
+        if (force)
+            k_fwd_generic<Q, T, false, true><<<nb, kGenericBlock, 0, s>>>(p, a, b, r);
+        else
+            k_fwd_generic<Q, T, false, false><<<nb, kGenericBlock, 0, s>>>(p, a, b, r);
+    }
+    return hipGetLastError();
+}
+
+template <int Q, class T>
+hipError_t adj_dispatch(const ProblemArgs &p, const void *state, const float *mu_in,
+                        float *mu_out, int final_t0, const ReduceArgs &r, unsigned nb,
+                        hipStream_t s)
+{
+    const T *st = static_cast<const T *>(state);
+    if (p.mask)
+        k_adj_generic<Q, T, true><<<nb, kGenericBlock, 0, s>>>(p, st, mu_in, mu_out, final_t0, r);
+    else
+        k_adj_generic<Q, T, false><<<nb, kGenericBlock, 0, s>>>(p, st, mu_in, mu_out, final_t0, r);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fwd_generic(const ProblemArgs &p, int storage, bool force, const void *src,
+                              void *dst, const ReduceArgs &r, unsigned nb, hipStream_t s)
+{
+    if (p.Q == 9)
+        return storage ? fwd_dispatch<9, __half>(p, force, src, dst, r, nb, s)
+                       : fwd_dispatch<9, float>(p, force, src, dst, r, nb, s);
+    return storage ? fwd_dispatch<19, __half>(p, force, src, dst, r, nb, s)
+                   : fwd_dispatch<19, float>(p, force, src, dst, r, nb, s);
+}
+
+hipError_t launch_adj_generic(const ProblemArgs &p, int storage, const void *state,
+                              const float *mu_in, float *mu_out, int final_t0,
+                              const ReduceArgs &r, unsigned nb, hipStream_t s)
+{
+    if (p.Q == 9)
+        return storage ? adj_dispatch<9, __half>(p, state, mu_in, mu_out, final_t0, r, nb, s)
+                       : adj_dispatch<9, float>(p, state, mu_in, mu_out, final_t0, r, nb, s);
+    return storage ? adj_dispatch<19, __half>(p, state, mu_in, mu_out, final_t0, r, nb, s)
+                   : adj_dispatch<19, float>(p, state, mu_in, mu_out, final_t0, r, nb, s);
+}
+
+hipError_t launch_adj_seed(const ProblemArgs &p, int storage, const void *state,
+                           const float *lambda, float *mu, hipStream_t s)
+{
+    const unsigned nb = grid_for(p.n);
+    if (p.D == 2) {
+        if (storage)
+            k_adj_seed<2, __half><<<nb, kGenericBlock, 0, s>>>(p, (const __half *)state, lambda, mu);
+        else
+            k_adj_seed<2, float><<<nb, kGenericBlock, 0, s>>>(p, (const float *)state, lambda, mu);
+    } else {
+        if (storage)
+            k_adj_seed<3, __half><<<nb, kGenericBlock, 0, s>>>(p, (const __half *)state, lambda, mu);
+        else
+            k_adj_seed<3, float><<<nb, kGenericBlock, 0, s>>>(p, (const float *)state, lambda, mu);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_set_state(const ProblemArgs &p, int storage, const float *drho,
+                            const float *u, void *dst, hipStream_t s)
+{
+    const unsigned nb = grid_for(p.n);
+    if (p.D == 2) {
+        if (storage)
+            k_set_state<2, __half><<<nb, kGenericBlock, 0, s>>>(p, drho, u, (__half *)dst);
+        else
+            k_set_state<2, float><<<nb, kGenericBlock, 0, s>>>(p, drho, u, (float *)dst);
+    } else {
+        if (storage)
+            k_set_state<3, __half><<<nb, kGenericBlock, 0, s>>>(p, drho, u, (__half *)dst);
+        else
+            k_set_state<3, float><<<nb, kGenericBlock, 0, s>>>(p, drho, u, (float *)dst);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const ProblemArgs &p, int storage, const void *src, float *drho,
+                          float *u, const ReduceArgs &r, unsigned nb, hipStream_t s)
+{
+    if (p.D == 2) {
+        if (storage)
+            k_moments<2, __half><<<nb, kGenericBlock, 0, s>>>(p, (const __half *)src, drho, u, r);
+        else
+            k_moments<2, float><<<nb, kGenericBlock, 0, s>>>(p, (const float *)src, drho, u, r);
+    } else {
+        if (storage)
+            k_moments<3, __half><<<nb, kGenericBlock, 0, s>>>(p, (const __half *)src, drho, u, r);
+        else
+            k_moments<3, float><<<nb, kGenericBlock, 0, s>>>(p, (const float *)src, drho, u, r);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_scan(const ProblemArgs &p, unsigned *d_out2, hipStream_t s)
+{
+    k_mask_scan<<<grid_for(p.n), kGenericBlock, 0, s>>>(p, d_out2);
+    return hipGetLastError();
+}
+
+unsigned generic_grid(long long n) { return grid_for(n); }
+
+}  // namespace lwacm

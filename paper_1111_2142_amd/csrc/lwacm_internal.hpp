@@ -1,0 +1,64 @@
+// lwacm_internal.hpp -- kernel argument blocks and launcher declarations
+// shared by the kernel files and the C ABI (host side of the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lwacm {
+
+constexpr int kMaxWallIds = 16;
+
+// Everything a kernel needs to know about the problem, passed by value.
+struct ProblemArgs {
+    int Q, D, nx, ny, nz;
+    long long n;             // nodes
+    float a;                 // 2 - 2/omega, the post-combine factor of Eq. ACM2.0
+    float A;                 // 3 (1 - a) = 3 (2/omega - 1)
+    float g[3];              // body acceleration (Eq. force)
+    float wall_term[kMaxWallIds][3];  // (1 - a) * 6 * rho0 * u_w per wall id (Eq. ACM2.0ccccbb)
+    float wall_da[kMaxWallIds][3];  // 6 * rho0 * u_w: minus d(wall_term)/da
+    float ld_scale[2];       // storage -> value: 2^-k (rho - 1, u); 1 for FP32
+    float st_scale[2];       // value -> storage: 2^k
+    const uint8_t *mask;     // nullptr: all fluid
+};
+
+// Scratch for the fixed-order grid reductions.
+struct ReduceArgs {
+    double *partials;  // NV * nblocks doubles
+    unsigned *counter; // zero between launches
+    double *out;       // NV doubles written by the last block
+    double *out2;      // optional second copy (history), may be null
+    int accumulate;    // 1: out[0] += total instead of out[k] = total
+    double out_scale;  // total is multiplied by this before it is written
+};
+
+// Generic kernels: one thread per node, neighbours read from global memory.
+hipError_t launch_fwd_generic(const ProblemArgs &p, int storage, bool force, const void *src,
+                              void *dst, const ReduceArgs &r, unsigned nblocks,
+                              hipStream_t stream);
+hipError_t launch_adj_generic(const ProblemArgs &p, int storage, const void *state,
+                              const float *mu_in, float *mu_out, int final_t0,
+                              const ReduceArgs &r, unsigned nblocks, hipStream_t stream);
+hipError_t launch_adj_seed(const ProblemArgs &p, int storage, const void *state,
+                           const float *lambda, float *mu, hipStream_t stream);
+hipError_t launch_set_state(const ProblemArgs &p, int storage, const float *drho,
+                            const float *u, void *dst, hipStream_t stream);
+hipError_t launch_moments(const ProblemArgs &p, int storage, const void *src, float *drho,
+                          float *u, const ReduceArgs &r, unsigned nblocks, hipStream_t stream);
+hipError_t launch_mask_scan(const ProblemArgs &p, unsigned *d_out2, hipStream_t stream);
+
+// D3Q19 z-marching tile kernel (returns hipErrorNotSupported if the problem
+// does not fit its constraints).
+bool march_supported(const ProblemArgs &p);
+unsigned march_num_blocks(const ProblemArgs &p);
+hipError_t launch_fwd_march(const ProblemArgs &p, int storage, bool force, const void *src,
+                            void *dst, const ReduceArgs &r, hipStream_t stream);
+
+// Number of blocks the generic grid-stride kernels use for n nodes.
+unsigned generic_grid(long long n);
+
+constexpr int kGenericBlock = 256;
+constexpr unsigned kGenericMaxBlocks = 4096;
+
+}  // namespace lwacm

@@ -1,0 +1,276 @@
+"""ctypes binding of ``liblwacm.so`` (the C ABI in ``include/lwacm.h``).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  The functions
+keep the C names; ``Solver`` bundles them for one problem.  There is no CPU
+fallback: without the built library every call raises.
+"""
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBRARY_PATH = os.path.join(_HERE, "liblwacm.so")
+
+LWACM_D2Q9, LWACM_D3Q19 = 9, 19
+LWACM_FP32, LWACM_FP16_DEV = 0, 1
+LWACM_OK, LWACM_EINVAL, LWACM_ENOMEM, LWACM_EDEVICE, LWACM_ENONFINITE, LWACM_EUNSUPPORTED = (
+    0, -1, -2, -3, -4, -5)
+LWACM_KERNEL_AUTO, LWACM_KERNEL_GENERIC, LWACM_KERNEL_MARCH = 0, 1, 2
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+class LWACMError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {lwacm_strerror(code)} ({code})")
+
+
+def load_library():
+    """Load liblwacm.so (torch is imported first so the HIP runtime it already
+    loaded is the one the library binds to)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBRARY_PATH):
+        raise RuntimeError(f"{LIBRARY_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(LIBRARY_PATH)
+    i, d, ll, sz = ctypes.c_int, ctypes.c_double, ctypes.c_longlong, ctypes.c_size_t
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "lwacm_state_bytes": (sz, [i, i, i, i, i]),
+        "lwacm_init": (i, [ctypes.POINTER(_vp), i, i, i, i, d, i, _vp, _vp, _vp, _vp, i, _vp,
+                           _vp, _vp]),
+        "lwacm_set_fp16_scales": (i, [_vp, i, i]),
+        "lwacm_set_variant": (i, [_vp, i]),
+        "lwacm_set_state": (i, [_vp, _vp, _vp]),
+        "lwacm_step": (i, [_vp, i]),
+        "lwacm_diagnostics": (i, [_vp, dp, dp]),
+        "lwacm_set_diag_history": (i, [_vp, _vp, i]),
+        "lwacm_moments": (i, [_vp, _vp, _vp, dp, dp]),
+        "lwacm_save_state": (i, [_vp, _vp]),
+        "lwacm_load_state": (i, [_vp, _vp, ll]),
+        "lwacm_current_state": (_vp, [_vp]),
+        "lwacm_step_count": (ll, [_vp]),
+        "lwacm_adjoint_seed": (i, [_vp, _vp, _vp, _vp]),
+        "lwacm_adjoint_step": (i, [_vp, _vp, _vp, _vp, _vp, i]),
+        "lwacm_destroy": (None, [_vp]),
+        "lwacm_strerror": (ctypes.c_char_p, [i]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int, where: str):
+    if code != LWACM_OK:
+        raise LWACMError(code, where)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(device: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+# ------------------------------------------------ C names, thin wrappers
+def lwacm_strerror(code: int) -> str:
+    return load_library().lwacm_strerror(code).decode()
+
+
+def lwacm_state_bytes(lattice: int, nx: int, ny: int, nz: int, storage: int) -> int:
+    return int(load_library().lwacm_state_bytes(lattice, nx, ny, nz, storage))
+
+
+def lwacm_init(lattice, nx, ny, nz, omega, storage, state_a: torch.Tensor,
+               state_b: torch.Tensor, mask: Optional[torch.Tensor], wall_u, g,
+               stream: ctypes.c_void_p, q: Optional[torch.Tensor] = None) -> ctypes.c_void_p:
+    lib = load_library()
+    ctx = ctypes.c_void_p()
+    wall_arr, n_ids = None, 0
+    if wall_u is not None:
+        flat = [float(v) for row in wall_u for v in row]
+        n_ids = len(flat) // 3
+        wall_arr = (ctypes.c_float * len(flat))(*flat)
+    g_arr = None
+    if g is not None:
+        gg = list(g) + [0.0] * (3 - len(g))
+        g_arr = (ctypes.c_float * 3)(*gg)
+    code = lib.lwacm_init(ctypes.byref(ctx), lattice, nx, ny, nz, float(omega), storage,
+                          _ptr(state_a), _ptr(state_b), _ptr(mask),
+                          ctypes.cast(wall_arr, _vp) if wall_arr is not None else None, n_ids,
+                          _ptr(q), ctypes.cast(g_arr, _vp) if g_arr is not None else None, stream)
+    _check(code, "lwacm_init")
+    return ctx
+
+
+def lwacm_set_fp16_scales(ctx, k_rho: int, k_u: int):
+    _check(load_library().lwacm_set_fp16_scales(ctx, k_rho, k_u), "lwacm_set_fp16_scales")
+
+
+def lwacm_set_variant(ctx, variant: int):
+    _check(load_library().lwacm_set_variant(ctx, variant), "lwacm_set_variant")
+
+
+def lwacm_set_state(ctx, drho: torch.Tensor, u: torch.Tensor):
+    _check(load_library().lwacm_set_state(ctx, _ptr(drho), _ptr(u)), "lwacm_set_state")
+
+
+def lwacm_step(ctx, nsteps: int):
+    _check(load_library().lwacm_step(ctx, int(nsteps)), "lwacm_step")
+
+
+def lwacm_diagnostics(ctx) -> Tuple[float, float]:
+    m, e = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().lwacm_diagnostics(ctx, ctypes.byref(m), ctypes.byref(e)),
+           "lwacm_diagnostics")
+    return m.value, e.value
+
+
+def lwacm_set_diag_history(ctx, hist: Optional[torch.Tensor]):
+    cap = 0 if hist is None else hist.numel() // 2
+    _check(load_library().lwacm_set_diag_history(ctx, _ptr(hist), cap), "lwacm_set_diag_history")
+
+
+def lwacm_moments(ctx, drho: Optional[torch.Tensor], u: Optional[torch.Tensor],
+                  want_diagnostics: bool = True):
+    lib = load_library()
+    if want_diagnostics:
+        m, e = ctypes.c_double(), ctypes.c_double()
+        _check(lib.lwacm_moments(ctx, _ptr(drho), _ptr(u), ctypes.byref(m), ctypes.byref(e)),
+               "lwacm_moments")
+        return m.value, e.value
+    _check(lib.lwacm_moments(ctx, _ptr(drho), _ptr(u), None, None), "lwacm_moments")
+    return None
+
+
+def lwacm_save_state(ctx, dst: torch.Tensor):
+    _check(load_library().lwacm_save_state(ctx, _ptr(dst)), "lwacm_save_state")
+
+
+def lwacm_load_state(ctx, src: torch.Tensor, step: int):
+    _check(load_library().lwacm_load_state(ctx, _ptr(src), int(step)), "lwacm_load_state")
+
+
+def lwacm_current_state(ctx) -> int:
+    return int(load_library().lwacm_current_state(ctx) or 0)
+
+
+def lwacm_step_count(ctx) -> int:
+    return int(load_library().lwacm_step_count(ctx))
+
+
+def lwacm_adjoint_seed(ctx, state_T: torch.Tensor, lam_T: torch.Tensor, mu: torch.Tensor):
+    _check(load_library().lwacm_adjoint_seed(ctx, _ptr(state_T), _ptr(lam_T), _ptr(mu)),
+           "lwacm_adjoint_seed")
+
+
+def lwacm_adjoint_step(ctx, state_t: torch.Tensor, mu_in: torch.Tensor, mu_out: torch.Tensor,
+                       dL_domega: torch.Tensor, final_t0: bool):
+    _check(load_library().lwacm_adjoint_step(ctx, _ptr(state_t), _ptr(mu_in), _ptr(mu_out),
+                                             _ptr(dL_domega), int(bool(final_t0))),
+           "lwacm_adjoint_step")
+
+
+def lwacm_destroy(ctx):
+    if ctx:
+        load_library().lwacm_destroy(ctx)
+
+
+# ------------------------------------------------------------- Solver
+class Solver:
+    """One LW-ACM problem on one GPU: owns the two state buffers (torch), the
+    mask tensor and the library context; every method forwards to the C ABI.
+
+    Fields are (nz, ny, nx) tensors for rho - 1 and (D, nz, ny, nx) for u.
+    """
+
+    def __init__(self, lattice: int, nx: int, ny: int, nz: int = 1, omega: float = 1.0,
+                 storage: int = LWACM_FP32, mask: Optional[torch.Tensor] = None,
+                 wall_u: Optional[Sequence[Sequence[float]]] = None,
+                 g: Optional[Sequence[float]] = None, device="cuda",
+                 variant: int = LWACM_KERNEL_AUTO, fp16_scales: Optional[Tuple[int, int]] = None):
+        load_library()
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise RuntimeError("the LW-ACM library runs on a GPU only")
+        self.lattice, self.nx, self.ny, self.nz = lattice, nx, ny, nz
+        self.D = 2 if lattice == LWACM_D2Q9 else 3
+        self.omega = float(omega)
+        self.storage = storage
+        nbytes = lwacm_state_bytes(lattice, nx, ny, nz, storage)
+        if nbytes == 0:
+            raise LWACMError(LWACM_EINVAL, "lwacm_state_bytes")
+        self.state_bytes = nbytes
+        self._a = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.mask = None
+        if mask is not None:
+            self.mask = torch.as_tensor(mask, dtype=torch.uint8).to(self.device).contiguous()
+            if self.mask.numel() != nx * ny * nz:
+                raise LWACMError(LWACM_EINVAL, "mask size")
+        self.ctx = lwacm_init(lattice, nx, ny, nz, omega, storage, self._a, self._b, self.mask,
+                              wall_u, g, _stream_handle(self.device))
+        if fp16_scales is not None:
+            lwacm_set_fp16_scales(self.ctx, *fp16_scales)
+        if variant != LWACM_KERNEL_AUTO:
+            lwacm_set_variant(self.ctx, variant)
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def set_state(self, drho: torch.Tensor, u: torch.Tensor):
+        drho = drho.to(self.device, torch.float32).contiguous()
+        u = u.to(self.device, torch.float32).contiguous()
+        if drho.numel() != self.nx * self.ny * self.nz or u.numel() != self.D * drho.numel():
+            raise LWACMError(LWACM_EINVAL, "set_state sizes")
+        lwacm_set_state(self.ctx, drho, u)
+
+    def step(self, n: int = 1):
+        lwacm_step(self.ctx, n)
+
+    def moments(self, diagnostics: bool = False):
+        drho = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        u = torch.empty((self.D,) + self.shape, dtype=torch.float32, device=self.device)
+        diag = lwacm_moments(self.ctx, drho, u, want_diagnostics=diagnostics)
+        return (drho, u, diag) if diagnostics else (drho, u)
+
+    def diagnostics(self):
+        return lwacm_diagnostics(self.ctx)
+
+    def new_state_buffer(self) -> torch.Tensor:
+        return torch.empty(self.state_bytes, dtype=torch.uint8, device=self.device)
+
+    def save_state(self, dst: Optional[torch.Tensor] = None) -> torch.Tensor:
+        dst = self.new_state_buffer() if dst is None else dst
+        lwacm_save_state(self.ctx, dst)
+        return dst
+
+    def load_state(self, src: torch.Tensor, step: int = 0):
+        lwacm_load_state(self.ctx, src, step)
+
+    @property
+    def step_count(self) -> int:
+        return lwacm_step_count(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lwacm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

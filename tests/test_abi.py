@@ -1,0 +1,85 @@
+"""The C ABI library loads and exports every entry point include/lwacm.h
+declares; host-only calls (sizes, error strings, argument checks that fail
+before any device work) behave as documented.  No GPU needed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lwacm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lwacm_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+    from paper_1111_2142_amd import lwacm as L
+    return L.load_library()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for required in ["lwacm_init", "lwacm_step", "lwacm_moments", "lwacm_adjoint_step",
+                     "lwacm_adjoint_seed", "lwacm_destroy", "lwacm_strerror",
+                     "lwacm_state_bytes"]:
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_state_bytes(lib):
+    from paper_1111_2142_amd import lwacm as L
+    assert L.lwacm_state_bytes(19, 256, 256, 256, 0) == 4 * 4 * 256 ** 3
+    assert L.lwacm_state_bytes(19, 256, 256, 256, 1) == 4 * 2 * 256 ** 3
+    assert L.lwacm_state_bytes(9, 512, 512, 1, 0) == 3 * 4 * 512 ** 2
+    assert L.lwacm_state_bytes(9, 8, 8, 2, 0) == 0      # D2Q9 needs nz = 1
+    assert L.lwacm_state_bytes(15, 8, 8, 8, 0) == 0     # unknown lattice
+    assert L.lwacm_state_bytes(19, 0, 8, 8, 0) == 0
+    assert L.lwacm_state_bytes(19, 8, 8, 8, 7) == 0
+
+
+def test_strerror_names_every_code(lib):
+    from paper_1111_2142_amd import lwacm as L
+    seen = set()
+    for code in range(0, -6, -1):
+        s = L.lwacm_strerror(code)
+        assert s and s != "unknown error code"
+        seen.add(s)
+    assert len(seen) == 6
+    assert L.lwacm_strerror(-99) == "unknown error code"
+
+
+def test_init_rejects_bad_arguments_before_device_work(lib):
+    from paper_1111_2142_amd import lwacm as L
+    ctx = ctypes.c_void_p()
+    fake_a, fake_b = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+
+    def init(**kw):
+        a = dict(lattice=19, nx=8, ny=8, nz=8, omega=1.5, storage=0, a=fake_a, b=fake_b,
+                 q=None)
+        a.update(kw)
+        return lib.lwacm_init(ctypes.byref(ctx), a["lattice"], a["nx"], a["ny"], a["nz"],
+                              a["omega"], a["storage"], a["a"], a["b"], None, None, 0, a["q"],
+                              None, None)
+
+    assert init(omega=2.0) == L.LWACM_EINVAL
+    assert init(omega=0.0) == L.LWACM_EINVAL
+    assert init(omega=float("nan")) == L.LWACM_EINVAL
+    assert init(a=None) == L.LWACM_EINVAL
+    assert init(b=fake_a) == L.LWACM_EINVAL            # the two buffers must differ
+    assert init(lattice=9) == L.LWACM_EINVAL            # nz = 8 with D2Q9
+    assert init(storage=3) == L.LWACM_EINVAL
+    assert init(q=ctypes.c_void_p(0x3000)) == L.LWACM_EUNSUPPORTED
+    assert ctx.value is None
+    assert lib.lwacm_step(None, 1) == L.LWACM_EINVAL
+    assert lib.lwacm_step_count(None) == -1

@@ -1,0 +1,314 @@
+"""GPU parity of the forward LW-ACM step (HIP library through its C ABI)
+against the FP64 oracle and against exact discrete solutions.
+
+Bars: u within 1e-5 relative L2 of the oracle for FP32 storage and 1e-3 for
+FP16-deviation storage; rho - 1 reported and bounded; mass conserved.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+from gpu_helpers import banner, fluid_of, gpu_run, need_gpu, oracle_run, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+FP16_TOL = 1e-3
+
+
+def _frac(s):
+    return float(Fraction(s)) if "/" in s or s.lstrip("-").isdigit() else float(s)
+
+
+# -------------------------------------------------------- exact values
+def test_hand_3x3_values_gpu(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "hand_3x3.json")))
+    for case in g["d2q9"]["cases"]:
+        banner(f"hand 3x3 d2q9 case {case['name']}")
+        drho = np.zeros((1, 3, 3))
+        u = np.zeros((2, 1, 3, 3))
+        drho[0, 1, 1] = _frac(case["centre_rho"]) - 1
+        u[:, 0, 1, 1] = [_frac(s) for s in case["centre_u"]]
+        dr, uu, _ = gpu_run(9, (1, 3, 3), _frac(g["d2q9"]["omega"]), drho, u, 1)
+        for e in case["expect"]:
+            x, y = e["node"]
+            assert abs(dr[0, y, x] - (_frac(e["rho"]) - 1)) < 2e-8, e
+            for k in range(2):
+                assert abs(uu[k, 0, y, x] - _frac(e["u"][k])) < 1e-8, (e, k)
+    h = g["d3q19"]
+    banner("hand 3x3x3 d3q19")
+    drho = np.zeros((3, 3, 3))
+    u = np.zeros((3, 3, 3, 3))
+    drho[1, 1, 1] = _frac(h["centre_rho"]) - 1
+    u[:, 1, 1, 1] = [_frac(s) for s in h["centre_u"]]
+    dr, uu, _ = gpu_run(19, (3, 3, 3), _frac(h["omega"]), drho, u, 1)
+    for e in h["expect"]:
+        x, y, z = e["node"]
+        assert abs(dr[z, y, x] - (_frac(e["rho"]) - 1)) < 2e-8, e
+        for k in range(3):
+            assert abs(uu[k, z, y, x] - _frac(e["u"][k])) < 1e-8, (e, k)
+
+
+# --------------------------------------------- the D2Q9 workloads
+def test_tgv2d_64_fp32_matches_oracle():
+    """64x64 Taylor-Green vortex, u0 = 0.01, omega = 1.6, 1000 steps."""
+    c = wl.TGV2D_64
+    banner(c.name)
+    drho, u = wl.taylor_green_2d(c.nx, c.u0)
+    dr, uu, s = gpu_run(9, (1, c.ny, c.nx), c.omega, drho, u, c.steps)
+    rdr, ru = oracle_run(9, (1, c.ny, c.nx), c.omega, drho, u, c.steps)
+    err_u = rel_l2(uu, ru)
+    err_r = rel_l2(dr, rdr)
+    banner(f"{c.name}: rel-L2 u {err_u:.3e} drho {err_r:.3e}")
+    assert err_u < FP32_TOL
+    assert err_r < 1e-3
+    m, e = s.diagnostics()
+    om, oe = oracle.diagnostics(oracle.Problem(q=9, nx=c.nx, ny=c.ny, omega=c.omega), 1 + rdr, ru)
+    assert abs(m - c.nodes) / c.nodes < 1e-9
+    assert abs(e - oe) / oe < 1e-5
+
+
+def test_channel_256x64_matches_oracle_and_transient():
+    """Body-forced channel with halfway bounce-back walls on rows 0 and 63
+    (omega = 1, g = 1e-6): GPU vs oracle after 2000 steps, and the full
+    20000 steps against the exact discrete transient of the walls."""
+    c = wl.CHANNEL_256x64
+    banner(c.name)
+    mask = wl.channel_mask(c.nx, c.ny)
+    drho = np.zeros((1, c.ny, c.nx))
+    u = np.zeros((2, 1, c.ny, c.nx))
+    fl = fluid_of(mask, (1, c.ny, c.nx))
+    dr, uu, _ = gpu_run(9, (1, c.ny, c.nx), c.omega, drho, u, 2000, mask=mask, g=c.g[:2])
+    rdr, ru = oracle_run(9, (1, c.ny, c.nx), c.omega, drho, u, 2000, mask=mask, g=c.g[:2])
+    err = rel_l2(uu[0], ru[0], fl)
+    banner(f"channel 2000 steps rel-L2 u {err:.3e}")
+    assert err < FP32_TOL
+    # full run vs the recurrence U+ = U + nu lap U + g with antisymmetric ghosts
+    dr, uu, _ = gpu_run(9, (1, c.ny, c.nx), c.omega, drho, u, c.steps, mask=mask, g=c.g[:2])
+    nu = wl.viscosity(c.omega)
+    N = c.ny - 2
+    U = np.zeros(N)
+    for _ in range(c.steps):
+        ext = np.concatenate([[-U[0]], U, [-U[-1]]])
+        U = U + nu * (ext[2:] - 2 * ext[1:-1] + ext[:-2]) + c.g[0]
+    prof = uu[0, 0, 1:c.ny - 1, :]
+    assert np.abs(prof - U[:, None]).max() / U.max() < 1e-5
+    assert np.abs(uu[1, 0, 1:c.ny - 1]).max() < 1e-9
+    y = np.arange(N)
+    U_inf = c.g[0] / (2 * nu) * (-y ** 2 + (N - 1) * y + N / 2)
+    rel = np.abs(prof[:, 0] - U_inf).max() / U_inf.max()
+    banner(f"channel 20000 steps: max|U - U_inf|/max U_inf = {rel:.3e}")
+    assert 1.5e-4 < rel < 2.5e-4
+
+
+# ------------------------------------------------ D3Q19 parity
+@pytest.mark.parametrize("storage", [0, 1])
+def test_tgv3d_48_matches_oracle(storage):
+    """3D Taylor-Green vortex at 48^3 (same u0 and omega as the 256^3
+    workload), 200 steps, FP32 and FP16-deviation storage."""
+    n, steps = 48, 200
+    banner(f"tgv3d {n}^3 storage={storage}")
+    drho, u = wl.taylor_green_3d(n, wl.TGV3D_256.u0)
+    dr, uu, _ = gpu_run(19, (n, n, n), wl.TGV3D_256.omega, drho, u, steps, storage=storage)
+    rdr, ru = oracle_run(19, (n, n, n), wl.TGV3D_256.omega, drho, u, steps)
+    err_u = rel_l2(uu, ru)
+    err_r = rel_l2(dr, rdr)
+    banner(f"tgv3d {n}^3 storage={storage}: rel-L2 u {err_u:.3e} drho {err_r:.3e}")
+    assert err_u < (FP32_TOL if storage == 0 else FP16_TOL)
+    assert err_r < (1e-3 if storage == 0 else 5e-2)
+
+
+@pytest.mark.parametrize("shape", [(19, 23, 37), (5, 7, 3), (1, 1, 1), (2, 64, 65)])
+def test_ragged_sizes_random_state(shape):
+    """Odd sizes (ragged tiles, wrap onto itself) with a random state."""
+    banner(f"ragged {shape}")
+    drho, u = wl.random_state(shape, 3, seed=21, du=0.05, drho=0.02)
+    dr, uu, _ = gpu_run(19, shape, 1.45, drho, u, 5)
+    rdr, ru = oracle_run(19, shape, 1.45, drho, u, 5)
+    assert rel_l2(uu, ru) < FP32_TOL
+    assert rel_l2(dr, rdr) < 1e-4
+
+
+def test_couette_d3q19_moving_wall_exact():
+    """Linear Couette profile U_w (y + 1/2)/N is an exact steady state of the
+    halfway bounce-back with the moving-wall term; FP32 keeps it to rounding."""
+    nx, ny, nz, Uw, omega = 8, 34, 6, 0.05, 1.3
+    banner("couette d3q19")
+    mask = wl.slab_mask_3d(nx, ny, nz, moving_top=True)
+    N = ny - 2
+    drho = np.zeros((nz, ny, nx))
+    u = np.zeros((3, nz, ny, nx))
+    u[0][:, 1:ny - 1, :] = (Uw * (np.arange(N) + 0.5) / N)[None, :, None]
+    dr, uu, _ = gpu_run(19, (nz, ny, nx), omega, drho, u, 500, mask=mask,
+                        wall_u=wl.wall_table((Uw, 0, 0)))
+    assert np.abs(uu[0][:, 1:ny - 1] - u[0][:, 1:ny - 1]).max() < 1e-7
+    assert np.abs(dr[:, 1:ny - 1]).max() < 1e-7
+
+
+def test_cavity_48_matches_oracle():
+    """Lid-driven cube (48^3 array, 46^3 fluid, lid (0.05,0,0), Re 1000
+    omega) for 300 steps: parity with the oracle, exact mass conservation
+    and the mirror symmetry u(x, N-1-y, z) = u(x,y,z) with u_y odd."""
+    c = wl.CAVITY_48
+    banner(c.name)
+    mask = wl.cavity_mask(c.nx)
+    table = wl.wall_table(c.lid)
+    drho = np.zeros((c.nz, c.ny, c.nx))
+    u = np.zeros((3, c.nz, c.ny, c.nx))
+    dr, uu, s = gpu_run(19, (c.nz, c.ny, c.nx), c.omega, drho, u, 300, mask=mask, wall_u=table)
+    rdr, ru = oracle_run(19, (c.nz, c.ny, c.nx), c.omega, drho, u, 300, mask=mask, wall_u=table)
+    fl = fluid_of(mask, (c.nz, c.ny, c.nx))
+    err = rel_l2(uu[:, fl], ru[:, fl])
+    banner(f"cavity48 300 steps rel-L2 u {err:.3e}")
+    assert err < FP32_TOL
+    m, _ = s.diagnostics()
+    nf = int(fl.sum())
+    assert abs(m - nf) / nf < 1e-9
+    mir = uu[:, :, ::-1, :].copy()
+    mir[1] = -mir[1]
+    assert np.abs(mir[:, fl] - uu[:, fl]).max() < 1e-7
+
+
+# --------------------------------------------- full-size properties
+def test_shear_wave_256_cubed_exact():
+    """At the 256^3 size, rho = 1 and u = (U(y),0,0) follow the exact
+    recurrence for any amplitude: a sine decays as lambda^t."""
+    n, omega, u0, steps = 256, 1.7, 0.02, 200
+    banner("shear wave 256^3")
+    drho, u = wl.shear_wave((n, n, n), 3, u0, 1)
+    dr, uu, _ = gpu_run(19, (n, n, n), omega, drho, u, steps)
+    lam = 1 - 4 * wl.viscosity(omega) * np.sin(np.pi / n) ** 2
+    ref = u[0] * lam ** steps
+    assert np.abs(uu[0] - ref).max() < 2e-6 * u0
+    assert np.abs(uu[1:]).max() < 1e-9
+    assert np.abs(dr).max() < 1e-7
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_tgv3d_256_one_step_sampled(storage):
+    """The 256^3 workload, one step from the Taylor-Green field, in the
+    launch configuration of the benchmark: 4096 seeded random nodes against
+    the oracle evaluated node by node."""
+    c = wl.TGV3D_256
+    banner(f"{c.name} one-step sampled storage={storage}")
+    drho, u = wl.taylor_green_3d(c.nx, c.u0)
+    dr, uu, _ = gpu_run(19, (c.nz, c.ny, c.nx), c.omega, drho, u, 1, storage=storage)
+    rng = np.random.Generator(np.random.PCG64(17))
+    idx = rng.integers(0, c.nodes, 4096)
+    if storage:
+        # the GPU starts from the FP16-quantised field: give the oracle the same input
+        s16 = 2.0 ** 14
+        u_in = (u * s16).astype(np.float16).astype(np.float64) / s16
+    else:
+        u_in = u.astype(np.float32).astype(np.float64)
+    p = oracle.Problem(q=19, nx=c.nx, ny=c.ny, nz=c.nz, omega=c.omega)
+    r_ref, u_ref = oracle.step_nodes(p, 1 + drho, u_in, idx)
+    got_u = uu.reshape(3, -1)[:, idx]
+    got_r = dr.reshape(-1)[idx]
+    tol_u = 1e-6 if storage == 0 else 1e-3
+    assert rel_l2(got_u, u_ref) < tol_u
+    assert np.abs(got_r - (r_ref - 1)).max() < (1e-8 if storage == 0 else 2e-6)
+
+
+def test_cavity_192_one_step_sampled():
+    """The 192^3 cavity with its mask, one step from a seeded random state in
+    the benchmark's launch configuration, against the oracle node by node;
+    half the samples lie on the fluid layer next to the walls."""
+    c = wl.CAVITY_192
+    banner(c.name + " sampled")
+    mask = wl.cavity_mask(c.nx)
+    table = wl.wall_table(c.lid)
+    drho, u = wl.random_state((c.nz, c.ny, c.nx), 3, seed=5, du=0.03, drho=0.01)
+    drho = drho.astype(np.float32).astype(np.float64)
+    u = u.astype(np.float32).astype(np.float64)
+    dr, uu, s = gpu_run(19, (c.nz, c.ny, c.nx), c.omega, drho, u, 1, mask=mask, wall_u=table)
+    # rho0 used by the library is the mean fluid density of the state it stored
+    fl = mask == 0
+    rho0 = 1.0 + drho[fl].astype(np.float32).astype(np.float64).mean()
+    rng = np.random.Generator(np.random.PCG64(3))
+    z = rng.integers(0, c.nz, 4096)
+    y = rng.integers(0, c.ny, 4096)
+    x = rng.integers(0, c.nx, 4096)
+    # half the samples on the layer next to the walls
+    x[:1024] = 1
+    z[1024:2048] = c.nz - 2
+    idx = (z * c.ny + y) * c.nx + x
+    p = oracle.Problem(q=19, nx=c.nx, ny=c.ny, nz=c.nz, omega=c.omega, mask=mask, wall_u=table,
+                       rho0=rho0)
+    r_ref, u_ref = oracle.step_nodes(p, 1 + drho, u, idx)
+    assert rel_l2(uu.reshape(3, -1)[:, idx], u_ref) < 1e-6
+    assert np.abs(dr.reshape(-1)[idx] - (r_ref - 1)).max() < 1e-8
+
+
+# ----------------------------------------------- determinism, API
+def test_bitwise_deterministic_and_checkpoint_resume():
+    """Two identical runs give bitwise-equal fields and diagnostics; a run
+    saved at step 30 and resumed in a new context reproduces step 60."""
+    L = need_gpu()
+    banner("determinism")
+    shape = (24, 20, 32)
+    drho, u = wl.random_state(shape, 3, seed=2, du=0.04, drho=0.01)
+    a = gpu_run(19, shape, 1.6, drho, u, 60)
+    b = gpu_run(19, shape, 1.6, drho, u, 60)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[2].diagnostics() == b[2].diagnostics()
+    nz, ny, nx = shape
+    s = L.Solver(19, nx, ny, nz, 1.6)
+    s.set_state(to_dev(drho), to_dev(u))
+    s.step(30)
+    ck = s.save_state()
+    s.close()
+    s2 = L.Solver(19, nx, ny, nz, 1.6)
+    s2.set_state(to_dev(drho), to_dev(u))
+    s2.load_state(ck, 30)
+    s2.step(30)
+    dr2, u2 = s2.moments()
+    assert s2.step_count == 60
+    assert np.array_equal(dr2.double().cpu().numpy(), a[0])
+    assert np.array_equal(u2.double().cpu().numpy(), a[1])
+
+
+def test_diagnostics_history_and_zero_steps():
+    L = need_gpu()
+    banner("diagnostics history")
+    n = 32
+    drho, u = wl.taylor_green_2d(n, 0.02)
+    s = L.Solver(9, n, n, 1, 1.6)
+    hist = torch.zeros(2 * 8, dtype=torch.float64, device="cuda")
+    L.lwacm_set_diag_history(s.ctx, hist)
+    s.set_state(to_dev(drho), to_dev(u))
+    s.step(0)
+    with pytest.raises(L.LWACMError):
+        s.diagnostics()      # no step ran yet
+    s.step(5)
+    h = hist.cpu().numpy().reshape(8, 2)
+    r, uu = oracle.run(oracle.Problem(q=9, nx=n, ny=n, omega=1.6), 1 + drho, u, 5)
+    _, e5 = oracle.diagnostics(oracle.Problem(q=9, nx=n, ny=n, omega=1.6), r, uu)
+    assert abs(h[5, 1] - e5) / e5 < 1e-5
+    assert np.all(h[1:6, 1] > 0) and np.all(np.diff(h[1:6, 1]) < 0)   # energy decays
+    m, e = s.diagnostics()
+    assert abs(e - h[5, 1]) == 0
+
+
+def test_invalid_arguments_raise():
+    L = need_gpu()
+    banner("invalid arguments")
+    with pytest.raises(L.LWACMError) as ei:
+        L.Solver(19, 8, 8, 8, 2.0)
+    assert ei.value.code == L.LWACM_EINVAL
+    with pytest.raises(L.LWACMError):
+        L.Solver(9, 8, 8, 2, 1.5)                   # D2Q9 with nz != 1
+    bad = np.zeros((1, 8, 8), dtype=np.uint8)
+    bad[0, 3, 3] = 5                                 # wall id beyond the table
+    with pytest.raises(L.LWACMError) as ei:
+        L.Solver(9, 8, 8, 1, 1.5, mask=to_dev(bad, torch.uint8), wall_u=wl.wall_table())
+    assert ei.value.code == L.LWACM_EINVAL
+    s = L.Solver(9, 8, 8, 1, 1.5)
+    with pytest.raises(L.LWACMError):
+        s.step(-1)
