@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forward-only", action="store_true",
                     help="time only the FP32 forward step (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="time a plain device copy of 256 MiB (the reference kernel for "
+                         "scaling HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -62,6 +65,17 @@ def main():
     L.load_library()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        dt = _events_time(lambda k: [dst.copy_(src) for _ in range(k)], args.steps, stream)
+        nbytes = 2 * src.numel() * 4
+        print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": args.steps,
+                          "ms_per_launch": dt / args.steps * 1e3,
+                          "GBs": nbytes * args.steps / dt / 1e9}), flush=True)
+        return
     n = args.n
     cfg = wl.TGV3D_256
     drho, u = wl.taylor_green_3d(n, cfg.u0)

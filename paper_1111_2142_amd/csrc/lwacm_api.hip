@@ -20,6 +20,7 @@ struct lwacm_ctx {
     int variant;  // requested LWACM_KERNEL_*
     bool force;
     double omega;
+    double a_exact;  // the a used by the kernels (1 - quantised h), as a double
     double rho0;
     void *buf[2];
     int cur;
@@ -33,6 +34,8 @@ struct lwacm_ctx {
     double *d_diag;     // [2] mass deviation, energy of the last step's output
     double *d_scratch;  // [2] for lwacm_moments
     unsigned *d_scan;   // [2] mask scan
+    uint8_t *d_cls;     // node classes for the march kernel (masked problems)
+    unsigned *d_bits;   // solid-upstream link bits for the march kernel
     double *d_hist;
     int hist_cap;
     long long steps;
@@ -83,6 +86,11 @@ ReduceArgs reduce_args(lwacm_ctx *c, double *out, double *out2)
     return r;
 }
 
+size_t state_bytes(const lwacm_ctx *c)
+{
+    return (size_t)(c->p.D + 1) * (size_t)c->p.n * (c->storage == LWACM_FP32 ? 4 : 2);
+}
+
 bool use_march(const lwacm_ctx *c)
 {
     if (c->variant == LWACM_KERNEL_GENERIC) return false;
@@ -96,6 +104,10 @@ void free_scratch(lwacm_ctx *c)
     if (c->d_diag) (void)hipFree(c->d_diag);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     if (c->d_scan) (void)hipFree(c->d_scan);
+    if (c->d_cls) (void)hipFree(c->d_cls);
+    if (c->d_bits) (void)hipFree(c->d_bits);
+    c->d_cls = nullptr;
+    c->d_bits = nullptr;
     c->d_partials = nullptr;
     c->d_counter = nullptr;
     c->d_diag = c->d_scratch = nullptr;
@@ -159,12 +171,25 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
     p.ny = ny;
     p.nz = nz;
     p.n = (long long)nx * ny * nz;
-    p.a = (float)(2.0 - 2.0 / omega);
-    p.A = (float)(3.0 * (2.0 / omega - 1.0));
+    // h = 1 - a = 2/omega - 1 is put on a grid fine enough that a = 1 - h and
+    // A = 3 h are both exact in FP32, so that a + A/3 = 1 holds exactly and
+    // the link terms conserve momentum to rounding (a mismatch of ~1e-8 would
+    // act like a source term every step).  The relative change of the
+    // viscosity nu = h/6 is at most 2^-25 / h.
+    {
+        const double h = 2.0 / omega - 1.0;
+        const double quantum = fabs(h) < 0.25 ? ldexp(1.0, -24)
+                               : (fabs(h) < 0.5 ? ldexp(1.0, -23) : ldexp(1.0, -22));
+        const double hq = nearbyint(h / quantum) * quantum;
+        p.a = (float)(1.0 - hq);
+        p.A = (float)(3.0 * hq);
+        c->a_exact = 1.0 - hq;
+    }
     p.mask = d_mask;
     if (h_g) {
         for (int k = 0; k < p.D; ++k) p.g[k] = h_g[k];
         c->force = true;
+        p.has_force = 1;
     }
     if (h_wall_u) {
         c->n_wall_ids = n_wall_ids;
@@ -208,6 +233,16 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
             }
             c->n_fluid = scan[1];
         }
+        if (e == hipSuccess && lwacm::march_supported(p)) {
+            e = hipMalloc(&c->d_cls, (size_t)p.n);
+            if (e == hipSuccess) e = hipMalloc(&c->d_bits, (size_t)p.n * sizeof(unsigned));
+            if (e != hipSuccess) {
+                free_scratch(c);
+                delete c;
+                return LWACM_ENOMEM;
+            }
+            e = lwacm::launch_classify(p, c->d_cls, c->d_bits, stream);
+        }
     }
     if (e != hipSuccess) {
         free_scratch(c);
@@ -248,6 +283,10 @@ int lwacm_set_state(lwacm_ctx *c, const float *d_drho, const float *d_u)
     set_scales(c);
     hipError_t e = lwacm::launch_set_state(c->p, c->storage, d_drho, d_u, c->buf[c->cur], c->stream);
     if (e != hipSuccess) return LWACM_EDEVICE;
+    // both buffers hold the state: solid nodes are never written by a step
+    e = hipMemcpyAsync(c->buf[c->cur ^ 1], c->buf[c->cur], state_bytes(c),
+                       hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return LWACM_EDEVICE;
     // rho0 = mean fluid density of the stored state (moving-wall term)
     ReduceArgs r = reduce_args(c, c->d_scratch, nullptr);
     e = lwacm::launch_moments(c->p, c->storage, c->buf[c->cur], nullptr, nullptr, r,
@@ -275,7 +314,8 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
         ReduceArgs r = reduce_args(c, c->d_diag, hist);
         const void *src = c->buf[c->cur];
         void *dst = c->buf[c->cur ^ 1];
-        hipError_t e = march ? lwacm::launch_fwd_march(c->p, c->storage, c->force, src, dst, r, c->stream)
+        hipError_t e = march ? lwacm::launch_fwd_march(c->p, c->storage, src, dst, c->d_cls,
+                                                       c->d_bits, r, c->stream)
                              : lwacm::launch_fwd_generic(c->p, c->storage, c->force, src, dst, r, gb,
                                                          c->stream);
         if (e != hipSuccess) return LWACM_EDEVICE;
@@ -336,6 +376,8 @@ int lwacm_load_state(lwacm_ctx *c, const void *d_src, long long step)
     if (!c || !d_src || step < 0) return LWACM_EINVAL;
     const size_t bytes = lwacm_state_bytes(c->lattice, c->p.nx, c->p.ny, c->p.nz, c->storage);
     hipError_t e = hipMemcpyAsync(c->buf[c->cur], d_src, bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->buf[c->cur ^ 1], d_src, bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return LWACM_EDEVICE;
     c->steps = step;
     c->diag_valid = false;

@@ -45,28 +45,41 @@ __host__ __device__ constexpr int link_opp(int i)
 template <int Q>
 struct Lattice;
 
-// D2Q9: weights 4/9, 1/9 (axis), 1/36 (diagonal), Eq. weight_factors.
+// Weights are carried as the exact integers 36 w_i, and sums are divided by
+// 36 once with div36().  FP32 constants such as 1/9 or 1/36 are rounded up
+// by ~1e-8, which would scale every step's momentum by (1 + 1e-8) and grow
+// a systematic error of ~1e-5 over 1000 steps.
+
+// D2Q9: w = 4/9, 1/9 (axis), 1/36 (diagonal), Eq. weight_factors.
 template <>
 struct Lattice<9> {
     static constexpr int Q = 9;
     static constexpr int D = 2;
-    __host__ __device__ static constexpr float w(int i)
+    __host__ __device__ static constexpr float w36(int i)
     {
-        return i == 0 ? 4.0f / 9.0f : (i <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f);
+        return i == 0 ? 16.0f : (i <= 4 ? 4.0f : 1.0f);
     }
 };
 
-// D3Q19: weights 1/3, 1/18 (axis), 1/36 (face diagonal), Eq. weight_factors_3d.
+// D3Q19: w = 1/3, 1/18 (axis), 1/36 (face diagonal), Eq. weight_factors_3d.
 template <>
 struct Lattice<19> {
     static constexpr int Q = 19;
     static constexpr int D = 3;
-    __host__ __device__ static constexpr float w(int i)
+    __host__ __device__ static constexpr float w36(int i)
     {
-        return i == 0 ? 1.0f / 3.0f
-                      : ((i <= 4 || i == 9 || i == 14) ? 1.0f / 18.0f : 1.0f / 36.0f);
+        return i == 0 ? 12.0f : ((i <= 4 || i == 9 || i == 14) ? 2.0f : 1.0f);
     }
 };
+
+// x / 36 with a double-word constant: the result is the nearest float in
+// all but rare ties, and, unlike x * fl(1/36), carries no systematic bias.
+__device__ __forceinline__ float div36(float x)
+{
+    constexpr float c_hi = 1.0f / 36.0f;
+    constexpr float c_lo = (float)(1.0 / 36.0 - (double)(1.0f / 36.0f));
+    return fmaf(x, c_hi, x * c_lo);
+}
 
 // ------------------------------------------------------ the link term
 // Pre-combined population of Eq. ACM2.0b (pre-combining step), in deviation

@@ -85,38 +85,47 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
         const Coord c = decompose(idx, p.nx, p.ny);
         const float rx = 1.0f + drx;
         const float Bx = -1.5f * (ux[0] * ux[0] + ux[1] * ux[1] + ux[2] * ux[2]);
-        float Dsum = 0.0f, J[3] = {0.0f, 0.0f, 0.0f};
+        // Forcing (Eq. force) adds the odd part 3 w_i rho_x (v_i . g) to every
+        // population.  It enters each link term through the addend of its FMA,
+        // where it meets an exact, node-dependent product; added to the final
+        // sum instead, the same small constant would round the same way every
+        // step and bias long runs.
+        float g3[3] = {0.0f, 0.0f, 0.0f};
+        if (FORCE)
+#pragma unroll
+            for (int k = 0; k < D; ++k) g3[k] = 3.0f * rx * p.g[k];
+        float D36 = 0.0f, J36[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const long long up = node_at(p, wrap_add(c.x, -link_cx(i), p.nx),
                                          wrap_add(c.y, -link_cy(i), p.ny),
                                          wrap_add(c.z, -link_cz(i), p.nz));
+            const float fg = FORCE ? vdot<Q>(i, g3) : 0.0f;
             float s;
             uint8_t m = 0;
             if (MASK) m = p.mask[up];
             if (MASK && m != 0) {
                 // bounce-back: own term of the opposite link + moving wall
                 const int ib = link_opp(i);
-                s = L::w(ib) * link_term_unweighted(drx, rx, vdot<Q>(ib, ux), Bx, p.A);
                 const float uw[3] = {p.wall_term[m][0], p.wall_term[m][1], p.wall_term[m][2]};
-                s = fmaf(L::w(i), vdot<Q>(i, uw), s);
+                s = link_term_unweighted(drx + fg, rx, vdot<Q>(ib, ux), Bx, p.A) + vdot<Q>(i, uw);
             } else {
                 float dry, uy[3];
                 load_state<D, T>(src, n, up, p, dry, uy);
                 const float By = -1.5f * (uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2]);
-                s = L::w(i) * link_term_unweighted(dry, 1.0f + dry, vdot<Q>(i, uy), By, p.A);
+                s = link_term_unweighted(dry + fg, 1.0f + dry, vdot<Q>(i, uy), By, p.A);
             }
-            Dsum += s;
-            if (link_cx(i) != 0) J[0] += link_cx(i) * s;
-            if (link_cy(i) != 0) J[1] += link_cy(i) * s;
-            if (link_cz(i) != 0) J[2] += link_cz(i) * s;
+            s *= L::w36(i);
+            D36 += s;
+            if (link_cx(i) != 0) J36[0] += link_cx(i) * s;
+            if (link_cy(i) != 0) J36[1] += link_cy(i) * s;
+            if (link_cz(i) != 0) J36[2] += link_cz(i) * s;
         }
-        // post-combine (sum_i v_i a f^(e,o)_i(x) = a rho_x u_x) and forcing
+        const float Dsum = div36(D36);
+        // post-combine: sum_i v_i a f^(e,o)_i(x) = a rho_x u_x
+        float J[3];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            J[k] = fmaf(p.a * rx, ux[k], J[k]);
-            if (FORCE) J[k] = fmaf(rx, p.g[k], J[k]);
-        }
+        for (int k = 0; k < D; ++k) J[k] = fmaf(p.a * rx, ux[k], div36(J36[k]));
         // u = J / (1 + D) evaluated as J - J * (D / (1 + D)): the rounding of
         // 1 + D then only touches the small correction term, which keeps the
         // FP32 error from accumulating over long runs.
@@ -181,13 +190,13 @@ __global__ __launch_bounds__(kGenericBlock) void k_adj_generic(ProblemArgs p, co
                 // the term bounces back into y itself along -v_k
                 m = muR_y - vdot<Q>(k, muJ_y);
                 const float wd[3] = {p.wall_da[wm][0], p.wall_da[wm][1], p.wall_da[wm][2]};
-                da = fmaf(L::w(k) * vdot<Q>(k, wd), m, da);
+                da = fmaf(L::w36(k) * (1.0f / 36.0f) * vdot<Q>(k, wd), m, da);
             } else {
                 float mt[3] = {mu_in[n + t], mu_in[2 * n + t], D == 3 ? mu_in[3 * n + t] : 0.0f};
                 m = mu_in[t] + vdot<Q>(k, mt);
             }
             const float cc = vdot<Q>(k, uy);
-            const float wm_ = L::w(k) * m;
+            const float wm_ = L::w36(k) * (1.0f / 36.0f) * m;
             // d s_k / d(rho-1) = w_k [1 + c (A + 9/2 c) - 3/2 |u|^2]
             lr = fmaf(wm_, 1.0f + cc * fmaf(4.5f, cc, p.A) + By, lr);
             // d s_k / d u = w_k rho [(A + 9 c) v_k - 3 u]

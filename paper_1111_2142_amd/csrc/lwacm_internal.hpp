@@ -14,8 +14,9 @@ struct ProblemArgs {
     int Q, D, nx, ny, nz;
     long long n;             // nodes
     float a;                 // 2 - 2/omega, the post-combine factor of Eq. ACM2.0
-    float A;                 // 3 (1 - a) = 3 (2/omega - 1)
+    float A;                 // 3 (1 - a) = 3 (2/omega - 1); a + A/3 == 1 exactly in FP32
     float g[3];              // body acceleration (Eq. force)
+    int has_force;           // g given (forced problems use the generic kernel)
     float wall_term[kMaxWallIds][3];  // (1 - a) * 6 * rho0 * u_w per wall id (Eq. ACM2.0ccccbb)
     float wall_da[kMaxWallIds][3];  // 6 * rho0 * u_w: minus d(wall_term)/da
     float ld_scale[2];       // storage -> value: 2^-k (rho - 1, u); 1 for FP32
@@ -48,12 +49,15 @@ hipError_t launch_moments(const ProblemArgs &p, int storage, const void *src, fl
                           float *u, const ReduceArgs &r, unsigned nblocks, hipStream_t stream);
 hipError_t launch_mask_scan(const ProblemArgs &p, unsigned *d_out2, hipStream_t stream);
 
-// D3Q19 z-marching tile kernel (returns hipErrorNotSupported if the problem
-// does not fit its constraints).
+// D3Q19 z-marching tile kernel.  Masked problems also need the per-node
+// classes and solid-upstream bit sets made by launch_classify (n bytes and
+// n unsigned).  Returns hipErrorNotSupported if the problem does not fit.
 bool march_supported(const ProblemArgs &p);
 unsigned march_num_blocks(const ProblemArgs &p);
-hipError_t launch_fwd_march(const ProblemArgs &p, int storage, bool force, const void *src,
-                            void *dst, const ReduceArgs &r, hipStream_t stream);
+hipError_t launch_classify(const ProblemArgs &p, uint8_t *cls, unsigned *bits, hipStream_t s);
+hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, void *dst,
+                            const uint8_t *cls, const unsigned *bits, const ReduceArgs &r,
+                            hipStream_t stream);
 
 // Number of blocks the generic grid-stride kernels use for n nodes.
 unsigned generic_grid(long long n);

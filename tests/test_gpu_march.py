@@ -1,0 +1,113 @@
+"""Parity of the D3Q19 z-marching tile kernel: against the FP64 oracle on
+sizes with partial z chunks, a single plane (the z neighbours wrap onto the
+node's own plane), FP16 storage, forcing and walls, and against the generic
+one-thread-per-node kernel."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from gpu_helpers import banner, fluid_of, gpu_run, need_gpu, oracle_run, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+MARCH, GENERIC = 2, 1
+
+
+@pytest.mark.parametrize("shape", [(40, 32, 64), (1, 16, 32), (3, 16, 32), (65, 48, 96)])
+@pytest.mark.parametrize("storage", [0, 1])
+def test_march_matches_oracle(shape, storage):
+    banner(f"march {shape} storage={storage}")
+    drho, u = wl.random_state(shape, 3, seed=13, du=0.04, drho=0.01)
+    if storage:
+        s16 = 2.0 ** 14
+        drho = (drho * s16).astype(np.float16).astype(np.float64) / s16
+        u = (u * s16).astype(np.float16).astype(np.float64) / s16
+    steps = 10
+    dr, uu, _ = gpu_run(19, shape, 1.62, drho, u, steps, storage=storage, variant=MARCH)
+    rdr, ru = oracle_run(19, shape, 1.62, drho, u, steps)
+    err = rel_l2(uu, ru)
+    banner(f"march {shape} storage={storage}: rel-L2 u {err:.3e}")
+    assert err < (1e-5 if storage == 0 else 1e-3)
+    assert rel_l2(dr, rdr) < (1e-4 if storage == 0 else 2e-2)
+
+
+def test_forced_problems_use_the_generic_kernel():
+    """Forcing is applied inside every link term by the generic kernel; the
+    march kernel declines forced problems and AUTO falls back."""
+    L = need_gpu()
+    shape = (20, 16, 32)
+    banner("forced march -> generic")
+    g = (1e-4, -2e-4, 5e-5)
+    s = L.Solver(19, 32, 16, 20, 1.3, g=g)
+    with pytest.raises(L.LWACMError) as ei:
+        L.lwacm_set_variant(s.ctx, MARCH)
+    assert ei.value.code == L.LWACM_EUNSUPPORTED
+    drho, u = wl.random_state(shape, 3, seed=14, du=0.03, drho=0.01)
+    dr, uu, _ = gpu_run(19, shape, 1.3, drho, u, 20, g=g)
+    rdr, ru = oracle_run(19, shape, 1.3, drho, u, 20, g=g)
+    assert rel_l2(uu, ru) < 1e-5
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_march_masked_cavity_matches_oracle(n):
+    """Lid-driven cube with the march kernel's bounce-back path."""
+    banner(f"march cavity {n}")
+    mask = wl.cavity_mask(n)
+    table = wl.wall_table((0.05, 0.0, 0.0))
+    shape = (n, n, n)
+    drho, u = np.zeros(shape), np.zeros((3,) + shape)
+    steps = 150
+    dr, uu, s = gpu_run(19, shape, 1.9, drho, u, steps, mask=mask, wall_u=table, variant=MARCH)
+    rdr, ru = oracle_run(19, shape, 1.9, drho, u, steps, mask=mask, wall_u=table)
+    fl = fluid_of(mask, shape)
+    err = rel_l2(uu[:, fl], ru[:, fl])
+    banner(f"march cavity {n}: rel-L2 u {err:.3e}")
+    assert err < 1e-5
+    m, _ = s.diagnostics()
+    nf = int(fl.sum())
+    assert abs(m - nf) / nf < 1e-9
+    # solid nodes are never written
+    assert np.all(uu[:, ~fl] == 0) and np.all(dr[~fl] == 0)
+
+
+def test_march_random_walls_with_moving_ids():
+    """Scattered solid nodes with two moving wall ids and random state."""
+    shape = (12, 32, 32)
+    banner("march random walls")
+    rng = np.random.Generator(np.random.PCG64(8))
+    mask = (rng.random(shape) < 0.08).astype(np.uint8)
+    mask[mask == 1] = rng.integers(1, 4, int(mask.sum())).astype(np.uint8)
+    table = np.array([[0, 0, 0], [0, 0, 0], [0.03, -0.01, 0.02], [-0.02, 0.0, 0.01]])
+    drho, u = wl.random_state(shape, 3, seed=9, du=0.03, drho=0.01)
+    drho = drho.astype(np.float32).astype(np.float64)
+    rho0 = 1.0 + drho[mask == 0].mean()
+    dr, uu, _ = gpu_run(19, shape, 1.5, drho, u, 8, mask=mask, wall_u=table, variant=MARCH)
+    rdr, ru = oracle_run(19, shape, 1.5, drho, u, 8, mask=mask, wall_u=table, rho0=rho0)
+    fl = fluid_of(mask, shape)
+    assert rel_l2(uu[:, fl], ru[:, fl]) < 1e-5
+    dg, ug, _ = gpu_run(19, shape, 1.5, drho, u, 8, mask=mask, wall_u=table, variant=GENERIC)
+    assert rel_l2(uu[:, fl], ug[:, fl]) < 1e-6
+
+
+def test_march_close_to_generic_and_deterministic():
+    shape = (64, 32, 64)
+    banner("march vs generic")
+    drho, u = wl.taylor_green_3d(64, 0.02)
+    drho = drho[:, :32, :]
+    u = u[:, :, :32, :]
+    a = gpu_run(19, shape, 1.7, drho, u, 50, variant=MARCH)
+    b = gpu_run(19, shape, 1.7, drho, u, 50, variant=GENERIC)
+    c = gpu_run(19, shape, 1.7, drho, u, 50, variant=MARCH)
+    assert rel_l2(a[1], b[1]) < 1e-6
+    assert np.array_equal(a[1], c[1]) and np.array_equal(a[0], c[0])
+    assert a[2].diagnostics() == c[2].diagnostics()
+
+
+def test_march_rejects_unsupported_shape():
+    L = need_gpu()
+    banner("march unsupported")
+    s = L.Solver(19, 48, 48, 48, 1.5)
+    with pytest.raises(L.LWACMError) as ei:
+        L.lwacm_set_variant(s.ctx, MARCH)
+    assert ei.value.code == L.LWACM_EUNSUPPORTED
