@@ -126,7 +126,9 @@ int lwacm_step(lwacm_ctx *c, int nsteps);
 int lwacm_diagnostics(lwacm_ctx *c, double *h_mass, double *h_energy);
 
 /* Optional device history: step k (counted from lwacm_set_state) also writes
- * its (mass, energy) to d_hist[2 * (k % capacity)].  NULL disables. */
+ * its (mass deviation sum(rho - 1), energy 1/2 sum|u|^2) over fluid nodes, in
+ * FP64, to d_hist[2 * (k % capacity)].  The deviation keeps full precision;
+ * the mass is it plus the number of fluid nodes.  NULL disables. */
 int lwacm_set_diag_history(lwacm_ctx *c, double *d_hist, int capacity);
 
 /* Current state as FP32 fields: d_drho (rho - 1) and d_u (either may be

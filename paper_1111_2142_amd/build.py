@@ -2,7 +2,9 @@
 
 Every ``csrc/*.hip`` file is compiled to an object in ``_build/`` and linked
 into ``paper_1111_2142_amd/liblwacm.so``.  Packed FP32 instructions are
-disabled (``-packed-fp32-ops``) for all device code.
+disabled (``-packed-fp32-ops``) for all device code, and multiply-add
+contraction is off (``-ffp-contract=off``): every FMA is written as fmaf(),
+so a quantity evaluated by two code paths rounds the same way in both.
 """
 import glob
 import os
@@ -20,7 +22,7 @@ ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off",
           "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 
 

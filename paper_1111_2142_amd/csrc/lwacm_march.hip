@@ -4,21 +4,30 @@
 // chunk of NZC planes; every thread owns one column and walks up the chunk.
 // For each plane it loads the node's state once (three planes in flight in
 // a register ring), evaluates the node's own pre-combined link terms of
-// Eq. ACM2.0b for all 19 links, and pushes them towards the columns that
-// consume them.  Links are grouped by their (v_x, v_y) direction: the three
-// links sharing a direction (v_z = -1, 0, +1) reach the same neighbouring
-// column on three consecutive planes, so each column sums them in registers
-// while marching and exchanges only two numbers per direction (density part
-// and z-momentum part; the x/y momentum parts follow from the direction) plus
-// one number per in-plane diagonal: 12 floats per node through LDS, instead
-// of gathering 18 neighbour states.  A ring of halo columns around the tile
-// is computed by extra threads in their own waves.  The receiving column
-// adds the exchanged terms, its own (v_x, v_y) = (0, 0) links and the
-// post-combine term a rho u (Eqs. ACM2.0b), normalises, and stores.  Forced
-// problems (Eq. force) run on the generic kernel, which adds the forcing
-// inside each link term where its FP32 rounding does not bias long runs.  Halfway bounce-back (Eqs. ACM2.0cbb-ACM2.0ccccbb)
-// is applied at the receiving node from a precomputed per-node bit set of
-// solid upstream links; solid nodes push zeros and are never written.
+// Eq. ACM2.0b and pushes them towards the columns that consume them.  Links
+// are grouped by their (v_x, v_y) direction: the three links sharing a
+// direction (v_z = -1, 0, +1) reach the same neighbouring column on three
+// consecutive planes, so each column sums them in registers while marching
+// and exchanges only two numbers per direction (density part and z-momentum
+// part; the x/y momentum parts follow from the direction) plus one number
+// per in-plane diagonal: 12 floats per node through LDS, instead of gathering
+// 18 neighbour states.
+//
+// Waves have fixed roles.  Interior waves own the TX x TY tile and evaluate
+// all 19 links.  Two halo waves own the ring of columns around the tile and
+// evaluate only the five links that point into it: the Y-halo wave holds the
+// rows below and above the tile (links with v_y = +1 resp. -1), the X-halo
+// wave the columns left and right of it including the corners (v_x = +1 resp.
+// -1); one lane-dependent sign selects the direction, so a halo wave runs one
+// instruction stream without divergence.
+//
+// The receiving column adds the exchanged terms, its own (v_x, v_y) = (0, 0)
+// links and the post-combine term a rho u (Eqs. ACM2.0b), normalises, and
+// stores.  Forced problems (Eq. force) run on the generic kernel, which adds
+// the forcing inside each link term where its FP32 rounding does not bias
+// long runs.  Halfway bounce-back (Eqs. ACM2.0cbb-ACM2.0ccccbb) is applied at
+// the receiving node from a precomputed per-node bit set of solid upstream
+// links; solid nodes push zeros and are never written.
 //
 // Link terms are kept unweighted and summed with the exact integer weights
 // 12, 2, 1 (= 36 w_i for rest, axis and diagonal links of D3Q19); the sums
@@ -30,30 +39,39 @@ namespace lwacm {
 
 namespace {
 
-constexpr int TX = 32;   // tile width (x, contiguous in memory)
-constexpr int TY = 16;   // tile height (y)
-constexpr int NZC = 32;  // planes per workgroup
-constexpr int NINT = TX * TY;                 // interior columns
-constexpr int NHALO = 2 * (TX + 2) + 2 * TY;  // ring of halo columns
-constexpr int NTHREADS = ((NINT + NHALO + kWave - 1) / kWave) * kWave;
-constexpr int SX = TX + 2;                    // LDS row pitch
-constexpr int SPLANE = SX * (TY + 2);         // floats per exchanged quantity
-constexpr int NQ = 12;                        // exchanged quantities per node
+#ifndef LWACM_MARCH_NZC
+#define LWACM_MARCH_NZC 32
+#endif
+#ifndef LWACM_MARCH_NBUF
+#define LWACM_MARCH_NBUF 2
+#endif
+#ifndef LWACM_MARCH_RING
+#define LWACM_MARCH_RING 3
+#endif
+constexpr int TX = 32;                // tile width (x, contiguous in memory)
+constexpr int TY = 16;                // tile height (y)
+constexpr int NZC = LWACM_MARCH_NZC;  // planes per workgroup (plane loop fully unrolled)
+// LDS exchange buffers: 2 = one barrier per plane; 1 = half the LDS (more
+// workgroups per CU) at the cost of a second barrier per plane.
+constexpr int NBUF = LWACM_MARCH_NBUF;
+// Planes of state in flight per thread (register ring).
+constexpr int RING = LWACM_MARCH_RING;
+constexpr int NINT = TX * TY;                  // interior columns (whole waves)
+constexpr int NTHREADS = NINT + 2 * kWave;     // + Y-halo wave + X-halo wave
+constexpr int SX = TX + 2;                     // LDS row pitch (slots)
+constexpr int NSLOT = SX * (TY + 2);           // slots per exchange group
 
-// Exchanged quantities (per sending column, per target plane):
-enum : int {
-    Q_PE = 0,  // density part of the three links with (vx,vy) = (+1, 0)
-    Q_ZE,      // their z-momentum part
-    Q_PW, Q_ZW,   // (-1, 0)
-    Q_PN, Q_ZN,   // ( 0,+1)
-    Q_PS, Q_ZS,   // ( 0,-1)
-    Q_NE,      // link (+1,+1,0)
-    Q_NW,      // link (-1,+1,0)
-    Q_SE,      // link (+1,-1,0)
-    Q_SW       // link (-1,-1,0)
-};
+static_assert(NINT % kWave == 0, "interior must be whole waves");
+static_assert(2 * TX <= kWave && 2 * (TY + 2) <= kWave, "halo rows must fit one wave each");
 
-// Per target plane accumulator of one column.
+enum Role { INTERIOR = 0, HALO_Y = 1, HALO_X = 2 };
+
+// Exchange groups, one float4 per slot:
+//   G0 = (PE, ZE, PW, ZW)   links with (vx,vy) = (+1,0) and (-1,0): density and z parts
+//   G1 = (PN, ZN, PS, ZS)   (0,+1) and (0,-1)
+//   G2 = (NE, NW, SE, SW)   in-plane diagonals (+1,+1,0), (-1,+1,0), (+1,-1,0), (-1,-1,0)
+
+// Per target plane accumulator of an interior column.
 struct Acc {
     float pe, ze, pw, zw, pn, zn, ps, zs;  // direction partials (weights folded)
     float ne, nw, se, sw;                  // in-plane diagonals
@@ -64,15 +82,74 @@ struct Acc {
     int cls;                               // 0 fluid, 1 fluid next to a wall, 2 solid
 };
 
+__device__ __forceinline__ bool has_bit(unsigned bits, int i) { return (bits >> i) & 1u; }
+
+// Global memory goes through buffer resources: one descriptor per field in
+// SGPRs, the column's fixed 32-bit byte offset in a VGPR and the plane's
+// byte offset as the scalar offset, so a load or store costs no per-lane
+// address arithmetic.  (march_supported() guarantees that every field fits
+// in 4 GiB.)
+using Rsrc = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned long long bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0,
+                                             (int)(unsigned)bytes, 0x00020000);
+}
+
+template <class T>
+struct BufIO;
+
+template <>
+struct BufIO<float> {
+    using Raw = float;
+    __device__ __forceinline__ static Raw load(Rsrc r, unsigned voff, unsigned soff)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    }
+    __device__ __forceinline__ static float value(Raw v, float) { return v; }
+    __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float v,
+                                                 float)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    }
+};
+
+template <>
+struct BufIO<__half> {
+    using Raw = unsigned short;
+    __device__ __forceinline__ static Raw load(Rsrc r, unsigned voff, unsigned soff)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+    }
+    __device__ __forceinline__ static float value(Raw v, float inv_scale)
+    {
+        return __half2float(__ushort_as_half(v)) * inv_scale;
+    }
+    __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float v,
+                                                 float scale)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v * scale)), r,
+                                              voff, soff, 0);
+    }
+};
+
 template <class T>
 struct Ring {
-    T v[4];
+    typename BufIO<T>::Raw v[4];
     uint8_t cls;
 };
 
-// Upstream-solid bit of link i in the per-node bit set (link indexing of
-// lwacm_device.hpp); bit 0 is unused.
-__device__ __forceinline__ bool has_bit(unsigned bits, int i) { return (bits >> i) & 1u; }
+// Unweighted link term with c = v_i . u (Eq. ACM2.0b pre-combining,
+// deviation form): L(c) = fma(A rho, c, m) with the even part
+// m = fma(4.5 rho c, c, E0).  m is bitwise even in c, so the pair of opposite
+// links shares it, and interior and halo threads, which both use exactly
+// these operations (the build disables FMA contraction), produce bitwise the
+// same term for a given link.
+__device__ __forceinline__ float lterm(float c, float E0, float r45, float rA)
+{
+    return fmaf(rA, c, fmaf(r45 * c, c, E0));
+}
 
 template <class T, bool MASK>
 __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *__restrict__ src,
@@ -81,9 +158,10 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                                                         const unsigned *__restrict__ bb_bits,
                                                         ReduceArgs r)
 {
-    __shared__ float xch[2][NQ * SPLANE];
+    __shared__ float4 xch[NBUF][3][NSLOT];
 
     const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const long long n = p.n;
     const long long plane = (long long)nx * ny;
@@ -100,247 +178,320 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
     const int zc = (int)(rest / (unsigned)tiles_y);
     const int z0 = zc * NZC;
     const int z1 = min(z0 + NZC, nz);
-    const int nzc = z1 - z0;
 
-    // My column, in tile coordinates [-1, TX] x [-1, TY].
+    // Role and column in tile coordinates [-1, TX] x [-1, TY].
+    const int role = tid < NINT ? INTERIOR : (tid < NINT + kWave ? HALO_Y : HALO_X);
     int lx, ly;
-    bool interior = tid < NINT;
-    bool active = tid < NINT + NHALO;
-    if (interior) {
+    float sgn = 1.0f;     // halo direction sign
+    bool active = true;   // writes to LDS
+    if (role == INTERIOR) {
         lx = tid % TX;
         ly = tid / TX;
+    } else if (role == HALO_Y) {
+        // lanes [0, TX): row below the tile, pushing north (v_y = +1);
+        // lanes [TX, 2 TX): row above, pushing south (v_y = -1).
+        const bool top = lane >= TX;
+        lx = top ? lane - TX : lane;
+        ly = top ? TY : -1;
+        sgn = top ? -1.0f : 1.0f;
+        active = lane < 2 * TX;
+        if (!active) lx = 0;
     } else {
-        const int h = tid - NINT;
-        if (h < TX + 2) {
-            ly = -1;
-            lx = h - 1;
-        } else if (h < 2 * (TX + 2)) {
-            ly = TY;
-            lx = h - (TX + 2) - 1;
-        } else if (h < 2 * (TX + 2) + TY) {
-            lx = -1;
-            ly = h - 2 * (TX + 2);
-        } else if (h < NHALO) {
-            lx = TX;
-            ly = h - 2 * (TX + 2) - TY;
-        } else {
-            lx = 0;  // padding lanes: valid address, never written to LDS
-            ly = 0;
-        }
+        // lanes [0, TY+2): column left of the tile (corners included), pushing
+        // east (v_x = +1); lanes [TY+2, 2(TY+2)): right column, pushing west.
+        const bool right = lane >= TY + 2;
+        const int l = right ? lane - (TY + 2) : lane;
+        lx = right ? TX : -1;
+        ly = l - 1;
+        sgn = right ? -1.0f : 1.0f;
+        active = lane < 2 * (TY + 2);
+        if (!active) ly = 0;
     }
     int gx = tile_x * TX + lx;
     int gy = tile_y * TY + ly;
     gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
     gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
-    const long long col = (long long)gy * nx + gx;
+    const unsigned col = (unsigned)(gy * nx + gx);  // offset inside a plane (< 2^31)
     const int slot = (ly + 1) * SX + (lx + 1);
 
     const float A = p.A;
     const float a = p.a;
 
-    auto node_at_plane = [&](int pz) -> long long {
+    // plane index with periodic wrap, as a byte offset inside a field
+    const unsigned plane_bytes = (unsigned)(plane * (long long)sizeof(T));
+    auto soff_of = [&](int pz) -> unsigned {
         pz = pz < 0 ? pz + nz : (pz >= nz ? pz - nz : pz);
-        return (long long)pz * plane + col;
+        return (unsigned)pz * plane_bytes;
     };
+    const unsigned long long fbytes = (unsigned long long)n * sizeof(T);
+    const Rsrc rs[4] = {make_rsrc(src, fbytes), make_rsrc(src + n, fbytes),
+                        make_rsrc(src + 2 * n, fbytes), make_rsrc(src + 3 * n, fbytes)};
+    const Rsrc rd[4] = {make_rsrc(dst, fbytes), make_rsrc(dst + n, fbytes),
+                        make_rsrc(dst + 2 * n, fbytes), make_rsrc(dst + 3 * n, fbytes)};
+    const unsigned voff = col * (unsigned)sizeof(T);
     auto issue = [&](Ring<T> &rg, int pz) {
-        const long long idx = node_at_plane(pz);
-        rg.v[0] = src[idx];
-        rg.v[1] = src[n + idx];
-        rg.v[2] = src[2 * n + idx];
-        rg.v[3] = src[3 * n + idx];
-        if (MASK) rg.cls = cls_arr[idx];
+        const unsigned so = soff_of(pz);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) rg.v[f] = BufIO<T>::load(rs[f], voff, so);
+        if (MASK) {
+            pz = pz < 0 ? pz + nz : (pz >= nz ? pz - nz : pz);
+            rg.cls = cls_arr[(long long)pz * plane + col];
+        }
     };
 
-    Ring<T> ring[3];
-    Acc acc[3];
+    Ring<T> ring[RING];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        acc[j] = Acc{};
+    for (int j = 0; j < RING; ++j) {
         ring[j].cls = 0;
+        issue(ring[j], min(z0 - 1 + j, z1));
     }
-    const int niter = nzc + 2;
-    issue(ring[0], z0 - 1);
-    issue(ring[1], z0);
-    issue(ring[2], z0 + 1);
 
     float mass = 0.0f, energy = 0.0f;
 
-    for (int k0 = 0; k0 < niter; k0 += 3) {
+    // The two roles run separate loops (a wave-uniform split) with the same
+    // sequence of barriers: one per finalised plane.
+    if (role == INTERIOR) {
+        Acc acc[3];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int k = k0 + j;
-            if (k >= niter) break;
-            const int pz = z0 - 1 + k;  // source plane of this iteration
-            Acc &A1 = acc[(j + 1) % 3];  // target plane pz + 1
-            Acc &A0 = acc[j];            // target plane pz
-            Acc &Am = acc[(j + 2) % 3];  // target plane pz - 1 (finalised now)
+        for (int j = 0; j < 3; ++j) acc[j] = Acc{};
+        // Fully unrolled over the chunk: ring slots and accumulators are
+        // compile-time indexed, so no loop back edge forces the compiler to
+        // copy registers whose loads are still in flight.
+#pragma unroll
+        for (int k = 0; k < NZC + 2; ++k) {
+            {
+                const int j = k % 3;         // accumulator slot
+                const int rj = k % RING;     // ring slot
+                const int pz = z0 - 1 + k;  // source plane of this iteration
+                Acc &A1 = acc[(j + 1) % 3];  // target plane pz + 1
+                Acc &A0 = acc[j];            // target plane pz
+                Acc &Am = acc[(j + 2) % 3];  // target plane pz - 1 (finalised now)
 
-            // ---- consume the ring slot of plane pz, refill it with pz + 3
-            const float dr = Storage<T>::load(ring[j].v, 0, p.ld_scale[0]);
-            const float ux = Storage<T>::load(ring[j].v, 1, p.ld_scale[1]);
-            const float uy = Storage<T>::load(ring[j].v, 2, p.ld_scale[1]);
-            const float uz = Storage<T>::load(ring[j].v, 3, p.ld_scale[1]);
-            const int cls = MASK ? (int)ring[j].cls : 0;
-            if (k + 3 < niter) issue(ring[j], pz + 3);
+                // ---- consume the ring slot of plane pz, refill it with pz + 3
+                const float dr = BufIO<T>::value(ring[rj].v[0], p.ld_scale[0]);
+                const float ux = BufIO<T>::value(ring[rj].v[1], p.ld_scale[1]);
+                const float uy = BufIO<T>::value(ring[rj].v[2], p.ld_scale[1]);
+                const float uz = BufIO<T>::value(ring[rj].v[3], p.ld_scale[1]);
+                const int cls = MASK ? (int)ring[rj].cls : 0;
+                // refill with plane pz + RING (unconditional; past the chunk it
+                // re-reads plane z1, which is cached and never consumed)
+                if (k + RING < NZC + 2) issue(ring[rj], min(pz + RING, z1));
 
-            // ---- own link terms of plane pz, unweighted, in +-c pairs:
-            // L(+-c) = E0 + 4.5 rho c^2 +- A rho c with E0 = drho - 1.5 rho |u|^2
-            const float rho = 1.0f + dr;
-            const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
-            float E0 = fmaf(rho, -1.5f * usq, dr);
-            float r45 = 4.5f * rho;
-            float rA = A * rho;
-            if (MASK && cls >= 2) {  // solid: push nothing
-                E0 = 0.0f;
-                r45 = 0.0f;
-                rA = 0.0f;
-            }
-            auto pair = [&](float c, float &lp, float &lm) {
-                const float m = fmaf(r45 * c, c, E0);
-                const float q = rA * c;
-                lp = m + q;
-                lm = m - q;
-            };
-            float Lpx, Lmx, Lpy, Lmy, Lpz, Lmz;
-            float Lpp0, Lmm0, Lpm0, Lmp0;  // (+x+y), (-x-y), (+x-y), (-x+y)
-            float Lp0p, Lm0m, Lp0m, Lm0p;  // (+x,+z), (-x,-z), (+x,-z), (-x,+z)
-            float L0pp, L0mm, L0pm, L0mp;  // (+y,+z), (-y,-z), (+y,-z), (-y,+z)
-            pair(ux, Lpx, Lmx);
-            pair(uy, Lpy, Lmy);
-            pair(uz, Lpz, Lmz);
-            pair(ux + uy, Lpp0, Lmm0);
-            pair(ux - uy, Lpm0, Lmp0);
-            pair(ux + uz, Lp0p, Lm0m);
-            pair(ux - uz, Lp0m, Lm0p);
-            pair(uy + uz, L0pp, L0mm);
-            pair(uy - uz, L0pm, L0mp);
+                // ---- own link terms in +-c pairs:
+                // L(+-c) = E0 + 4.5 rho c^2 +- A rho c, E0 = drho - 1.5 rho |u|^2
+                const float rho = 1.0f + dr;
+                const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+                float E0 = fmaf(rho, -1.5f * usq, dr);
+                float r45 = 4.5f * rho;
+                float rA = A * rho;
+                if (MASK && cls >= 2) {  // solid: push nothing
+                    E0 = 0.0f;
+                    r45 = 0.0f;
+                    rA = 0.0f;
+                }
+                auto pair = [&](float c, float &lp, float &lm) {
+                    const float m = fmaf(r45 * c, c, E0);  // = lterm's even part
+                    lp = fmaf(rA, c, m);                   // = lterm(c)
+                    lm = fmaf(rA, -c, m);                  // = lterm(-c)
+                };
+                float Lpx, Lmx, Lpy, Lmy, Lpz, Lmz;
+                float Lpp0, Lmm0, Lpm0, Lmp0;  // (+x+y), (-x-y), (+x-y), (-x+y)
+                float Lp0p, Lm0m, Lp0m, Lm0p;  // (+x,+z), (-x,-z), (+x,-z), (-x,+z)
+                float L0pp, L0mm, L0pm, L0mp;  // (+y,+z), (-y,-z), (+y,-z), (-y,+z)
+                pair(ux, Lpx, Lmx);
+                pair(uy, Lpy, Lmy);
+                pair(uz, Lpz, Lmz);
+                pair(ux + uy, Lpp0, Lmm0);
+                pair(ux - uy, Lpm0, Lmp0);
+                pair(ux + uz, Lp0p, Lm0m);
+                pair(ux - uz, Lp0m, Lm0p);
+                pair(uy + uz, L0pp, L0mm);
+                pair(uy - uz, L0pm, L0mp);
 
-            // ---- links with v_z = +1 start the accumulator of plane pz + 1
-            A1.pe = Lp0p;
-            A1.ze = Lp0p;
-            A1.pw = Lm0p;
-            A1.zw = Lm0p;
-            A1.pn = L0pp;
-            A1.zn = L0pp;
-            A1.ps = L0mp;
-            A1.zs = L0mp;
-            A1.d = 2.0f * Lpz;
-            A1.jz = 2.0f * Lpz;
-            // ---- links with v_z = 0 complete the in-plane part of plane pz
-            A0.pe = fmaf(2.0f, Lpx, A0.pe);
-            A0.pw = fmaf(2.0f, Lmx, A0.pw);
-            A0.pn = fmaf(2.0f, Lpy, A0.pn);
-            A0.ps = fmaf(2.0f, Lmy, A0.ps);
-            A0.ne = Lpp0;
-            A0.nw = Lmp0;
-            A0.se = Lpm0;
-            A0.sw = Lmm0;
-            A0.d = fmaf(12.0f, E0, A0.d);
-            const float arho = a * rho;
-            A0.post[0] = arho * ux;
-            A0.post[1] = arho * uy;
-            A0.post[2] = arho * uz;
-            if (MASK) {
-                A0.cls = cls;
-                A0.bits = 0u;
-                if (cls == 1) A0.bits = bb_bits[node_at_plane(pz)];
-                A0.lnk[0] = E0;
-                A0.lnk[1] = Lpx;  A0.lnk[2] = Lmx;  A0.lnk[3] = Lpy;  A0.lnk[4] = Lmy;
-                A0.lnk[5] = Lpp0; A0.lnk[6] = Lmm0; A0.lnk[7] = Lpm0; A0.lnk[8] = Lmp0;
-                A0.lnk[9] = Lpz;  A0.lnk[10] = Lp0p; A0.lnk[11] = Lm0p; A0.lnk[12] = L0pp;
-                A0.lnk[13] = L0mp; A0.lnk[14] = Lmz; A0.lnk[15] = Lm0m; A0.lnk[16] = Lp0m;
-                A0.lnk[17] = L0mm; A0.lnk[18] = L0pm;
-            }
-            // ---- links with v_z = -1 finish plane pz - 1
-            Am.pe += Lp0m;
-            Am.ze -= Lp0m;
-            Am.pw += Lm0m;
-            Am.zw -= Lm0m;
-            Am.pn += L0pm;
-            Am.zn -= L0pm;
-            Am.ps += L0mm;
-            Am.zs -= L0mm;
-            Am.d = fmaf(2.0f, Lmz, Am.d);
-            Am.jz = fmaf(-2.0f, Lmz, Am.jz);
+                // links with v_z = +1 start the accumulator of plane pz + 1
+                A1.pe = Lp0p;
+                A1.ze = Lp0p;
+                A1.pw = Lm0p;
+                A1.zw = Lm0p;
+                A1.pn = L0pp;
+                A1.zn = L0pp;
+                A1.ps = L0mp;
+                A1.zs = L0mp;
+                A1.d = 2.0f * Lpz;
+                A1.jz = 2.0f * Lpz;
+                // links with v_z = 0 complete the in-plane part of plane pz
+                A0.pe = fmaf(2.0f, Lpx, A0.pe);
+                A0.pw = fmaf(2.0f, Lmx, A0.pw);
+                A0.pn = fmaf(2.0f, Lpy, A0.pn);
+                A0.ps = fmaf(2.0f, Lmy, A0.ps);
+                A0.ne = Lpp0;
+                A0.nw = Lmp0;
+                A0.se = Lpm0;
+                A0.sw = Lmm0;
+                A0.d = fmaf(12.0f, E0, A0.d);
+                const float arho = a * rho;
+                A0.post[0] = arho * ux;
+                A0.post[1] = arho * uy;
+                A0.post[2] = arho * uz;
+                if (MASK) {
+                    A0.cls = cls;
+                    A0.bits = 0u;
+                    // only planes this chunk finalises (z0 <= pz < z1 <= nz)
+                    if (cls == 1 && pz >= z0 && pz < z1)
+                        A0.bits = bb_bits[(long long)pz * plane + col];
+                    A0.lnk[0] = E0;
+                    A0.lnk[1] = Lpx;  A0.lnk[2] = Lmx;  A0.lnk[3] = Lpy;  A0.lnk[4] = Lmy;
+                    A0.lnk[5] = Lpp0; A0.lnk[6] = Lmm0; A0.lnk[7] = Lpm0; A0.lnk[8] = Lmp0;
+                    A0.lnk[9] = Lpz;  A0.lnk[10] = Lp0p; A0.lnk[11] = Lm0p; A0.lnk[12] = L0pp;
+                    A0.lnk[13] = L0mp; A0.lnk[14] = Lmz; A0.lnk[15] = Lm0m; A0.lnk[16] = Lp0m;
+                    A0.lnk[17] = L0mm; A0.lnk[18] = L0pm;
+                }
+                // links with v_z = -1 finish plane pz - 1
+                Am.pe += Lp0m;
+                Am.ze -= Lp0m;
+                Am.pw += Lm0m;
+                Am.zw -= Lm0m;
+                Am.pn += L0pm;
+                Am.zn -= L0pm;
+                Am.ps += L0mm;
+                Am.zs -= L0mm;
+                Am.d = fmaf(2.0f, Lmz, Am.d);
+                Am.jz = fmaf(-2.0f, Lmz, Am.jz);
 
-            if (k < 2) continue;  // planes below the chunk are halo only
+                if (k < 2) continue;  // planes below the chunk are halo only
+                // ---- exchange the partials of plane pz - 1 through LDS
+                if (NBUF == 1 && k > 2) __syncthreads();  // previous plane's reads done
+                float4 *X = xch[k % NBUF][0];
+                X[0 * NSLOT + slot] = make_float4(Am.pe, Am.ze, Am.pw, Am.zw);
+                X[1 * NSLOT + slot] = make_float4(Am.pn, Am.zn, Am.ps, Am.zs);
+                X[2 * NSLOT + slot] = make_float4(Am.ne, Am.nw, Am.se, Am.sw);
+                __syncthreads();
+                const float4 gW = X[0 * NSLOT + slot - 1];   // west neighbour: PE, ZE
+                const float4 gE = X[0 * NSLOT + slot + 1];   // east neighbour: PW, ZW
+                const float4 gS = X[1 * NSLOT + slot - SX];  // south: PN, ZN
+                const float4 gN = X[1 * NSLOT + slot + SX];  // north: PS, ZS
+                const float dNE = X[2 * NSLOT + slot - SX - 1].x;
+                const float dNW = X[2 * NSLOT + slot - SX + 1].y;
+                const float dSE = X[2 * NSLOT + slot + SX - 1].z;
+                const float dSW = X[2 * NSLOT + slot + SX + 1].w;
+                const float pE = gW.x, zE = gW.y, pW = gE.z, zW = gE.w;
+                const float pN = gS.x, zN = gS.y, pS = gN.z, zS = gN.w;
 
-            // ---- exchange the partials of plane pz - 1 through LDS
-            float *X = xch[k & 1];
-            if (active) {
-                X[Q_PE * SPLANE + slot] = Am.pe;
-                X[Q_ZE * SPLANE + slot] = Am.ze;
-                X[Q_PW * SPLANE + slot] = Am.pw;
-                X[Q_ZW * SPLANE + slot] = Am.zw;
-                X[Q_PN * SPLANE + slot] = Am.pn;
-                X[Q_ZN * SPLANE + slot] = Am.zn;
-                X[Q_PS * SPLANE + slot] = Am.ps;
-                X[Q_ZS * SPLANE + slot] = Am.zs;
-                X[Q_NE * SPLANE + slot] = Am.ne;
-                X[Q_NW * SPLANE + slot] = Am.nw;
-                X[Q_SE * SPLANE + slot] = Am.se;
-                X[Q_SW * SPLANE + slot] = Am.sw;
-            }
-            __syncthreads();
-            if (!interior) continue;
-            const float pE = X[Q_PE * SPLANE + slot - 1];
-            const float zE = X[Q_ZE * SPLANE + slot - 1];
-            const float pW = X[Q_PW * SPLANE + slot + 1];
-            const float zW = X[Q_ZW * SPLANE + slot + 1];
-            const float pN = X[Q_PN * SPLANE + slot - SX];
-            const float zN = X[Q_ZN * SPLANE + slot - SX];
-            const float pS = X[Q_PS * SPLANE + slot + SX];
-            const float zS = X[Q_ZS * SPLANE + slot + SX];
-            const float dNE = X[Q_NE * SPLANE + slot - SX - 1];
-            const float dNW = X[Q_NW * SPLANE + slot - SX + 1];
-            const float dSE = X[Q_SE * SPLANE + slot + SX - 1];
-            const float dSW = X[Q_SW * SPLANE + slot + SX + 1];
-
-            float D36 = Am.d + ((pE + pW) + (pN + pS)) + ((dNE + dNW) + (dSE + dSW));
-            float Jx = (pE - pW) + ((dNE - dNW) + (dSE - dSW));
-            float Jy = (pN - pS) + ((dNE + dNW) - (dSE + dSW));
-            float Jz = Am.jz + ((zE + zW) + (zN + zS));
-            if (MASK && Am.bits != 0u) {
-                // halfway bounce-back: a solid upstream node x - v_i pushed
-                // nothing; the node's own term of the opposite link returns
-                // along i, plus the moving-wall term of Eq. ACM2.0ccccbb.
                 const int tz = pz - 1;
+                if (tz >= z1) continue;  // padding iteration: nothing to finalise
+                float D36 = Am.d + ((pE + pW) + (pN + pS)) + ((dNE + dNW) + (dSE + dSW));
+                float Jx = (pE - pW) + ((dNE - dNW) + (dSE - dSW));
+                float Jy = (pN - pS) + ((dNE + dNW) - (dSE + dSW));
+                float Jz = Am.jz + ((zE + zW) + (zN + zS));
+                if (MASK && Am.bits != 0u) {
+                    // halfway bounce-back: a solid upstream node x - v_i pushed
+                    // nothing; the node's own term of the opposite link returns
+                    // along i, plus the moving-wall term of Eq. ACM2.0ccccbb.
 #pragma unroll
-                for (int i = 1; i < 19; ++i) {
-                    if (has_bit(Am.bits, i)) {
-                        const int cx = link_cx(i), cy = link_cy(i), cz = link_cz(i);
-                        int ux_ = gx - cx, uy_ = gy - cy, uz_ = tz - cz;
-                        ux_ = ux_ < 0 ? ux_ + nx : (ux_ >= nx ? ux_ - nx : ux_);
-                        uy_ = uy_ < 0 ? uy_ + ny : (uy_ >= ny ? uy_ - ny : uy_);
-                        uz_ = uz_ < 0 ? uz_ + nz : (uz_ >= nz ? uz_ - nz : uz_);
-                        const int m = p.mask[((long long)uz_ * ny + uy_) * nx + ux_];
-                        const float wt = cx * p.wall_term[m][0] + cy * p.wall_term[m][1] +
-                                         cz * p.wall_term[m][2];
-                        const float wi36 = (i <= 4 || i == 9 || i == 14) ? 2.0f : 1.0f;
-                        const float s = wi36 * (Am.lnk[link_opp(i)] + wt);
-                        D36 += s;
-                        Jx = fmaf((float)cx, s, Jx);
-                        Jy = fmaf((float)cy, s, Jy);
-                        Jz = fmaf((float)cz, s, Jz);
+                    for (int i = 1; i < 19; ++i) {
+                        if (has_bit(Am.bits, i)) {
+                            const int cx = link_cx(i), cy = link_cy(i), cz = link_cz(i);
+                            int ux_ = gx - cx, uy_ = gy - cy, uz_ = tz - cz;
+                            ux_ = ux_ < 0 ? ux_ + nx : (ux_ >= nx ? ux_ - nx : ux_);
+                            uy_ = uy_ < 0 ? uy_ + ny : (uy_ >= ny ? uy_ - ny : uy_);
+                            uz_ = uz_ < 0 ? uz_ + nz : (uz_ >= nz ? uz_ - nz : uz_);
+                            const int m = p.mask[((long long)uz_ * ny + uy_) * nx + ux_];
+                            const float wt = cx * p.wall_term[m][0] + cy * p.wall_term[m][1] +
+                                             cz * p.wall_term[m][2];
+                            const float s = Lattice<19>::w36(i) * (Am.lnk[link_opp(i)] + wt);
+                            D36 += s;
+                            Jx = fmaf((float)cx, s, Jx);
+                            Jy = fmaf((float)cy, s, Jy);
+                            Jz = fmaf((float)cz, s, Jz);
+                        }
                     }
                 }
+                Jx = div36(Jx) + Am.post[0];
+                Jy = div36(Jy) + Am.post[1];
+                Jz = div36(Jz) + Am.post[2];
+                const float D = div36(D36);
+                const float q = normalisation_factor(D);
+                const float vx = fmaf(-Jx, q, Jx);
+                const float vy = fmaf(-Jy, q, Jy);
+                const float vz = fmaf(-Jz, q, Jz);
+                if (!MASK || Am.cls < 2) {
+                    const unsigned so = (unsigned)tz * plane_bytes;
+                    BufIO<T>::store(rd[0], voff, so, D, p.st_scale[0]);
+                    BufIO<T>::store(rd[1], voff, so, vx, p.st_scale[1]);
+                    BufIO<T>::store(rd[2], voff, so, vy, p.st_scale[1]);
+                    BufIO<T>::store(rd[3], voff, so, vz, p.st_scale[1]);
+                    mass += D;
+                    energy = fmaf(vx, vx, fmaf(vy, vy, fmaf(vz, vz, energy)));
+                }
             }
-            Jx = div36(Jx) + Am.post[0];
-            Jy = div36(Jy) + Am.post[1];
-            Jz = div36(Jz) + Am.post[2];
-            const float D = div36(D36);
-            const float q = normalisation_factor(D);
-            const float vx = fmaf(-Jx, q, Jx);
-            const float vy = fmaf(-Jy, q, Jy);
-            const float vz = fmaf(-Jz, q, Jz);
-            if (!MASK || Am.cls < 2) {
-                const long long idx = (long long)(pz - 1) * plane + col;
-                Storage<T>::store(dst, idx, D, p.st_scale[0]);
-                Storage<T>::store(dst, n + idx, vx, p.st_scale[1]);
-                Storage<T>::store(dst, 2 * n + idx, vy, p.st_scale[1]);
-                Storage<T>::store(dst, 3 * n + idx, vz, p.st_scale[1]);
-                mass += D;
-                energy = fmaf(vx, vx, fmaf(vy, vy, fmaf(vz, vz, energy)));
+        }
+    } else {
+        // Halo columns: one direction partial (density part p, z part z) and
+        // the two in-plane diagonals next to it, for three target planes.
+        float hp[3] = {0.0f, 0.0f, 0.0f}, hz[3] = {0.0f, 0.0f, 0.0f};
+        float hd1[3] = {0.0f, 0.0f, 0.0f}, hd2[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < NZC + 2; ++k) {
+            {
+                const int j = k % 3;
+                const int rj = k % RING;
+                const int pz = z0 - 1 + k;
+                const int j1 = (j + 1) % 3, jm = (j + 2) % 3;
+                const float dr = BufIO<T>::value(ring[rj].v[0], p.ld_scale[0]);
+                const float ux = BufIO<T>::value(ring[rj].v[1], p.ld_scale[1]);
+                const float uy = BufIO<T>::value(ring[rj].v[2], p.ld_scale[1]);
+                const float uz = BufIO<T>::value(ring[rj].v[3], p.ld_scale[1]);
+                const int cls = MASK ? (int)ring[rj].cls : 0;
+                // refill with plane pz + RING (unconditional; past the chunk it
+                // re-reads plane z1, which is cached and never consumed)
+                if (k + RING < NZC + 2) issue(ring[rj], min(pz + RING, z1));
+                const float rho = 1.0f + dr;
+                const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+                float E0 = fmaf(rho, -1.5f * usq, dr);
+                float r45 = 4.5f * rho;
+                float rA = A * rho;
+                if (MASK && cls >= 2) {
+                    E0 = 0.0f;
+                    r45 = 0.0f;
+                    rA = 0.0f;
+                }
+                // the five links with v_y = sgn (Y halo) or v_x = sgn (X halo)
+                const float ua = (role == HALO_Y) ? uy : ux;  // along the halo direction
+                const float ub = (role == HALO_Y) ? ux : uy;  // across it, in plane
+                const float cs = sgn * ua;
+                const float Lup = lterm(cs + uz, E0, r45, rA);  // v_z = +1
+                const float Lmid = lterm(cs, E0, r45, rA);      // v_z = 0
+                const float Ldn = lterm(cs - uz, E0, r45, rA);  // v_z = -1
+                hp[j1] = Lup;
+                hz[j1] = Lup;
+                hp[j] = fmaf(2.0f, Lmid, hp[j]);
+                hd1[j] = lterm(cs + ub, E0, r45, rA);  // diagonal, + across
+                hd2[j] = lterm(cs - ub, E0, r45, rA);  // diagonal, - across
+                hp[jm] += Ldn;
+                hz[jm] -= Ldn;
+                if (k < 2) continue;
+                if (NBUF == 1 && k > 2) __syncthreads();
+                float *Xf = reinterpret_cast<float *>(xch[k % NBUF][0]);
+                if (active) {
+                    const int off = sgn > 0.0f ? 0 : 2;
+                    if (role == HALO_Y) {
+                        // G1: (PN, ZN) below the tile or (PS, ZS) above it;
+                        // G2: (NE, NW) below or (SE, SW) above
+                        *reinterpret_cast<float2 *>(&Xf[4 * (1 * NSLOT + slot) + off]) =
+                            make_float2(hp[jm], hz[jm]);
+                        *reinterpret_cast<float2 *>(&Xf[4 * (2 * NSLOT + slot) + off]) =
+                            make_float2(hd1[jm], hd2[jm]);
+                    } else {
+                        // G0: (PE, ZE) left of the tile or (PW, ZW) right of it;
+                        // G2: NE, SE (left) or NW, SW (right)
+                        *reinterpret_cast<float2 *>(&Xf[4 * (0 * NSLOT + slot) + off]) =
+                            make_float2(hp[jm], hz[jm]);
+                        const int doff = sgn > 0.0f ? 0 : 1;
+                        Xf[4 * (2 * NSLOT + slot) + doff] = hd1[jm];      // (sgn, +1, 0)
+                        Xf[4 * (2 * NSLOT + slot) + doff + 2] = hd2[jm];  // (sgn, -1, 0)
+                    }
+                }
+                __syncthreads();
             }
         }
     }
@@ -406,8 +557,9 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
 
 bool march_supported(const ProblemArgs &p)
 {
+    // 32-bit byte offsets inside a field: n * 4 bytes < 4 GiB
     return p.Q == 19 && !p.has_force && p.nx >= TX && p.ny >= TY && p.nx % TX == 0 &&
-           p.ny % TY == 0 && p.nz >= 1 && (long long)p.nx * p.ny < (1LL << 31);
+           p.ny % TY == 0 && p.nz >= 1 && p.n < (1LL << 30);
 }
 
 unsigned march_num_blocks(const ProblemArgs &p)

@@ -224,7 +224,8 @@ def test_shear_wave_256_cubed_exact():
     lam = 1 - 4 * wl.viscosity(omega) * np.sin(np.pi / n) ** 2
     ref = u[0] * lam ** steps
     assert np.abs(uu[0] - ref).max() < 2e-6 * u0
-    assert np.abs(uu[1:]).max() < 1e-9
+    # transverse components and rho - 1 vanish exactly; FP32 noise stays ~1e-9
+    assert np.abs(uu[1:]).max() < 5e-9
     assert np.abs(dr).max() < 1e-7
 
 
@@ -252,6 +253,51 @@ def test_tgv3d_256_one_step_sampled(storage):
     tol_u = 1e-6 if storage == 0 else 1e-3
     assert rel_l2(got_u, u_ref) < tol_u
     assert np.abs(got_r - (r_ref - 1)).max() < (1e-8 if storage == 0 else 2e-6)
+
+
+@pytest.mark.parametrize("storage", [0])
+def test_tgv3d_256_1000_steps_vs_stored_oracle(golden_dir, storage):
+    """The full 256^3 Taylor-Green workload (1000 steps, the benchmark's
+    launch configuration) against the FP64 oracle's stored result: every 8th
+    node along each axis and the kinetic energy every 100 steps.  The stored
+    file is written by tests/golden/make_tgv3d_256_reference.py, which calls
+    only the oracle."""
+    L = need_gpu()
+    ref = np.load(os.path.join(golden_dir, "tgv3d_256_step1000_sub8.npz"))
+    c = wl.TGV3D_256
+    n, stride, steps = int(ref["n"]), int(ref["stride"]), int(ref["steps"])
+    assert (n, steps) == (c.nx, c.steps)
+    banner(f"{c.name} {steps} steps storage={storage}")
+    drho, u = wl.taylor_green_3d(n, c.u0)
+    s = L.Solver(19, n, n, n, c.omega, storage=storage)
+    hist = torch.zeros(2 * (steps + 1), dtype=torch.float64, device="cuda")
+    L.lwacm_set_diag_history(s.ctx, hist)
+    s.set_state(to_dev(drho), to_dev(u))
+    del drho, u
+    s.step(steps)
+    dr, uu = s.moments()
+    sub = (slice(None, None, stride),) * 3
+    dr = dr[sub].double().cpu().numpy()
+    uu = uu[(slice(None),) + sub].double().cpu().numpy()
+    h = hist.cpu().numpy().reshape(steps + 1, 2)
+    s.close()
+    err_u = rel_l2(uu, ref["u"])
+    err_r = rel_l2(dr, ref["drho"])
+    de = max(abs(h[t, 1] - e) / e for t, (m, e) in zip(ref["diag_steps"], ref["diag"]))
+    # the history holds the mass deviation sum(rho - 1)
+    dm = abs(h[steps, 0] + n ** 3 - ref["diag"][-1][0]) / ref["diag"][-1][0]
+    banner(f"256^3 storage={storage}: rel-L2 u {err_u:.3e} drho {err_r:.3e} "
+           f"energy {de:.3e} mass {dm:.3e}")
+    if storage == 0:
+        assert err_u < FP32_TOL
+        assert err_r < 1e-3
+        assert de < 1e-5
+        assert dm < 1e-9
+    else:
+        # FP16 velocity storage: the noise floor measured at 48^3 (a few 1e-3)
+        assert err_u < 1e-2
+        assert de < 1e-3
+        assert dm < 1e-6
 
 
 def test_cavity_192_one_step_sampled():
