@@ -25,6 +25,23 @@ METRIC = "MLUPS D3Q19 256^3 FP32 (vs FP16-store); adjoint/forward step time rati
 HBM_PEAK_GBS = 8000.0
 
 
+def _measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from its FETCH_SIZE/WRITE_SIZE counter
+    runs (scaled by the copy-kernel calibration), or None when the kernel's
+    sources changed since the counters were taken."""
+    import hashlib
+    pkg = os.path.join(ROOT, "paper_1111_2142_amd")
+    try:
+        rec = json.load(open(os.path.join(pkg, "measured_traffic.json")))[kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(pkg, f), "rb") as fh:
+            h.update(fh.read())
+    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def _events_time(fn, n, stream):
     import torch
     start = torch.cuda.Event(enable_timing=True)
@@ -84,9 +101,9 @@ def main():
     nodes = n ** 3
     del drho, u
 
-    def make(storage):
+    def make(storage, rounding=L.LWACM_ROUND_STOCHASTIC):
         s = L.Solver(L.LWACM_D3Q19, n, n, n, cfg.omega, storage=storage, device=dev,
-                     variant=args.variant)
+                     variant=args.variant, fp16_rounding=(rounding, 0))
         s.set_state(drho_t, u_t)
         return s
 
@@ -122,8 +139,12 @@ def main():
                    "omega": cfg.omega, "u0": cfg.u0, "storage": "fp32",
                    "diagnostics": "fused FP64 mass+energy every step"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": None, "algorithmic_bytes": int(bytes32)},
     }
+    if n == 256 and args.variant in (0, 2):
+        result["roofline"]["kernel"] = "k_fwd_march<float,false>"
+        result["roofline"]["traffic"] = _measured_traffic("k_fwd_march<float,false>")
     if args.forward_only:
         print(json.dumps(result), flush=True)
         return
@@ -138,9 +159,14 @@ def main():
     print(f"[bench] fp16 forward: {ms16:.4f} ms/step, {mlups16:.0f} MLUPS", file=sys.stderr,
           flush=True)
     s16.close()
+    s16n = make(L.LWACM_FP16_DEV, L.LWACM_ROUND_NEAREST)
+    s16n.step(args.warmup)
+    dt16n = _events_time(s16n.step, args.steps, stream)
+    s16n.close()
     result["fp16_store"] = {"value": round(mlups16, 1), "unit": "MLUPS",
-                            "ms_per_step": round(ms16, 5),
-                            "achieved_GBs": round(16.0 * nodes / dt16 * args.steps / 1e9, 1)}
+                            "ms_per_step": round(ms16, 5), "rounding": "stochastic (pcg4d)",
+                            "achieved_GBs": round(16.0 * nodes / dt16 * args.steps / 1e9, 1),
+                            "ms_per_step_nearest_rounding": round(dt16n / args.steps * 1e3, 5)}
 
     # ---- reverse step at the same size (reads state_t and mu_t, writes mu_{t-1})
     st = s32.save_state()
@@ -178,14 +204,15 @@ def main():
         r0 = 1.0 + d0
         del d0
         oracle.run(p, r0, u0, 1)   # warm-up (page-in)
-        nsteps_cpu = 2
+        nsteps_cpu = 24
         t0 = time.perf_counter()
         oracle.run(p, r0, u0, nsteps_cpu)
         dtc = time.perf_counter() - t0
         result["cpu_baseline"] = {
             "value": round(nodes * nsteps_cpu / dtc / 1e6, 3), "unit": "MLUPS",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{nsteps_cpu} steps of the full {n}^3 D3Q19 grid (FP64, OpenMP over z-y rows)"}
+            "sample": f"{nsteps_cpu} steps of the full {n}^3 D3Q19 Taylor-Green grid "
+                      "(FP64, OpenMP over z-y rows)"}
         print(f"[bench] cpu oracle: {result['cpu_baseline']['value']} MLUPS on "
               f"{oracle.num_threads()} threads", file=sys.stderr, flush=True)
     print(json.dumps(result), flush=True)

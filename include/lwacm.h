@@ -17,8 +17,9 @@
  *    each): structure of arrays, field-major: field 0 is rho - 1, fields
  *    1..D are u_x, u_y (, u_z).  Storage LWACM_FP32 holds float; storage
  *    LWACM_FP16_DEV holds IEEE half values of (field * 2^k), with k set by
- *    lwacm_set_fp16_scales (default 14 for both), rounded to nearest even.
- *    Arithmetic is always FP32.
+ *    lwacm_set_fp16_scales (default 14 for both).  Initial states are
+ *    rounded to nearest even; step outputs are rounded stochastically by
+ *    default (lwacm_set_fp16_rounding).  Arithmetic is always FP32.
  *  - FP32 field arguments (d_drho, d_u, d_lambda, d_mu) are device arrays
  *    in the same SoA order: d_drho has nodes floats, d_u has D * nodes.
  *  - Every call is asynchronous on the stream given to lwacm_init unless it
@@ -52,6 +53,9 @@ enum {
     LWACM_ENONFINITE = -4,  /* mass or kinetic energy is not finite (blow-up) */
     LWACM_EUNSUPPORTED = -5 /* valid request this build does not implement */
 };
+
+/* Rounding of step outputs into FP16 storage (lwacm_set_fp16_rounding). */
+enum { LWACM_ROUND_NEAREST = 0, LWACM_ROUND_STOCHASTIC = 1 };
 
 /* Kernel selection for lwacm_set_variant. */
 enum {
@@ -102,6 +106,20 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
 /* FP16 storage scales: stored value = field * 2^k (k_rho for rho - 1, k_u for
  * u).  0 <= k <= 24.  Takes effect at the next lwacm_set_state. */
 int lwacm_set_fp16_scales(lwacm_ctx *c, int k_rho, int k_u);
+
+/* Rounding of step outputs for FP16 storage.  LWACM_ROUND_STOCHASTIC (the
+ * default, seed 0) rounds |v * 2^k| up to the next FP16 magnitude when
+ * frac + U >= 1, frac being its position between the two neighbouring FP16
+ * magnitudes and U uniform in [0, 1) from the top 13 bits (top 24 bits in the
+ * FP16 subnormal range) of one 32-bit word of the pcg4d hash (Jarzynski and
+ * Olano, JCGT 2020) of (x, y, z, t ^ seed): word 0 for rho - 1, words 1..D
+ * for u, t the index of the step that produces the state.  The stored value
+ * is then unbiased, so velocity changes smaller than an FP16 spacing
+ * (1e-6 per step against 1e-5 spacing in the 256^3 Taylor-Green flow) are
+ * kept on average instead of being rounded away, and a recomputed step
+ * draws the same bits.  LWACM_ROUND_NEAREST rounds to nearest even.
+ * LWACM_EINVAL for another mode; no effect with FP32 storage. */
+int lwacm_set_fp16_rounding(lwacm_ctx *c, int mode, uint32_t seed);
 
 /* Choose the kernel (LWACM_KERNEL_*); LWACM_EUNSUPPORTED if the kernel
  * cannot run this problem. */

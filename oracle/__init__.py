@@ -58,6 +58,14 @@ def _load():
                                         ctypes.POINTER(ctypes.c_int), _dp,
                                         ctypes.POINTER(ctypes.c_int)]
     lib.oracle_lattice_info.restype = ctypes.c_int
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    lib.oracle_round_fp16_sr.argtypes = [ctypes.c_double, ctypes.c_uint32]
+    lib.oracle_round_fp16_sr.restype = ctypes.c_double
+    lib.oracle_store_fp16_sr.argtypes = [ctypes.c_int] * 4 + [ctypes.c_uint32] * 2 + \
+        [ctypes.c_int] * 2 + [_dp, _dp]
+    lib.oracle_store_fp16_sr.restype = ctypes.c_int
+    lib.oracle_pcg4d.argtypes = [u32p, u32p]
+    lib.oracle_pcg4d.restype = None
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -185,6 +193,32 @@ def run(p: Problem, rho, u, nsteps: int, callback: Optional[Callable] = None):
         if callback is not None:
             callback(t + 1, a_r, a_u)
     return a_r, a_u
+
+
+def pcg4d(words):
+    """The four 32-bit words of the pcg4d hash of four 32-bit words."""
+    a = np.ascontiguousarray(np.asarray(words, dtype=np.uint32).reshape(4))
+    out = np.zeros(4, dtype=np.uint32)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    _load().oracle_pcg4d(a.ctypes.data_as(u32p), out.ctypes.data_as(u32p))
+    return out
+
+
+def round_fp16_sr(y: float, r: int) -> float:
+    """Stochastic rounding of the real y to an IEEE half value, random word r."""
+    return float(_load().oracle_round_fp16_sr(float(y), int(r) & 0xFFFFFFFF))
+
+
+def store_fp16_sr(p: Problem, t: int, rho, u, seed: int = 0, k_rho: int = 14, k_u: int = 14):
+    """(rho, u) as FP16 storage with stochastic rounding holds the output of
+    step t: rho - 1 and u scaled by 2^k, rounded, scaled back.  Returns copies."""
+    rho = _f64(rho, p.shape).copy()
+    u = _f64(u, (p.d,) + p.shape).copy()
+    rc = _load().oracle_store_fp16_sr(p.q, p.nx, p.ny, p.nz, int(t) & 0xFFFFFFFF,
+                                      int(seed) & 0xFFFFFFFF, k_rho, k_u, _ptr(rho), _ptr(u))
+    if rc:
+        raise ValueError("oracle_store_fp16_sr: bad lattice")
+    return rho, u
 
 
 def diagnostics(p: Problem, rho, u):

@@ -27,6 +27,7 @@ struct lwacm_ctx {
     float wall_u[lwacm::kMaxWallIds][3];
     int n_wall_ids;
     int k_rho, k_u;
+    uint32_t sr_seed;
     hipStream_t stream;
     double *d_partials;
     size_t n_partial_blocks;
@@ -164,6 +165,8 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
     c->buf[1] = d_state_b;
     c->stream = stream;
     c->k_rho = c->k_u = 14;
+    c->sr_seed = 0;
+    c->p.fp16_sr = 1;
     ProblemArgs &p = c->p;
     p.Q = lattice;
     p.D = lattice == LWACM_D2Q9 ? 2 : 3;
@@ -262,6 +265,14 @@ int lwacm_set_fp16_scales(lwacm_ctx *c, int k_rho, int k_u)
     return LWACM_OK;
 }
 
+int lwacm_set_fp16_rounding(lwacm_ctx *c, int mode, uint32_t seed)
+{
+    if (!c || (mode != LWACM_ROUND_NEAREST && mode != LWACM_ROUND_STOCHASTIC)) return LWACM_EINVAL;
+    c->p.fp16_sr = mode == LWACM_ROUND_STOCHASTIC;
+    c->sr_seed = seed;
+    return LWACM_OK;
+}
+
 int lwacm_set_variant(lwacm_ctx *c, int variant)
 {
     if (!c) return LWACM_EINVAL;
@@ -314,6 +325,7 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
         ReduceArgs r = reduce_args(c, c->d_diag, hist);
         const void *src = c->buf[c->cur];
         void *dst = c->buf[c->cur ^ 1];
+        c->p.sr_word = (uint32_t)(c->steps + 1) ^ c->sr_seed;
         hipError_t e = march ? lwacm::launch_fwd_march(c->p, c->storage, src, dst, c->d_cls,
                                                        c->d_bits, r, c->stream)
                              : lwacm::launch_fwd_generic(c->p, c->storage, c->force, src, dst, r, gb,

@@ -119,10 +119,69 @@ struct Storage<float> {
     {
         p[i] = v;
     }
+    __device__ __forceinline__ static void store_sr(float *p, long long i, float v, float, uint32_t)
+    {
+        p[i] = v;
+    }
 };
 
-// FP16 deviation storage: value * 2^k rounded to nearest even; the scale
-// arguments are 2^-k on load and 2^k on store (exact in FP32).
+// ------------------------------------------- stochastic FP16 rounding
+// Counter-based random bits: the pcg4d hash of Jarzynski and Olano, "Hash
+// Functions for GPU Rendering", JCGT 9(3), 2020.  Four 32-bit words in, four
+// out; the step stores field f of node (x, y, z) at step t with word f of
+// pcg4d(x, y, z, t ^ seed), so every run and every recomputation of a step
+// draws the same bits.
+struct U32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U32x4 pcg4d(uint32_t x, uint32_t y, uint32_t z, uint32_t w)
+{
+    U32x4 v = {x * 1664525u + 1013904223u, y * 1664525u + 1013904223u,
+               z * 1664525u + 1013904223u, w * 1664525u + 1013904223u};
+    v.x += v.y * v.w;
+    v.y += v.z * v.x;
+    v.z += v.x * v.y;
+    v.w += v.y * v.z;
+    v.x ^= v.x >> 16;
+    v.y ^= v.y >> 16;
+    v.z ^= v.z >> 16;
+    v.w ^= v.w >> 16;
+    v.x += v.y * v.w;
+    v.y += v.z * v.x;
+    v.z += v.x * v.y;
+    v.w += v.y * v.z;
+    return v;
+}
+
+// FP32 -> FP16 bits with stochastic rounding: |y| lies between two adjacent
+// FP16 magnitudes lo <= |y| < hi and is rounded to hi when
+// frac + U >= 1, frac = (|y| - lo) / (hi - lo), U uniform from the random
+// word r (its top 13 bits in the normal range, where FP32 carries 13 more
+// mantissa bits than FP16; its top 24 bits in the subnormal range, where the
+// FP16 spacing is 2^-24).  The expected stored value is y itself, so updates
+// smaller than one FP16 spacing are not lost; round to nearest would drop them.
+__device__ __forceinline__ unsigned short half_bits_sr(float y, uint32_t r)
+{
+    const uint32_t b = __float_as_uint(y);
+    uint32_t mag = b & 0x7fffffffu;
+    if (mag >= 0x38800000u) {  // |y| >= 2^-14
+        // adding U * 2^13 to the 13 discarded bits carries exactly when frac + U >= 1
+        mag = (mag + (r >> 19)) & ~0x1fffu;
+    } else {
+        const float m = __uint_as_float(mag) * 16777216.0f;  // |y| / 2^-24, exact
+        const float lo = floorf(m);
+        const float u = (float)(r >> 8) * 5.9604644775390625e-8f;  // (r >> 8) * 2^-24
+        const float up = (u >= 1.0f - (m - lo)) ? 1.0f : 0.0f;
+        mag = __float_as_uint((lo + up) * 5.9604644775390625e-8f);
+    }
+    // the value is now an FP16 number (or beyond the FP16 range: converts to inf)
+    return __half_as_ushort(__float2half_rn(__uint_as_float(mag | (b & 0x80000000u))));
+}
+
+// FP16 deviation storage: value * 2^k, the scale arguments are 2^-k on load
+// and 2^k on store (exact in FP32).  store() rounds to nearest even (initial
+// states); store_sr() rounds stochastically with random word r (steps).
 template <>
 struct Storage<__half> {
     __device__ __forceinline__ static float load(const __half *p, long long i, float inv_scale)
@@ -132,6 +191,11 @@ struct Storage<__half> {
     __device__ __forceinline__ static void store(__half *p, long long i, float v, float scale)
     {
         p[i] = __float2half_rn(v * scale);
+    }
+    __device__ __forceinline__ static void store_sr(__half *p, long long i, float v, float scale,
+                                                    uint32_t r)
+    {
+        p[i] = __ushort_as_half(half_bits_sr(v * scale, r));
     }
 };
 

@@ -12,6 +12,8 @@
 // Reverse step: every source node y collects, for each of its links k, the
 // cotangent weight of the node that consumes its term (y + v_k, or y itself
 // through bounce-back) and applies the transposed derivative of the link term.
+#include <type_traits>
+
 #include "lwacm_device.hpp"
 #include "lwacm_internal.hpp"
 
@@ -131,12 +133,21 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
         // FP32 error from accumulating over long runs.
         const float q = normalisation_factor(Dsum);
         float e = 0.0f;
-        Storage<T>::store(dst, idx, Dsum, p.st_scale[0]);
+        float out[4] = {Dsum, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const float uk = fmaf(-J[k], q, J[k]);
-            Storage<T>::store(dst, (k + 1) * n + idx, uk, p.st_scale[1]);
-            e = fmaf(uk, uk, e);
+            out[k + 1] = fmaf(-J[k], q, J[k]);
+            e = fmaf(out[k + 1], out[k + 1], e);
+        }
+        if (std::is_same<T, __half>::value && p.fp16_sr) {
+            const U32x4 h = pcg4d((uint32_t)c.x, (uint32_t)c.y, (uint32_t)c.z, p.sr_word);
+            const uint32_t rw[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+            for (int k = 0; k <= D; ++k)
+                Storage<T>::store_sr(dst, k * n + idx, out[k], p.st_scale[k > 0], rw[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k <= D; ++k) Storage<T>::store(dst, k * n + idx, out[k], p.st_scale[k > 0]);
         }
         acc[0] += (double)Dsum;
         acc[1] += 0.5 * (double)e;

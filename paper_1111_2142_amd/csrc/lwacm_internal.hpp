@@ -21,6 +21,8 @@ struct ProblemArgs {
     float wall_da[kMaxWallIds][3];  // 6 * rho0 * u_w: minus d(wall_term)/da
     float ld_scale[2];       // storage -> value: 2^-k (rho - 1, u); 1 for FP32
     float st_scale[2];       // value -> storage: 2^k
+    int fp16_sr;             // FP16 storage: 1 stochastic rounding of step outputs, 0 nearest
+    uint32_t sr_word;        // fourth pcg4d input of this step: t ^ seed
     const uint8_t *mask;     // nullptr: all fluid
 };
 

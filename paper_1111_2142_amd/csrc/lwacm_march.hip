@@ -32,6 +32,8 @@
 // Link terms are kept unweighted and summed with the exact integer weights
 // 12, 2, 1 (= 36 w_i for rest, axis and diagonal links of D3Q19); the sums
 // are divided by 36 once at the end (div36: no systematic rounding bias).
+#include <type_traits>
+
 #include "lwacm_device.hpp"
 #include "lwacm_internal.hpp"
 
@@ -113,6 +115,11 @@ struct BufIO<float> {
     {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
     }
+    __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float v,
+                                                    float, uint32_t)
+    {
+        store(r, voff, soff, v, 1.0f);
+    }
 };
 
 template <>
@@ -131,6 +138,11 @@ struct BufIO<__half> {
     {
         __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v * scale)), r,
                                               voff, soff, 0);
+    }
+    __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float v,
+                                                    float scale, uint32_t bits)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(half_bits_sr(v * scale, bits), r, voff, soff, 0);
     }
 };
 
@@ -416,10 +428,18 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 const float vz = fmaf(-Jz, q, Jz);
                 if (!MASK || Am.cls < 2) {
                     const unsigned so = (unsigned)tz * plane_bytes;
-                    BufIO<T>::store(rd[0], voff, so, D, p.st_scale[0]);
-                    BufIO<T>::store(rd[1], voff, so, vx, p.st_scale[1]);
-                    BufIO<T>::store(rd[2], voff, so, vy, p.st_scale[1]);
-                    BufIO<T>::store(rd[3], voff, so, vz, p.st_scale[1]);
+                    if (std::is_same<T, __half>::value && p.fp16_sr) {
+                        const U32x4 h = pcg4d((uint32_t)gx, (uint32_t)gy, (uint32_t)tz, p.sr_word);
+                        BufIO<T>::store_sr(rd[0], voff, so, D, p.st_scale[0], h.x);
+                        BufIO<T>::store_sr(rd[1], voff, so, vx, p.st_scale[1], h.y);
+                        BufIO<T>::store_sr(rd[2], voff, so, vy, p.st_scale[1], h.z);
+                        BufIO<T>::store_sr(rd[3], voff, so, vz, p.st_scale[1], h.w);
+                    } else {
+                        BufIO<T>::store(rd[0], voff, so, D, p.st_scale[0]);
+                        BufIO<T>::store(rd[1], voff, so, vx, p.st_scale[1]);
+                        BufIO<T>::store(rd[2], voff, so, vy, p.st_scale[1]);
+                        BufIO<T>::store(rd[3], voff, so, vz, p.st_scale[1]);
+                    }
                     mass += D;
                     energy = fmaf(vx, vx, fmaf(vy, vy, fmaf(vz, vz, energy)));
                 }

@@ -19,6 +19,7 @@ LWACM_FP32, LWACM_FP16_DEV = 0, 1
 LWACM_OK, LWACM_EINVAL, LWACM_ENOMEM, LWACM_EDEVICE, LWACM_ENONFINITE, LWACM_EUNSUPPORTED = (
     0, -1, -2, -3, -4, -5)
 LWACM_KERNEL_AUTO, LWACM_KERNEL_GENERIC, LWACM_KERNEL_MARCH = 0, 1, 2
+LWACM_ROUND_NEAREST, LWACM_ROUND_STOCHASTIC = 0, 1
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -47,6 +48,7 @@ def load_library():
         "lwacm_init": (i, [ctypes.POINTER(_vp), i, i, i, i, d, i, _vp, _vp, _vp, _vp, i, _vp,
                            _vp, _vp]),
         "lwacm_set_fp16_scales": (i, [_vp, i, i]),
+        "lwacm_set_fp16_rounding": (i, [_vp, i, ctypes.c_uint32]),
         "lwacm_set_variant": (i, [_vp, i]),
         "lwacm_set_state": (i, [_vp, _vp, _vp]),
         "lwacm_step": (i, [_vp, i]),
@@ -116,6 +118,11 @@ def lwacm_init(lattice, nx, ny, nz, omega, storage, state_a: torch.Tensor,
 
 def lwacm_set_fp16_scales(ctx, k_rho: int, k_u: int):
     _check(load_library().lwacm_set_fp16_scales(ctx, k_rho, k_u), "lwacm_set_fp16_scales")
+
+
+def lwacm_set_fp16_rounding(ctx, mode: int, seed: int = 0):
+    _check(load_library().lwacm_set_fp16_rounding(ctx, mode, seed & 0xFFFFFFFF),
+           "lwacm_set_fp16_rounding")
 
 
 def lwacm_set_variant(ctx, variant: int):
@@ -199,7 +206,8 @@ class Solver:
                  storage: int = LWACM_FP32, mask: Optional[torch.Tensor] = None,
                  wall_u: Optional[Sequence[Sequence[float]]] = None,
                  g: Optional[Sequence[float]] = None, device="cuda",
-                 variant: int = LWACM_KERNEL_AUTO, fp16_scales: Optional[Tuple[int, int]] = None):
+                 variant: int = LWACM_KERNEL_AUTO, fp16_scales: Optional[Tuple[int, int]] = None,
+                 fp16_rounding: Optional[Tuple[int, int]] = None):
         load_library()
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -223,6 +231,8 @@ class Solver:
                               wall_u, g, _stream_handle(self.device))
         if fp16_scales is not None:
             lwacm_set_fp16_scales(self.ctx, *fp16_scales)
+        if fp16_rounding is not None:
+            lwacm_set_fp16_rounding(self.ctx, *fp16_rounding)
         if variant != LWACM_KERNEL_AUTO:
             lwacm_set_variant(self.ctx, variant)
 

@@ -473,3 +473,112 @@ def test_gradient_through_many_steps_matches_central_differences():
 def test_oracle_rejects_unknown_lattice():
     with pytest.raises(ValueError):
         oracle.lattice_info(15)
+
+
+# ------------------------------------- FP16 storage: stochastic rounding
+def _half_neighbours(y):
+    """The FP16 magnitudes lo <= |y| <= hi next to |y| (numpy's float16)."""
+    a = abs(y)
+    h = np.float16(a)                     # nearest, from numpy
+    if float(h) > a:
+        return float(np.nextafter(h, np.float16(0))), float(h)
+    if float(h) < a:
+        return float(h), float(np.nextafter(h, np.float16(np.inf)))
+    return float(h), float(h)
+
+
+def test_round_fp16_sr_threshold_convention():
+    """|y| goes up when frac + U >= 1: U from the top 13 bits of the word in
+    the normal range, from the top 24 bits in the subnormal range."""
+    y = 1.0 + 2.0 ** -10 * 3 / 8            # spacing 2^-10 at 1, frac = 3/8
+    lo, hi = 1.0, 1.0 + 2.0 ** -10
+    assert oracle.round_fp16_sr(y, (5119 << 19) | 0x7FFFF) == lo
+    assert oracle.round_fp16_sr(y, 5120 << 19) == hi
+    assert oracle.round_fp16_sr(-y, 5120 << 19) == -hi
+    s = 2.0 ** -24                          # subnormal spacing, frac = 1/4
+    assert oracle.round_fp16_sr(s / 4, ((3 << 22) - 1) << 8) == 0.0
+    assert oracle.round_fp16_sr(s / 4, (3 << 22) << 8) == s
+    # the largest half is 65504, the next magnitude (65536) overflows
+    assert oracle.round_fp16_sr(65510.0, 0) == 65504.0
+    assert oracle.round_fp16_sr(65510.0, 0xFFFFFFFF) == np.inf
+    # just under 2^-14 the rounding can step up into the normal range
+    assert oracle.round_fp16_sr(2.0 ** -14 - s / 2, 0xFFFFFFFF) == 2.0 ** -14
+
+
+def test_round_fp16_sr_lands_on_a_neighbour_and_keeps_halves():
+    rng = np.random.Generator(np.random.PCG64(11))
+    ys = np.concatenate([rng.uniform(-2, 2, 300) * 10.0 ** rng.integers(-9, 4, 300),
+                         rng.uniform(-1, 1, 50) * 2.0 ** -14])
+    for y in ys:
+        lo, hi = _half_neighbours(y)
+        for r in rng.integers(0, 2 ** 32, 4):
+            got = oracle.round_fp16_sr(y, int(r))
+            assert abs(got) in (lo, hi), (y, r, got)
+            assert np.sign(got) in (0.0, np.sign(y))
+    halves = rng.integers(0, 0x7C00, 400).astype(np.uint16).view(np.float16).astype(np.float64)
+    for h in halves:
+        for r in (0, 0xFFFFFFFF, int(rng.integers(0, 2 ** 32))):
+            assert oracle.round_fp16_sr(h, r) == h
+            assert oracle.round_fp16_sr(-h, r) == -h
+
+
+def test_round_fp16_sr_is_unbiased():
+    """Mean over uniform random words equals y (5 sigma), normal and subnormal."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    words = rng.integers(0, 2 ** 32, 8192)
+    for y in (0.3141592653589793, -1.0e-3 - 1e-9, 327.68 + 1.0 / 3, 3.0e-6, -7.1e-8, 2.0e-8):
+        lo, hi = _half_neighbours(y)
+        got = np.array([oracle.round_fp16_sr(y, int(r)) for r in words])
+        f = (abs(y) - lo) / (hi - lo)
+        sigma = (hi - lo) * np.sqrt(f * (1 - f) / len(words)) + 1e-300
+        assert abs(got.mean() - y) < 5 * sigma + (hi - lo) * 2.0 ** -13, y
+
+
+def test_pcg4d_words_are_uniform_and_balanced():
+    """Each output word of pcg4d over a grid of counters: its top 13 bits fill
+    64 bins evenly (chi-square) and every bit is set half of the time."""
+    counts = np.zeros((4, 64))
+    ones = np.zeros((4, 32))
+    m = 0
+    for t in (1, 2, 1000):
+        for z in range(2):
+            for y in range(16):
+                for x in range(128):
+                    w = oracle.pcg4d([x, y, z, t])
+                    counts[np.arange(4), (w >> 26).astype(int)] += 1
+                    ones += (w[:, None] >> np.arange(32, dtype=np.uint32)) & 1
+                    m += 1
+    expect = m / 64
+    chi2 = ((counts - expect) ** 2 / expect).sum(axis=1)
+    assert np.all(chi2 < 120), chi2        # 63 degrees of freedom: mean 63, sd 11
+    assert np.all(np.abs(ones - m / 2) < 5 * np.sqrt(m / 4)), ones
+
+
+def test_fp16_storage_rounding_preserves_slow_decay():
+    """A 128^2 Taylor-Green vortex at omega = 1.7 changes u by ~1e-6 per step,
+    below one FP16 spacing (~1e-5 at u = 0.02).  Stored with round-to-nearest
+    its kinetic energy stalls; stored with stochastic rounding (the oracle's
+    own rounding) it decays as in FP64."""
+    n, omega, steps = 128, 1.7, 1000
+    drho, u = wl.taylor_green_2d(n, 0.02)
+    p = oracle.Problem(q=9, nx=n, ny=n, omega=omega)
+    rr, ru = oracle.run(p, 1 + drho, u, steps)
+    e_ref = oracle.diagnostics(p, rr, ru)[1]
+
+    def rne(a):
+        return (a * 2.0 ** 14).astype(np.float16).astype(np.float64) / 2.0 ** 14
+
+    r1, u1 = 1 + rne(drho), rne(u)
+    r2, u2 = r1.copy(), u1.copy()
+    for t in range(1, steps + 1):
+        r1, u1 = oracle.step(p, r1, u1)
+        r1, u1 = 1 + rne(r1 - 1), rne(u1)
+        r2, u2 = oracle.step(p, r2, u2)
+        r2, u2 = oracle.store_fp16_sr(p, t, r2, u2)
+    e_rne = oracle.diagnostics(p, r1, u1)[1]
+    e_sr = oracle.diagnostics(p, r2, u2)[1]
+    e0 = oracle.diagnostics(p, 1 + drho, u)[1]
+    assert e_ref < 0.9 * e0                          # the flow does decay
+    assert abs(e_rne / e_ref - 1) > 1e-2             # nearest: stalls
+    assert abs(e_sr / e_ref - 1) < 1e-3              # stochastic: tracks FP64
+    assert np.linalg.norm(u2 - ru) / np.linalg.norm(ru) < 2e-3
