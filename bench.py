@@ -63,7 +63,9 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 generic, 2 march")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forward-only", action="store_true",
-                    help="time only the FP32 forward step (for profiler runs)")
+                    help="time only the forward step of the 256^3 workload (for profiler runs)")
+    ap.add_argument("--storage", choices=["fp32", "fp16"], default="fp32",
+                    help="storage of the --forward-only run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of 256 MiB (the reference kernel for "
                          "scaling HBM byte counters) and exit")
@@ -106,6 +108,14 @@ def main():
                      variant=args.variant, fp16_rounding=(rounding, 0))
         s.set_state(drho_t, u_t)
         return s
+
+    if args.forward_only and args.storage == "fp16":
+        s16 = make(L.LWACM_FP16_DEV)
+        s16.step(args.warmup)
+        dt = _events_time(s16.step, args.steps, stream)
+        print(f"[bench] fp16 forward: {dt / args.steps * 1e3:.4f} ms/step", file=sys.stderr,
+              flush=True)
+        return
 
     # ---- FP32 forward (the headline)
     s32 = make(L.LWACM_FP32)
@@ -195,6 +205,57 @@ def main():
     s32.close()
     del mu_a, mu_b, lam, st
     torch.cuda.empty_cache()
+    dw.zero_()
+
+    # ---- lid-driven cavity 192^3 (mask active, moving lid)
+    c4 = wl.CAVITY_192
+    m4 = torch.as_tensor(wl.cavity_mask(c4.nx), device=dev)
+    s4 = L.Solver(L.LWACM_D3Q19, c4.nx, c4.ny, c4.nz, c4.omega, mask=m4,
+                  wall_u=[list(r) for r in wl.wall_table(c4.lid)], device=dev)
+    s4.set_state(torch.zeros((c4.nz, c4.ny, c4.nx), device=dev),
+                 torch.zeros((3, c4.nz, c4.ny, c4.nx), device=dev))
+    s4.step(args.warmup)
+    dt4 = _events_time(s4.step, args.steps, stream)
+    s4.close()
+    fluid4 = (c4.nx - 2) * (c4.ny - 2) * (c4.nz - 2)
+    ms4 = dt4 / args.steps * 1e3
+    print(f"[bench] cavity 192^3: {ms4:.4f} ms/step", file=sys.stderr, flush=True)
+    result["cavity_192"] = {
+        "value": round(fluid4 * args.steps / dt4 / 1e6, 1), "unit": "MLUPS (fluid nodes)",
+        "ms_per_step": round(ms4, 5), "omega": c4.omega, "lid": list(c4.lid),
+        "achieved_GBs_33B": round(33.0 * c4.nx * c4.ny * c4.nz / (ms4 * 1e-3) / 1e9, 1)}
+    del m4
+
+    # ---- differentiable D2Q9 512^2: reverse / forward at the gradient workload (launch-bound)
+    c5 = wl.ADJOINT_512
+    s5 = L.Solver(L.LWACM_D2Q9, c5.nx, c5.ny, 1, c5.omega, device=dev)
+    d5, u5 = wl.divergence_free_field(c5.nx, 8, c5.u0, seed=0)
+    s5.set_state(torch.as_tensor(d5, dtype=torch.float32, device=dev),
+                 torch.as_tensor(u5, dtype=torch.float32, device=dev))
+    s5.step(args.warmup)
+    dt5f = _events_time(s5.step, args.steps, stream)
+    st5 = s5.save_state()
+    m5a = torch.zeros((3, 1, c5.ny, c5.nx), dtype=torch.float32, device=dev)
+    m5b = torch.zeros_like(m5a)
+    lam5 = torch.zeros_like(m5a)
+    lam5[1:] = torch.as_tensor(u5, dtype=torch.float32, device=dev)
+    L.lwacm_adjoint_seed(s5.ctx, st5, lam5, m5a)
+
+    def adj5(k):
+        a, b = m5a, m5b
+        for _ in range(k):
+            L.lwacm_adjoint_step(s5.ctx, st5, a, b, dw, False)
+            a, b = b, a
+
+    adj5(3)
+    dt5a = _events_time(adj5, args.steps, stream)
+    s5.close()
+    result["adjoint_d2q9_512"] = {
+        "forward_ms": round(dt5f / args.steps * 1e3, 5),
+        "reverse_ms": round(dt5a / args.steps * 1e3, 5),
+        "adjoint_forward_ratio": round(dt5a / dt5f, 3)}
+    print(f"[bench] d2q9 512^2: forward {dt5f / args.steps * 1e3:.4f} ms, reverse "
+          f"{dt5a / args.steps * 1e3:.4f} ms", file=sys.stderr, flush=True)
 
     # ---- FP64 CPU oracle on a bounded sample of the same workload
     if not args.no_cpu_baseline:

@@ -37,6 +37,7 @@ struct lwacm_ctx {
     unsigned *d_scan;   // [2] mask scan
     uint8_t *d_cls;     // node classes for the march kernel (masked problems)
     unsigned *d_bits;   // solid-upstream link bits for the march kernel
+    float4 *d_wallg;    // moving-wall geometry sums for the march kernel (moving walls only)
     double *d_hist;
     int hist_cap;
     long long steps;
@@ -59,7 +60,9 @@ void set_wall_terms(lwacm_ctx *c)
             const double uw = (m < c->n_wall_ids) ? c->wall_u[m][k] : 0.0;
             c->p.wall_da[m][k] = (float)(6.0 * c->rho0 * uw);
             c->p.wall_term[m][k] = (float)((1.0 - a) * 6.0 * c->rho0 * uw);
+            c->p.wall_u[m][k] = (float)uw;
         }
+    c->p.wall_scale = (float)((1.0 - a) * 6.0 * c->rho0);
 }
 
 void set_scales(lwacm_ctx *c)
@@ -107,8 +110,10 @@ void free_scratch(lwacm_ctx *c)
     if (c->d_scan) (void)hipFree(c->d_scan);
     if (c->d_cls) (void)hipFree(c->d_cls);
     if (c->d_bits) (void)hipFree(c->d_bits);
+    if (c->d_wallg) (void)hipFree(c->d_wallg);
     c->d_cls = nullptr;
     c->d_bits = nullptr;
+    c->d_wallg = nullptr;
     c->d_partials = nullptr;
     c->d_counter = nullptr;
     c->d_diag = c->d_scratch = nullptr;
@@ -237,14 +242,19 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
             c->n_fluid = scan[1];
         }
         if (e == hipSuccess && lwacm::march_supported(p)) {
+            bool moving = false;
+            for (int m = 1; m < lwacm::kMaxWallIds; ++m)
+                for (int k = 0; k < 3; ++k) moving = moving || p.wall_u[m][k] != 0.0f;
             e = hipMalloc(&c->d_cls, (size_t)p.n);
             if (e == hipSuccess) e = hipMalloc(&c->d_bits, (size_t)p.n * sizeof(unsigned));
+            if (e == hipSuccess && moving)
+                e = hipMalloc(&c->d_wallg, (size_t)p.n * sizeof(float4));
             if (e != hipSuccess) {
                 free_scratch(c);
                 delete c;
                 return LWACM_ENOMEM;
             }
-            e = lwacm::launch_classify(p, c->d_cls, c->d_bits, stream);
+            e = lwacm::launch_classify(p, c->d_cls, c->d_bits, c->d_wallg, stream);
         }
     }
     if (e != hipSuccess) {
@@ -327,7 +337,7 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
         void *dst = c->buf[c->cur ^ 1];
         c->p.sr_word = (uint32_t)(c->steps + 1) ^ c->sr_seed;
         hipError_t e = march ? lwacm::launch_fwd_march(c->p, c->storage, src, dst, c->d_cls,
-                                                       c->d_bits, r, c->stream)
+                                                       c->d_bits, c->d_wallg, r, c->stream)
                              : lwacm::launch_fwd_generic(c->p, c->storage, c->force, src, dst, r, gb,
                                                          c->stream);
         if (e != hipSuccess) return LWACM_EDEVICE;

@@ -19,6 +19,8 @@ struct ProblemArgs {
     int has_force;           // g given (forced problems use the generic kernel)
     float wall_term[kMaxWallIds][3];  // (1 - a) * 6 * rho0 * u_w per wall id (Eq. ACM2.0ccccbb)
     float wall_da[kMaxWallIds][3];  // 6 * rho0 * u_w: minus d(wall_term)/da
+    float wall_u[kMaxWallIds][3];   // wall velocities u_w per wall id (0 for fluid id 0)
+    float wall_scale;               // (1 - a) * 6 * rho0: wall_term = wall_scale * u_w
     float ld_scale[2];       // storage -> value: 2^-k (rho - 1, u); 1 for FP32
     float st_scale[2];       // value -> storage: 2^k
     int fp16_sr;             // FP16 storage: 1 stochastic rounding of step outputs, 0 nearest
@@ -56,10 +58,14 @@ hipError_t launch_mask_scan(const ProblemArgs &p, unsigned *d_out2, hipStream_t 
 // n unsigned).  Returns hipErrorNotSupported if the problem does not fit.
 bool march_supported(const ProblemArgs &p);
 unsigned march_num_blocks(const ProblemArgs &p);
-hipError_t launch_classify(const ProblemArgs &p, uint8_t *cls, unsigned *bits, hipStream_t s);
+// Moving walls also need a per-node float4 of geometry sums (wallg, n
+// entries; may be null when every wall is at rest).
+constexpr unsigned kMovingWallFlag = 1u << 31;  // in bits: node sees a moving wall
+hipError_t launch_classify(const ProblemArgs &p, uint8_t *cls, unsigned *bits, float4 *wallg,
+                           hipStream_t s);
 hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, void *dst,
-                            const uint8_t *cls, const unsigned *bits, const ReduceArgs &r,
-                            hipStream_t stream);
+                            const uint8_t *cls, const unsigned *bits, const float4 *wallg,
+                            const ReduceArgs &r, hipStream_t stream);
 
 // Number of blocks the generic grid-stride kernels use for n nodes.
 unsigned generic_grid(long long n);

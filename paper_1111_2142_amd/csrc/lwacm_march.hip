@@ -33,6 +33,7 @@
 // 12, 2, 1 (= 36 w_i for rest, axis and diagonal links of D3Q19); the sums
 // are divided by 36 once at the end (div36: no systematic rounding bias).
 #include <type_traits>
+#include <utility>
 
 #include "lwacm_device.hpp"
 #include "lwacm_internal.hpp"
@@ -74,12 +75,28 @@ enum Role { INTERIOR = 0, HALO_Y = 1, HALO_X = 2 };
 //   G2 = (NE, NW, SE, SW)   in-plane diagonals (+1,+1,0), (-1,+1,0), (+1,-1,0), (-1,-1,0)
 
 // Per target plane accumulator of an interior column.
+// Compile-time loop: f(std::integral_constant<int, K>) for K = 0 .. N-1.
+// The plane loop runs through it so that every ring and accumulator index is
+// a constant expression from the start and all per-plane state stays in
+// registers.
+template <class F, int... K>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, K...>)
+{
+    (f(std::integral_constant<int, K>{}), ...);
+}
+
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 struct Acc {
     float pe, ze, pw, zw, pn, zn, ps, zs;  // direction partials (weights folded)
     float ne, nw, se, sw;                  // in-plane diagonals
     float d, jz;                           // own column: rest + (0,0,+-1) links
     float post[3];                         // a rho u of the node itself
-    float lnk[19];                         // own link terms (bounce-back only)
+    float own[6];                          // E0, 4.5 rho, A rho, u (bounce-back only)
     unsigned bits;                         // solid upstream links (bounce-back only)
     int cls;                               // 0 fluid, 1 fluid next to a wall, 2 solid
 };
@@ -168,6 +185,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                                                         T *__restrict__ dst,
                                                         const uint8_t *__restrict__ cls_arr,
                                                         const unsigned *__restrict__ bb_bits,
+                                                        const float4 *__restrict__ wallg,
                                                         ReduceArgs r)
 {
     __shared__ float4 xch[NBUF][3][NSLOT];
@@ -269,8 +287,8 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
         // Fully unrolled over the chunk: ring slots and accumulators are
         // compile-time indexed, so no loop back edge forces the compiler to
         // copy registers whose loads are still in flight.
-#pragma unroll
-        for (int k = 0; k < NZC + 2; ++k) {
+        static_for<NZC + 2>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
             {
                 const int j = k % 3;         // accumulator slot
                 const int rj = k % RING;     // ring slot
@@ -351,12 +369,12 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                     // only planes this chunk finalises (z0 <= pz < z1 <= nz)
                     if (cls == 1 && pz >= z0 && pz < z1)
                         A0.bits = bb_bits[(long long)pz * plane + col];
-                    A0.lnk[0] = E0;
-                    A0.lnk[1] = Lpx;  A0.lnk[2] = Lmx;  A0.lnk[3] = Lpy;  A0.lnk[4] = Lmy;
-                    A0.lnk[5] = Lpp0; A0.lnk[6] = Lmm0; A0.lnk[7] = Lpm0; A0.lnk[8] = Lmp0;
-                    A0.lnk[9] = Lpz;  A0.lnk[10] = Lp0p; A0.lnk[11] = Lm0p; A0.lnk[12] = L0pp;
-                    A0.lnk[13] = L0mp; A0.lnk[14] = Lmz; A0.lnk[15] = Lm0m; A0.lnk[16] = Lp0m;
-                    A0.lnk[17] = L0mm; A0.lnk[18] = L0pm;
+                    A0.own[0] = E0;
+                    A0.own[1] = r45;
+                    A0.own[2] = rA;
+                    A0.own[3] = ux;
+                    A0.own[4] = uy;
+                    A0.own[5] = uz;
                 }
                 // links with v_z = -1 finish plane pz - 1
                 Am.pe += Lp0m;
@@ -370,7 +388,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 Am.d = fmaf(2.0f, Lmz, Am.d);
                 Am.jz = fmaf(-2.0f, Lmz, Am.jz);
 
-                if (k < 2) continue;  // planes below the chunk are halo only
+                if (k < 2) return;  // planes below the chunk are halo only
                 // ---- exchange the partials of plane pz - 1 through LDS
                 if (NBUF == 1 && k > 2) __syncthreads();  // previous plane's reads done
                 float4 *X = xch[k % NBUF][0];
@@ -390,7 +408,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 const float pN = gS.x, zN = gS.y, pS = gN.z, zS = gN.w;
 
                 const int tz = pz - 1;
-                if (tz >= z1) continue;  // padding iteration: nothing to finalise
+                if (tz >= z1) return;  // padding iteration: nothing to finalise
                 float D36 = Am.d + ((pE + pW) + (pN + pS)) + ((dNE + dNW) + (dSE + dSW));
                 float Jx = (pE - pW) + ((dNE - dNW) + (dSE - dSW));
                 float Jy = (pN - pS) + ((dNE + dNW) - (dSE + dSW));
@@ -398,24 +416,32 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 if (MASK && Am.bits != 0u) {
                     // halfway bounce-back: a solid upstream node x - v_i pushed
                     // nothing; the node's own term of the opposite link returns
-                    // along i, plus the moving-wall term of Eq. ACM2.0ccccbb.
+                    // along i (recomputed from the node's saved coefficients:
+                    // the same FMAs as pair(), so the same value).
 #pragma unroll
                     for (int i = 1; i < 19; ++i) {
                         if (has_bit(Am.bits, i)) {
                             const int cx = link_cx(i), cy = link_cy(i), cz = link_cz(i);
-                            int ux_ = gx - cx, uy_ = gy - cy, uz_ = tz - cz;
-                            ux_ = ux_ < 0 ? ux_ + nx : (ux_ >= nx ? ux_ - nx : ux_);
-                            uy_ = uy_ < 0 ? uy_ + ny : (uy_ >= ny ? uy_ - ny : uy_);
-                            uz_ = uz_ < 0 ? uz_ + nz : (uz_ >= nz ? uz_ - nz : uz_);
-                            const int m = p.mask[((long long)uz_ * ny + uy_) * nx + ux_];
-                            const float wt = cx * p.wall_term[m][0] + cy * p.wall_term[m][1] +
-                                             cz * p.wall_term[m][2];
-                            const float s = Lattice<19>::w36(i) * (Am.lnk[link_opp(i)] + wt);
+                            float c = 0.0f;  // v_i . u, summed in the order pair() uses
+                            if (cx != 0) c = cx > 0 ? c + Am.own[3] : c - Am.own[3];
+                            if (cy != 0) c = cy > 0 ? c + Am.own[4] : c - Am.own[4];
+                            if (cz != 0) c = cz > 0 ? c + Am.own[5] : c - Am.own[5];
+                            const float m = fmaf(Am.own[1] * c, c, Am.own[0]);
+                            const float s = Lattice<19>::w36(i) * fmaf(Am.own[2], -c, m);
                             D36 += s;
                             Jx = fmaf((float)cx, s, Jx);
                             Jy = fmaf((float)cy, s, Jy);
                             Jz = fmaf((float)cz, s, Jz);
                         }
+                    }
+                    // moving walls (Eq. ACM2.0ccccbb): (1 - a) 6 rho0 times the
+                    // node's geometry sums of 36 w_i (1, v_i) (v_i . u_w)
+                    if (Am.bits & kMovingWallFlag) {
+                        const float4 g = wallg[(long long)tz * plane + col];
+                        D36 = fmaf(p.wall_scale, g.x, D36);
+                        Jx = fmaf(p.wall_scale, g.y, Jx);
+                        Jy = fmaf(p.wall_scale, g.z, Jy);
+                        Jz = fmaf(p.wall_scale, g.w, Jz);
                     }
                 }
                 Jx = div36(Jx) + Am.post[0];
@@ -444,14 +470,14 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                     energy = fmaf(vx, vx, fmaf(vy, vy, fmaf(vz, vz, energy)));
                 }
             }
-        }
+        });
     } else {
         // Halo columns: one direction partial (density part p, z part z) and
         // the two in-plane diagonals next to it, for three target planes.
         float hp[3] = {0.0f, 0.0f, 0.0f}, hz[3] = {0.0f, 0.0f, 0.0f};
         float hd1[3] = {0.0f, 0.0f, 0.0f}, hd2[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int k = 0; k < NZC + 2; ++k) {
+        static_for<NZC + 2>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
             {
                 const int j = k % 3;
                 const int rj = k % RING;
@@ -489,7 +515,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 hd2[j] = lterm(cs - ub, E0, r45, rA);  // diagonal, - across
                 hp[jm] += Ldn;
                 hz[jm] -= Ldn;
-                if (k < 2) continue;
+                if (k < 2) return;
                 if (NBUF == 1 && k > 2) __syncthreads();
                 float *Xf = reinterpret_cast<float *>(xch[k % NBUF][0]);
                 if (active) {
@@ -513,7 +539,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 }
                 __syncthreads();
             }
-        }
+        });
     }
 
     double v[2] = {(double)mass, 0.5 * (double)energy};
@@ -532,7 +558,12 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
 // Node classes and solid-upstream bit sets for the bounce-back of the march
 // kernel: class 0 fluid with only fluid upstream nodes, 1 fluid with at
 // least one solid upstream node (bit i set when x - v_i is solid), 2 solid.
-__global__ __launch_bounds__(256) void k_classify(ProblemArgs p, uint8_t *cls, unsigned *bits)
+// For a fluid node whose solid upstream nodes include a moving wall, the
+// flag bit is set and wallg holds sum_i 36 w_i (v_i . u_w(x - v_i)) times
+// (1, v_i) over its bounce-back links: the moving-wall term per unit of
+// (1 - a) 6 rho0, which depends on the geometry only.
+__global__ __launch_bounds__(256) void k_classify(ProblemArgs p, uint8_t *cls, unsigned *bits,
+                                                  float4 *wallg)
 {
     for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < p.n;
          idx += (long long)gridDim.x * blockDim.x) {
@@ -546,13 +577,32 @@ __global__ __launch_bounds__(256) void k_classify(ProblemArgs p, uint8_t *cls, u
         const int z = (int)(t / p.ny);
         const int y = (int)(t - (long long)z * p.ny);
         unsigned bb = 0u;
+        float g[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        bool moving = false;
 #pragma unroll
         for (int i = 1; i < 19; ++i) {
-            int ux = x - link_cx(i), uy = y - link_cy(i), uz = z - link_cz(i);
+            const int cx = link_cx(i), cy = link_cy(i), cz = link_cz(i);
+            int ux = x - cx, uy = y - cy, uz = z - cz;
             ux = ux < 0 ? ux + p.nx : (ux >= p.nx ? ux - p.nx : ux);
             uy = uy < 0 ? uy + p.ny : (uy >= p.ny ? uy - p.ny : uy);
             uz = uz < 0 ? uz + p.nz : (uz >= p.nz ? uz - p.nz : uz);
-            if (p.mask[((long long)uz * p.ny + uy) * p.nx + ux] != 0) bb |= 1u << i;
+            const int m = p.mask[((long long)uz * p.ny + uy) * p.nx + ux];
+            if (m != 0) {
+                bb |= 1u << i;
+                const float vu = cx * p.wall_u[m][0] + cy * p.wall_u[m][1] + cz * p.wall_u[m][2];
+                if (vu != 0.0f) {
+                    moving = true;
+                    const float s = Lattice<19>::w36(i) * vu;
+                    g[0] += s;
+                    g[1] += cx * s;
+                    g[2] += cy * s;
+                    g[3] += cz * s;
+                }
+            }
+        }
+        if (moving && wallg) {
+            bb |= kMovingWallFlag;
+            wallg[idx] = make_float4(g[0], g[1], g[2], g[3]);
         }
         cls[idx] = bb ? 1 : 0;
         bits[idx] = bb;
@@ -561,15 +611,16 @@ __global__ __launch_bounds__(256) void k_classify(ProblemArgs p, uint8_t *cls, u
 
 template <class T>
 hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint8_t *cls,
-                    const unsigned *bits, const ReduceArgs &r, hipStream_t s)
+                    const unsigned *bits, const float4 *wallg, const ReduceArgs &r,
+                    hipStream_t s)
 {
     const unsigned nb = march_num_blocks(p);
     const T *a = static_cast<const T *>(src);
     T *b = static_cast<T *>(dst);
     if (p.mask)
-        k_fwd_march<T, true><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, r);
+        k_fwd_march<T, true><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
     else
-        k_fwd_march<T, false><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, r);
+        k_fwd_march<T, false><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
     return hipGetLastError();
 }
 
@@ -590,21 +641,22 @@ unsigned march_num_blocks(const ProblemArgs &p)
     return (unsigned)(tiles * chunks);
 }
 
-hipError_t launch_classify(const ProblemArgs &p, uint8_t *cls, unsigned *bits, hipStream_t s)
+hipError_t launch_classify(const ProblemArgs &p, uint8_t *cls, unsigned *bits, float4 *wallg,
+                           hipStream_t s)
 {
     long long nb = (p.n + 255) / 256;
     if (nb > 4096) nb = 4096;
-    k_classify<<<(unsigned)nb, 256, 0, s>>>(p, cls, bits);
+    k_classify<<<(unsigned)nb, 256, 0, s>>>(p, cls, bits, wallg);
     return hipGetLastError();
 }
 
 hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, void *dst,
-                            const uint8_t *cls, const unsigned *bits, const ReduceArgs &r,
-                            hipStream_t s)
+                            const uint8_t *cls, const unsigned *bits, const float4 *wallg,
+                            const ReduceArgs &r, hipStream_t s)
 {
     if (!march_supported(p) || (p.mask && (!cls || !bits))) return hipErrorNotSupported;
-    return storage ? dispatch<__half>(p, src, dst, cls, bits, r, s)
-                   : dispatch<float>(p, src, dst, cls, bits, r, s);
+    return storage ? dispatch<__half>(p, src, dst, cls, bits, wallg, r, s)
+                   : dispatch<float>(p, src, dst, cls, bits, wallg, r, s);
 }
 
 }  // namespace lwacm
