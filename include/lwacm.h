@@ -14,14 +14,19 @@
  *    ((z * ny) + y) * nx + x, x fastest.  Every axis is periodic; walls are
  *    solid nodes of the mask.
  *  - State buffers (caller-owned device memory, lwacm_state_bytes() bytes
- *    each): structure of arrays, field-major: field 0 is rho - 1, fields
- *    1..D are u_x, u_y (, u_z).  Storage LWACM_FP32 holds float; storage
+ *    each): node-interleaved, the D+1 values of node i side by side at
+ *    elements (D+1)*i .. (D+1)*i + D: rho - 1, then u_x, u_y (, u_z), so a
+ *    D3Q19 node is one 16-byte (FP32) or 8-byte (FP16) access.  Callers treat
+ *    the buffers as opaque (lwacm_set_state, lwacm_moments, save/load
+ *    convert or copy them).  Storage LWACM_FP32 holds float; storage
  *    LWACM_FP16_DEV holds IEEE half values of (field * 2^k), with k set by
  *    lwacm_set_fp16_scales (default 14 for both).  Initial states are
  *    rounded to nearest even; step outputs are rounded stochastically by
  *    default (lwacm_set_fp16_rounding).  Arithmetic is always FP32.
  *  - FP32 field arguments (d_drho, d_u, d_lambda, d_mu) are device arrays
- *    in the same SoA order: d_drho has nodes floats, d_u has D * nodes.
+ *    in field-major (structure of arrays) order: d_drho has nodes floats,
+ *    d_u has D * nodes (all u_x, then all u_y, ...), d_lambda and d_mu have
+ *    (D+1) * nodes (field 0 first).
  *  - Every call is asynchronous on the stream given to lwacm_init unless it
  *    returns host values (stated per call).  Pointers are not retained
  *    beyond the call unless stated.
@@ -173,7 +178,7 @@ long long lwacm_step_count(lwacm_ctx *c);
  * Notation: one forward step maps state_t to state_{t+1}; its outputs are
  * rho+ = 1 + D and u+ = J / rho+ with D = sum of link terms and J the new
  * momentum.  The reverse sweep carries mu_t = (dL/dD, dL/dJ) of step t, a
- * (D+1)-field FP32 array in the state's SoA order.
+ * (D+1)-field FP32 array in field-major order.
  *
  * lwacm_adjoint_seed: mu_{T-1} from the loss cotangent lambda_T = (dL/d(rho-1),
  *   dL/du) of the final state and that state (storage format):

@@ -105,26 +105,6 @@ __device__ __forceinline__ float normalisation_factor(float D)
     return D * __builtin_amdgcn_rcpf(1.0f + D);
 }
 
-// ------------------------------------------------------- storage formats
-template <class T>
-struct Storage;
-
-template <>
-struct Storage<float> {
-    __device__ __forceinline__ static float load(const float *p, long long i, float)
-    {
-        return p[i];
-    }
-    __device__ __forceinline__ static void store(float *p, long long i, float v, float)
-    {
-        p[i] = v;
-    }
-    __device__ __forceinline__ static void store_sr(float *p, long long i, float v, float, uint32_t)
-    {
-        p[i] = v;
-    }
-};
-
 // ------------------------------------------- stochastic FP16 rounding
 // Counter-based random bits: the pcg4d hash of Jarzynski and Olano, "Hash
 // Functions for GPU Rendering", JCGT 9(3), 2020.  Four 32-bit words in, four
@@ -179,23 +159,98 @@ __device__ __forceinline__ unsigned short half_bits_sr(float y, uint32_t r)
     return __half_as_ushort(__float2half_rn(__uint_as_float(mag | (b & 0x80000000u))));
 }
 
-// FP16 deviation storage: value * 2^k, the scale arguments are 2^-k on load
-// and 2^k on store (exact in FP32).  store() rounds to nearest even (initial
-// states); store_sr() rounds stochastically with random word r (steps).
-template <>
-struct Storage<__half> {
-    __device__ __forceinline__ static float load(const __half *p, long long i, float inv_scale)
+// ------------------------------------------------------- storage formats
+// The state is node-interleaved: node idx holds its NF = D + 1 values
+// (rho - 1, u_x, u_y[, u_z]) at elements NF * idx .. NF * idx + NF - 1, so a
+// D3Q19 node is one 16-byte (FP32) or 8-byte (FP16) access.  FP16 storage
+// holds half(value * 2^k) with k_rho for field 0 and k_u for the velocity;
+// the scale arguments are 2^-k on load and 2^k on store (exact in FP32).
+// store() rounds to nearest even (initial states); store_sr() rounds
+// stochastically with one random word per field (step outputs).
+template <class T, int NF>
+struct NodeState;
+
+template <int NF>
+struct NodeState<float, NF> {
+    __device__ __forceinline__ static void load(const float *s, long long idx, const float (&)[2],
+                                                float (&v)[NF])
     {
-        return __half2float(p[i]) * inv_scale;
+        if constexpr (NF == 4) {
+            const float4 q = reinterpret_cast<const float4 *>(s)[idx];
+            v[0] = q.x;
+            v[1] = q.y;
+            v[2] = q.z;
+            v[3] = q.w;
+        } else {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[f] = s[NF * idx + f];
+        }
     }
-    __device__ __forceinline__ static void store(__half *p, long long i, float v, float scale)
+    __device__ __forceinline__ static void store(float *s, long long idx, const float (&v)[NF],
+                                                 const float (&)[2])
     {
-        p[i] = __float2half_rn(v * scale);
+        if constexpr (NF == 4) {
+            reinterpret_cast<float4 *>(s)[idx] = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) s[NF * idx + f] = v[f];
+        }
     }
-    __device__ __forceinline__ static void store_sr(__half *p, long long i, float v, float scale,
-                                                    uint32_t r)
+    __device__ __forceinline__ static void store_sr(float *s, long long idx, const float (&v)[NF],
+                                                    const float (&sc)[2], const uint32_t (&)[4])
     {
-        p[i] = __ushort_as_half(half_bits_sr(v * scale, r));
+        store(s, idx, v, sc);
+    }
+};
+
+template <int NF>
+struct NodeState<__half, NF> {
+    __device__ __forceinline__ static float unpack(uint32_t w, int hi, float scale)
+    {
+        return __half2float(__ushort_as_half((unsigned short)(hi ? w >> 16 : w & 0xffffu))) * scale;
+    }
+    __device__ __forceinline__ static void load(const __half *s, long long idx,
+                                                const float (&ld)[2], float (&v)[NF])
+    {
+        if constexpr (NF == 4) {
+            const uint2 q = reinterpret_cast<const uint2 *>(s)[idx];
+            v[0] = unpack(q.x, 0, ld[0]);
+            v[1] = unpack(q.x, 1, ld[1]);
+            v[2] = unpack(q.y, 0, ld[1]);
+            v[3] = unpack(q.y, 1, ld[1]);
+        } else {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[f] = __half2float(s[NF * idx + f]) * ld[f > 0];
+        }
+    }
+    // bits[f]: FP16 bit pattern of field f
+    __device__ __forceinline__ static void put(__half *s, long long idx,
+                                               const unsigned short (&bits)[NF])
+    {
+        if constexpr (NF == 4) {
+            reinterpret_cast<uint2 *>(s)[idx] =
+                make_uint2((uint32_t)bits[0] | ((uint32_t)bits[1] << 16),
+                           (uint32_t)bits[2] | ((uint32_t)bits[3] << 16));
+        } else {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) s[NF * idx + f] = __ushort_as_half(bits[f]);
+        }
+    }
+    __device__ __forceinline__ static void store(__half *s, long long idx, const float (&v)[NF],
+                                                 const float (&st)[2])
+    {
+        unsigned short b[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) b[f] = __half_as_ushort(__float2half_rn(v[f] * st[f > 0]));
+        put(s, idx, b);
+    }
+    __device__ __forceinline__ static void store_sr(__half *s, long long idx, const float (&v)[NF],
+                                                    const float (&st)[2], const uint32_t (&r)[4])
+    {
+        unsigned short b[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) b[f] = half_bits_sr(v[f] * st[f > 0], r[f]);
+        put(s, idx, b);
     }
 };
 

@@ -46,14 +46,17 @@ __device__ __forceinline__ long long node_at(const ProblemArgs &p, int x, int y,
     return ((long long)z * p.ny + y) * p.nx + x;
 }
 
+// State of node idx (node-interleaved storage): rho - 1 and u (u[2] = 0 in 2D).
 template <int D, class T>
-__device__ __forceinline__ void load_state(const T *s, long long n, long long idx,
-                                           const ProblemArgs &p, float &drho, float (&u)[3])
+__device__ __forceinline__ void load_state(const T *s, long long idx, const ProblemArgs &p,
+                                           float &drho, float (&u)[3])
 {
-    drho = Storage<T>::load(s, idx, p.ld_scale[0]);
-    u[0] = Storage<T>::load(s, n + idx, p.ld_scale[1]);
-    u[1] = Storage<T>::load(s, 2 * n + idx, p.ld_scale[1]);
-    u[2] = (D == 3) ? Storage<T>::load(s, 3 * n + idx, p.ld_scale[1]) : 0.0f;
+    float v[D + 1];
+    NodeState<T, D + 1>::load(s, idx, p.ld_scale, v);
+    drho = v[0];
+    u[0] = v[1];
+    u[1] = v[2];
+    u[2] = (D == 3) ? v[D] : 0.0f;
 }
 
 template <int Q>
@@ -77,11 +80,15 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
     for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
          idx += (long long)gridDim.x * blockDim.x) {
         float drx, ux[3];
-        load_state<D, T>(src, n, idx, p, drx, ux);
+        load_state<D, T>(src, idx, p, drx, ux);
         if (MASK && p.mask[idx] != 0) {
             // solid node: never updated, copied through to the other buffer
-            Storage<T>::store(dst, idx, drx, p.st_scale[0]);
-            for (int k = 0; k < D; ++k) Storage<T>::store(dst, (k + 1) * n + idx, ux[k], p.st_scale[1]);
+            // (a stored value converts back to itself exactly)
+            float v[D + 1];
+            v[0] = drx;
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[k + 1] = ux[k];
+            NodeState<T, D + 1>::store(dst, idx, v, p.st_scale);
             continue;
         }
         const Coord c = decompose(idx, p.nx, p.ny);
@@ -113,7 +120,7 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
                 s = link_term_unweighted(drx + fg, rx, vdot<Q>(ib, ux), Bx, p.A) + vdot<Q>(i, uw);
             } else {
                 float dry, uy[3];
-                load_state<D, T>(src, n, up, p, dry, uy);
+                load_state<D, T>(src, up, p, dry, uy);
                 const float By = -1.5f * (uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2]);
                 s = link_term_unweighted(dry + fg, 1.0f + dry, vdot<Q>(i, uy), By, p.A);
             }
@@ -133,7 +140,8 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
         // FP32 error from accumulating over long runs.
         const float q = normalisation_factor(Dsum);
         float e = 0.0f;
-        float out[4] = {Dsum, 0.0f, 0.0f, 0.0f};
+        float out[D + 1];
+        out[0] = Dsum;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             out[k + 1] = fmaf(-J[k], q, J[k]);
@@ -142,12 +150,9 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
         if (std::is_same<T, __half>::value && p.fp16_sr) {
             const U32x4 h = pcg4d((uint32_t)c.x, (uint32_t)c.y, (uint32_t)c.z, p.sr_word);
             const uint32_t rw[4] = {h.x, h.y, h.z, h.w};
-#pragma unroll
-            for (int k = 0; k <= D; ++k)
-                Storage<T>::store_sr(dst, k * n + idx, out[k], p.st_scale[k > 0], rw[k]);
+            NodeState<T, D + 1>::store_sr(dst, idx, out, p.st_scale, rw);
         } else {
-#pragma unroll
-            for (int k = 0; k <= D; ++k) Storage<T>::store(dst, k * n + idx, out[k], p.st_scale[k > 0]);
+            NodeState<T, D + 1>::store(dst, idx, out, p.st_scale);
         }
         acc[0] += (double)Dsum;
         acc[1] += 0.5 * (double)e;
@@ -182,7 +187,7 @@ __global__ __launch_bounds__(kGenericBlock) void k_adj_generic(ProblemArgs p, co
             continue;
         }
         float dry, uy[3];
-        load_state<D, T>(state, n, idx, p, dry, uy);
+        load_state<D, T>(state, idx, p, dry, uy);
         const float ry = 1.0f + dry;
         const float By = -1.5f * (uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2]);
         const Coord c = decompose(idx, p.nx, p.ny);
@@ -264,7 +269,7 @@ __global__ __launch_bounds__(kGenericBlock) void k_adj_seed(ProblemArgs p, const
             continue;
         }
         float dr, u[3];
-        load_state<D, T>(state, n, idx, p, dr, u);
+        load_state<D, T>(state, idx, p, dr, u);
         const float inv = 1.0f / (1.0f + dr);
         float lu_u = 0.0f;
         for (int j = 0; j < D; ++j) lu_u = fmaf(lam[(j + 1) * n + idx], u[j], lu_u);
@@ -281,9 +286,10 @@ __global__ __launch_bounds__(kGenericBlock) void k_set_state(ProblemArgs p, cons
     const long long n = p.n;
     for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
          idx += (long long)gridDim.x * blockDim.x) {
-        Storage<T>::store(dst, idx, drho[idx], p.st_scale[0]);
-        for (int k = 0; k < D; ++k)
-            Storage<T>::store(dst, (k + 1) * n + idx, u[k * n + idx], p.st_scale[1]);
+        float v[D + 1];
+        v[0] = drho[idx];
+        for (int k = 0; k < D; ++k) v[k + 1] = u[k * n + idx];
+        NodeState<T, D + 1>::store(dst, idx, v, p.st_scale);
     }
 }
 
@@ -297,7 +303,7 @@ __global__ __launch_bounds__(kGenericBlock) void k_moments(ProblemArgs p, const 
     for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
          idx += (long long)gridDim.x * blockDim.x) {
         float dr, uu[3];
-        load_state<D, T>(src, n, idx, p, dr, uu);
+        load_state<D, T>(src, idx, p, dr, uu);
         if (drho) drho[idx] = dr;
         if (u)
             for (int k = 0; k < D; ++k) u[k * n + idx] = uu[k];

@@ -103,12 +103,16 @@ struct Acc {
 
 __device__ __forceinline__ bool has_bit(unsigned bits, int i) { return (bits >> i) & 1u; }
 
-// Global memory goes through buffer resources: one descriptor per field in
-// SGPRs, the column's fixed 32-bit byte offset in a VGPR and the plane's
-// byte offset as the scalar offset, so a load or store costs no per-lane
-// address arithmetic.  (march_supported() guarantees that every field fits
-// in 4 GiB.)
+// Global memory goes through buffer resources: one descriptor per state
+// buffer in SGPRs, the column's fixed 32-bit byte offset in a VGPR and the
+// plane's byte offset as the scalar offset, so a load or store costs no
+// per-lane address arithmetic.  The state is node-interleaved, so one node of
+// one plane is a single 16-byte (FP32) or 8-byte (FP16) access.
+// (march_supported() guarantees that a state buffer fits in 4 GiB.)
 using Rsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned long long bytes)
 {
@@ -119,53 +123,78 @@ __device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned long long b
 template <class T>
 struct BufIO;
 
+// Element access uses explicit .x/.y/.z/.w selection and whole-vector casts:
+// this compiler narrows a 128-bit load to its first dword when elements of
+// the loaded vector are taken apart with __builtin_bit_cast one by one.
 template <>
 struct BufIO<float> {
-    using Raw = float;
+    using Raw = f32x4;
+    static constexpr unsigned kNodeBytes = 16;
     __device__ __forceinline__ static Raw load(Rsrc r, unsigned voff, unsigned soff)
     {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+        return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
     }
-    __device__ __forceinline__ static float value(Raw v, float) { return v; }
-    __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float v,
-                                                 float)
+    // field f (0: rho - 1, 1..3: u) of a loaded node
+    __device__ __forceinline__ static float value(const Raw &v, int f, float)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+        return f == 0 ? v.x : (f == 1 ? v.y : (f == 2 ? v.z : v.w));
     }
-    __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float v,
-                                                    float, uint32_t)
+    __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float d,
+                                                 float ux, float uy, float uz, const float (&)[2])
     {
-        store(r, voff, soff, v, 1.0f);
+        const f32x4 v = {d, ux, uy, uz};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+    }
+    __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float d,
+                                                    float ux, float uy, float uz,
+                                                    const float (&sc)[2], const U32x4 &)
+    {
+        store(r, voff, soff, d, ux, uy, uz, sc);
     }
 };
 
 template <>
 struct BufIO<__half> {
-    using Raw = unsigned short;
+    using Raw = u32x2;
+    static constexpr unsigned kNodeBytes = 8;
     __device__ __forceinline__ static Raw load(Rsrc r, unsigned voff, unsigned soff)
     {
-        return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+        return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
     }
-    __device__ __forceinline__ static float value(Raw v, float inv_scale)
+    __device__ __forceinline__ static float value(const Raw &v, int f, float inv_scale)
     {
-        return __half2float(__ushort_as_half(v)) * inv_scale;
+        const unsigned w = (f >> 1) ? v.y : v.x;
+        const unsigned short h = (unsigned short)((f & 1) ? w >> 16 : w & 0xffffu);
+        return __half2float(__ushort_as_half(h)) * inv_scale;
     }
-    __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float v,
-                                                 float scale)
+    __device__ __forceinline__ static void put(Rsrc r, unsigned voff, unsigned soff,
+                                               unsigned short b0, unsigned short b1,
+                                               unsigned short b2, unsigned short b3)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v * scale)), r,
-                                              voff, soff, 0);
+        const Raw v = {(unsigned)b0 | ((unsigned)b1 << 16), (unsigned)b2 | ((unsigned)b3 << 16)};
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
     }
-    __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float v,
-                                                    float scale, uint32_t bits)
+    __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float d,
+                                                 float ux, float uy, float uz,
+                                                 const float (&st)[2])
     {
-        __builtin_amdgcn_raw_buffer_store_b16(half_bits_sr(v * scale, bits), r, voff, soff, 0);
+        put(r, voff, soff, __half_as_ushort(__float2half_rn(d * st[0])),
+            __half_as_ushort(__float2half_rn(ux * st[1])),
+            __half_as_ushort(__float2half_rn(uy * st[1])),
+            __half_as_ushort(__float2half_rn(uz * st[1])));
+    }
+    __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float d,
+                                                    float ux, float uy, float uz,
+                                                    const float (&st)[2], const U32x4 &h)
+    {
+        put(r, voff, soff, half_bits_sr(d * st[0], h.x), half_bits_sr(ux * st[1], h.y),
+            half_bits_sr(uy * st[1], h.z), half_bits_sr(uz * st[1], h.w));
     }
 };
 
 template <class T>
 struct Ring {
-    typename BufIO<T>::Raw v[4];
+    typename BufIO<T>::Raw v;  // the node's stored values on one plane
     uint8_t cls;
 };
 
@@ -247,22 +276,20 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
     const float A = p.A;
     const float a = p.a;
 
-    // plane index with periodic wrap, as a byte offset inside a field
-    const unsigned plane_bytes = (unsigned)(plane * (long long)sizeof(T));
+    // plane index with periodic wrap, as a byte offset inside the state
+    constexpr unsigned NB = BufIO<T>::kNodeBytes;
+    const unsigned plane_bytes = (unsigned)(plane * (long long)NB);
     auto soff_of = [&](int pz) -> unsigned {
         pz = pz < 0 ? pz + nz : (pz >= nz ? pz - nz : pz);
         return (unsigned)pz * plane_bytes;
     };
-    const unsigned long long fbytes = (unsigned long long)n * sizeof(T);
-    const Rsrc rs[4] = {make_rsrc(src, fbytes), make_rsrc(src + n, fbytes),
-                        make_rsrc(src + 2 * n, fbytes), make_rsrc(src + 3 * n, fbytes)};
-    const Rsrc rd[4] = {make_rsrc(dst, fbytes), make_rsrc(dst + n, fbytes),
-                        make_rsrc(dst + 2 * n, fbytes), make_rsrc(dst + 3 * n, fbytes)};
-    const unsigned voff = col * (unsigned)sizeof(T);
+    const unsigned long long sbytes = (unsigned long long)n * NB;
+    const Rsrc rs = make_rsrc(src, sbytes);
+    const Rsrc rd = make_rsrc(dst, sbytes);
+    const unsigned voff = col * NB;
     auto issue = [&](Ring<T> &rg, int pz) {
         const unsigned so = soff_of(pz);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) rg.v[f] = BufIO<T>::load(rs[f], voff, so);
+        rg.v = BufIO<T>::load(rs, voff, so);
         if (MASK) {
             pz = pz < 0 ? pz + nz : (pz >= nz ? pz - nz : pz);
             rg.cls = cls_arr[(long long)pz * plane + col];
@@ -298,10 +325,10 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 Acc &Am = acc[(j + 2) % 3];  // target plane pz - 1 (finalised now)
 
                 // ---- consume the ring slot of plane pz, refill it with pz + 3
-                const float dr = BufIO<T>::value(ring[rj].v[0], p.ld_scale[0]);
-                const float ux = BufIO<T>::value(ring[rj].v[1], p.ld_scale[1]);
-                const float uy = BufIO<T>::value(ring[rj].v[2], p.ld_scale[1]);
-                const float uz = BufIO<T>::value(ring[rj].v[3], p.ld_scale[1]);
+                const float dr = BufIO<T>::value(ring[rj].v, 0, p.ld_scale[0]);
+                const float ux = BufIO<T>::value(ring[rj].v, 1, p.ld_scale[1]);
+                const float uy = BufIO<T>::value(ring[rj].v, 2, p.ld_scale[1]);
+                const float uz = BufIO<T>::value(ring[rj].v, 3, p.ld_scale[1]);
                 const int cls = MASK ? (int)ring[rj].cls : 0;
                 // refill with plane pz + RING (unconditional; past the chunk it
                 // re-reads plane z1, which is cached and never consumed)
@@ -456,15 +483,9 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                     const unsigned so = (unsigned)tz * plane_bytes;
                     if (std::is_same<T, __half>::value && p.fp16_sr) {
                         const U32x4 h = pcg4d((uint32_t)gx, (uint32_t)gy, (uint32_t)tz, p.sr_word);
-                        BufIO<T>::store_sr(rd[0], voff, so, D, p.st_scale[0], h.x);
-                        BufIO<T>::store_sr(rd[1], voff, so, vx, p.st_scale[1], h.y);
-                        BufIO<T>::store_sr(rd[2], voff, so, vy, p.st_scale[1], h.z);
-                        BufIO<T>::store_sr(rd[3], voff, so, vz, p.st_scale[1], h.w);
+                        BufIO<T>::store_sr(rd, voff, so, D, vx, vy, vz, p.st_scale, h);
                     } else {
-                        BufIO<T>::store(rd[0], voff, so, D, p.st_scale[0]);
-                        BufIO<T>::store(rd[1], voff, so, vx, p.st_scale[1]);
-                        BufIO<T>::store(rd[2], voff, so, vy, p.st_scale[1]);
-                        BufIO<T>::store(rd[3], voff, so, vz, p.st_scale[1]);
+                        BufIO<T>::store(rd, voff, so, D, vx, vy, vz, p.st_scale);
                     }
                     mass += D;
                     energy = fmaf(vx, vx, fmaf(vy, vy, fmaf(vz, vz, energy)));
@@ -483,10 +504,10 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 const int rj = k % RING;
                 const int pz = z0 - 1 + k;
                 const int j1 = (j + 1) % 3, jm = (j + 2) % 3;
-                const float dr = BufIO<T>::value(ring[rj].v[0], p.ld_scale[0]);
-                const float ux = BufIO<T>::value(ring[rj].v[1], p.ld_scale[1]);
-                const float uy = BufIO<T>::value(ring[rj].v[2], p.ld_scale[1]);
-                const float uz = BufIO<T>::value(ring[rj].v[3], p.ld_scale[1]);
+                const float dr = BufIO<T>::value(ring[rj].v, 0, p.ld_scale[0]);
+                const float ux = BufIO<T>::value(ring[rj].v, 1, p.ld_scale[1]);
+                const float uy = BufIO<T>::value(ring[rj].v, 2, p.ld_scale[1]);
+                const float uz = BufIO<T>::value(ring[rj].v, 3, p.ld_scale[1]);
                 const int cls = MASK ? (int)ring[rj].cls : 0;
                 // refill with plane pz + RING (unconditional; past the chunk it
                 // re-reads plane z1, which is cached and never consumed)
@@ -628,9 +649,9 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
 
 bool march_supported(const ProblemArgs &p)
 {
-    // 32-bit byte offsets inside a field: n * 4 bytes < 4 GiB
+    // 32-bit byte offsets inside a state buffer: n * 16 bytes < 4 GiB
     return p.Q == 19 && !p.has_force && p.nx >= TX && p.ny >= TY && p.nx % TX == 0 &&
-           p.ny % TY == 0 && p.nz >= 1 && p.n < (1LL << 30);
+           p.ny % TY == 0 && p.nz >= 1 && p.n < (1LL << 28);
 }
 
 unsigned march_num_blocks(const ProblemArgs &p)

@@ -197,8 +197,9 @@ def test_fp16_stored_bits_match_oracle_rounding(case, rounding):
     n = nx * ny * nz
 
     def decode(bits):
-        h = bits.view(np.float16).astype(np.float64) / 2.0 ** 14
-        return 1.0 + h[:n].reshape(shape), h[n:].reshape((d,) + shape)
+        # node-interleaved storage: (rho - 1, u) of each node side by side
+        h = (bits.view(np.float16).astype(np.float64) / 2.0 ** 14).reshape(n, d + 1)
+        return 1.0 + h[:, 0].reshape(shape), h[:, 1:].T.reshape((d,) + shape)
 
     # the oracle starts from the halves the GPU stored (FP64 -> FP32 -> FP16
     # here, which may differ from FP64 -> FP16 by one unit)
@@ -211,7 +212,8 @@ def test_fp16_stored_bits_match_oracle_rounding(case, rounding):
             r, uu = oracle.store_fp16_sr(p, t, r, uu, seed=seed)
         else:
             r, uu = 1.0 + _q16(r - 1.0), _q16(uu)
-        want = np.concatenate([_half_bits(r - 1.0).reshape(-1), _half_bits(uu).reshape(-1)])
+        want = np.concatenate([_half_bits(r - 1.0).reshape(1, -1), _half_bits(uu).reshape(d, -1)])
+        want = np.ascontiguousarray(want.T).reshape(-1)   # node-interleaved
         assert got.shape == (n * (d + 1),)
         gv = got.view(np.float16).astype(np.float64) / 2.0 ** 14
         wh = want.view(np.float16)
@@ -277,6 +279,116 @@ def test_cavity_48_matches_oracle():
     mir = uu[:, :, ::-1, :].copy()
     mir[1] = -mir[1]
     assert np.abs(mir[:, fl] - uu[:, fl]).max() < 1e-7
+
+
+def _cavity_centrelines(u, n):
+    """u_x(z) through the cavity centre and u_z(x) through it, fluid nodes
+    only, each the mean of the 2 x 2 columns around the centre."""
+    c = slice(n // 2 - 1, n // 2 + 1)
+    return u[0][1:n - 1, c, c].mean(axis=(1, 2)), u[2][c, c, 1:n - 1].mean(axis=(0, 1))
+
+
+def test_cavity_48_5000_and_50000_steps_vs_stored_oracle(golden_dir):
+    """The 48^3 lid-driven cube against the oracle's stored run
+    (tests/golden/make_cavity48_reference.py): the whole field after 5000
+    steps (transient: u within 1e-5) and after 50000 steps (the steady
+    state).  At omega = 1.97 the flow damps perturbations slowly, and over
+    50000 steps storing the state in FP32 alone moves u by more than 1e-5:
+    the bar there is twice that FP32-storage floor, which the oracle itself
+    shows when its state is rounded to FP32 after every step
+    (tests/golden/make_cavity48_fp32_floor.py)."""
+    L = need_gpu()
+    ref = np.load(os.path.join(golden_dir, "cavity48_steps5000_50000.npz"))
+    floor = json.load(open(os.path.join(golden_dir, "cavity48_fp32_floor.json")))
+    c = wl.CAVITY_48
+    n = c.nx
+    assert int(ref["n"]) == n and abs(float(ref["omega"]) - c.omega) < 1e-12
+    mask = wl.cavity_mask(n)
+    fl = mask == 0
+    s = L.Solver(19, n, n, n, c.omega, mask=to_dev(mask, torch.uint8),
+                 wall_u=[list(r) for r in wl.wall_table(c.lid)])
+    s.set_state(torch.zeros((n, n, n), device="cuda"), torch.zeros((3, n, n, n), device="cuda"))
+    done = 0
+    for steps in (5000, 50000):
+        banner(f"{c.name} {steps} steps")
+        s.step(steps - done)
+        done = steps
+        dr, uu = s.moments()
+        dr = dr.double().cpu().numpy()
+        uu = uu.double().cpu().numpy()
+        err_u = rel_l2(uu[:, fl], ref[f"u_{steps}"][:, fl])
+        err_r = rel_l2(dr[fl], ref[f"drho_{steps}"][fl])
+        banner(f"cavity48 {steps} steps: rel-L2 u {err_u:.3e} drho {err_r:.3e}; "
+               f"FP32-storage floor u {floor[f'u_{steps}']:.3e} drho {floor[f'drho_{steps}']:.3e}")
+        assert err_u < max(FP32_TOL, 2.0 * floor[f"u_{steps}"])
+        assert err_r < max(1e-4, 2.0 * floor[f"drho_{steps}"])
+    m, _ = s.diagnostics()
+    assert abs(m - fl.sum()) / fl.sum() < 1e-9
+    gx, gz = _cavity_centrelines(uu, n)
+    assert np.abs(gx - ref["ux_z"]).max() < 1e-3 * c.lid[0]
+    assert np.abs(gz - ref["uz_x"]).max() < 1e-3 * c.lid[0]
+    s.close()
+
+
+def _gpu_cavity_centrelines(n, steps):
+    """GPU run of the lid-driven cube on an n^3 array at Re = 1000 on its
+    fluid width n - 2; centreline profiles (u_x(z), u_z(x)) / u_lid."""
+    L = need_gpu()
+    lid = (0.05, 0.0, 0.0)
+    omega = wl.omega_for_viscosity(lid[0] * (n - 2) / 1000.0)
+    mask = torch.as_tensor(wl.cavity_mask(n), device="cuda")
+    s = L.Solver(19, n, n, n, omega, mask=mask, wall_u=[list(r) for r in wl.wall_table(lid)])
+    s.set_state(torch.zeros((n, n, n), device="cuda"), torch.zeros((3, n, n, n), device="cuda"))
+    s.step(steps)
+    _, uu = s.moments()
+    m, e = s.diagnostics()
+    nf = (n - 2) ** 3
+    assert abs(m - nf) / nf < 1e-9 and np.isfinite(e)
+    c_ = slice(n // 2 - 1, n // 2 + 1)
+    ux_z = uu[0, 1:n - 1, c_, c_].double().mean(dim=(1, 2)).cpu().numpy()
+    uz_x = uu[2, c_, c_, 1:n - 1].double().mean(dim=(0, 1)).cpu().numpy()
+    s.close()
+    return ux_z / lid[0], uz_x / lid[0]
+
+
+def test_cavity_192_50000_steps_centrelines_near_48_oracle(golden_dir):
+    """The 192^3 cube (the benchmark's masked workload, march kernel) after
+    50000 steps against the 48^3 oracle's centreline profiles, both at
+    Re = 1000 on their fluid width, as u / u_lid against position / L.  The
+    grids differ by 4x in resolution, so this is a discretisation check, not
+    parity (parity unpinned: no resolved reference data): the profiles agree
+    to within 10 % of the lid speed, and the extrema of the profiles (the
+    strength of the primary vortex) converge: a 96^3 run lies closer to
+    192^3 than the 48^3 oracle does.  (50000 steps are a different number of
+    lid turnovers on each grid, so the full profiles also differ by how far
+    each run has settled.)"""
+    ref = np.load(os.path.join(golden_dir, "cavity48_steps5000_50000.npz"))
+    c = wl.CAVITY_192
+    banner(f"{c.name} {c.steps} steps")
+    gx192, gz192 = _gpu_cavity_centrelines(c.nx, c.steps)
+    gx96, gz96 = _gpu_cavity_centrelines(96, c.steps)
+    ulid = c.lid[0]
+
+    def pos(n):
+        return (np.arange(1, n - 1) - 0.5) / (n - 2)
+
+    def dist(px, fx, pz, fz, p_ref, gx_ref, gz_ref):
+        return max(np.abs(np.interp(p_ref, px, fx) - gx_ref).max(),
+                   np.abs(np.interp(p_ref, pz, fz) - gz_ref).max())
+
+    p48 = pos(int(ref["n"]))
+    g48x, g48z = ref["ux_z"] / ulid, ref["uz_x"] / ulid
+    d48 = dist(pos(c.nx), gx192, pos(c.nx), gz192, p48, g48x, g48z)
+
+    def extrema(gx, gz):
+        return np.array([gx.min(), gz.min(), gz.max()])
+
+    e192, e96, e48 = extrema(gx192, gz192), extrema(gx96, gz96), extrema(g48x, g48z)
+    banner(f"cavity centrelines: max |du|/u_lid 48^3 oracle vs 192^3 {d48:.3e}; extrema "
+           f"(min u_x, min u_z, max u_z)/u_lid 192^3 {np.round(e192, 4)}, 96^3 {np.round(e96, 4)}, "
+           f"48^3 {np.round(e48, 4)}")
+    assert d48 < 0.1
+    assert np.all(np.abs(e96 - e192) < np.abs(e48 - e192))
 
 
 # --------------------------------------------- full-size properties
