@@ -62,11 +62,12 @@ enum {
 /* Rounding of step outputs into FP16 storage (lwacm_set_fp16_rounding). */
 enum { LWACM_ROUND_NEAREST = 0, LWACM_ROUND_STOCHASTIC = 1 };
 
-/* Kernel selection for lwacm_set_variant. */
+/* Kernel selection for lwacm_set_variant (forward and reverse steps). */
 enum {
-    LWACM_KERNEL_AUTO = 0,    /* fastest kernel that supports the problem */
+    LWACM_KERNEL_AUTO = 0,    /* fastest kernels that support the problem */
     LWACM_KERNEL_GENERIC = 1, /* one thread per node, neighbours from global memory */
-    LWACM_KERNEL_MARCH = 2    /* D3Q19 z-marching tile kernel */
+    LWACM_KERNEL_MARCH = 2    /* D3Q19 z-marching tile kernels (nx % 32 == 0, ny % 16 == 0;
+                                 the forward one without body force) */
 };
 
 /* Bytes of one state buffer: (D+1) * nodes * (4 for FP32, 2 for FP16).
@@ -177,8 +178,10 @@ long long lwacm_step_count(lwacm_ctx *c);
  *
  * Notation: one forward step maps state_t to state_{t+1}; its outputs are
  * rho+ = 1 + D and u+ = J / rho+ with D = sum of link terms and J the new
- * momentum.  The reverse sweep carries mu_t = (dL/dD, dL/dJ) of step t, a
- * (D+1)-field FP32 array in field-major order.
+ * momentum.  The reverse sweep carries mu_t = (dL/dD, dL/dJ) of step t:
+ * (D+1) * nodes FP32 values, node-interleaved like the state (mu_R, mu_J of
+ * node i at (D+1)*i ..), an intermediate the caller only passes along.
+ * lambda_T (input of the seed) and the final gradient are field-major.
  *
  * lwacm_adjoint_seed: mu_{T-1} from the loss cotangent lambda_T = (dL/d(rho-1),
  *   dL/du) of the final state and that state (storage format):
@@ -188,7 +191,7 @@ long long lwacm_step_count(lwacm_ctx *c);
  *   and mu_t, computes lambda_t = dL/d state_t and writes
  *     final_t0 == 0: mu_{t-1} = (lambda_rho - lambda_u . u_t / rho_t, lambda_u / rho_t)
  *     final_t0 != 0: lambda_t itself (the gradient with respect to the
- *                    initial (rho - 1, u)),
+ *                    initial (rho - 1, u)), field-major,
  *   and adds this step's dL/domega to *d_dL_domega (device FP64 scalar,
  *   fixed-order reduction: bitwise reproducible).  rho0 and the walls are
  *   constants of the problem.  d_mu_out must not alias d_mu_in.

@@ -63,6 +63,7 @@ void set_wall_terms(lwacm_ctx *c)
             c->p.wall_u[m][k] = (float)uw;
         }
     c->p.wall_scale = (float)((1.0 - a) * 6.0 * c->rho0);
+    c->p.wall6rho0 = (float)(6.0 * c->rho0);
 }
 
 void set_scales(lwacm_ctx *c)
@@ -210,6 +211,8 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
     size_t nb = lwacm::kGenericMaxBlocks;
     const size_t mb = lwacm::march_num_blocks(p);
     if (mb > nb) nb = mb;
+    const size_t ab = lwacm::adj_march_num_blocks(p);
+    if (ab > nb) nb = ab;
     c->n_partial_blocks = nb;
     hipError_t e = hipMalloc(&c->d_partials, 2 * nb * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->d_counter, sizeof(unsigned));
@@ -241,7 +244,7 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
             }
             c->n_fluid = scan[1];
         }
-        if (e == hipSuccess && lwacm::march_supported(p)) {
+        if (e == hipSuccess && (lwacm::march_supported(p) || lwacm::adj_march_supported(p))) {
             bool moving = false;
             for (int m = 1; m < lwacm::kMaxWallIds; ++m)
                 for (int k = 0; k < 3; ++k) moving = moving || p.wall_u[m][k] != 0.0f;
@@ -431,6 +434,9 @@ int lwacm_adjoint_step(lwacm_ctx *c, const void *d_state_t, const float *d_mu_in
     ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
     r.accumulate = 1;
     r.out_scale = 2.0 / (c->omega * c->omega);  // da/domega for a = 2 - 2/omega
+    if (c->variant != LWACM_KERNEL_GENERIC && lwacm::adj_march_supported(c->p))
+        return dev_err(lwacm::launch_adj_march(c->p, c->storage, d_state_t, d_mu_in, d_mu_out,
+                                               c->d_bits, c->d_wallg, final_t0, r, c->stream));
     return dev_err(lwacm::launch_adj_generic(c->p, c->storage, d_state_t, d_mu_in, d_mu_out,
                                              final_t0, r, lwacm::generic_grid(c->p.n), c->stream));
 }

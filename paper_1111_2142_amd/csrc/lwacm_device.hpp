@@ -42,6 +42,14 @@ __host__ __device__ constexpr int link_opp(int i)
     return t[i];
 }
 
+// Index of the D3Q19 link with velocity (cx, cy, cz), -1 if none.
+__host__ __device__ constexpr int link_index(int cx, int cy, int cz)
+{
+    for (int i = 0; i < 19; ++i)
+        if (link_cx(i) == cx && link_cy(i) == cy && link_cz(i) == cz) return i;
+    return -1;
+}
+
 template <int Q>
 struct Lattice;
 

@@ -59,6 +59,37 @@ __device__ __forceinline__ void load_state(const T *s, long long idx, const Prob
     u[2] = (D == 3) ? v[D] : 0.0f;
 }
 
+// The reverse sweep's mu (dL/dD, dL/dJ) between steps: node-interleaved
+// FP32, D+1 values per node (one 16-byte access in 3D).
+template <int D>
+__device__ __forceinline__ void load_mu(const float *mu, long long idx, float &r, float (&j)[3])
+{
+    if constexpr (D == 3) {
+        const float4 q = reinterpret_cast<const float4 *>(mu)[idx];
+        r = q.x;
+        j[0] = q.y;
+        j[1] = q.z;
+        j[2] = q.w;
+    } else {
+        r = mu[3 * idx];
+        j[0] = mu[3 * idx + 1];
+        j[1] = mu[3 * idx + 2];
+        j[2] = 0.0f;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void store_mu(float *mu, long long idx, float r, const float (&j)[3])
+{
+    if constexpr (D == 3) {
+        reinterpret_cast<float4 *>(mu)[idx] = make_float4(r, j[0], j[1], j[2]);
+    } else {
+        mu[3 * idx] = r;
+        mu[3 * idx + 1] = j[0];
+        mu[3 * idx + 2] = j[1];
+    }
+}
+
 template <int Q>
 __device__ __forceinline__ float vdot(int i, const float (&u)[3])
 {
@@ -182,8 +213,12 @@ __global__ __launch_bounds__(kGenericBlock) void k_adj_generic(ProblemArgs p, co
     for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
          idx += (long long)gridDim.x * blockDim.x) {
         if (MASK && p.mask[idx] != 0) {
-            mu_out[idx] = 0.0f;
-            for (int k = 0; k < D; ++k) mu_out[(k + 1) * n + idx] = 0.0f;
+            if (final_t0) {
+                for (int k = 0; k <= D; ++k) mu_out[k * n + idx] = 0.0f;
+            } else {
+                const float z[3] = {0.0f, 0.0f, 0.0f};
+                store_mu<D>(mu_out, idx, 0.0f, z);
+            }
             continue;
         }
         float dry, uy[3];
@@ -191,8 +226,8 @@ __global__ __launch_bounds__(kGenericBlock) void k_adj_generic(ProblemArgs p, co
         const float ry = 1.0f + dry;
         const float By = -1.5f * (uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2]);
         const Coord c = decompose(idx, p.nx, p.ny);
-        const float muR_y = mu_in[idx];
-        float muJ_y[3] = {mu_in[n + idx], mu_in[2 * n + idx], D == 3 ? mu_in[3 * n + idx] : 0.0f};
+        float muR_y, muJ_y[3];
+        load_mu<D>(mu_in, idx, muR_y, muJ_y);
         float lr = 0.0f, lu[3] = {0.0f, 0.0f, 0.0f}, da = 0.0f;
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
@@ -208,8 +243,9 @@ __global__ __launch_bounds__(kGenericBlock) void k_adj_generic(ProblemArgs p, co
                 const float wd[3] = {p.wall_da[wm][0], p.wall_da[wm][1], p.wall_da[wm][2]};
                 da = fmaf(L::w36(k) * (1.0f / 36.0f) * vdot<Q>(k, wd), m, da);
             } else {
-                float mt[3] = {mu_in[n + t], mu_in[2 * n + t], D == 3 ? mu_in[3 * n + t] : 0.0f};
-                m = mu_in[t] + vdot<Q>(k, mt);
+                float mr, mt[3];
+                load_mu<D>(mu_in, t, mr, mt);
+                m = mr + vdot<Q>(k, mt);
             }
             const float cc = vdot<Q>(k, uy);
             const float wm_ = L::w36(k) * (1.0f / 36.0f) * m;
@@ -235,6 +271,7 @@ __global__ __launch_bounds__(kGenericBlock) void k_adj_generic(ProblemArgs p, co
         }
         da = fmaf(ry, mJu, da);
         if (final_t0) {
+            // the gradient with respect to the initial state, field-major
             mu_out[idx] = lr;
 #pragma unroll
             for (int j = 0; j < D; ++j) mu_out[(j + 1) * n + idx] = lu[j];
@@ -244,9 +281,10 @@ __global__ __launch_bounds__(kGenericBlock) void k_adj_generic(ProblemArgs p, co
             float lu_u = 0.0f;
 #pragma unroll
             for (int j = 0; j < D; ++j) lu_u = fmaf(lu[j], uy[j], lu_u);
-            mu_out[idx] = lr - lu_u * inv;
+            float mj[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int j = 0; j < D; ++j) mu_out[(j + 1) * n + idx] = lu[j] * inv;
+            for (int j = 0; j < D; ++j) mj[j] = lu[j] * inv;
+            store_mu<D>(mu_out, idx, lr - lu_u * inv, mj);
         }
         acc[0] += (double)da;
     }
@@ -264,8 +302,9 @@ __global__ __launch_bounds__(kGenericBlock) void k_adj_seed(ProblemArgs p, const
     const long long n = p.n;
     for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
          idx += (long long)gridDim.x * blockDim.x) {
+        float mj[3] = {0.0f, 0.0f, 0.0f};
         if (p.mask && p.mask[idx] != 0) {
-            for (int k = 0; k <= D; ++k) mu[k * n + idx] = 0.0f;
+            store_mu<D>(mu, idx, 0.0f, mj);
             continue;
         }
         float dr, u[3];
@@ -273,8 +312,8 @@ __global__ __launch_bounds__(kGenericBlock) void k_adj_seed(ProblemArgs p, const
         const float inv = 1.0f / (1.0f + dr);
         float lu_u = 0.0f;
         for (int j = 0; j < D; ++j) lu_u = fmaf(lam[(j + 1) * n + idx], u[j], lu_u);
-        mu[idx] = lam[idx] - lu_u * inv;
-        for (int j = 0; j < D; ++j) mu[(j + 1) * n + idx] = lam[(j + 1) * n + idx] * inv;
+        for (int j = 0; j < D; ++j) mj[j] = lam[(j + 1) * n + idx] * inv;
+        store_mu<D>(mu, idx, lam[idx] - lu_u * inv, mj);
     }
 }
 

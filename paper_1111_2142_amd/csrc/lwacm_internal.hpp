@@ -21,6 +21,7 @@ struct ProblemArgs {
     float wall_da[kMaxWallIds][3];  // 6 * rho0 * u_w: minus d(wall_term)/da
     float wall_u[kMaxWallIds][3];   // wall velocities u_w per wall id (0 for fluid id 0)
     float wall_scale;               // (1 - a) * 6 * rho0: wall_term = wall_scale * u_w
+    float wall6rho0;                // 6 * rho0: wall_da = wall6rho0 * u_w
     float ld_scale[2];       // storage -> value: 2^-k (rho - 1, u); 1 for FP32
     float st_scale[2];       // value -> storage: 2^k
     int fp16_sr;             // FP16 storage: 1 stochastic rounding of step outputs, 0 nearest
@@ -63,6 +64,16 @@ unsigned march_num_blocks(const ProblemArgs &p);
 constexpr unsigned kMovingWallFlag = 1u << 31;  // in bits: node sees a moving wall
 hipError_t launch_classify(const ProblemArgs &p, uint8_t *cls, unsigned *bits, float4 *wallg,
                            hipStream_t s);
+// D3Q19 reverse step as a z-marching tile kernel (any mask, with or without
+// force); mu_in / mu_out node-interleaved, or field-major output when
+// final_t0.  Masked problems need the bit sets (and wallg for moving walls)
+// of launch_classify.
+bool adj_march_supported(const ProblemArgs &p);
+unsigned adj_march_num_blocks(const ProblemArgs &p);
+hipError_t launch_adj_march(const ProblemArgs &p, int storage, const void *state,
+                            const float *mu_in, float *mu_out, const unsigned *bits,
+                            const float4 *wallg, int final_t0, const ReduceArgs &r,
+                            hipStream_t stream);
 hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, void *dst,
                             const uint8_t *cls, const unsigned *bits, const float4 *wallg,
                             const ReduceArgs &r, hipStream_t stream);

@@ -65,6 +65,9 @@ def test_single_reverse_step_matches_oracle(case, final):
                        rho0=rho0)
     lr, lu, dwo = oracle.vjp(p, 1 + drho, u, lam[0], lam[1:])
     got = out.double().cpu().numpy()
+    if not final:
+        # mu between steps is node-interleaved: (mu_R, mu_J) of each node side by side
+        got = got.reshape(-1).reshape(nx * ny * nz, d + 1).T.reshape((d + 1,) + shape)
     if final:
         assert rel_l2(got[0], lr) < 1e-5
         assert rel_l2(got[1:], lu) < 1e-5
@@ -96,6 +99,129 @@ def _gpu_gradient(n, drho, u0, u_tgt, steps, K, omega):
     loss = ((u_T.double() - to_dev(u_tgt, torch.float64)) ** 2).sum()
     loss.backward()
     return loss.item(), u0_t.grad.double().cpu().numpy(), om.grad.item()
+
+
+def _march_case(case):
+    """Seeded one-step reverse-mode cases on grids the D3Q19 tile kernels take
+    (nx % 32 == 0, ny % 16 == 0), with ragged z chunks."""
+    rng = np.random.Generator(np.random.PCG64(41))
+    shape = {"periodic": (12, 16, 32), "walls_force": (40, 32, 64), "cavity": (34, 32, 32),
+             "ragged": (3, 16, 32)}[case]
+    nz, ny, nx = shape
+    mask = wall = g = None
+    if case == "walls_force":
+        mask = wl.slab_mask_3d(nx, ny, nz, moving_top=True)
+        wall = wl.wall_table((0.05, 0.0, 0.02))
+        g = (2e-3, -1e-3, 5e-4)
+    if case == "cavity":
+        mask = np.zeros(shape, dtype=np.uint8)
+        mask[0], mask[:, 0], mask[:, -1], mask[:, :, 0], mask[:, :, -1] = 1, 1, 1, 1, 1
+        mask[-1] = 2
+        wall = wl.wall_table((0.05, 0.01, 0.0))
+    drho, u = wl.random_state(shape, 3, seed=9, du=0.05, drho=0.02)
+    drho = drho.astype(np.float32).astype(np.float64)
+    u = u.astype(np.float32).astype(np.float64)
+    lam = rng.standard_normal((4,) + shape).astype(np.float32).astype(np.float64)
+    if mask is not None:
+        lam[:, mask != 0] = 0
+    return shape, mask, wall, g, drho, u, lam
+
+
+def _reverse_step(L, shape, mask, wall, g, drho, u, lam, final, variant, storage=0):
+    nz, ny, nx = shape
+    s = L.Solver(19, nx, ny, nz, 1.55, storage=storage,
+                 mask=None if mask is None else to_dev(mask, torch.uint8),
+                 wall_u=None if wall is None else [list(r) for r in wall], g=g, variant=variant)
+    s.set_state(to_dev(drho), to_dev(u))
+    st0 = s.save_state()
+    dr0, u0 = s.moments()  # the state as stored (FP16 storage rounds it)
+    s.step(1)
+    st1 = s.save_state()
+    mu = torch.empty((4,) + shape, dtype=torch.float32, device="cuda")
+    out = torch.empty_like(mu)
+    dw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    L.lwacm_adjoint_seed(s.ctx, st1, to_dev(lam), mu)
+    L.lwacm_adjoint_step(s.ctx, st0, mu, out, dw, final)
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    if not final:
+        got = got.reshape(-1).reshape(nx * ny * nz, 4).T.reshape((4,) + shape)
+    s.close()
+    return got, float(dw.item()), dr0.double().cpu().numpy(), u0.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("case", ["periodic", "walls_force", "cavity", "ragged"])
+@pytest.mark.parametrize("final", [True, False])
+def test_march_reverse_step_matches_oracle(case, final):
+    """The D3Q19 reverse tile kernel (one step) against the oracle's reverse
+    mode: cotangents of the inputs (or mu of the step before) and dL/domega."""
+    L = need_gpu()
+    banner(f"march reverse step {case} final={final}")
+    shape, mask, wall, g, drho, u, lam = _march_case(case)
+    nz, ny, nx = shape
+    got, dw, _, _ = _reverse_step(L, shape, mask, wall, g, drho, u, lam, final, L.LWACM_KERNEL_AUTO)
+    rho0 = 1.0 if mask is None else 1.0 + drho[mask == 0].mean()
+    p = oracle.Problem(q=19, nx=nx, ny=ny, nz=nz, omega=1.55, mask=mask, wall_u=wall, g=g,
+                       rho0=rho0)
+    lr, lu, dwo = oracle.vjp(p, 1 + drho, u, lam[0], lam[1:])
+    if final:
+        want_r, want_u = lr, lu
+    else:
+        inv = 1.0 / (1.0 + drho)
+        want_r = lr - (lu * u).sum(0) * inv
+        want_u = lu * inv
+        if mask is not None:
+            want_r[mask != 0] = 0
+            want_u[:, mask != 0] = 0
+    e_r, e_u = rel_l2(got[0], want_r), rel_l2(got[1:], want_u)
+    banner(f"march reverse {case} final={final}: rel-L2 {e_r:.2e} {e_u:.2e}, "
+           f"dL/domega {dw:.6e} vs {dwo:.6e}")
+    assert e_r < 1e-5 and e_u < 1e-5
+    assert abs(dw - dwo) <= 1e-5 * abs(dwo) + 1e-9
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+@pytest.mark.parametrize("case", ["walls_force", "cavity"])
+def test_march_reverse_step_matches_generic(case, storage):
+    """Tile and generic reverse kernels agree on the same stored states
+    (FP32 and FP16 storage)."""
+    L = need_gpu()
+    banner(f"march vs generic reverse {case} storage={storage}")
+    shape, mask, wall, g, drho, u, lam = _march_case(case)
+    a = _reverse_step(L, shape, mask, wall, g, drho, u, lam, False, L.LWACM_KERNEL_AUTO, storage)
+    b = _reverse_step(L, shape, mask, wall, g, drho, u, lam, False, L.LWACM_KERNEL_GENERIC, storage)
+    assert rel_l2(a[0], b[0]) < 2e-6
+    assert abs(a[1] - b[1]) <= 2e-6 * abs(b[1])
+
+
+def test_march_gradient_64_cubed_matches_oracle():
+    """A checkpointed 40-step D3Q19 gradient (64 x 32 x 16 periodic, seeded
+    random start, loss sum |u_T - u*|^2) through the tile kernels against the
+    oracle's reverse sweep."""
+    L = need_gpu()
+    from paper_1111_2142_amd.autograd import lwacm_run
+    banner("march gradient 64x32x16")
+    shape = (16, 32, 64)
+    nz, ny, nx = shape
+    drho, u0 = wl.random_state(shape, 3, seed=12, du=0.02, drho=0.005)
+    _, ut = wl.random_state(shape, 3, seed=13, du=0.02, drho=0.0)
+    drho = drho.astype(np.float32).astype(np.float64)
+    u0 = u0.astype(np.float32).astype(np.float64)
+    steps, K, omega = 40, 8, 1.6
+    d_t = to_dev(drho).requires_grad_(True)
+    u_t = to_dev(u0).requires_grad_(True)
+    w_t = torch.tensor(omega, dtype=torch.float64, requires_grad=True)
+    _, uT = lwacm_run(d_t, u_t, w_t, steps, L.LWACM_D3Q19, K=K)
+    loss = ((uT.double() - to_dev(ut, torch.float64)) ** 2).sum()
+    loss.backward()
+    p = oracle.Problem(q=19, nx=nx, ny=ny, nz=nz, omega=omega)
+    gr, gu, gw, _ = oracle.gradient(
+        p, 1 + drho, u0, steps, lambda r, uu: (np.zeros_like(r), 2 * (uu - ut)), K=K)
+    e_u = rel_l2(u_t.grad.double().cpu().numpy(), gu)
+    e_r = rel_l2(d_t.grad.double().cpu().numpy(), gr)
+    banner(f"march gradient: rel-L2 du0 {e_u:.3e} drho0 {e_r:.3e}, domega {float(w_t.grad):.6e} vs {gw:.6e}")
+    assert e_u < 1e-4 and e_r < 1e-4
+    assert abs(float(w_t.grad) - gw) < 1e-4 * abs(gw)
 
 
 def test_gradient_32_matches_oracle_and_finite_differences():
