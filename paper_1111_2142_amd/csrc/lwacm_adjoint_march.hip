@@ -17,8 +17,8 @@
 //
 // Design (gfx950).  A workgroup owns a 32 x 16 tile of columns and a chunk of
 // 32 planes, as the forward march kernel.  Every plane of mu (tile plus a
-// one-column halo ring, node-interleaved float4) passes once through a
-// rolling window of four LDS planes; each interior thread then reads its 18
+// one-column halo ring) passes once through a rolling window of four LDS
+// planes, its four components in separate arrays; each interior thread then reads its 18
 // neighbours' mu from the three planes around its own, accumulates the ten
 // moments with integer weights 36 w_k (pairs of opposite links share one
 // expansion), and finishes the node from its own state, which it loads
@@ -148,14 +148,16 @@ __device__ __forceinline__ void add_pair(Mom &M, float w36, float mp, float mm)
     if (DY && DZ) M.yz += (DY * DZ > 0) ? sp : -sp;
 }
 
-// m = mu_R + v . mu_J for a float4 (mu_R, mu_J) and link v
+// m = mu_R + v . mu_J of the node in window slot s, for link v.  The window
+// keeps mu_R, mu_Jx, mu_Jy, mu_Jz in separate arrays (4-byte lane stride,
+// no bank conflicts) and a link reads only the components it needs.
 template <int DX, int DY, int DZ>
-__device__ __forceinline__ float link_m(const float4 &q)
+__device__ __forceinline__ float link_m(const float (*W)[NSLOT], int s)
 {
-    float m = q.x;
-    if (DX) m = DX > 0 ? m + q.y : m - q.y;
-    if (DY) m = DY > 0 ? m + q.z : m - q.z;
-    if (DZ) m = DZ > 0 ? m + q.w : m - q.w;
+    float m = W[0][s];
+    if (DX) m = DX > 0 ? m + W[1][s] : m - W[1][s];
+    if (DY) m = DY > 0 ? m + W[2][s] : m - W[2][s];
+    if (DZ) m = DZ > 0 ? m + W[3][s] : m - W[3][s];
     return m;
 }
 
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_march(ProblemArgs p, const T *
                                                         const float4 *__restrict__ wallg,
                                                         int final_t0, ReduceArgs r)
 {
-    __shared__ float4 win[NWIN][NSLOT];
+    __shared__ float win[NWIN][4][NSLOT];
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -245,7 +247,10 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_march(ProblemArgs p, const T *
         // ---- mu of plane pz into window slot pz % NWIN (k-indexed: same order)
         if (active) {
             const f32x4 q = rmu_ring[rj];
-            win[k % NWIN][slot] = make_float4(q.x, q.y, q.z, q.w);
+            win[k % NWIN][0][slot] = q.x;
+            win[k % NWIN][1][slot] = q.y;
+            win[k % NWIN][2][slot] = q.z;
+            win[k % NWIN][3][slot] = q.w;
         }
         float cur_st[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (role == INTERIOR)
@@ -272,30 +277,21 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_march(ProblemArgs p, const T *
                 reinterpret_cast<float4 *>(mu_out)[idx] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
         } else if (role == INTERIOR && k >= 2 && tz < z1) {
-            const float4 *Wm = win[(k - 2) % NWIN];  // plane tz - 1
-            const float4 *W0 = win[(k - 1) % NWIN];  // plane tz
-            const float4 *Wp = win[k % NWIN];        // plane tz + 1
-            const float4 own = W0[slot];
-            // neighbours t = y + v_k
-            const float4 qE = W0[slot + 1], qW = W0[slot - 1];
-            const float4 qN = W0[slot + SX], qS = W0[slot - SX];
-            const float4 qNE = W0[slot + SX + 1], qSW = W0[slot - SX - 1];
-            const float4 qSE = W0[slot - SX + 1], qNW = W0[slot + SX - 1];
-            const float4 qU = Wp[slot], qD = Wm[slot];
-            const float4 qEU = Wp[slot + 1], qWD = Wm[slot - 1];
-            const float4 qED = Wm[slot + 1], qWU = Wp[slot - 1];
-            const float4 qNU = Wp[slot + SX], qSD = Wm[slot - SX];
-            const float4 qND = Wm[slot + SX], qSU = Wp[slot - SX];
-            // cotangents of the 18 moving links, (+v, -v) pairs
-            float m[18] = {link_m<1, 0, 0>(qE),   link_m<-1, 0, 0>(qW),
-                           link_m<0, 1, 0>(qN),   link_m<0, -1, 0>(qS),
-                           link_m<0, 0, 1>(qU),   link_m<0, 0, -1>(qD),
-                           link_m<1, 1, 0>(qNE),  link_m<-1, -1, 0>(qSW),
-                           link_m<1, -1, 0>(qSE), link_m<-1, 1, 0>(qNW),
-                           link_m<1, 0, 1>(qEU),  link_m<-1, 0, -1>(qWD),
-                           link_m<1, 0, -1>(qED), link_m<-1, 0, 1>(qWU),
-                           link_m<0, 1, 1>(qNU),  link_m<0, -1, -1>(qSD),
-                           link_m<0, 1, -1>(qND), link_m<0, -1, 1>(qSU)};
+            const float(*Wm)[NSLOT] = win[(k - 2) % NWIN];  // plane tz - 1
+            const float(*W0)[NSLOT] = win[(k - 1) % NWIN];  // plane tz
+            const float(*Wp)[NSLOT] = win[k % NWIN];        // plane tz + 1
+            const float4 own = make_float4(W0[0][slot], W0[1][slot], W0[2][slot], W0[3][slot]);
+            // cotangents of the 18 moving links from the neighbours t = y + v_k,
+            // in (+v, -v) pairs
+            float m[18] = {link_m<1, 0, 0>(W0, slot + 1),        link_m<-1, 0, 0>(W0, slot - 1),
+                           link_m<0, 1, 0>(W0, slot + SX),       link_m<0, -1, 0>(W0, slot - SX),
+                           link_m<0, 0, 1>(Wp, slot),            link_m<0, 0, -1>(Wm, slot),
+                           link_m<1, 1, 0>(W0, slot + SX + 1),   link_m<-1, -1, 0>(W0, slot - SX - 1),
+                           link_m<1, -1, 0>(W0, slot - SX + 1),  link_m<-1, 1, 0>(W0, slot + SX - 1),
+                           link_m<1, 0, 1>(Wp, slot + 1),        link_m<-1, 0, -1>(Wm, slot - 1),
+                           link_m<1, 0, -1>(Wm, slot + 1),       link_m<-1, 0, 1>(Wp, slot - 1),
+                           link_m<0, 1, 1>(Wp, slot + SX),       link_m<0, -1, -1>(Wm, slot - SX),
+                           link_m<0, 1, -1>(Wm, slot + SX),      link_m<0, -1, 1>(Wp, slot - SX)};
             unsigned bits = 0u;
             if (MASK) bits = bb_bits[(long long)tz * plane + col];
             if (MASK && bits != 0u) {

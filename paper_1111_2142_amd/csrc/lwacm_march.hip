@@ -69,10 +69,12 @@ static_assert(2 * TX <= kWave && 2 * (TY + 2) <= kWave, "halo rows must fit one 
 
 enum Role { INTERIOR = 0, HALO_Y = 1, HALO_X = 2 };
 
-// Exchange groups, one float4 per slot:
-//   G0 = (PE, ZE, PW, ZW)   links with (vx,vy) = (+1,0) and (-1,0): density and z parts
-//   G1 = (PN, ZN, PS, ZS)   (0,+1) and (0,-1)
-//   G2 = (NE, NW, SE, SW)   in-plane diagonals (+1,+1,0), (-1,+1,0), (+1,-1,0), (-1,-1,0)
+// Exchanged quantities per slot, in arrays of one kind each so that every
+// LDS access has a 4- or 8-byte lane stride (no bank conflicts):
+//   xp[0..3] = (PE, ZE), (PW, ZW), (PN, ZN), (PS, ZS): density and z parts of
+//              the links with (vx, vy) = (+1,0), (-1,0), (0,+1), (0,-1)
+//   xd[0..3] = NE, NW, SE, SW: in-plane diagonals (+1,+1,0), (-1,+1,0),
+//              (+1,-1,0), (-1,-1,0)
 
 // Per target plane accumulator of an interior column.
 // Compile-time loop: f(std::integral_constant<int, K>) for K = 0 .. N-1.
@@ -217,7 +219,8 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                                                         const float4 *__restrict__ wallg,
                                                         ReduceArgs r)
 {
-    __shared__ float4 xch[NBUF][3][NSLOT];
+    __shared__ float2 xp[NBUF][4][NSLOT];
+    __shared__ float xd[NBUF][4][NSLOT];
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -418,21 +421,27 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 if (k < 2) return;  // planes below the chunk are halo only
                 // ---- exchange the partials of plane pz - 1 through LDS
                 if (NBUF == 1 && k > 2) __syncthreads();  // previous plane's reads done
-                float4 *X = xch[k % NBUF][0];
-                X[0 * NSLOT + slot] = make_float4(Am.pe, Am.ze, Am.pw, Am.zw);
-                X[1 * NSLOT + slot] = make_float4(Am.pn, Am.zn, Am.ps, Am.zs);
-                X[2 * NSLOT + slot] = make_float4(Am.ne, Am.nw, Am.se, Am.sw);
+                float2(*P)[NSLOT] = xp[k % NBUF];
+                float(*Dg)[NSLOT] = xd[k % NBUF];
+                P[0][slot] = make_float2(Am.pe, Am.ze);
+                P[1][slot] = make_float2(Am.pw, Am.zw);
+                P[2][slot] = make_float2(Am.pn, Am.zn);
+                P[3][slot] = make_float2(Am.ps, Am.zs);
+                Dg[0][slot] = Am.ne;
+                Dg[1][slot] = Am.nw;
+                Dg[2][slot] = Am.se;
+                Dg[3][slot] = Am.sw;
                 __syncthreads();
-                const float4 gW = X[0 * NSLOT + slot - 1];   // west neighbour: PE, ZE
-                const float4 gE = X[0 * NSLOT + slot + 1];   // east neighbour: PW, ZW
-                const float4 gS = X[1 * NSLOT + slot - SX];  // south: PN, ZN
-                const float4 gN = X[1 * NSLOT + slot + SX];  // north: PS, ZS
-                const float dNE = X[2 * NSLOT + slot - SX - 1].x;
-                const float dNW = X[2 * NSLOT + slot - SX + 1].y;
-                const float dSE = X[2 * NSLOT + slot + SX - 1].z;
-                const float dSW = X[2 * NSLOT + slot + SX + 1].w;
-                const float pE = gW.x, zE = gW.y, pW = gE.z, zW = gE.w;
-                const float pN = gS.x, zN = gS.y, pS = gN.z, zS = gN.w;
+                const float2 gW = P[0][slot - 1];   // west neighbour: PE, ZE
+                const float2 gE = P[1][slot + 1];   // east neighbour: PW, ZW
+                const float2 gS = P[2][slot - SX];  // south: PN, ZN
+                const float2 gN = P[3][slot + SX];  // north: PS, ZS
+                const float dNE = Dg[0][slot - SX - 1];
+                const float dNW = Dg[1][slot - SX + 1];
+                const float dSE = Dg[2][slot + SX - 1];
+                const float dSW = Dg[3][slot + SX + 1];
+                const float pE = gW.x, zE = gW.y, pW = gE.x, zW = gE.y;
+                const float pN = gS.x, zN = gS.y, pS = gN.x, zS = gN.y;
 
                 const int tz = pz - 1;
                 if (tz >= z1) return;  // padding iteration: nothing to finalise
@@ -538,24 +547,22 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 hz[jm] -= Ldn;
                 if (k < 2) return;
                 if (NBUF == 1 && k > 2) __syncthreads();
-                float *Xf = reinterpret_cast<float *>(xch[k % NBUF][0]);
+                float2(*P)[NSLOT] = xp[k % NBUF];
+                float(*Dg)[NSLOT] = xd[k % NBUF];
                 if (active) {
-                    const int off = sgn > 0.0f ? 0 : 2;
+                    const int hi = sgn > 0.0f ? 0 : 1;
                     if (role == HALO_Y) {
-                        // G1: (PN, ZN) below the tile or (PS, ZS) above it;
-                        // G2: (NE, NW) below or (SE, SW) above
-                        *reinterpret_cast<float2 *>(&Xf[4 * (1 * NSLOT + slot) + off]) =
-                            make_float2(hp[jm], hz[jm]);
-                        *reinterpret_cast<float2 *>(&Xf[4 * (2 * NSLOT + slot) + off]) =
-                            make_float2(hd1[jm], hd2[jm]);
+                        // (PN, ZN) below the tile or (PS, ZS) above it;
+                        // diagonals (NE, NW) below or (SE, SW) above
+                        P[2 + hi][slot] = make_float2(hp[jm], hz[jm]);
+                        Dg[2 * hi][slot] = hd1[jm];
+                        Dg[2 * hi + 1][slot] = hd2[jm];
                     } else {
-                        // G0: (PE, ZE) left of the tile or (PW, ZW) right of it;
-                        // G2: NE, SE (left) or NW, SW (right)
-                        *reinterpret_cast<float2 *>(&Xf[4 * (0 * NSLOT + slot) + off]) =
-                            make_float2(hp[jm], hz[jm]);
-                        const int doff = sgn > 0.0f ? 0 : 1;
-                        Xf[4 * (2 * NSLOT + slot) + doff] = hd1[jm];      // (sgn, +1, 0)
-                        Xf[4 * (2 * NSLOT + slot) + doff + 2] = hd2[jm];  // (sgn, -1, 0)
+                        // (PE, ZE) left of the tile or (PW, ZW) right of it;
+                        // diagonals NE, SE (left) or NW, SW (right)
+                        P[hi][slot] = make_float2(hp[jm], hz[jm]);
+                        Dg[hi][slot] = hd1[jm];      // (sgn, +1, 0)
+                        Dg[hi + 2][slot] = hd2[jm];  // (sgn, -1, 0)
                     }
                 }
                 __syncthreads();
