@@ -153,8 +153,8 @@ def main():
                      "traffic": None, "kernel": None, "algorithmic_bytes": int(bytes32)},
     }
     if n == 256 and args.variant in (0, 2):
-        result["roofline"]["kernel"] = "k_fwd_march<float,false>"
-        result["roofline"]["traffic"] = _measured_traffic("k_fwd_march<float,false>")
+        result["roofline"]["kernel"] = "k_fwd_march<float,false,128>"
+        result["roofline"]["traffic"] = _measured_traffic("k_fwd_march<float,false,128>")
     if args.forward_only:
         print(json.dumps(result), flush=True)
         return

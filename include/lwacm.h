@@ -131,6 +131,13 @@ int lwacm_set_fp16_rounding(lwacm_ctx *c, int mode, uint32_t seed);
  * cannot run this problem. */
 int lwacm_set_variant(lwacm_ctx *c, int variant);
 
+/* Planes per workgroup of the forward D3Q19 tile kernel: 32, 64 or 128
+ * (LWACM_EINVAL otherwise; LWACM_EUNSUPPORTED if the tile kernel cannot run
+ * this problem).  lwacm_init picks the depth that minimises the plane steps
+ * per compute unit, ceil(workgroups / CUs) * (depth + 2); this call
+ * overrides it (tuning, tests).  Results do not depend on the depth. */
+int lwacm_set_march_chunk(lwacm_ctx *c, int planes);
+
 /* Load the state from FP32 fields (rho - 1 and u, SoA), converting to the
  * storage format, and set rho0 (the mean fluid density used by moving walls,
  * Section 3.2) to the mean of 1 + d_drho over fluid nodes.  Resets the step

@@ -16,7 +16,7 @@
 //     dL/da       = -3 rho u.M1 + rho mu_J(y).u  (+ the moving-wall term).
 //
 // Design (gfx950).  A workgroup owns a 32 x 16 tile of columns and a chunk of
-// 32 planes, as the forward march kernel.  Every plane of mu (tile plus a
+// 64 planes, as the forward march kernel.  Every plane of mu (tile plus a
 // one-column halo ring) passes once through a rolling window of four LDS
 // planes, its four components in separate arrays; each interior thread then reads its 18
 // neighbours' mu from the three planes around its own, accumulates the ten
@@ -36,10 +36,16 @@ namespace lwacm {
 
 namespace {
 
+#ifndef LWACM_ADJ_NZC
+#define LWACM_ADJ_NZC 64
+#endif
+#ifndef LWACM_ADJ_RING
+#define LWACM_ADJ_RING 2
+#endif
 constexpr int TX = 32;
 constexpr int TY = 16;
-constexpr int NZC = 32;
-constexpr int RING = 3;                     // planes of loads in flight per thread
+constexpr int NZC = LWACM_ADJ_NZC;          // planes per workgroup
+constexpr int RING = LWACM_ADJ_RING;        // planes of loads in flight per thread
 constexpr int NWIN = 4;                     // LDS window planes
 constexpr int NINT = TX * TY;
 constexpr int NTHREADS = NINT + 2 * kWave;  // + Y-halo wave + X-halo wave

@@ -208,6 +208,13 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
     set_scales(c);
     set_wall_terms(c);
 
+    if (lwacm::march_supported(p)) {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 256;
+        p.march_nzc = lwacm::march_choose_nzc(p, ncu);
+    }
     size_t nb = lwacm::kGenericMaxBlocks;
     const size_t mb = lwacm::march_num_blocks(p);
     if (mb > nb) nb = mb;
@@ -283,6 +290,19 @@ int lwacm_set_fp16_rounding(lwacm_ctx *c, int mode, uint32_t seed)
     if (!c || (mode != LWACM_ROUND_NEAREST && mode != LWACM_ROUND_STOCHASTIC)) return LWACM_EINVAL;
     c->p.fp16_sr = mode == LWACM_ROUND_STOCHASTIC;
     c->sr_seed = seed;
+    return LWACM_OK;
+}
+
+int lwacm_set_march_chunk(lwacm_ctx *c, int planes)
+{
+    if (!c || (planes != 32 && planes != 64 && planes != 128)) return LWACM_EINVAL;
+    if (!lwacm::march_supported(c->p)) return LWACM_EUNSUPPORTED;
+    const int keep = c->p.march_nzc;
+    c->p.march_nzc = planes;
+    if (lwacm::march_num_blocks(c->p) > c->n_partial_blocks) {  // reduction scratch too small
+        c->p.march_nzc = keep;
+        return LWACM_EUNSUPPORTED;
+    }
     return LWACM_OK;
 }
 

@@ -27,6 +27,7 @@ struct ProblemArgs {
     int fp16_sr;             // FP16 storage: 1 stochastic rounding of step outputs, 0 nearest
     uint32_t sr_word;        // fourth pcg4d input of this step: t ^ seed
     const uint8_t *mask;     // nullptr: all fluid
+    int march_nzc;           // planes per workgroup of the forward tile kernel (0: unused)
 };
 
 // Scratch for the fixed-order grid reductions.
@@ -58,7 +59,8 @@ hipError_t launch_mask_scan(const ProblemArgs &p, unsigned *d_out2, hipStream_t 
 // classes and solid-upstream bit sets made by launch_classify (n bytes and
 // n unsigned).  Returns hipErrorNotSupported if the problem does not fit.
 bool march_supported(const ProblemArgs &p);
-unsigned march_num_blocks(const ProblemArgs &p);
+int march_choose_nzc(const ProblemArgs &p, int ncu);  // chunk depth for a device of ncu CUs
+unsigned march_num_blocks(const ProblemArgs &p);       // uses p.march_nzc
 // Moving walls also need a per-node float4 of geometry sums (wallg, n
 // entries; may be null when every wall is at rest).
 constexpr unsigned kMovingWallFlag = 1u << 31;  // in bits: node sees a moving wall

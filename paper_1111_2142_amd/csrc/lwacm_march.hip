@@ -42,9 +42,6 @@ namespace lwacm {
 
 namespace {
 
-#ifndef LWACM_MARCH_NZC
-#define LWACM_MARCH_NZC 32
-#endif
 #ifndef LWACM_MARCH_NBUF
 #define LWACM_MARCH_NBUF 2
 #endif
@@ -53,7 +50,9 @@ namespace {
 #endif
 constexpr int TX = 32;                // tile width (x, contiguous in memory)
 constexpr int TY = 16;                // tile height (y)
-constexpr int NZC = LWACM_MARCH_NZC;  // planes per workgroup (plane loop fully unrolled)
+// Planes per workgroup: a template parameter (the plane loop is fully
+// unrolled), chosen per problem among kChunkDepths by march_choose_nzc().
+constexpr int kChunkDepths[3] = {32, 64, 128};
 // LDS exchange buffers: 2 = one barrier per plane; 1 = half the LDS (more
 // workgroups per CU) at the cost of a second barrier per plane.
 constexpr int NBUF = LWACM_MARCH_NBUF;
@@ -211,7 +210,7 @@ __device__ __forceinline__ float lterm(float c, float E0, float r45, float rA)
     return fmaf(rA, c, fmaf(r45 * c, c, E0));
 }
 
-template <class T, bool MASK>
+template <class T, bool MASK, int NZC>
 __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *__restrict__ src,
                                                         T *__restrict__ dst,
                                                         const uint8_t *__restrict__ cls_arr,
@@ -645,10 +644,18 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
     const unsigned nb = march_num_blocks(p);
     const T *a = static_cast<const T *>(src);
     T *b = static_cast<T *>(dst);
-    if (p.mask)
-        k_fwd_march<T, true><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
-    else
-        k_fwd_march<T, false><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
+#define LWACM_LAUNCH(Z)                                                                   \
+    if (p.mask)                                                                           \
+        k_fwd_march<T, true, Z><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);    \
+    else                                                                                  \
+        k_fwd_march<T, false, Z><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
+    switch (p.march_nzc) {
+    case 32: LWACM_LAUNCH(32) break;
+    case 64: LWACM_LAUNCH(64) break;
+    case 128: LWACM_LAUNCH(128) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef LWACM_LAUNCH
     return hipGetLastError();
 }
 
@@ -661,12 +668,35 @@ bool march_supported(const ProblemArgs &p)
            p.ny % TY == 0 && p.nz >= 1 && p.n < (1LL << 28);
 }
 
+static long long march_blocks_for(const ProblemArgs &p, int nzc)
+{
+    const long long tiles = (long long)(p.nx / TX) * (p.ny / TY);
+    return tiles * ((p.nz + nzc - 1) / nzc);
+}
+
+int march_choose_nzc(const ProblemArgs &p, int ncu)
+{
+    // Per-CU work: the workgroups a CU receives run one after the other or
+    // share it, so the step time follows ceil(blocks / CUs) * (chunk planes +
+    // the two halo planes).  Ties go to the deeper chunk (fewer halo planes).
+    if (ncu < 1) ncu = 1;
+    int best = kChunkDepths[0];
+    long long best_cost = -1;
+    for (int c : kChunkDepths) {
+        const long long nb = march_blocks_for(p, c);
+        const long long cost = ((nb + ncu - 1) / ncu) * (c + 2);
+        if (best_cost < 0 || cost <= best_cost) {
+            best = c;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
 unsigned march_num_blocks(const ProblemArgs &p)
 {
-    if (!march_supported(p)) return 0;
-    const long long tiles = (long long)(p.nx / TX) * (p.ny / TY);
-    const long long chunks = (p.nz + NZC - 1) / NZC;
-    return (unsigned)(tiles * chunks);
+    if (!march_supported(p) || p.march_nzc <= 0) return 0;
+    return (unsigned)march_blocks_for(p, p.march_nzc);
 }
 
 hipError_t launch_classify(const ProblemArgs &p, uint8_t *cls, unsigned *bits, float4 *wallg,

@@ -50,6 +50,7 @@ def load_library():
         "lwacm_set_fp16_scales": (i, [_vp, i, i]),
         "lwacm_set_fp16_rounding": (i, [_vp, i, ctypes.c_uint32]),
         "lwacm_set_variant": (i, [_vp, i]),
+        "lwacm_set_march_chunk": (i, [_vp, i]),
         "lwacm_set_state": (i, [_vp, _vp, _vp]),
         "lwacm_step": (i, [_vp, i]),
         "lwacm_diagnostics": (i, [_vp, dp, dp]),
@@ -123,6 +124,10 @@ def lwacm_set_fp16_scales(ctx, k_rho: int, k_u: int):
 def lwacm_set_fp16_rounding(ctx, mode: int, seed: int = 0):
     _check(load_library().lwacm_set_fp16_rounding(ctx, mode, seed & 0xFFFFFFFF),
            "lwacm_set_fp16_rounding")
+
+
+def lwacm_set_march_chunk(ctx, planes: int):
+    _check(load_library().lwacm_set_march_chunk(ctx, planes), "lwacm_set_march_chunk")
 
 
 def lwacm_set_variant(ctx, variant: int):

@@ -111,3 +111,56 @@ def test_march_rejects_unsupported_shape():
     with pytest.raises(L.LWACMError) as ei:
         L.lwacm_set_variant(s.ctx, MARCH)
     assert ei.value.code == L.LWACM_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("masked", [False, True])
+@pytest.mark.parametrize("storage", [0, 1])
+def test_march_chunk_depths_agree_bitwise(masked, storage):
+    """Every chunk depth of the tile kernel (32, 64, 128 planes per workgroup)
+    on a grid that is ragged for all of them (150 planes) gives bitwise the
+    same fields; depth 128 also matches the oracle."""
+    L = need_gpu()
+    shape = (150, 32, 64)
+    nz, ny, nx = shape
+    banner(f"march chunk depths masked={masked} storage={storage}")
+    drho, u = wl.random_state(shape, 3, seed=21, du=0.03, drho=0.01)
+    mask = wall = None
+    if masked:
+        mask = np.zeros(shape, dtype=np.uint8)
+        mask[0], mask[:, 0], mask[:, :, 0] = 1, 1, 1
+        mask[-1] = 2
+        wall = wl.wall_table((0.04, 0.01, 0.0))
+    outs = []
+    for planes in (32, 64, 128):
+        s = L.Solver(19, nx, ny, nz, 1.7, storage=storage, variant=MARCH,
+                     mask=None if mask is None else to_dev(mask, torch.uint8),
+                     wall_u=None if wall is None else [list(r) for r in wall])
+        L.lwacm_set_march_chunk(s.ctx, planes)
+        s.set_state(to_dev(drho), to_dev(u))
+        s.step(5)
+        dr, uu = s.moments()
+        outs.append((dr.cpu().numpy(), uu.cpu().numpy()))
+        s.close()
+    for dr, uu in outs[1:]:
+        assert np.array_equal(dr, outs[0][0]) and np.array_equal(uu, outs[0][1])
+    if storage == 0:
+        rdr, ru = oracle_run(19, shape, 1.7, drho.astype(np.float32).astype(np.float64),
+                             u.astype(np.float32).astype(np.float64), 5, mask=mask, wall_u=wall,
+                             rho0=1.0 if mask is None else
+                             1.0 + drho[mask == 0].astype(np.float32).astype(np.float64).mean())
+        fl = fluid_of(mask, shape)
+        err = rel_l2(outs[2][1].astype(np.float64)[:, fl], ru[:, fl])
+        banner(f"chunk 128 vs oracle: rel-L2 u {err:.3e}")
+        assert err < 1e-5
+
+
+def test_march_chunk_rejects_bad_depth():
+    L = need_gpu()
+    s = L.Solver(19, 32, 16, 8, 1.7)
+    with pytest.raises(L.LWACMError):
+        L.lwacm_set_march_chunk(s.ctx, 48)
+    s.close()
+    s = L.Solver(19, 20, 16, 8, 1.7)   # nx not a multiple of 32: no tile kernel
+    with pytest.raises(L.LWACMError):
+        L.lwacm_set_march_chunk(s.ctx, 64)
+    s.close()
