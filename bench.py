@@ -66,6 +66,8 @@ def main():
                     help="time only the forward step of the 256^3 workload (for profiler runs)")
     ap.add_argument("--storage", choices=["fp32", "fp16"], default="fp32",
                     help="storage of the --forward-only run")
+    ap.add_argument("--reverse-only", action="store_true",
+                    help="time only the reverse (adjoint) step of the 256^3 workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of 256 MiB (the reference kernel for "
                          "scaling HBM byte counters) and exit")
@@ -108,6 +110,29 @@ def main():
                      variant=args.variant, fp16_rounding=(rounding, 0))
         s.set_state(drho_t, u_t)
         return s
+
+    if args.reverse_only:
+        s = make(L.LWACM_FP32)
+        s.step(2)
+        st = s.save_state()
+        mu_a = torch.zeros((4, n, n, n), dtype=torch.float32, device=dev)
+        mu_b = torch.zeros_like(mu_a)
+        lam = torch.zeros_like(mu_a)
+        lam[1:] = u_t
+        dw = torch.zeros(1, dtype=torch.float64, device=dev)
+        L.lwacm_adjoint_seed(s.ctx, st, lam, mu_a)
+
+        def rev(k):
+            a_, b_ = mu_a, mu_b
+            for _ in range(k):
+                L.lwacm_adjoint_step(s.ctx, st, a_, b_, dw, False)
+                a_, b_ = b_, a_
+
+        rev(args.warmup)
+        dt = _events_time(rev, args.steps, stream)
+        print(f"[bench] reverse step: {dt / args.steps * 1e3:.4f} ms/step", file=sys.stderr,
+              flush=True)
+        return
 
     if args.forward_only and args.storage == "fp16":
         s16 = make(L.LWACM_FP16_DEV)
@@ -176,7 +201,10 @@ def main():
     result["fp16_store"] = {"value": round(mlups16, 1), "unit": "MLUPS",
                             "ms_per_step": round(ms16, 5), "rounding": "stochastic (pcg4d)",
                             "achieved_GBs": round(16.0 * nodes / dt16 * args.steps / 1e9, 1),
-                            "ms_per_step_nearest_rounding": round(dt16n / args.steps * 1e3, 5)}
+                            "ms_per_step_nearest_rounding": round(dt16n / args.steps * 1e3, 5),
+                            "kernel": "k_fwd_march<__half,false,128>" if n == 256 else None,
+                            "traffic": _measured_traffic("k_fwd_march<__half,false,128>")
+                            if n == 256 else None}
 
     # ---- reverse step at the same size (reads state_t and mu_t, writes mu_{t-1})
     st = s32.save_state()
@@ -201,7 +229,10 @@ def main():
     result["adjoint"] = {"ms_per_step": round(msa, 5),
                          "adjoint_forward_ratio": round(msa / ms32, 3),
                          "with_recompute_ratio": round((msa + ms32) / ms32, 3),
-                         "achieved_GBs": round(48.0 * nodes / (msa * 1e-3) / 1e9, 1)}
+                         "achieved_GBs": round(48.0 * nodes / (msa * 1e-3) / 1e9, 1),
+                         "kernel": "k_adj_march<float,false>" if n == 256 else None,
+                         "traffic": _measured_traffic("k_adj_march<float,false>")
+                         if n == 256 else None}
     s32.close()
     del mu_a, mu_b, lam, st
     torch.cuda.empty_cache()
