@@ -378,10 +378,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_march(ProblemArgs p, const T *
     });
 
     double v[1] = {(double)da};
-    double tot[1];
-    if (grid_sum_last_block<1>(v, r.partials, r.counter, gridDim.x, blockIdx.x, tot) &&
-        threadIdx.x == 0)
-        r.out[0] += tot[0] * r.out_scale;
+    store_block_partials<1>(v, r.partials, blockIdx.x);
 }
 
 template <class T>
@@ -418,8 +415,10 @@ hipError_t launch_adj_march(const ProblemArgs &p, int storage, const void *state
                             hipStream_t stream)
 {
     if (!adj_march_supported(p) || (p.mask && !bits)) return hipErrorNotSupported;
-    return storage ? dispatch<__half>(p, state, mu_in, mu_out, bits, wallg, final_t0, r, stream)
-                   : dispatch<float>(p, state, mu_in, mu_out, bits, wallg, final_t0, r, stream);
+    const hipError_t e =
+        storage ? dispatch<__half>(p, state, mu_in, mu_out, bits, wallg, final_t0, r, stream)
+                : dispatch<float>(p, state, mu_in, mu_out, bits, wallg, final_t0, r, stream);
+    return e != hipSuccess ? e : launch_reduce(r, 1, adj_march_num_blocks(p), stream);
 }
 
 }  // namespace lwacm

@@ -31,7 +31,6 @@ struct lwacm_ctx {
     hipStream_t stream;
     double *d_partials;
     size_t n_partial_blocks;
-    unsigned *d_counter;
     double *d_diag;     // [2] mass deviation, energy of the last step's output
     double *d_scratch;  // [2] for lwacm_moments
     unsigned *d_scan;   // [2] mask scan
@@ -83,7 +82,6 @@ ReduceArgs reduce_args(lwacm_ctx *c, double *out, double *out2)
 {
     ReduceArgs r;
     r.partials = c->d_partials;
-    r.counter = c->d_counter;
     r.out = out;
     r.out2 = out2;
     r.accumulate = 0;
@@ -105,7 +103,6 @@ bool use_march(const lwacm_ctx *c)
 void free_scratch(lwacm_ctx *c)
 {
     if (c->d_partials) (void)hipFree(c->d_partials);
-    if (c->d_counter) (void)hipFree(c->d_counter);
     if (c->d_diag) (void)hipFree(c->d_diag);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     if (c->d_scan) (void)hipFree(c->d_scan);
@@ -116,7 +113,6 @@ void free_scratch(lwacm_ctx *c)
     c->d_bits = nullptr;
     c->d_wallg = nullptr;
     c->d_partials = nullptr;
-    c->d_counter = nullptr;
     c->d_diag = c->d_scratch = nullptr;
     c->d_scan = nullptr;
 }
@@ -222,7 +218,6 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
     if (ab > nb) nb = ab;
     c->n_partial_blocks = nb;
     hipError_t e = hipMalloc(&c->d_partials, 2 * nb * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&c->d_counter, sizeof(unsigned));
     if (e == hipSuccess) e = hipMalloc(&c->d_diag, 2 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->d_scratch, 2 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->d_scan, 2 * sizeof(unsigned));
@@ -231,8 +226,7 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
         delete c;
         return LWACM_ENOMEM;
     }
-    e = hipMemsetAsync(c->d_counter, 0, sizeof(unsigned), stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d_diag, 0, 2 * sizeof(double), stream);
+    e = hipMemsetAsync(c->d_diag, 0, 2 * sizeof(double), stream);
 
     c->n_fluid = (unsigned long long)p.n;
     if (e == hipSuccess && d_mask) {

@@ -167,6 +167,19 @@ __device__ __forceinline__ unsigned short half_bits_sr(float y, uint32_t r)
     return __half_as_ushort(__float2half_rn(__uint_as_float(mag | (b & 0x80000000u))));
 }
 
+// Wait states after a buffer store whose offset comes from an SGPR.  This
+// compiler assumes such a store needs none before its data registers are
+// rewritten; on gfx950 the trailing lanes of a wide store then pick up the
+// next instruction's results (observed as corrupted nodes in the last plane
+// of a tile kernel's chunk).  Two wait states, fenced by scheduling barriers
+// so that nothing moves between the store and the nops.
+__device__ __forceinline__ void store_data_guard()
+{
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_nop 1");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // ------------------------------------------------------- storage formats
 // The state is node-interleaved: node idx holds its NF = D + 1 values
 // (rho - 1, u_x, u_y[, u_z]) at elements NF * idx .. NF * idx + NF - 1, so a
@@ -295,44 +308,19 @@ __device__ __forceinline__ void block_sum(double (&v)[NV])
     __syncthreads();
 }
 
-// Grid-wide sum of NV doubles per block.  Each block stores its block sum in
-// partials[NV*bid + k]; the block that finishes last (counted with an
-// agent-scope atomic) adds all partials in a fixed order, so the result does
-// not depend on scheduling.  Returns true in every thread of that last block;
-// thread 0 of it then holds the totals in `out` and has reset the counter.
+// Deterministic grid-wide sums, first pass: each block stores the fixed-tree
+// sum of its NV doubles in partials[NV * bid + k]; a second, one-block kernel
+// (k_reduce_partials) adds the partials in a fixed order.  The kernel
+// boundary makes the partials visible, so no device-scope fences are needed:
+// on this chip such a fence writes back and invalidates the whole L2 of an
+// XCD, once per block.
 template <int NV>
-__device__ bool grid_sum_last_block(double (&v)[NV], double *partials, unsigned *counter,
-                                    unsigned nblocks, unsigned bid, double (&out)[NV])
+__device__ __forceinline__ void store_block_partials(double (&v)[NV], double *partials, unsigned bid)
 {
-    __shared__ unsigned s_last;
     block_sum<NV>(v);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
 #pragma unroll
-        for (int k = 0; k < NV; ++k)
-            __hip_atomic_store(&partials[(size_t)NV * bid + k], v[k], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        unsigned prev = atomicAdd(counter, 1u);
-        s_last = (prev == nblocks - 1) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
-    double acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    for (unsigned b = threadIdx.x; b < nblocks; b += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < NV; ++k)
-            acc[k] += __hip_atomic_load(&partials[(size_t)NV * b + k], __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-    block_sum<NV>(acc);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) out[k] = acc[k];
-        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return true;
+        for (int k = 0; k < NV; ++k) partials[(size_t)NV * bid + k] = v[k];
 }
 
 }  // namespace lwacm

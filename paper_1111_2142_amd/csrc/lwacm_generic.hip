@@ -188,16 +188,7 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
         acc[0] += (double)Dsum;
         acc[1] += 0.5 * (double)e;
     }
-    double tot[2];
-    if (grid_sum_last_block<2>(acc, r.partials, r.counter, gridDim.x, blockIdx.x, tot) &&
-        threadIdx.x == 0) {
-        r.out[0] = tot[0];
-        r.out[1] = tot[1];
-        if (r.out2) {
-            r.out2[0] = tot[0];
-            r.out2[1] = tot[1];
-        }
-    }
+    store_block_partials<2>(acc, r.partials, blockIdx.x);
 }
 
 template <int Q, class T, bool MASK>
@@ -288,10 +279,7 @@ __global__ __launch_bounds__(kGenericBlock) void k_adj_generic(ProblemArgs p, co
         }
         acc[0] += (double)da;
     }
-    double tot[1];
-    if (grid_sum_last_block<1>(acc, r.partials, r.counter, gridDim.x, blockIdx.x, tot) &&
-        threadIdx.x == 0)
-        r.out[0] += tot[0] * r.out_scale;
+    store_block_partials<1>(acc, r.partials, blockIdx.x);
 }
 
 template <int D, class T>
@@ -352,12 +340,7 @@ __global__ __launch_bounds__(kGenericBlock) void k_moments(ProblemArgs p, const 
         acc[0] += (double)dr;
         acc[1] += 0.5 * (double)e;
     }
-    double tot[2];
-    if (grid_sum_last_block<2>(acc, r.partials, r.counter, gridDim.x, blockIdx.x, tot) &&
-        threadIdx.x == 0) {
-        r.out[0] = tot[0];
-        r.out[1] = tot[1];
-    }
+    store_block_partials<2>(acc, r.partials, blockIdx.x);
 }
 
 // Largest mask value and number of fluid nodes (integer atomics: exact).
@@ -422,27 +405,69 @@ hipError_t adj_dispatch(const ProblemArgs &p, const void *state, const float *mu
     return hipGetLastError();
 }
 
+// Second pass of the grid reductions: one block adds the NV partial sums of
+// nblocks blocks in a fixed order (strided per thread, then a fixed tree).
+template <int NV>
+__global__ __launch_bounds__(kGenericBlock) void k_reduce_partials(ReduceArgs r, unsigned nblocks)
+{
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (unsigned b = threadIdx.x; b < nblocks; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] += r.partials[(size_t)NV * b + k];
+    block_sum<NV>(acc);
+    if (threadIdx.x == 0) {
+        if (r.accumulate) {
+            r.out[0] += acc[0] * r.out_scale;
+        } else {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) acc[k] *= r.out_scale;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                r.out[k] = acc[k];
+                if (r.out2) r.out2[k] = acc[k];
+            }
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_reduce(const ReduceArgs &r, int nv, unsigned nblocks, hipStream_t s)
+{
+    if (nv == 1)
+        k_reduce_partials<1><<<1, kGenericBlock, 0, s>>>(r, nblocks);
+    else
+        k_reduce_partials<2><<<1, kGenericBlock, 0, s>>>(r, nblocks);
+    return hipGetLastError();
+}
 
 hipError_t launch_fwd_generic(const ProblemArgs &p, int storage, bool force, const void *src,
                               void *dst, const ReduceArgs &r, unsigned nb, hipStream_t s)
 {
+    hipError_t e;
     if (p.Q == 9)
-        return storage ? fwd_dispatch<9, __half>(p, force, src, dst, r, nb, s)
-                       : fwd_dispatch<9, float>(p, force, src, dst, r, nb, s);
-    return storage ? fwd_dispatch<19, __half>(p, force, src, dst, r, nb, s)
-                   : fwd_dispatch<19, float>(p, force, src, dst, r, nb, s);
+        e = storage ? fwd_dispatch<9, __half>(p, force, src, dst, r, nb, s)
+                    : fwd_dispatch<9, float>(p, force, src, dst, r, nb, s);
+    else
+        e = storage ? fwd_dispatch<19, __half>(p, force, src, dst, r, nb, s)
+                    : fwd_dispatch<19, float>(p, force, src, dst, r, nb, s);
+    return e != hipSuccess ? e : launch_reduce(r, 2, nb, s);
 }
 
 hipError_t launch_adj_generic(const ProblemArgs &p, int storage, const void *state,
                               const float *mu_in, float *mu_out, int final_t0,
                               const ReduceArgs &r, unsigned nb, hipStream_t s)
 {
+    hipError_t e;
     if (p.Q == 9)
-        return storage ? adj_dispatch<9, __half>(p, state, mu_in, mu_out, final_t0, r, nb, s)
-                       : adj_dispatch<9, float>(p, state, mu_in, mu_out, final_t0, r, nb, s);
-    return storage ? adj_dispatch<19, __half>(p, state, mu_in, mu_out, final_t0, r, nb, s)
-                   : adj_dispatch<19, float>(p, state, mu_in, mu_out, final_t0, r, nb, s);
+        e = storage ? adj_dispatch<9, __half>(p, state, mu_in, mu_out, final_t0, r, nb, s)
+                    : adj_dispatch<9, float>(p, state, mu_in, mu_out, final_t0, r, nb, s);
+    else
+        e = storage ? adj_dispatch<19, __half>(p, state, mu_in, mu_out, final_t0, r, nb, s)
+                    : adj_dispatch<19, float>(p, state, mu_in, mu_out, final_t0, r, nb, s);
+    return e != hipSuccess ? e : launch_reduce(r, 1, nb, s);
 }
 
 hipError_t launch_adj_seed(const ProblemArgs &p, int storage, const void *state,
@@ -495,7 +520,8 @@ hipError_t launch_moments(const ProblemArgs &p, int storage, const void *src, fl
         else
             k_moments<3, float><<<nb, kGenericBlock, 0, s>>>(p, (const float *)src, drho, u, r);
     }
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch_reduce(r, 2, nb, s);
 }
 
 hipError_t launch_mask_scan(const ProblemArgs &p, unsigned *d_out2, hipStream_t s)

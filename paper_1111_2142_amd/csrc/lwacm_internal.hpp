@@ -30,15 +30,18 @@ struct ProblemArgs {
     int march_nzc;           // planes per workgroup of the forward tile kernel (0: unused)
 };
 
-// Scratch for the fixed-order grid reductions.
+// Scratch and destination of the fixed-order grid reductions: a kernel stores
+// NV partial sums per block, then launch_reduce() adds them in order.
 struct ReduceArgs {
     double *partials;  // NV * nblocks doubles
-    unsigned *counter; // zero between launches
-    double *out;       // NV doubles written by the last block
+    double *out;       // NV doubles
     double *out2;      // optional second copy (history), may be null
     int accumulate;    // 1: out[0] += total instead of out[k] = total
     double out_scale;  // total is multiplied by this before it is written
 };
+
+// Second pass of a grid reduction over nblocks blocks of NV (1 or 2) values.
+hipError_t launch_reduce(const ReduceArgs &r, int nv, unsigned nblocks, hipStream_t stream);
 
 // Generic kernels: one thread per node, neighbours read from global memory.
 hipError_t launch_fwd_generic(const ProblemArgs &p, int storage, bool force, const void *src,

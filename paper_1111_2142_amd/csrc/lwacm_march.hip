@@ -145,6 +145,7 @@ struct BufIO<float> {
     {
         const f32x4 v = {d, ux, uy, uz};
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+        store_data_guard();
     }
     __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float d,
                                                     float ux, float uy, float uz,
@@ -174,6 +175,7 @@ struct BufIO<__half> {
     {
         const Raw v = {(unsigned)b0 | ((unsigned)b1 << 16), (unsigned)b2 | ((unsigned)b3 << 16)};
         __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+        store_data_guard();
     }
     __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float d,
                                                  float ux, float uy, float uz,
@@ -570,16 +572,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
     }
 
     double v[2] = {(double)mass, 0.5 * (double)energy};
-    double tot[2];
-    if (grid_sum_last_block<2>(v, r.partials, r.counter, gridDim.x, blockIdx.x, tot) &&
-        threadIdx.x == 0) {
-        r.out[0] = tot[0];
-        r.out[1] = tot[1];
-        if (r.out2) {
-            r.out2[0] = tot[0];
-            r.out2[1] = tot[1];
-        }
-    }
+    store_block_partials<2>(v, r.partials, blockIdx.x);
 }
 
 // Node classes and solid-upstream bit sets for the bounce-back of the march
@@ -713,8 +706,9 @@ hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, 
                             const ReduceArgs &r, hipStream_t s)
 {
     if (!march_supported(p) || (p.mask && (!cls || !bits))) return hipErrorNotSupported;
-    return storage ? dispatch<__half>(p, src, dst, cls, bits, wallg, r, s)
-                   : dispatch<float>(p, src, dst, cls, bits, wallg, r, s);
+    const hipError_t e = storage ? dispatch<__half>(p, src, dst, cls, bits, wallg, r, s)
+                                 : dispatch<float>(p, src, dst, cls, bits, wallg, r, s);
+    return e != hipSuccess ? e : launch_reduce(r, 2, march_num_blocks(p), s);
 }
 
 }  // namespace lwacm

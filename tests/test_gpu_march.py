@@ -164,3 +164,52 @@ def test_march_chunk_rejects_bad_depth():
     with pytest.raises(L.LWACMError):
         L.lwacm_set_march_chunk(s.ctx, 64)
     s.close()
+
+
+def test_march_256_cubed_repeat_runs_bitwise_equal():
+    """Regression: at 256^3 every chunk depth gives bitwise the same fields
+    run after run over 200 steps, and so does the reverse kernel over 40
+    chained steps.  (Without wait states after the tile kernel's buffer
+    stores, the last plane of a chunk picked up the next instruction's
+    register values in a few lanes, intermittently.)"""
+    L = need_gpu()
+    n = 256
+    banner("256^3 repeat-run determinism")
+    drho, u = wl.taylor_green_3d(n, 0.02)
+    d0, u0 = to_dev(drho), to_dev(u)
+
+    def fwd(planes):
+        s = L.Solver(19, n, n, n, 1.7, variant=MARCH)
+        L.lwacm_set_march_chunk(s.ctx, planes)
+        s.set_state(d0, u0)
+        s.step(200)
+        dr, uu = s.moments()
+        s.close()
+        return dr, uu
+
+    ref = fwd(128)
+    assert bool(torch.isfinite(ref[1]).all())
+    for planes in (128, 64, 32):
+        dr, uu = fwd(planes)
+        assert torch.equal(dr, ref[0]) and torch.equal(uu, ref[1]), planes
+
+    s = L.Solver(19, n, n, n, 1.7)
+    s.set_state(d0, u0)
+    s.step(2)
+    st = s.save_state()
+    lam = torch.zeros((4, n, n, n), device="cuda")
+    lam[1:] = u0
+
+    def rev():
+        a = torch.zeros_like(lam)
+        b = torch.zeros_like(lam)
+        dw = torch.zeros(1, dtype=torch.float64, device="cuda")
+        L.lwacm_adjoint_seed(s.ctx, st, lam, a)
+        for _ in range(20):
+            L.lwacm_adjoint_step(s.ctx, st, a, b, dw, False)
+            L.lwacm_adjoint_step(s.ctx, st, b, a, dw, False)
+        return a.clone(), float(dw.item())
+
+    (ra, wa), (rb, wb) = rev(), rev()
+    s.close()
+    assert torch.equal(ra, rb) and wa == wb and bool(torch.isfinite(ra).all())
