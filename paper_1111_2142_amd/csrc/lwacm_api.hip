@@ -82,6 +82,9 @@ ReduceArgs reduce_args(lwacm_ctx *c, double *out, double *out2)
 {
     ReduceArgs r;
     r.partials = c->d_partials;
+    r.prev_partials = nullptr;
+    r.prev_nblocks = 0;
+    r.prev_out = r.prev_out2 = nullptr;
     r.out = out;
     r.out2 = out2;
     r.accumulate = 0;
@@ -217,7 +220,9 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
     const size_t ab = lwacm::adj_march_num_blocks(p);
     if (ab > nb) nb = ab;
     c->n_partial_blocks = nb;
-    hipError_t e = hipMalloc(&c->d_partials, 2 * nb * sizeof(double));
+    // two partial sets of 2 doubles per block: a forward step defers its second
+    // reduction pass into the next step's launch
+    hipError_t e = hipMalloc(&c->d_partials, 4 * nb * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->d_diag, 2 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->d_scratch, 2 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->d_scan, 2 * sizeof(unsigned));
@@ -345,23 +350,36 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
 {
     if (!c || nsteps < 0) return LWACM_EINVAL;
     const bool march = use_march(c);
-    const unsigned gb = lwacm::generic_grid(c->p.n);
+    const unsigned nb = march ? lwacm::march_num_blocks(c->p) : lwacm::generic_grid(c->p.n);
+    double *part[2] = {c->d_partials, c->d_partials + 2 * c->n_partial_blocks};
+    ReduceArgs prev = reduce_args(c, c->d_diag, nullptr);
     for (int s = 0; s < nsteps; ++s) {
         double *hist = nullptr;
         if (c->d_hist) hist = c->d_hist + 2 * (size_t)((c->steps + 1) % c->hist_cap);
         ReduceArgs r = reduce_args(c, c->d_diag, hist);
+        r.partials = part[s & 1];
+        if (s > 0) {  // this launch finishes the previous step's sums
+            r.prev_partials = prev.partials;
+            r.prev_nblocks = nb;
+            r.prev_out = prev.out;
+            r.prev_out2 = prev.out2;
+        }
         const void *src = c->buf[c->cur];
         void *dst = c->buf[c->cur ^ 1];
         c->p.sr_word = (uint32_t)(c->steps + 1) ^ c->sr_seed;
         hipError_t e = march ? lwacm::launch_fwd_march(c->p, c->storage, src, dst, c->d_cls,
                                                        c->d_bits, c->d_wallg, r, c->stream)
-                             : lwacm::launch_fwd_generic(c->p, c->storage, c->force, src, dst, r, gb,
+                             : lwacm::launch_fwd_generic(c->p, c->storage, c->force, src, dst, r, nb,
                                                          c->stream);
         if (e != hipSuccess) return LWACM_EDEVICE;
+        prev = r;
         c->cur ^= 1;
         c->steps += 1;
         c->diag_valid = true;
     }
+    // the last step's sums: mass/energy and history complete when the call's work is
+    if (nsteps > 0 && lwacm::launch_reduce(prev, 2, nb, c->stream) != hipSuccess)
+        return LWACM_EDEVICE;
     return LWACM_OK;
 }
 

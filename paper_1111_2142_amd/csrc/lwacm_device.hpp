@@ -10,6 +10,9 @@
 namespace lwacm {
 
 constexpr int kWave = 64;
+// Threads that add the per-block partials in the second pass of a grid
+// reduction (one stride, then the block's fixed tree).
+constexpr unsigned kReduceThreads = 256;
 
 // ---------------------------------------------------------------- lattices
 // Link velocities grouped by their z component (Appendix A lists the groups
@@ -314,6 +317,28 @@ __device__ __forceinline__ void block_sum(double (&v)[NV])
 // boundary makes the partials visible, so no device-scope fences are needed:
 // on this chip such a fence writes back and invalidates the whole L2 of an
 // XCD, once per block.
+// Second pass of the previous step's (mass, energy) sums, run by block 0 of
+// the next forward launch: the same fixed order as k_reduce_partials.
+__device__ __forceinline__ void finish_previous_sums(const double *prev, unsigned nblocks,
+                                                     double *out, double *out2)
+{
+    double acc[2] = {0.0, 0.0};
+    if (threadIdx.x < kReduceThreads)
+        for (unsigned b = threadIdx.x; b < nblocks; b += kReduceThreads) {
+            acc[0] += prev[2 * (size_t)b];
+            acc[1] += prev[2 * (size_t)b + 1];
+        }
+    block_sum<2>(acc);  // further waves add exact zeros
+    if (threadIdx.x == 0) {
+        out[0] = acc[0];
+        out[1] = acc[1];
+        if (out2) {
+            out2[0] = acc[0];
+            out2[1] = acc[1];
+        }
+    }
+}
+
 template <int NV>
 __device__ __forceinline__ void store_block_partials(double (&v)[NV], double *partials, unsigned bid)
 {

@@ -189,6 +189,8 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
         acc[1] += 0.5 * (double)e;
     }
     store_block_partials<2>(acc, r.partials, blockIdx.x);
+    if (blockIdx.x == 0 && r.prev_nblocks)
+        finish_previous_sums(r.prev_partials, r.prev_nblocks, r.prev_out, r.prev_out2);
 }
 
 template <int Q, class T, bool MASK>
@@ -413,7 +415,7 @@ __global__ __launch_bounds__(kGenericBlock) void k_reduce_partials(ReduceArgs r,
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    for (unsigned b = threadIdx.x; b < nblocks; b += blockDim.x)
+    for (unsigned b = threadIdx.x; b < nblocks; b += kReduceThreads)
 #pragma unroll
         for (int k = 0; k < NV; ++k) acc[k] += r.partials[(size_t)NV * b + k];
     block_sum<NV>(acc);
@@ -437,23 +439,20 @@ __global__ __launch_bounds__(kGenericBlock) void k_reduce_partials(ReduceArgs r,
 hipError_t launch_reduce(const ReduceArgs &r, int nv, unsigned nblocks, hipStream_t s)
 {
     if (nv == 1)
-        k_reduce_partials<1><<<1, kGenericBlock, 0, s>>>(r, nblocks);
+        k_reduce_partials<1><<<1, kReduceThreads, 0, s>>>(r, nblocks);
     else
-        k_reduce_partials<2><<<1, kGenericBlock, 0, s>>>(r, nblocks);
+        k_reduce_partials<2><<<1, kReduceThreads, 0, s>>>(r, nblocks);
     return hipGetLastError();
 }
 
 hipError_t launch_fwd_generic(const ProblemArgs &p, int storage, bool force, const void *src,
                               void *dst, const ReduceArgs &r, unsigned nb, hipStream_t s)
 {
-    hipError_t e;
     if (p.Q == 9)
-        e = storage ? fwd_dispatch<9, __half>(p, force, src, dst, r, nb, s)
-                    : fwd_dispatch<9, float>(p, force, src, dst, r, nb, s);
-    else
-        e = storage ? fwd_dispatch<19, __half>(p, force, src, dst, r, nb, s)
-                    : fwd_dispatch<19, float>(p, force, src, dst, r, nb, s);
-    return e != hipSuccess ? e : launch_reduce(r, 2, nb, s);
+        return storage ? fwd_dispatch<9, __half>(p, force, src, dst, r, nb, s)
+                       : fwd_dispatch<9, float>(p, force, src, dst, r, nb, s);
+    return storage ? fwd_dispatch<19, __half>(p, force, src, dst, r, nb, s)
+                   : fwd_dispatch<19, float>(p, force, src, dst, r, nb, s);
 }
 
 hipError_t launch_adj_generic(const ProblemArgs &p, int storage, const void *state,

@@ -38,11 +38,20 @@ struct ReduceArgs {
     double *out2;      // optional second copy (history), may be null
     int accumulate;    // 1: out[0] += total instead of out[k] = total
     double out_scale;  // total is multiplied by this before it is written
+    // Deferred second pass of the previous step (forward steps only): block 0
+    // of this launch adds prev_nblocks pairs of prev_partials (stored by the
+    // previous kernel) into prev_out / prev_out2.  prev_nblocks == 0: none.
+    const double *prev_partials;
+    unsigned prev_nblocks;
+    double *prev_out;
+    double *prev_out2;
 };
 
 // Second pass of a grid reduction over nblocks blocks of NV (1 or 2) values.
 hipError_t launch_reduce(const ReduceArgs &r, int nv, unsigned nblocks, hipStream_t stream);
 
+// The forward launchers store per-block partials only; the caller runs the
+// second pass (launch_reduce, or deferred into the next step's launch).
 // Generic kernels: one thread per node, neighbours read from global memory.
 hipError_t launch_fwd_generic(const ProblemArgs &p, int storage, bool force, const void *src,
                               void *dst, const ReduceArgs &r, unsigned nblocks,

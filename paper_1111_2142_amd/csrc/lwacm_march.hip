@@ -573,6 +573,8 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
 
     double v[2] = {(double)mass, 0.5 * (double)energy};
     store_block_partials<2>(v, r.partials, blockIdx.x);
+    if (blockIdx.x == 0 && r.prev_nblocks)
+        finish_previous_sums(r.prev_partials, r.prev_nblocks, r.prev_out, r.prev_out2);
 }
 
 // Node classes and solid-upstream bit sets for the bounce-back of the march
@@ -706,9 +708,8 @@ hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, 
                             const ReduceArgs &r, hipStream_t s)
 {
     if (!march_supported(p) || (p.mask && (!cls || !bits))) return hipErrorNotSupported;
-    const hipError_t e = storage ? dispatch<__half>(p, src, dst, cls, bits, wallg, r, s)
-                                 : dispatch<float>(p, src, dst, cls, bits, wallg, r, s);
-    return e != hipSuccess ? e : launch_reduce(r, 2, march_num_blocks(p), s);
+    return storage ? dispatch<__half>(p, src, dst, cls, bits, wallg, r, s)
+                   : dispatch<float>(p, src, dst, cls, bits, wallg, r, s);
 }
 
 }  // namespace lwacm
