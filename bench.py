@@ -297,14 +297,22 @@ def main():
         del d0
         oracle.run(p, r0, u0, 1)   # warm-up (page-in)
         nsteps_cpu = 24
+        threads = oracle.num_threads()
         t0 = time.perf_counter()
         oracle.run(p, r0, u0, nsteps_cpu)
         dtc = time.perf_counter() - t0
+        # the same update on one thread, one step
+        oracle.set_num_threads(1)
+        t0 = time.perf_counter()
+        oracle.run(p, r0, u0, 1)
+        dt1 = time.perf_counter() - t0
+        oracle.set_num_threads(threads)
         result["cpu_baseline"] = {
             "value": round(nodes * nsteps_cpu / dtc / 1e6, 3), "unit": "MLUPS",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": threads, "kind": "oracle",
             "sample": f"{nsteps_cpu} steps of the full {n}^3 D3Q19 Taylor-Green grid "
-                      "(FP64, OpenMP over z-y rows)"}
+                      "(FP64, OpenMP over z-y rows); single_thread: 1 step on 1 thread",
+            "single_thread": round(nodes / dt1 / 1e6, 3)}
         print(f"[bench] cpu oracle: {result['cpu_baseline']['value']} MLUPS on "
               f"{oracle.num_threads()} threads", file=sys.stderr, flush=True)
     print(json.dumps(result), flush=True)

@@ -66,6 +66,8 @@ def _load():
     lib.oracle_store_fp16_sr.restype = ctypes.c_int
     lib.oracle_pcg4d.argtypes = [u32p, u32p]
     lib.oracle_pcg4d.restype = None
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -81,6 +83,11 @@ def _ptr(a: Optional[np.ndarray], p=_dp):
 def num_threads() -> int:
     """Threads the oracle's parallel loops use (OMP_NUM_THREADS)."""
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's parallel loops from now on."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def lattice_info(q: int):

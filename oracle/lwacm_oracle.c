@@ -234,6 +234,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Set the number of threads of the parallel loops (timing of the oracle). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_lattice_info(int q, int *d, int *v_out, double *w_out, int *opp_out)
 {
     lattice_t L;
