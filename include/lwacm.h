@@ -66,8 +66,12 @@ enum { LWACM_ROUND_NEAREST = 0, LWACM_ROUND_STOCHASTIC = 1 };
 enum {
     LWACM_KERNEL_AUTO = 0,    /* fastest kernels that support the problem */
     LWACM_KERNEL_GENERIC = 1, /* one thread per node, neighbours from global memory */
-    LWACM_KERNEL_MARCH = 2    /* D3Q19 z-marching tile kernels (nx % 32 == 0, ny % 16 == 0;
-                                 the forward one without body force) */
+    LWACM_KERNEL_MARCH = 2,   /* D3Q19 z-marching tile kernels (nx % 32 == 0, ny % 16 == 0;
+                                 the forward one without body force), one step per launch */
+    LWACM_KERNEL_MARCH2 = 3   /* as MARCH, and the forward steps of FP32 problems without
+                                 walls (nz >= 2) two per launch: the intermediate state stays
+                                 on chip, halving the HBM bytes per update; results are
+                                 bitwise those of single steps.  AUTO includes it. */
 };
 
 /* Bytes of one state buffer: (D+1) * nodes * (4 for FP32, 2 for FP16).
@@ -148,7 +152,10 @@ int lwacm_set_state(lwacm_ctx *c, const float *d_drho, const float *d_u);
  * wall rules), toggling the two state buffers.  Each step also reduces the
  * mass sum(rho) and kinetic energy 1/2 sum|u|^2 of its output over fluid
  * nodes in FP64 (per-block partials, fixed-order final sum: bitwise
- * reproducible); see lwacm_diagnostics.  Asynchronous. */
+ * reproducible); see lwacm_diagnostics.  Where LWACM_KERNEL_MARCH2 applies,
+ * pairs of steps run as one launch (an odd count starts with a single step);
+ * the state, the diagnostics and the history are the same as with single
+ * steps.  Asynchronous. */
 int lwacm_step(lwacm_ctx *c, int nsteps);
 
 /* Mass and energy of the state after the most recent lwacm_step (host

@@ -85,6 +85,10 @@ ReduceArgs reduce_args(lwacm_ctx *c, double *out, double *out2)
     r.prev_partials = nullptr;
     r.prev_nblocks = 0;
     r.prev_out = r.prev_out2 = nullptr;
+    r.partials_b = nullptr;
+    r.prev_partials_b = nullptr;
+    r.prev_nblocks_b = 0;
+    r.prev_out_b = r.prev_out2_b = nullptr;
     r.out = out;
     r.out2 = out2;
     r.accumulate = 0;
@@ -101,6 +105,18 @@ bool use_march(const lwacm_ctx *c)
 {
     if (c->variant == LWACM_KERNEL_GENERIC) return false;
     return lwacm::march_supported(c->p);
+}
+
+// Two steps per launch: FP32 state, AUTO or MARCH2 selection.
+bool use_march2(const lwacm_ctx *c)
+{
+    if (c->variant != LWACM_KERNEL_AUTO && c->variant != LWACM_KERNEL_MARCH2) return false;
+    return c->storage == LWACM_FP32 && lwacm::march2_supported(c->p);
+}
+
+double *hist_slot(lwacm_ctx *c, long long step)
+{
+    return c->d_hist ? c->d_hist + 2 * (size_t)(step % c->hist_cap) : nullptr;
 }
 
 void free_scratch(lwacm_ctx *c)
@@ -219,10 +235,13 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
     if (mb > nb) nb = mb;
     const size_t ab = lwacm::adj_march_num_blocks(p);
     if (ab > nb) nb = ab;
+    const size_t fb = lwacm::march2_num_blocks(p);
+    if (fb > nb) nb = fb;
     c->n_partial_blocks = nb;
-    // two partial sets of 2 doubles per block: a forward step defers its second
-    // reduction pass into the next step's launch
-    hipError_t e = hipMalloc(&c->d_partials, 4 * nb * sizeof(double));
+    // four partial sets of 2 doubles per block: a forward launch (one or two
+    // steps) defers its second reduction passes into the next launch, so the
+    // sets of two consecutive launches are live at once
+    hipError_t e = hipMalloc(&c->d_partials, 8 * nb * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->d_diag, 2 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->d_scratch, 2 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->d_scan, 2 * sizeof(unsigned));
@@ -298,7 +317,8 @@ int lwacm_set_march_chunk(lwacm_ctx *c, int planes)
     if (!lwacm::march_supported(c->p)) return LWACM_EUNSUPPORTED;
     const int keep = c->p.march_nzc;
     c->p.march_nzc = planes;
-    if (lwacm::march_num_blocks(c->p) > c->n_partial_blocks) {  // reduction scratch too small
+    if (lwacm::march_num_blocks(c->p) > c->n_partial_blocks ||
+        lwacm::march2_num_blocks(c->p) > c->n_partial_blocks) {  // reduction scratch too small
         c->p.march_nzc = keep;
         return LWACM_EUNSUPPORTED;
     }
@@ -309,6 +329,11 @@ int lwacm_set_variant(lwacm_ctx *c, int variant)
 {
     if (!c) return LWACM_EINVAL;
     if (variant == LWACM_KERNEL_AUTO || variant == LWACM_KERNEL_GENERIC) {
+        c->variant = variant;
+        return LWACM_OK;
+    }
+    if (variant == LWACM_KERNEL_MARCH2) {
+        if (c->storage != LWACM_FP32 || !lwacm::march2_supported(c->p)) return LWACM_EUNSUPPORTED;
         c->variant = variant;
         return LWACM_OK;
     }
@@ -350,36 +375,66 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
 {
     if (!c || nsteps < 0) return LWACM_EINVAL;
     const bool march = use_march(c);
-    const unsigned nb = march ? lwacm::march_num_blocks(c->p) : lwacm::generic_grid(c->p.n);
-    double *part[2] = {c->d_partials, c->d_partials + 2 * c->n_partial_blocks};
-    ReduceArgs prev = reduce_args(c, c->d_diag, nullptr);
-    for (int s = 0; s < nsteps; ++s) {
-        double *hist = nullptr;
-        if (c->d_hist) hist = c->d_hist + 2 * (size_t)((c->steps + 1) % c->hist_cap);
-        ReduceArgs r = reduce_args(c, c->d_diag, hist);
-        r.partials = part[s & 1];
-        if (s > 0) {  // this launch finishes the previous step's sums
-            r.prev_partials = prev.partials;
-            r.prev_nblocks = nb;
-            r.prev_out = prev.out;
-            r.prev_out2 = prev.out2;
+    const bool fuse = march && use_march2(c);
+    const unsigned nb1 = march ? lwacm::march_num_blocks(c->p) : lwacm::generic_grid(c->p.n);
+    const unsigned nb2 = fuse ? lwacm::march2_num_blocks(c->p) : 0u;
+    const size_t set = 2 * c->n_partial_blocks;  // doubles per partial set
+    // Steps whose partials are stored but not yet added up (oldest first): the
+    // next launch's block 0 adds them, or the final passes after the loop.
+    struct Pending {
+        double *partials, *out, *out2;
+        unsigned nblocks;
+    } pend[2];
+    int npend = 0;
+    int s = 0;
+    for (int launch = 0; s < nsteps; ++launch) {
+        // an odd step count starts with one single step, then pairs
+        const bool two = fuse && (nsteps - s) % 2 == 0;
+        double *part = c->d_partials + 2 * set * (size_t)(launch & 1);
+        ReduceArgs r = reduce_args(c, c->d_diag, hist_slot(c, c->steps + 1));
+        r.partials = part;
+        if (two) r.partials_b = part + set;
+        if (npend > 0) {
+            r.prev_partials = pend[0].partials;
+            r.prev_nblocks = pend[0].nblocks;
+            r.prev_out = pend[0].out;
+            r.prev_out2 = pend[0].out2;
+        }
+        if (npend > 1) {
+            r.prev_partials_b = pend[1].partials;
+            r.prev_nblocks_b = pend[1].nblocks;
+            r.prev_out_b = pend[1].out;
+            r.prev_out2_b = pend[1].out2;
         }
         const void *src = c->buf[c->cur];
         void *dst = c->buf[c->cur ^ 1];
         c->p.sr_word = (uint32_t)(c->steps + 1) ^ c->sr_seed;
-        hipError_t e = march ? lwacm::launch_fwd_march(c->p, c->storage, src, dst, c->d_cls,
-                                                       c->d_bits, c->d_wallg, r, c->stream)
-                             : lwacm::launch_fwd_generic(c->p, c->storage, c->force, src, dst, r, nb,
-                                                         c->stream);
+        hipError_t e;
+        if (two)
+            e = lwacm::launch_fwd_march2(c->p, static_cast<const float *>(src),
+                                         static_cast<float *>(dst), r, c->stream);
+        else if (march)
+            e = lwacm::launch_fwd_march(c->p, c->storage, src, dst, c->d_cls, c->d_bits,
+                                        c->d_wallg, r, c->stream);
+        else
+            e = lwacm::launch_fwd_generic(c->p, c->storage, c->force, src, dst, r, nb1, c->stream);
         if (e != hipSuccess) return LWACM_EDEVICE;
-        prev = r;
+        const unsigned nb = two ? nb2 : nb1;
+        npend = 0;
+        pend[npend++] = {r.partials, r.out, r.out2, nb};
+        if (two) pend[npend++] = {r.partials_b, c->d_diag, hist_slot(c, c->steps + 2), nb};
         c->cur ^= 1;
-        c->steps += 1;
+        c->steps += two ? 2 : 1;
+        s += two ? 2 : 1;
         c->diag_valid = true;
     }
-    // the last step's sums: mass/energy and history complete when the call's work is
-    if (nsteps > 0 && lwacm::launch_reduce(prev, 2, nb, c->stream) != hipSuccess)
-        return LWACM_EDEVICE;
+    // the last launch's sums: mass/energy and history complete when the call's work is
+    for (int i = 0; i < npend; ++i) {
+        ReduceArgs r = reduce_args(c, pend[i].out, pend[i].out2);
+        r.partials = pend[i].partials;
+        if (lwacm::launch_reduce(r, 2, pend[i].nblocks, c->stream) != hipSuccess)
+            return LWACM_EDEVICE;
+    }
     return LWACM_OK;
 }
 

@@ -45,6 +45,14 @@ struct ReduceArgs {
     unsigned prev_nblocks;
     double *prev_out;
     double *prev_out2;
+    // Two-step launches (launch_fwd_march2): partials of the second step, and
+    // a second deferred sum (the second step of a previous two-step launch),
+    // finished after the first.  Single-step kernels ignore these fields.
+    double *partials_b;
+    const double *prev_partials_b;
+    unsigned prev_nblocks_b;
+    double *prev_out_b;
+    double *prev_out2_b;
 };
 
 // Second pass of a grid reduction over nblocks blocks of NV (1 or 2) values.
@@ -91,6 +99,15 @@ hipError_t launch_adj_march(const ProblemArgs &p, int storage, const void *state
 hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, void *dst,
                             const uint8_t *cls, const unsigned *bits, const float4 *wallg,
                             const ReduceArgs &r, hipStream_t stream);
+// Two D3Q19 forward steps per launch on FP32 state (same tiles as the
+// single-step kernel, its chunk depth halved while deeper than nz;
+// unmasked problems without body force, nz >= 8).  Stores the first step's
+// partials in r.partials and the second step's in r.partials_b (2 doubles
+// per block each); finishes up to two deferred sums of earlier steps.
+bool march2_supported(const ProblemArgs &p);
+unsigned march2_num_blocks(const ProblemArgs &p);
+hipError_t launch_fwd_march2(const ProblemArgs &p, const float *src, float *dst,
+                             const ReduceArgs &r, hipStream_t stream);
 
 // Number of blocks the generic grid-stride kernels use for n nodes.
 unsigned generic_grid(long long n);

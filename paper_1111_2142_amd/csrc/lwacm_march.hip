@@ -32,11 +32,7 @@
 // Link terms are kept unweighted and summed with the exact integer weights
 // 12, 2, 1 (= 36 w_i for rest, axis and diagonal links of D3Q19); the sums
 // are divided by 36 once at the end (div36: no systematic rounding bias).
-#include <type_traits>
-#include <utility>
-
-#include "lwacm_device.hpp"
-#include "lwacm_internal.hpp"
+#include "lwacm_march_common.hpp"
 
 namespace lwacm {
 
@@ -67,150 +63,6 @@ static_assert(NINT % kWave == 0, "interior must be whole waves");
 static_assert(2 * TX <= kWave && 2 * (TY + 2) <= kWave, "halo rows must fit one wave each");
 
 enum Role { INTERIOR = 0, HALO_Y = 1, HALO_X = 2 };
-
-// Exchanged quantities per slot, in arrays of one kind each so that every
-// LDS access has a 4- or 8-byte lane stride (no bank conflicts):
-//   xp[0..3] = (PE, ZE), (PW, ZW), (PN, ZN), (PS, ZS): density and z parts of
-//              the links with (vx, vy) = (+1,0), (-1,0), (0,+1), (0,-1)
-//   xd[0..3] = NE, NW, SE, SW: in-plane diagonals (+1,+1,0), (-1,+1,0),
-//              (+1,-1,0), (-1,-1,0)
-
-// Per target plane accumulator of an interior column.
-// Compile-time loop: f(std::integral_constant<int, K>) for K = 0 .. N-1.
-// The plane loop runs through it so that every ring and accumulator index is
-// a constant expression from the start and all per-plane state stays in
-// registers.
-template <class F, int... K>
-__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, K...>)
-{
-    (f(std::integral_constant<int, K>{}), ...);
-}
-
-template <int N, class F>
-__device__ __forceinline__ void static_for(F &&f)
-{
-    static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
-
-struct Acc {
-    float pe, ze, pw, zw, pn, zn, ps, zs;  // direction partials (weights folded)
-    float ne, nw, se, sw;                  // in-plane diagonals
-    float d, jz;                           // own column: rest + (0,0,+-1) links
-    float post[3];                         // a rho u of the node itself
-    float own[6];                          // E0, 4.5 rho, A rho, u (bounce-back only)
-    unsigned bits;                         // solid upstream links (bounce-back only)
-    int cls;                               // 0 fluid, 1 fluid next to a wall, 2 solid
-};
-
-__device__ __forceinline__ bool has_bit(unsigned bits, int i) { return (bits >> i) & 1u; }
-
-// Global memory goes through buffer resources: one descriptor per state
-// buffer in SGPRs, the column's fixed 32-bit byte offset in a VGPR and the
-// plane's byte offset as the scalar offset, so a load or store costs no
-// per-lane address arithmetic.  The state is node-interleaved, so one node of
-// one plane is a single 16-byte (FP32) or 8-byte (FP16) access.
-// (march_supported() guarantees that a state buffer fits in 4 GiB.)
-using Rsrc = __amdgpu_buffer_rsrc_t;
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned long long bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0,
-                                             (int)(unsigned)bytes, 0x00020000);
-}
-
-template <class T>
-struct BufIO;
-
-// Element access uses explicit .x/.y/.z/.w selection and whole-vector casts:
-// this compiler narrows a 128-bit load to its first dword when elements of
-// the loaded vector are taken apart with __builtin_bit_cast one by one.
-template <>
-struct BufIO<float> {
-    using Raw = f32x4;
-    static constexpr unsigned kNodeBytes = 16;
-    __device__ __forceinline__ static Raw load(Rsrc r, unsigned voff, unsigned soff)
-    {
-        return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
-    }
-    // field f (0: rho - 1, 1..3: u) of a loaded node
-    __device__ __forceinline__ static float value(const Raw &v, int f, float)
-    {
-        return f == 0 ? v.x : (f == 1 ? v.y : (f == 2 ? v.z : v.w));
-    }
-    __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float d,
-                                                 float ux, float uy, float uz, const float (&)[2])
-    {
-        const f32x4 v = {d, ux, uy, uz};
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
-        store_data_guard();
-    }
-    __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float d,
-                                                    float ux, float uy, float uz,
-                                                    const float (&sc)[2], const U32x4 &)
-    {
-        store(r, voff, soff, d, ux, uy, uz, sc);
-    }
-};
-
-template <>
-struct BufIO<__half> {
-    using Raw = u32x2;
-    static constexpr unsigned kNodeBytes = 8;
-    __device__ __forceinline__ static Raw load(Rsrc r, unsigned voff, unsigned soff)
-    {
-        return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
-    }
-    __device__ __forceinline__ static float value(const Raw &v, int f, float inv_scale)
-    {
-        const unsigned w = (f >> 1) ? v.y : v.x;
-        const unsigned short h = (unsigned short)((f & 1) ? w >> 16 : w & 0xffffu);
-        return __half2float(__ushort_as_half(h)) * inv_scale;
-    }
-    __device__ __forceinline__ static void put(Rsrc r, unsigned voff, unsigned soff,
-                                               unsigned short b0, unsigned short b1,
-                                               unsigned short b2, unsigned short b3)
-    {
-        const Raw v = {(unsigned)b0 | ((unsigned)b1 << 16), (unsigned)b2 | ((unsigned)b3 << 16)};
-        __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
-        store_data_guard();
-    }
-    __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float d,
-                                                 float ux, float uy, float uz,
-                                                 const float (&st)[2])
-    {
-        put(r, voff, soff, __half_as_ushort(__float2half_rn(d * st[0])),
-            __half_as_ushort(__float2half_rn(ux * st[1])),
-            __half_as_ushort(__float2half_rn(uy * st[1])),
-            __half_as_ushort(__float2half_rn(uz * st[1])));
-    }
-    __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float d,
-                                                    float ux, float uy, float uz,
-                                                    const float (&st)[2], const U32x4 &h)
-    {
-        put(r, voff, soff, half_bits_sr(d * st[0], h.x), half_bits_sr(ux * st[1], h.y),
-            half_bits_sr(uy * st[1], h.z), half_bits_sr(uz * st[1], h.w));
-    }
-};
-
-template <class T>
-struct Ring {
-    typename BufIO<T>::Raw v;  // the node's stored values on one plane
-    uint8_t cls;
-};
-
-// Unweighted link term with c = v_i . u (Eq. ACM2.0b pre-combining,
-// deviation form): L(c) = fma(A rho, c, m) with the even part
-// m = fma(4.5 rho c, c, E0).  m is bitwise even in c, so the pair of opposite
-// links shares it, and interior and halo threads, which both use exactly
-// these operations (the build disables FMA contraction), produce bitwise the
-// same term for a given link.
-__device__ __forceinline__ float lterm(float c, float E0, float r45, float rA)
-{
-    return fmaf(rA, c, fmaf(r45 * c, c, E0));
-}
 
 template <class T, bool MASK, int NZC>
 __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *__restrict__ src,
@@ -338,157 +190,22 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 // re-reads plane z1, which is cached and never consumed)
                 if (k + RING < NZC + 2) issue(ring[rj], min(pz + RING, z1));
 
-                // ---- own link terms in +-c pairs:
-                // L(+-c) = E0 + 4.5 rho c^2 +- A rho c, E0 = drho - 1.5 rho |u|^2
-                const float rho = 1.0f + dr;
-                const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
-                float E0 = fmaf(rho, -1.5f * usq, dr);
-                float r45 = 4.5f * rho;
-                float rA = A * rho;
-                if (MASK && cls >= 2) {  // solid: push nothing
-                    E0 = 0.0f;
-                    r45 = 0.0f;
-                    rA = 0.0f;
-                }
-                auto pair = [&](float c, float &lp, float &lm) {
-                    const float m = fmaf(r45 * c, c, E0);  // = lterm's even part
-                    lp = fmaf(rA, c, m);                   // = lterm(c)
-                    lm = fmaf(rA, -c, m);                  // = lterm(-c)
-                };
-                float Lpx, Lmx, Lpy, Lmy, Lpz, Lmz;
-                float Lpp0, Lmm0, Lpm0, Lmp0;  // (+x+y), (-x-y), (+x-y), (-x+y)
-                float Lp0p, Lm0m, Lp0m, Lm0p;  // (+x,+z), (-x,-z), (+x,-z), (-x,+z)
-                float L0pp, L0mm, L0pm, L0mp;  // (+y,+z), (-y,-z), (+y,-z), (-y,+z)
-                pair(ux, Lpx, Lmx);
-                pair(uy, Lpy, Lmy);
-                pair(uz, Lpz, Lmz);
-                pair(ux + uy, Lpp0, Lmm0);
-                pair(ux - uy, Lpm0, Lmp0);
-                pair(ux + uz, Lp0p, Lm0m);
-                pair(ux - uz, Lp0m, Lm0p);
-                pair(uy + uz, L0pp, L0mm);
-                pair(uy - uz, L0pm, L0mp);
-
-                // links with v_z = +1 start the accumulator of plane pz + 1
-                A1.pe = Lp0p;
-                A1.ze = Lp0p;
-                A1.pw = Lm0p;
-                A1.zw = Lm0p;
-                A1.pn = L0pp;
-                A1.zn = L0pp;
-                A1.ps = L0mp;
-                A1.zs = L0mp;
-                A1.d = 2.0f * Lpz;
-                A1.jz = 2.0f * Lpz;
-                // links with v_z = 0 complete the in-plane part of plane pz
-                A0.pe = fmaf(2.0f, Lpx, A0.pe);
-                A0.pw = fmaf(2.0f, Lmx, A0.pw);
-                A0.pn = fmaf(2.0f, Lpy, A0.pn);
-                A0.ps = fmaf(2.0f, Lmy, A0.ps);
-                A0.ne = Lpp0;
-                A0.nw = Lmp0;
-                A0.se = Lpm0;
-                A0.sw = Lmm0;
-                A0.d = fmaf(12.0f, E0, A0.d);
-                const float arho = a * rho;
-                A0.post[0] = arho * ux;
-                A0.post[1] = arho * uy;
-                A0.post[2] = arho * uz;
-                if (MASK) {
-                    A0.cls = cls;
-                    A0.bits = 0u;
-                    // only planes this chunk finalises (z0 <= pz < z1 <= nz)
-                    if (cls == 1 && pz >= z0 && pz < z1)
-                        A0.bits = bb_bits[(long long)pz * plane + col];
-                    A0.own[0] = E0;
-                    A0.own[1] = r45;
-                    A0.own[2] = rA;
-                    A0.own[3] = ux;
-                    A0.own[4] = uy;
-                    A0.own[5] = uz;
-                }
-                // links with v_z = -1 finish plane pz - 1
-                Am.pe += Lp0m;
-                Am.ze -= Lp0m;
-                Am.pw += Lm0m;
-                Am.zw -= Lm0m;
-                Am.pn += L0pm;
-                Am.zn -= L0pm;
-                Am.ps += L0mm;
-                Am.zs -= L0mm;
-                Am.d = fmaf(2.0f, Lmz, Am.d);
-                Am.jz = fmaf(-2.0f, Lmz, Am.jz);
+                push_column<MASK>(dr, ux, uy, uz, cls, A, a, A1, A0, Am);
+                // only planes this chunk finalises (z0 <= pz < z1 <= nz)
+                if (MASK && cls == 1 && pz >= z0 && pz < z1)
+                    A0.bits = bb_bits[(long long)pz * plane + col];
 
                 if (k < 2) return;  // planes below the chunk are halo only
                 // ---- exchange the partials of plane pz - 1 through LDS
                 if (NBUF == 1 && k > 2) __syncthreads();  // previous plane's reads done
-                float2(*P)[NSLOT] = xp[k % NBUF];
-                float(*Dg)[NSLOT] = xd[k % NBUF];
-                P[0][slot] = make_float2(Am.pe, Am.ze);
-                P[1][slot] = make_float2(Am.pw, Am.zw);
-                P[2][slot] = make_float2(Am.pn, Am.zn);
-                P[3][slot] = make_float2(Am.ps, Am.zs);
-                Dg[0][slot] = Am.ne;
-                Dg[1][slot] = Am.nw;
-                Dg[2][slot] = Am.se;
-                Dg[3][slot] = Am.sw;
+                const Xchg<NSLOT> X{xp[k % NBUF], xd[k % NBUF]};
+                put_slot(X, slot, Am);
                 __syncthreads();
-                const float2 gW = P[0][slot - 1];   // west neighbour: PE, ZE
-                const float2 gE = P[1][slot + 1];   // east neighbour: PW, ZW
-                const float2 gS = P[2][slot - SX];  // south: PN, ZN
-                const float2 gN = P[3][slot + SX];  // north: PS, ZS
-                const float dNE = Dg[0][slot - SX - 1];
-                const float dNW = Dg[1][slot - SX + 1];
-                const float dSE = Dg[2][slot + SX - 1];
-                const float dSW = Dg[3][slot + SX + 1];
-                const float pE = gW.x, zE = gW.y, pW = gE.x, zW = gE.y;
-                const float pN = gS.x, zN = gS.y, pS = gN.x, zS = gN.y;
-
                 const int tz = pz - 1;
                 if (tz >= z1) return;  // padding iteration: nothing to finalise
-                float D36 = Am.d + ((pE + pW) + (pN + pS)) + ((dNE + dNW) + (dSE + dSW));
-                float Jx = (pE - pW) + ((dNE - dNW) + (dSE - dSW));
-                float Jy = (pN - pS) + ((dNE + dNW) - (dSE + dSW));
-                float Jz = Am.jz + ((zE + zW) + (zN + zS));
-                if (MASK && Am.bits != 0u) {
-                    // halfway bounce-back: a solid upstream node x - v_i pushed
-                    // nothing; the node's own term of the opposite link returns
-                    // along i (recomputed from the node's saved coefficients:
-                    // the same FMAs as pair(), so the same value).
-#pragma unroll
-                    for (int i = 1; i < 19; ++i) {
-                        if (has_bit(Am.bits, i)) {
-                            const int cx = link_cx(i), cy = link_cy(i), cz = link_cz(i);
-                            float c = 0.0f;  // v_i . u, summed in the order pair() uses
-                            if (cx != 0) c = cx > 0 ? c + Am.own[3] : c - Am.own[3];
-                            if (cy != 0) c = cy > 0 ? c + Am.own[4] : c - Am.own[4];
-                            if (cz != 0) c = cz > 0 ? c + Am.own[5] : c - Am.own[5];
-                            const float m = fmaf(Am.own[1] * c, c, Am.own[0]);
-                            const float s = Lattice<19>::w36(i) * fmaf(Am.own[2], -c, m);
-                            D36 += s;
-                            Jx = fmaf((float)cx, s, Jx);
-                            Jy = fmaf((float)cy, s, Jy);
-                            Jz = fmaf((float)cz, s, Jz);
-                        }
-                    }
-                    // moving walls (Eq. ACM2.0ccccbb): (1 - a) 6 rho0 times the
-                    // node's geometry sums of 36 w_i (1, v_i) (v_i . u_w)
-                    if (Am.bits & kMovingWallFlag) {
-                        const float4 g = wallg[(long long)tz * plane + col];
-                        D36 = fmaf(p.wall_scale, g.x, D36);
-                        Jx = fmaf(p.wall_scale, g.y, Jx);
-                        Jy = fmaf(p.wall_scale, g.z, Jy);
-                        Jz = fmaf(p.wall_scale, g.w, Jz);
-                    }
-                }
-                Jx = div36(Jx) + Am.post[0];
-                Jy = div36(Jy) + Am.post[1];
-                Jz = div36(Jz) + Am.post[2];
-                const float D = div36(D36);
-                const float q = normalisation_factor(D);
-                const float vx = fmaf(-Jx, q, Jx);
-                const float vy = fmaf(-Jy, q, Jy);
-                const float vz = fmaf(-Jz, q, Jz);
+                const NodeOut o = finalize<MASK, NSLOT, SX>(X, slot, Am, p, wallg,
+                                                            (long long)tz * plane + col);
+                const float D = o.D, vx = o.vx, vy = o.vy, vz = o.vz;
                 if (!MASK || Am.cls < 2) {
                     const unsigned so = (unsigned)tz * plane_bytes;
                     if (std::is_same<T, __half>::value && p.fp16_sr) {
@@ -522,50 +239,13 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 // refill with plane pz + RING (unconditional; past the chunk it
                 // re-reads plane z1, which is cached and never consumed)
                 if (k + RING < NZC + 2) issue(ring[rj], min(pz + RING, z1));
-                const float rho = 1.0f + dr;
-                const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
-                float E0 = fmaf(rho, -1.5f * usq, dr);
-                float r45 = 4.5f * rho;
-                float rA = A * rho;
-                if (MASK && cls >= 2) {
-                    E0 = 0.0f;
-                    r45 = 0.0f;
-                    rA = 0.0f;
-                }
-                // the five links with v_y = sgn (Y halo) or v_x = sgn (X halo)
-                const float ua = (role == HALO_Y) ? uy : ux;  // along the halo direction
-                const float ub = (role == HALO_Y) ? ux : uy;  // across it, in plane
-                const float cs = sgn * ua;
-                const float Lup = lterm(cs + uz, E0, r45, rA);  // v_z = +1
-                const float Lmid = lterm(cs, E0, r45, rA);      // v_z = 0
-                const float Ldn = lterm(cs - uz, E0, r45, rA);  // v_z = -1
-                hp[j1] = Lup;
-                hz[j1] = Lup;
-                hp[j] = fmaf(2.0f, Lmid, hp[j]);
-                hd1[j] = lterm(cs + ub, E0, r45, rA);  // diagonal, + across
-                hd2[j] = lterm(cs - ub, E0, r45, rA);  // diagonal, - across
-                hp[jm] += Ldn;
-                hz[jm] -= Ldn;
+                push_halo<MASK>(dr, ux, uy, uz, cls, A, role == HALO_Y, sgn, hp[j1], hz[j1], hp[j],
+                                hd1[j], hd2[j], hp[jm], hz[jm]);
                 if (k < 2) return;
                 if (NBUF == 1 && k > 2) __syncthreads();
-                float2(*P)[NSLOT] = xp[k % NBUF];
-                float(*Dg)[NSLOT] = xd[k % NBUF];
-                if (active) {
-                    const int hi = sgn > 0.0f ? 0 : 1;
-                    if (role == HALO_Y) {
-                        // (PN, ZN) below the tile or (PS, ZS) above it;
-                        // diagonals (NE, NW) below or (SE, SW) above
-                        P[2 + hi][slot] = make_float2(hp[jm], hz[jm]);
-                        Dg[2 * hi][slot] = hd1[jm];
-                        Dg[2 * hi + 1][slot] = hd2[jm];
-                    } else {
-                        // (PE, ZE) left of the tile or (PW, ZW) right of it;
-                        // diagonals NE, SE (left) or NW, SW (right)
-                        P[hi][slot] = make_float2(hp[jm], hz[jm]);
-                        Dg[hi][slot] = hd1[jm];      // (sgn, +1, 0)
-                        Dg[hi + 2][slot] = hd2[jm];  // (sgn, -1, 0)
-                    }
-                }
+                if (active)
+                    put_halo(Xchg<NSLOT>{xp[k % NBUF], xd[k % NBUF]}, slot, role == HALO_Y, sgn,
+                             hp[jm], hz[jm], hd1[jm], hd2[jm]);
                 __syncthreads();
             }
         });

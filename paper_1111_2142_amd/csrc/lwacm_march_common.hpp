@@ -1,0 +1,457 @@
+// lwacm_march_common.hpp -- pieces shared by the D3Q19 z-marching tile
+// kernels: compile-time plane loop, per-plane accumulators, buffer-resource
+// loads and stores of the node-interleaved state, and the link term.
+#pragma once
+
+#include <type_traits>
+#include <utility>
+
+#include "lwacm_device.hpp"
+#include "lwacm_internal.hpp"
+
+namespace lwacm {
+
+namespace {
+
+// Compile-time loop: f(std::integral_constant<int, K>) for K = 0 .. N-1.
+// The plane loop runs through it so that every ring and accumulator index is
+// a constant expression from the start and all per-plane state stays in
+// registers.
+template <class F, int... K>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, K...>)
+{
+    (f(std::integral_constant<int, K>{}), ...);
+}
+
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Plane loop of N >= 9 iterations in small code: six specialised iterations,
+// a loop unrolled by three (the period of the accumulator and load-ring
+// rotations, so every register index stays a compile-time constant and the
+// back edge needs no copies), then three to five specialised iterations, so
+// that every loop iteration has a plane left to prefetch.  The body is called
+// as body(k, K) with the iteration index k and a std::integral_constant K:
+// K = k in the specialised iterations, K = k % 3 - 3 in the loop, so that
+// k % 3, the early-iteration phases and the prefetch condition are all
+// compile-time constants.
+template <int N, class F>
+__device__ __forceinline__ void plane_loop(F &&body)
+{
+    static_assert(N >= 9, "plane loop needs at least nine iterations");
+    constexpr int T = 3 + (N - 9) % 3;  // specialised tail iterations
+    static_for<6>([&](auto kc) { body((int)decltype(kc)::value, kc); });
+#pragma unroll 1
+    for (int k = 6; k < N - T; k += 3) {
+        body(k, std::integral_constant<int, -3>{});
+        body(k + 1, std::integral_constant<int, -2>{});
+        body(k + 2, std::integral_constant<int, -1>{});
+    }
+    static_for<T>([&](auto tc) {
+        constexpr int k = N - T + decltype(tc)::value;
+        body(k, std::integral_constant<int, k>{});
+    });
+}
+
+// What a plane-loop body needs to know about iteration K at compile time.
+template <int K, int N, int RING>
+struct PlaneIter {
+    static constexpr int j = K >= 0 ? K % 3 : K + 3;     // k % 3
+    static constexpr int phase = K >= 0 && K < 5 ? K : 5;  // min(k, 5)
+    static constexpr bool refill = K < 0 || K + RING < N;  // a plane left to prefetch
+};
+
+// Per target plane accumulator of an interior column.
+struct Acc {
+    float pe, ze, pw, zw, pn, zn, ps, zs;  // direction partials (weights folded)
+    float ne, nw, se, sw;                  // in-plane diagonals
+    float d, jz;                           // own column: rest + (0,0,+-1) links
+    float post[3];                         // a rho u of the node itself
+    float own[6];                          // E0, 4.5 rho, A rho, u (bounce-back only)
+    unsigned bits;                         // solid upstream links (bounce-back only)
+    int cls;                               // 0 fluid, 1 fluid next to a wall, 2 solid
+};
+
+__device__ __forceinline__ bool has_bit(unsigned bits, int i) { return (bits >> i) & 1u; }
+
+// Global memory goes through buffer resources: one descriptor per state
+// buffer in SGPRs, the column's fixed 32-bit byte offset in a VGPR and the
+// plane's byte offset as the scalar offset, so a load or store costs no
+// per-lane address arithmetic.  The state is node-interleaved, so one node of
+// one plane is a single 16-byte (FP32) or 8-byte (FP16) access.
+// (march_supported() guarantees that a state buffer fits in 4 GiB.)
+using Rsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned long long bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0,
+                                             (int)(unsigned)bytes, 0x00020000);
+}
+
+template <class T>
+struct BufIO;
+
+// Element access uses explicit .x/.y/.z/.w selection and whole-vector casts:
+// this compiler narrows a 128-bit load to its first dword when elements of
+// the loaded vector are taken apart with __builtin_bit_cast one by one.
+template <>
+struct BufIO<float> {
+    using Raw = f32x4;
+    static constexpr unsigned kNodeBytes = 16;
+    __device__ __forceinline__ static Raw load(Rsrc r, unsigned voff, unsigned soff)
+    {
+        return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    }
+    // field f (0: rho - 1, 1..3: u) of a loaded node
+    __device__ __forceinline__ static float value(const Raw &v, int f, float)
+    {
+        return f == 0 ? v.x : (f == 1 ? v.y : (f == 2 ? v.z : v.w));
+    }
+    __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float d,
+                                                 float ux, float uy, float uz, const float (&)[2])
+    {
+        const f32x4 v = {d, ux, uy, uz};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+        store_data_guard();
+    }
+    __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float d,
+                                                    float ux, float uy, float uz,
+                                                    const float (&sc)[2], const U32x4 &)
+    {
+        store(r, voff, soff, d, ux, uy, uz, sc);
+    }
+};
+
+template <>
+struct BufIO<__half> {
+    using Raw = u32x2;
+    static constexpr unsigned kNodeBytes = 8;
+    __device__ __forceinline__ static Raw load(Rsrc r, unsigned voff, unsigned soff)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    }
+    __device__ __forceinline__ static float value(const Raw &v, int f, float inv_scale)
+    {
+        const unsigned w = (f >> 1) ? v.y : v.x;
+        const unsigned short h = (unsigned short)((f & 1) ? w >> 16 : w & 0xffffu);
+        return __half2float(__ushort_as_half(h)) * inv_scale;
+    }
+    __device__ __forceinline__ static void put(Rsrc r, unsigned voff, unsigned soff,
+                                               unsigned short b0, unsigned short b1,
+                                               unsigned short b2, unsigned short b3)
+    {
+        const Raw v = {(unsigned)b0 | ((unsigned)b1 << 16), (unsigned)b2 | ((unsigned)b3 << 16)};
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+        store_data_guard();
+    }
+    __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float d,
+                                                 float ux, float uy, float uz,
+                                                 const float (&st)[2])
+    {
+        put(r, voff, soff, __half_as_ushort(__float2half_rn(d * st[0])),
+            __half_as_ushort(__float2half_rn(ux * st[1])),
+            __half_as_ushort(__float2half_rn(uy * st[1])),
+            __half_as_ushort(__float2half_rn(uz * st[1])));
+    }
+    __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float d,
+                                                    float ux, float uy, float uz,
+                                                    const float (&st)[2], const U32x4 &h)
+    {
+        put(r, voff, soff, half_bits_sr(d * st[0], h.x), half_bits_sr(ux * st[1], h.y),
+            half_bits_sr(uy * st[1], h.z), half_bits_sr(uz * st[1], h.w));
+    }
+};
+
+template <class T>
+struct Ring {
+    typename BufIO<T>::Raw v;  // the node's stored values on one plane
+    uint8_t cls;
+};
+
+// Unweighted link term with c = v_i . u (Eq. ACM2.0b pre-combining,
+// deviation form): L(c) = fma(A rho, c, m) with the even part
+// m = fma(4.5 rho c, c, E0).  m is bitwise even in c, so the pair of opposite
+// links shares it, and interior and halo threads, which both use exactly
+// these operations (the build disables FMA contraction), produce bitwise the
+// same term for a given link.
+__device__ __forceinline__ float lterm(float c, float E0, float r45, float rA)
+{
+    return fmaf(rA, c, fmaf(r45 * c, c, E0));
+}
+
+
+// Exchanged quantities per LDS slot, in arrays of one kind each so that every
+// LDS access has a 4- or 8-byte lane stride (no bank conflicts):
+//   P[0..3] = (PE, ZE), (PW, ZW), (PN, ZN), (PS, ZS): density and z parts of
+//             the links with (vx, vy) = (+1,0), (-1,0), (0,+1), (0,-1)
+//   Dg[0..3] = NE, NW, SE, SW: in-plane diagonals (+1,+1,0), (-1,+1,0),
+//              (+1,-1,0), (-1,-1,0)
+template <int NS>
+struct Xchg {
+    float2 (*P)[NS];
+    float (*Dg)[NS];
+};
+
+// The 18 moving links of a node with state (drho, u) on source plane pz,
+// pre-combined (Eq. ACM2.0b) and pushed, with integer weights 36 w_i folded
+// in, into the accumulators of its column: links with v_z = +1 start A1
+// (plane pz + 1), links with v_z = 0 complete the in-plane part of A0 (plane
+// pz) together with the rest link and the post-combine term a rho u, links
+// with v_z = -1 finish Am (plane pz - 1).  Opposite links share the even part
+// m(c) = E0 + 4.5 rho c^2 with E0 = drho - 1.5 rho |u|^2; a solid node pushes
+// zeros.  With MASK, A0 also keeps the class and the coefficients that the
+// bounce-back of its own links needs (its bit set is the caller's).
+template <bool MASK>
+__device__ __forceinline__ void push_column(float dr, float ux, float uy, float uz, int cls,
+                                            float A, float a, Acc &A1, Acc &A0, Acc &Am)
+{
+    const float rho = 1.0f + dr;
+    const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+    float E0 = fmaf(rho, -1.5f * usq, dr);
+    float r45 = 4.5f * rho;
+    float rA = A * rho;
+    if (MASK && cls >= 2) {  // solid: push nothing
+        E0 = 0.0f;
+        r45 = 0.0f;
+        rA = 0.0f;
+    }
+    auto pair = [&](float c, float &lp, float &lm) {
+        const float m = fmaf(r45 * c, c, E0);  // = lterm's even part
+        lp = fmaf(rA, c, m);                   // = lterm(c)
+        lm = fmaf(rA, -c, m);                  // = lterm(-c)
+    };
+    float Lpx, Lmx, Lpy, Lmy, Lpz, Lmz;
+    float Lpp0, Lmm0, Lpm0, Lmp0;  // (+x+y), (-x-y), (+x-y), (-x+y)
+    float Lp0p, Lm0m, Lp0m, Lm0p;  // (+x,+z), (-x,-z), (+x,-z), (-x,+z)
+    float L0pp, L0mm, L0pm, L0mp;  // (+y,+z), (-y,-z), (+y,-z), (-y,+z)
+    pair(ux, Lpx, Lmx);
+    pair(uy, Lpy, Lmy);
+    pair(uz, Lpz, Lmz);
+    pair(ux + uy, Lpp0, Lmm0);
+    pair(ux - uy, Lpm0, Lmp0);
+    pair(ux + uz, Lp0p, Lm0m);
+    pair(ux - uz, Lp0m, Lm0p);
+    pair(uy + uz, L0pp, L0mm);
+    pair(uy - uz, L0pm, L0mp);
+
+    // links with v_z = +1 start the accumulator of plane pz + 1
+    A1.pe = Lp0p;
+    A1.ze = Lp0p;
+    A1.pw = Lm0p;
+    A1.zw = Lm0p;
+    A1.pn = L0pp;
+    A1.zn = L0pp;
+    A1.ps = L0mp;
+    A1.zs = L0mp;
+    A1.d = 2.0f * Lpz;
+    A1.jz = 2.0f * Lpz;
+    // links with v_z = 0 complete the in-plane part of plane pz
+    A0.pe = fmaf(2.0f, Lpx, A0.pe);
+    A0.pw = fmaf(2.0f, Lmx, A0.pw);
+    A0.pn = fmaf(2.0f, Lpy, A0.pn);
+    A0.ps = fmaf(2.0f, Lmy, A0.ps);
+    A0.ne = Lpp0;
+    A0.nw = Lmp0;
+    A0.se = Lpm0;
+    A0.sw = Lmm0;
+    A0.d = fmaf(12.0f, E0, A0.d);
+    const float arho = a * rho;
+    A0.post[0] = arho * ux;
+    A0.post[1] = arho * uy;
+    A0.post[2] = arho * uz;
+    if (MASK) {
+        A0.cls = cls;
+        A0.bits = 0u;
+        A0.own[0] = E0;
+        A0.own[1] = r45;
+        A0.own[2] = rA;
+        A0.own[3] = ux;
+        A0.own[4] = uy;
+        A0.own[5] = uz;
+    }
+    // links with v_z = -1 finish plane pz - 1
+    Am.pe += Lp0m;
+    Am.ze -= Lp0m;
+    Am.pw += Lm0m;
+    Am.zw -= Lm0m;
+    Am.pn += L0pm;
+    Am.zn -= L0pm;
+    Am.ps += L0mm;
+    Am.zs -= L0mm;
+    Am.d = fmaf(2.0f, Lmz, Am.d);
+    Am.jz = fmaf(-2.0f, Lmz, Am.jz);
+}
+
+// A column's finished partials of one plane into its LDS slot.
+template <int NS>
+__device__ __forceinline__ void put_slot(const Xchg<NS> &X, int slot, const Acc &Am)
+{
+    X.P[0][slot] = make_float2(Am.pe, Am.ze);
+    X.P[1][slot] = make_float2(Am.pw, Am.zw);
+    X.P[2][slot] = make_float2(Am.pn, Am.zn);
+    X.P[3][slot] = make_float2(Am.ps, Am.zs);
+    X.Dg[0][slot] = Am.ne;
+    X.Dg[1][slot] = Am.nw;
+    X.Dg[2][slot] = Am.se;
+    X.Dg[3][slot] = Am.sw;
+}
+
+struct NodeOut {
+    float D, vx, vy, vz;  // new drho and u of Eqs. ACM2.0b
+};
+
+// Partials that the eight in-plane neighbour columns pushed into a node's
+// column for one plane (LDS slots around `slot`, row pitch SXP).
+struct Gathered {
+    float pE, zE, pW, zW, pN, zN, pS, zS;  // axis directions: density and z parts
+    float dNE, dNW, dSE, dSW;              // in-plane diagonals
+};
+
+template <int NS, int SXP>
+__device__ __forceinline__ Gathered gather(const Xchg<NS> &X, int slot)
+{
+    const float2 gW = X.P[0][slot - 1];    // west neighbour: PE, ZE
+    const float2 gE = X.P[1][slot + 1];    // east neighbour: PW, ZW
+    const float2 gS = X.P[2][slot - SXP];  // south: PN, ZN
+    const float2 gN = X.P[3][slot + SXP];  // north: PS, ZS
+    Gathered g;
+    g.pE = gW.x;
+    g.zE = gW.y;
+    g.pW = gE.x;
+    g.zW = gE.y;
+    g.pN = gS.x;
+    g.zN = gS.y;
+    g.pS = gN.x;
+    g.zS = gN.y;
+    g.dNE = X.Dg[0][slot - SXP - 1];
+    g.dNW = X.Dg[1][slot - SXP + 1];
+    g.dSE = X.Dg[2][slot + SXP - 1];
+    g.dSW = X.Dg[3][slot + SXP + 1];
+    return g;
+}
+
+// New moments of a node (Eqs. ACM2.0b): the links arriving from the
+// neighbour columns, the column's own partials and post-combine term,
+// halfway bounce-back of the links whose upstream node is solid (Eqs.
+// ACM2.0cbb-ACM2.0ccccbb: the node's own term of the opposite link returns,
+// recomputed from its saved coefficients with the same operations, plus the
+// moving-wall term from the geometry sums wallg[widx]), then the
+// normalisation by 1 + D.
+template <bool MASK>
+__device__ __forceinline__ NodeOut finish(const Gathered &g, const Acc &Am, const ProblemArgs &p,
+                                          const float4 *wallg, long long widx)
+{
+    float D36 = Am.d + ((g.pE + g.pW) + (g.pN + g.pS)) + ((g.dNE + g.dNW) + (g.dSE + g.dSW));
+    float Jx = (g.pE - g.pW) + ((g.dNE - g.dNW) + (g.dSE - g.dSW));
+    float Jy = (g.pN - g.pS) + ((g.dNE + g.dNW) - (g.dSE + g.dSW));
+    float Jz = Am.jz + ((g.zE + g.zW) + (g.zN + g.zS));
+    if (MASK && Am.bits != 0u) {
+#pragma unroll
+        for (int i = 1; i < 19; ++i) {
+            if (has_bit(Am.bits, i)) {
+                const int cx = link_cx(i), cy = link_cy(i), cz = link_cz(i);
+                float c = 0.0f;  // v_i . u, summed in the order push_column uses
+                if (cx != 0) c = cx > 0 ? c + Am.own[3] : c - Am.own[3];
+                if (cy != 0) c = cy > 0 ? c + Am.own[4] : c - Am.own[4];
+                if (cz != 0) c = cz > 0 ? c + Am.own[5] : c - Am.own[5];
+                const float m = fmaf(Am.own[1] * c, c, Am.own[0]);
+                const float s = Lattice<19>::w36(i) * fmaf(Am.own[2], -c, m);
+                D36 += s;
+                Jx = fmaf((float)cx, s, Jx);
+                Jy = fmaf((float)cy, s, Jy);
+                Jz = fmaf((float)cz, s, Jz);
+            }
+        }
+        // moving walls (Eq. ACM2.0ccccbb): (1 - a) 6 rho0 times the node's
+        // geometry sums of 36 w_i (1, v_i) (v_i . u_w)
+        if (Am.bits & kMovingWallFlag) {
+            const float4 w = wallg[widx];
+            D36 = fmaf(p.wall_scale, w.x, D36);
+            Jx = fmaf(p.wall_scale, w.y, Jx);
+            Jy = fmaf(p.wall_scale, w.z, Jy);
+            Jz = fmaf(p.wall_scale, w.w, Jz);
+        }
+    }
+    Jx = div36(Jx) + Am.post[0];
+    Jy = div36(Jy) + Am.post[1];
+    Jz = div36(Jz) + Am.post[2];
+    NodeOut o;
+    o.D = div36(D36);
+    const float q = normalisation_factor(o.D);
+    o.vx = fmaf(-Jx, q, Jx);
+    o.vy = fmaf(-Jy, q, Jy);
+    o.vz = fmaf(-Jz, q, Jz);
+    return o;
+}
+
+template <bool MASK, int NS, int SXP>
+__device__ __forceinline__ NodeOut finalize(const Xchg<NS> &X, int slot, const Acc &Am,
+                                            const ProblemArgs &p, const float4 *wallg,
+                                            long long widx)
+{
+    return finish<MASK>(gather<NS, SXP>(X, slot), Am, p, wallg, widx);
+}
+
+// A halo column pushes only the five links that point into the tile: those
+// with v_y = sgn (isY: a row below or above the tile) or v_x = sgn (a column
+// left or right of it, corners included).  The terms go into the halo's
+// partials of target planes pz + 1 (p1, z1), pz (p0 and the two in-plane
+// diagonals d1 = across +1, d2 = across -1) and pz - 1 (pm, zm).  The same
+// operations as push_column's pairs, so interior and halo produce bitwise
+// the same term for a given link.
+template <bool MASK>
+__device__ __forceinline__ void push_halo(float dr, float ux, float uy, float uz, int cls,
+                                          float A, bool isY, float sgn, float &p1, float &z1,
+                                          float &p0, float &d1, float &d2, float &pm, float &zm)
+{
+    const float rho = 1.0f + dr;
+    const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+    float E0 = fmaf(rho, -1.5f * usq, dr);
+    float r45 = 4.5f * rho;
+    float rA = A * rho;
+    if (MASK && cls >= 2) {
+        E0 = 0.0f;
+        r45 = 0.0f;
+        rA = 0.0f;
+    }
+    const float ua = isY ? uy : ux;  // along the halo direction
+    const float ub = isY ? ux : uy;  // across it, in plane
+    const float cs = sgn * ua;
+    const float Lup = lterm(cs + uz, E0, r45, rA);  // v_z = +1
+    const float Lmid = lterm(cs, E0, r45, rA);      // v_z = 0
+    const float Ldn = lterm(cs - uz, E0, r45, rA);  // v_z = -1
+    p1 = Lup;
+    z1 = Lup;
+    p0 = fmaf(2.0f, Lmid, p0);
+    d1 = lterm(cs + ub, E0, r45, rA);
+    d2 = lterm(cs - ub, E0, r45, rA);
+    pm += Ldn;
+    zm -= Ldn;
+}
+
+// A halo column's finished partials of one plane into the slots that its
+// inward neighbours read: (PN, ZN) and diagonals NE, NW below the tile,
+// (PS, ZS), SE, SW above it; (PE, ZE), NE, SE left of it, (PW, ZW), NW, SW
+// right of it.
+template <int NS>
+__device__ __forceinline__ void put_halo(const Xchg<NS> &X, int slot, bool isY, float sgn, float p,
+                                         float z, float d1, float d2)
+{
+    const int hi = sgn > 0.0f ? 0 : 1;
+    const int ip = isY ? 2 + hi : hi;
+    const int i1 = isY ? 2 * hi : hi;
+    const int i2 = isY ? 2 * hi + 1 : hi + 2;
+    X.P[ip][slot] = make_float2(p, z);
+    X.Dg[i1][slot] = d1;
+    X.Dg[i2][slot] = d2;
+}
+
+}  // namespace
+
+}  // namespace lwacm

@@ -18,7 +18,7 @@ LWACM_D2Q9, LWACM_D3Q19 = 9, 19
 LWACM_FP32, LWACM_FP16_DEV = 0, 1
 LWACM_OK, LWACM_EINVAL, LWACM_ENOMEM, LWACM_EDEVICE, LWACM_ENONFINITE, LWACM_EUNSUPPORTED = (
     0, -1, -2, -3, -4, -5)
-LWACM_KERNEL_AUTO, LWACM_KERNEL_GENERIC, LWACM_KERNEL_MARCH = 0, 1, 2
+LWACM_KERNEL_AUTO, LWACM_KERNEL_GENERIC, LWACM_KERNEL_MARCH, LWACM_KERNEL_MARCH2 = 0, 1, 2, 3
 LWACM_ROUND_NEAREST, LWACM_ROUND_STOCHASTIC = 0, 1
 
 _lib = None
