@@ -3,10 +3,12 @@
 Workload: D3Q19 Taylor-Green vortex on a 256^3 periodic grid (u0 = 0.02,
 omega = 1.7), synthetic initial field, state resident in HBM.  A timed step
 is one full forward step (gather, link terms, post-combine, normalisation,
-store, fused FP64 mass/energy reduction).  Reported beside it: the same
-step with FP16-deviation storage, the reverse (adjoint) step and the
-checkpointed forward+reverse cost, the roofline of the forward kernel, and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+store, fused FP64 mass/energy reduction); the library runs FP32 steps two
+per launch (the intermediate state stays on chip).  Reported beside it: the
+single-step kernel, the same step with FP16-deviation storage, the reverse
+(adjoint) step and the checkpointed forward+reverse cost, the rooflines of
+the forward kernel (HBM at 32 bytes per lattice update, and VALU issue),
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
@@ -23,12 +25,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS D3Q19 256^3 FP32 (vs FP16-store); adjoint/forward step time ratio"
 HBM_PEAK_GBS = 8000.0
+# VALU issue: 256 CUs x 4 SIMDs, one wave64 FP32 instruction per 4 cycles, 2.4 GHz
+VALU_WAVE_INSTS_PER_S = 1024 * 2.4e9 / 4
+FP32_PEAK_TFLOPS = 157.3           # packed FP32 FMA (published vector peak)
+FP32_UNPACKED_TFLOPS = 78.6        # one FP32 FMA per lane per cycle (this build: no packing)
+# FP32 operations of one lattice update in the tile kernels (Eqs. ACM2.0b as
+# implemented, mass/energy sums included): 47 FMA, 40 add/sub, 22 mul, 1 rcp
+FLOPS_PER_UPDATE = 2 * 47 + 40 + 22 + 1
 
 
-def _measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from its FETCH_SIZE/WRITE_SIZE counter
-    runs (scaled by the copy-kernel calibration), or None when the kernel's
-    sources changed since the counters were taken."""
+def _measured(kernel: str, key: str = "hbm_bytes_per_launch"):
+    """A counter-derived figure of `kernel` (HBM bytes per launch from its
+    FETCH_SIZE/WRITE_SIZE runs scaled by the copy-kernel calibration, or its
+    VALU instructions per launch), or None when the kernel's sources changed
+    since the counters were taken."""
     import hashlib
     pkg = os.path.join(ROOT, "paper_1111_2142_amd")
     try:
@@ -39,7 +49,11 @@ def _measured_traffic(kernel: str):
     for f in rec["sources"]:
         with open(os.path.join(pkg, f), "rb") as fh:
             h.update(fh.read())
-    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+    return rec.get(key) if h.hexdigest() == rec["sources_sha256"] else None
+
+
+def _measured_traffic(kernel: str):
+    return _measured(kernel, "hbm_bytes_per_launch")
 
 
 def _events_time(fn, n, stream):
@@ -60,7 +74,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 generic, 2 march")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="0 auto, 1 generic, 2 march (one step per launch), 3 march2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forward-only", action="store_true",
                     help="time only the forward step of the 256^3 workload (for profiler runs)")
@@ -157,6 +172,10 @@ def main():
 
     bytes32 = 32.0 * nodes
     achieved = bytes32 / (ms32 * 1e-3) / 1e9
+    fused = n == 256 and args.variant in (0, 3) and args.steps % 2 == 0
+    kname = "k_fwd_march2<128>" if fused else "k_fwd_march<float,false,128>"
+    per_launch = 2 if fused else 1
+    t_launch = ms32 * 1e-3 * per_launch  # seconds per launch of the dominant kernel
     result = {
         "metric": METRIC,
         "value": round(mlups32, 1),
@@ -175,17 +194,48 @@ def main():
                    "diagnostics": "fused FP64 mass+energy every step"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": None, "algorithmic_bytes": int(bytes32)},
+                     "traffic": None, "kernel": None,
+                     "algorithmic_bytes": int(bytes32 * per_launch),
+                     "updates_per_launch": per_launch,
+                     "basis": "32 B per lattice update (one state read and one write per "
+                              "update, the single-step minimum) x updates per launch / launch "
+                              "time; the two-step kernel moves 16 B per update (traffic) and "
+                              "is bound by VALU issue (valu)"},
     }
-    if n == 256 and args.variant in (0, 2):
-        result["roofline"]["kernel"] = "k_fwd_march<float,false,128>"
-        result["roofline"]["traffic"] = _measured_traffic("k_fwd_march<float,false,128>")
+    if n == 256 and args.variant in (0, 2, 3):
+        result["roofline"]["kernel"] = kname
+        result["roofline"]["traffic"] = _measured_traffic(kname)
+        vi = _measured(kname, "valu_insts_per_launch")
+        tflops = FLOPS_PER_UPDATE * nodes * per_launch / t_launch / 1e12
+        result["valu"] = {
+            "kernel": kname, "insts_per_launch": vi,
+            "issue_frac": None if vi is None else
+            round(vi / (VALU_WAVE_INSTS_PER_S * t_launch), 4),
+            "flops_per_update": FLOPS_PER_UPDATE, "achieved_tflops": round(tflops, 2),
+            "peak_tflops": FP32_PEAK_TFLOPS, "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
+            "peak_unpacked_tflops": FP32_UNPACKED_TFLOPS,
+            "frac_unpacked": round(tflops / FP32_UNPACKED_TFLOPS, 4)}
     if args.forward_only:
         print(json.dumps(result), flush=True)
         return
 
+    # ---- the single-step tile kernel (32 B of HBM per update)
+    s1 = L.Solver(L.LWACM_D3Q19, n, n, n, cfg.omega, device=dev, variant=L.LWACM_KERNEL_MARCH)
+    s1.set_state(drho_t, u_t)
+    s1.step(args.warmup)
+    dt1 = _events_time(s1.step, args.steps, stream)
+    s1.close()
+    ms1 = dt1 / args.steps * 1e3
+    print(f"[bench] fp32 single-step kernel: {ms1:.4f} ms/step", file=sys.stderr, flush=True)
+    result["single_step"] = {
+        "value": round(nodes * args.steps / dt1 / 1e6, 1), "unit": "MLUPS",
+        "ms_per_step": round(ms1, 5),
+        "achieved_GBs": round(32.0 * nodes / (ms1 * 1e-3) / 1e9, 1),
+        "frac": round(32.0 * nodes / (ms1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernel": "k_fwd_march<float,false,128>" if n == 256 else None,
+        "traffic": _measured_traffic("k_fwd_march<float,false,128>") if n == 256 else None}
+
     # ---- FP16-deviation storage
-    s32_state = None
     s16 = make(L.LWACM_FP16_DEV)
     s16.step(args.warmup)
     dt16 = _events_time(s16.step, args.steps, stream)
@@ -228,6 +278,7 @@ def main():
     print(f"[bench] reverse step: {msa:.4f} ms/step", file=sys.stderr, flush=True)
     result["adjoint"] = {"ms_per_step": round(msa, 5),
                          "adjoint_forward_ratio": round(msa / ms32, 3),
+                         "adjoint_single_step_ratio": round(msa / ms1, 3),
                          "with_recompute_ratio": round((msa + ms32) / ms32, 3),
                          "achieved_GBs": round(48.0 * nodes / (msa * 1e-3) / 1e9, 1),
                          "kernel": "k_adj_march<float,false>" if n == 256 else None,
