@@ -82,7 +82,8 @@ def main():
     ap.add_argument("--storage", choices=["fp32", "fp16"], default="fp32",
                     help="storage of the --forward-only run")
     ap.add_argument("--reverse-only", action="store_true",
-                    help="time only the reverse (adjoint) step of the 256^3 workload")
+                    help="time only the reverse (adjoint) step of the 256^3 workload (two per "
+                         "launch; --variant 2: one per launch)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of 256 MiB (the reference kernel for "
                          "scaling HBM byte counters) and exit")
@@ -137,11 +138,19 @@ def main():
         dw = torch.zeros(1, dtype=torch.float64, device=dev)
         L.lwacm_adjoint_seed(s.ctx, st, lam, mu_a)
 
+        two = args.variant in (0, 3)
+
         def rev(k):
             a_, b_ = mu_a, mu_b
-            for _ in range(k):
-                L.lwacm_adjoint_step(s.ctx, st, a_, b_, dw, False)
-                a_, b_ = b_, a_
+            if two:
+                for _ in range(k // 2):
+                    if not L.lwacm_adjoint_step2(s.ctx, st, st, a_, b_, dw, False):
+                        raise RuntimeError("two-step reverse kernel declined the 256^3 problem")
+                    a_, b_ = b_, a_
+            else:
+                for _ in range(k):
+                    L.lwacm_adjoint_step(s.ctx, st, a_, b_, dw, False)
+                    a_, b_ = b_, a_
 
         rev(args.warmup)
         dt = _events_time(rev, args.steps, stream)
@@ -264,26 +273,45 @@ def main():
     lam = torch.zeros_like(mu_a)
     lam[1:] = u_t
     L.lwacm_adjoint_seed(s32.ctx, st, lam, mu_a)
-    nadj = max(10, args.steps // 4)
+    nadj = 2 * max(5, args.steps // 8)  # even: the sweep runs two reverse steps per launch
 
-    def adj(k):
+    def adj(k, two=True):
         a, b = mu_a, mu_b
-        for _ in range(k):
-            L.lwacm_adjoint_step(s32.ctx, st, a, b, dw, False)
-            a, b = b, a
+        if two:
+            for _ in range(k // 2):
+                if not L.lwacm_adjoint_step2(s32.ctx, st, st, a, b, dw, False):
+                    raise RuntimeError("two-step reverse kernel declined the problem")
+                a, b = b, a
+        else:
+            for _ in range(k):
+                L.lwacm_adjoint_step(s32.ctx, st, a, b, dw, False)
+                a, b = b, a
 
-    adj(3)
+    adj(4)
     dta = _events_time(adj, nadj, stream)
     msa = dta / nadj * 1e3
-    print(f"[bench] reverse step: {msa:.4f} ms/step", file=sys.stderr, flush=True)
+    adj(4, False)
+    dta1 = _events_time(lambda k: adj(k, False), nadj, stream)
+    msa1 = dta1 / nadj * 1e3
+    print(f"[bench] reverse step: {msa:.4f} ms/step (two per launch), {msa1:.4f} ms one per "
+          f"launch", file=sys.stderr, flush=True)
     result["adjoint"] = {"ms_per_step": round(msa, 5),
                          "adjoint_forward_ratio": round(msa / ms32, 3),
-                         "adjoint_single_step_ratio": round(msa / ms1, 3),
                          "with_recompute_ratio": round((msa + ms32) / ms32, 3),
-                         "achieved_GBs": round(48.0 * nodes / (msa * 1e-3) / 1e9, 1),
-                         "kernel": "k_adj_march<float,false>" if n == 256 else None,
-                         "traffic": _measured_traffic("k_adj_march<float,false>")
-                         if n == 256 else None}
+                         "achieved_GBs": round(32.0 * nodes / (msa * 1e-3) / 1e9, 1),
+                         "basis": "reverse steps two per launch (lwacm_adjoint_step2): state_t, "
+                                  "state_t-1, mu in, mu out = 32 B per node and step",
+                         "kernel": "k_adj_march2<float,false,64>" if n == 256 else None,
+                         "traffic": _measured_traffic("k_adj_march2<float,false,64>")
+                         if n == 256 else None,
+                         "one_step_kernel": {
+                             "ms_per_step": round(msa1, 5),
+                             "adjoint_forward_ratio": round(msa1 / ms32, 3),
+                             "ratio_to_single_step_forward": round(msa1 / ms1, 3),
+                             "achieved_GBs": round(48.0 * nodes / (msa1 * 1e-3) / 1e9, 1),
+                             "kernel": "k_adj_march<float,false>" if n == 256 else None,
+                             "traffic": _measured_traffic("k_adj_march<float,false>")
+                             if n == 256 else None}}
     s32.close()
     del mu_a, mu_b, lam, st
     torch.cuda.empty_cache()

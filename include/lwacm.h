@@ -215,6 +215,22 @@ int lwacm_adjoint_seed(lwacm_ctx *c, const void *d_state_T, const float *d_lambd
 int lwacm_adjoint_step(lwacm_ctx *c, const void *d_state_t, const float *d_mu_in, float *d_mu_out,
                        double *d_dL_domega, int final_t0);
 
+/*
+ * lwacm_adjoint_step2: two reverse steps in one launch (D3Q19 tile-kernel
+ * grids without walls, nz >= 8; variant AUTO or MARCH2): the same result as
+ *     lwacm_adjoint_step(c, d_state_t,   d_mu_in, tmp,      w, 0);
+ *     lwacm_adjoint_step(c, d_state_tm1, tmp,     d_mu_out, w, final_t0);
+ * (bitwise in d_mu_out; *d_dL_domega receives the same two additions) with
+ * the intermediate mu kept on chip: 32 instead of 48 bytes of HBM per node
+ * and step.  d_state_t and d_state_tm1 are the inputs of forward steps t and
+ * t - 1 (storage format); d_mu_in = mu_t, node-interleaved.  final_t0: the
+ * second step is step 0, write its lambda field-major.  LWACM_EUNSUPPORTED
+ * (nothing launched) where the kernel does not apply; then call
+ * lwacm_adjoint_step twice.  d_mu_out must not alias d_mu_in.  Asynchronous.
+ */
+int lwacm_adjoint_step2(lwacm_ctx *c, const void *d_state_t, const void *d_state_tm1,
+                        const float *d_mu_in, float *d_mu_out, double *d_dL_domega, int final_t0);
+
 /* Release the library's scratch.  Caller buffers are untouched. */
 void lwacm_destroy(lwacm_ctx *c);
 

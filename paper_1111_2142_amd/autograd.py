@@ -5,7 +5,7 @@ Forward: run ``nsteps`` steps from (rho0 - 1, u0), saving the state (storage
 format) every ``K`` steps.  Backward: seed mu from the loss cotangent of the
 final state, then for each segment from last to first restore its
 checkpoint, recompute the segment's states into a K-slot buffer and apply
-the reverse step K times.  The omega gradient is accumulated in FP64 on the
+the reverse step K times (two per launch where the library supports it).  The omega gradient is accumulated in FP64 on the
 device.  Every arithmetic step runs in the library's kernels; this module
 only sequences the calls.
 """
@@ -63,9 +63,16 @@ class _Run(torch.autograd.Function):
                 solver.save_state(seg_buf[j])
                 if j + 1 < nseg:
                     solver.step(1)
-            for j in reversed(range(nseg)):
-                final = (t0 + j == 0)
-                L.lwacm_adjoint_step(solver.ctx, seg_buf[j], mu, mu_next, dw, final)
+            # reverse steps two per launch where the library can (the same
+            # result as two single calls), single steps otherwise
+            j = nseg - 1
+            while j >= 0:
+                if j >= 1 and L.lwacm_adjoint_step2(solver.ctx, seg_buf[j], seg_buf[j - 1], mu,
+                                                    mu_next, dw, t0 + j - 1 == 0):
+                    j -= 2
+                else:
+                    L.lwacm_adjoint_step(solver.ctx, seg_buf[j], mu, mu_next, dw, t0 + j == 0)
+                    j -= 1
                 mu, mu_next = mu_next, mu
         if ctx.nsteps == 0:
             mu = lam

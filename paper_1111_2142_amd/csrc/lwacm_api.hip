@@ -237,6 +237,8 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
     if (ab > nb) nb = ab;
     const size_t fb = lwacm::march2_num_blocks(p);
     if (fb > nb) nb = fb;
+    const size_t rb = lwacm::adj_march2_num_blocks(p);
+    if (rb > nb) nb = rb;
     c->n_partial_blocks = nb;
     // four partial sets of 2 doubles per block: a forward launch (one or two
     // steps) defers its second reduction passes into the next launch, so the
@@ -526,6 +528,23 @@ int lwacm_adjoint_step(lwacm_ctx *c, const void *d_state_t, const float *d_mu_in
                                                c->d_bits, c->d_wallg, final_t0, r, c->stream));
     return dev_err(lwacm::launch_adj_generic(c->p, c->storage, d_state_t, d_mu_in, d_mu_out,
                                              final_t0, r, lwacm::generic_grid(c->p.n), c->stream));
+}
+
+int lwacm_adjoint_step2(lwacm_ctx *c, const void *d_state_t, const void *d_state_tm1,
+                        const float *d_mu_in, float *d_mu_out, double *d_dL_domega, int final_t0)
+{
+    if (!c || !d_state_t || !d_state_tm1 || !d_mu_in || !d_mu_out || !d_dL_domega ||
+        d_mu_in == d_mu_out)
+        return LWACM_EINVAL;
+    if ((c->variant != LWACM_KERNEL_AUTO && c->variant != LWACM_KERNEL_MARCH2) ||
+        !lwacm::adj_march2_supported(c->p))
+        return LWACM_EUNSUPPORTED;
+    ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
+    r.accumulate = 1;
+    r.out_scale = 2.0 / (c->omega * c->omega);  // da/domega for a = 2 - 2/omega
+    r.partials_b = c->d_partials + c->n_partial_blocks;
+    return dev_err(lwacm::launch_adj_march2(c->p, c->storage, d_state_t, d_state_tm1, d_mu_in,
+                                            d_mu_out, final_t0, r, c->stream));
 }
 
 void lwacm_destroy(lwacm_ctx *c)

@@ -99,6 +99,16 @@ hipError_t launch_adj_march(const ProblemArgs &p, int storage, const void *state
 hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, void *dst,
                             const uint8_t *cls, const unsigned *bits, const float4 *wallg,
                             const ReduceArgs &r, hipStream_t stream);
+// Two D3Q19 reverse steps per launch (steps t and t - 1, unmasked, nz >= 8):
+// mu_in = mu_t, state_t and state_tm1 the inputs of forward steps t and
+// t - 1; writes mu_{t-2}, or the field-major gradient when final_t0.  Stores
+// the two steps' dL/da partials in r.partials and r.partials_b (one double
+// per block each) and adds them to r.out in that order.
+bool adj_march2_supported(const ProblemArgs &p);
+unsigned adj_march2_num_blocks(const ProblemArgs &p);
+hipError_t launch_adj_march2(const ProblemArgs &p, int storage, const void *state_t,
+                             const void *state_tm1, const float *mu_in, float *mu_out,
+                             int final_t0, const ReduceArgs &r, hipStream_t stream);
 // Two D3Q19 forward steps per launch on FP32 state (same tiles as the
 // single-step kernel, its chunk depth halved while deeper than nz;
 // unmasked problems without body force, nz >= 8).  Stores the first step's

@@ -36,16 +36,11 @@ constexpr int TX = 32;
 constexpr int TY = 16;
 constexpr int RING = 3;                              // planes of step t in flight per thread
 constexpr int NINT = TX * TY;                        // tile columns: waves 0-7
-constexpr int NRING = 2 * (TX + 2) + 2 * TY;         // columns around the tile
-constexpr int NHALO = 2 * (TX + 2) + 2 * (TY + 4);   // columns at distance two
-constexpr int RING0 = NINT;                          // first thread of each role
-constexpr int HALO0 = NINT + 2 * kWave;
+constexpr int HALO0 = NINT + 2 * kWave;              // first thread of the outer ring
 constexpr int NTHREADS = NINT + 4 * kWave;
 constexpr int SX1 = TX + 4, NS1 = SX1 * (TY + 4);    // first-step exchange slots
 constexpr int SX2 = TX + 2, NS2 = SX2 * (TY + 2);    // second-step exchange slots
 
-static_assert(NINT % kWave == 0, "tile must be whole waves");
-static_assert(NRING <= 2 * kWave && NHALO <= 2 * kWave, "rings must fit two waves each");
 
 // Second pass of up to two previous steps' (mass, energy) sums, by block 0:
 // the same fixed order as k_reduce_partials, the older step written first.
@@ -102,76 +97,22 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
     const long long n = p.n;
     const long long plane = (long long)nx * ny;
 
-    // XCD-aware order: consecutive blocks of one XCD get neighbouring tiles.
-    const unsigned nb = gridDim.x;
-    const unsigned b = blockIdx.x;
-    const unsigned lb = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + b / 8u : b;
-    const int tiles_x = nx / TX;
-    const int tiles_y = ny / TY;
-    const int tile_x = (int)(lb % (unsigned)tiles_x);
-    const unsigned rest = lb / (unsigned)tiles_x;
-    const int tile_y = (int)(rest % (unsigned)tiles_y);
-    const int zc = (int)(rest / (unsigned)tiles_y);
+    const TileIdx ti = tile_of_block(nx, ny, TX, TY);
     // Every chunk is NZC planes deep (nz >= NZC): a ragged last chunk is moved
     // down to end at nz.  Planes it shares with the chunk below are written
     // twice with bitwise the same values and counted in the sums only once,
     // from zs on, so each block sums the planes the single-step kernel's
     // block of the same index sums.
-    const int zs = zc * NZC;
+    const int zs = ti.zc * NZC;
     const int z0 = min(zs, nz - NZC);
     const int z1 = z0 + NZC;
 
-    // Column of this thread in tile coordinates [-2, TX + 1] x [-2, TY + 1].
-    int lx = 0, ly = 0;
-    float sgn = 1.0f;     // outer ring: direction sign of its inward links
-    bool isY = false;     // outer ring: row below/above (true) or column left/right
-    bool active = true;   // writes to LDS
-    if (tid < NINT) {
-        lx = tid % TX;
-        ly = tid / TX;
-    } else if (tid < HALO0) {
-        const int q = tid - RING0;
-        if (q < TX + 2) {  // row below the tile, corners included
-            lx = q - 1;
-            ly = -1;
-        } else if (q < 2 * (TX + 2)) {  // row above
-            lx = q - (TX + 2) - 1;
-            ly = TY;
-        } else if (q < 2 * (TX + 2) + TY) {  // column left of the tile
-            lx = -1;
-            ly = q - 2 * (TX + 2);
-        } else if (q < NRING) {  // column right of it
-            lx = TX;
-            ly = q - 2 * (TX + 2) - TY;
-        } else {
-            active = false;
-        }
-    } else {
-        const int q = tid - HALO0;
-        if (q < TY + 4) {  // outer left column (corners included), pushing east
-            lx = -2;
-            ly = q - 2;
-        } else if (q < 2 * (TY + 4)) {  // outer right column, pushing west
-            lx = TX + 1;
-            ly = q - (TY + 4) - 2;
-            sgn = -1.0f;
-        } else if (q < 2 * (TY + 4) + TX + 2) {  // outer bottom row, pushing north
-            isY = true;
-            lx = q - 2 * (TY + 4) - 1;
-            ly = -2;
-        } else if (q < NHALO) {  // outer top row, pushing south
-            isY = true;
-            lx = q - 2 * (TY + 4) - (TX + 2) - 1;
-            ly = TY + 1;
-            sgn = -1.0f;
-        } else {
-            active = false;
-        }
-    }
-    int gx = tile_x * TX + lx;
-    int gy = tile_y * TY + ly;
-    gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
-    gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+    const Col2 c2 = col2_of<TX, TY>(tid);
+    const int lx = c2.lx, ly = c2.ly;
+    const float sgn = c2.sgn;
+    const bool isY = c2.isY, active = c2.active;
+    const int gx = wrap_index(ti.tile_x * TX + lx, nx);
+    const int gy = wrap_index(ti.tile_y * TY + ly, ny);
     const unsigned col = (unsigned)(gy * nx + gx);  // offset inside a plane (< 2^31)
     const int slot1 = (ly + 2) * SX1 + (lx + 2);
     const int slot2 = (ly + 1) * SX2 + (lx + 1);    // tile and first ring only
@@ -187,7 +128,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
     const float a = p.a;
 
     // plane index with periodic wrap (nz >= NZC >= 2, so one period suffices)
-    auto wrapz = [&](int pz) { return pz < 0 ? pz + nz : (pz >= nz ? pz - nz : pz); };
+    auto wrapz = [&](int pz) { return wrap_index(pz, nz); };
     constexpr unsigned NB = BufIO<float>::kNodeBytes;
     const unsigned plane_bytes = (unsigned)(plane * (long long)NB);
     const unsigned long long sbytes = (unsigned long long)n * NB;

@@ -452,6 +452,98 @@ __device__ __forceinline__ void put_halo(const Xchg<NS> &X, int slot, bool isY, 
     X.Dg[i2][slot] = d2;
 }
 
+// Thread roles of the two-step kernels (tile TX x TY, one thread per
+// column): threads [0, TX*TY) own the tile; the next two waves the ring of
+// columns around it (rows below/above it with the corners, then the columns
+// left/right of it); the last two waves the ring at distance two (columns
+// left/right with the corners, then the rows below/above).  For that outer
+// ring, isY and sgn give the direction of its inward links (a row below the
+// tile pushes north: isY, sgn = +1).  Idle lanes have active = false and a
+// valid column (0, 0).
+struct Col2 {
+    int lx, ly;   // tile coordinates, [-2, TX + 1] x [-2, TY + 1]
+    float sgn;
+    bool isY, active;
+};
+
+template <int TX, int TY>
+__device__ __forceinline__ Col2 col2_of(int tid)
+{
+    constexpr int NINT = TX * TY;
+    constexpr int RING0 = NINT, HALO0 = NINT + 2 * kWave;
+    constexpr int NRING = 2 * (TX + 2) + 2 * TY;
+    constexpr int NHALO = 2 * (TX + 2) + 2 * (TY + 4);
+    static_assert(NINT % kWave == 0, "tile must be whole waves");
+    static_assert(NRING <= 2 * kWave && NHALO <= 2 * kWave, "rings must fit two waves each");
+    Col2 c{0, 0, 1.0f, false, true};
+    if (tid < NINT) {
+        c.lx = tid % TX;
+        c.ly = tid / TX;
+    } else if (tid < HALO0) {
+        const int q = tid - RING0;
+        if (q < TX + 2) {  // row below the tile, corners included
+            c.lx = q - 1;
+            c.ly = -1;
+        } else if (q < 2 * (TX + 2)) {  // row above
+            c.lx = q - (TX + 2) - 1;
+            c.ly = TY;
+        } else if (q < 2 * (TX + 2) + TY) {  // column left of the tile
+            c.lx = -1;
+            c.ly = q - 2 * (TX + 2);
+        } else if (q < NRING) {  // column right of it
+            c.lx = TX;
+            c.ly = q - 2 * (TX + 2) - TY;
+        } else {
+            c.active = false;
+        }
+    } else {
+        const int q = tid - HALO0;
+        if (q < TY + 4) {  // outer left column (corners included), pushing east
+            c.lx = -2;
+            c.ly = q - 2;
+        } else if (q < 2 * (TY + 4)) {  // outer right column, pushing west
+            c.lx = TX + 1;
+            c.ly = q - (TY + 4) - 2;
+            c.sgn = -1.0f;
+        } else if (q < 2 * (TY + 4) + TX + 2) {  // outer bottom row, pushing north
+            c.isY = true;
+            c.lx = q - 2 * (TY + 4) - 1;
+            c.ly = -2;
+        } else if (q < NHALO) {  // outer top row, pushing south
+            c.isY = true;
+            c.lx = q - 2 * (TY + 4) - (TX + 2) - 1;
+            c.ly = TY + 1;
+            c.sgn = -1.0f;
+        } else {
+            c.active = false;
+        }
+    }
+    return c;
+}
+
+// Workgroup -> (tile_x, tile_y, chunk) with an XCD-aware order: consecutive
+// workgroups of one XCD get neighbouring tiles.
+struct TileIdx {
+    int tile_x, tile_y, zc;
+};
+
+__device__ __forceinline__ TileIdx tile_of_block(int nx, int ny, int TXv, int TYv)
+{
+    const unsigned nb = gridDim.x;
+    const unsigned b = blockIdx.x;
+    const unsigned lb = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + b / 8u : b;
+    const int tiles_x = nx / TXv;
+    const int tiles_y = ny / TYv;
+    TileIdx t;
+    t.tile_x = (int)(lb % (unsigned)tiles_x);
+    const unsigned rest = lb / (unsigned)tiles_x;
+    t.tile_y = (int)(rest % (unsigned)tiles_y);
+    t.zc = (int)(rest / (unsigned)tiles_y);
+    return t;
+}
+
+__device__ __forceinline__ int wrap_index(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
 }  // namespace
 
 }  // namespace lwacm

@@ -62,6 +62,7 @@ def load_library():
         "lwacm_step_count": (ll, [_vp]),
         "lwacm_adjoint_seed": (i, [_vp, _vp, _vp, _vp]),
         "lwacm_adjoint_step": (i, [_vp, _vp, _vp, _vp, _vp, i]),
+        "lwacm_adjoint_step2": (i, [_vp, _vp, _vp, _vp, _vp, _vp, i]),
         "lwacm_destroy": (None, [_vp]),
         "lwacm_strerror": (ctypes.c_char_p, [i]),
     }
@@ -192,6 +193,18 @@ def lwacm_adjoint_step(ctx, state_t: torch.Tensor, mu_in: torch.Tensor, mu_out: 
     _check(load_library().lwacm_adjoint_step(ctx, _ptr(state_t), _ptr(mu_in), _ptr(mu_out),
                                              _ptr(dL_domega), int(bool(final_t0))),
            "lwacm_adjoint_step")
+
+
+def lwacm_adjoint_step2(ctx, state_t: torch.Tensor, state_tm1: torch.Tensor, mu_in: torch.Tensor,
+                        mu_out: torch.Tensor, dL_domega: torch.Tensor, final_t0: bool) -> bool:
+    """Two reverse steps in one launch; False (nothing done) where the two-step
+    kernel does not apply, so the caller runs lwacm_adjoint_step twice."""
+    code = load_library().lwacm_adjoint_step2(ctx, _ptr(state_t), _ptr(state_tm1), _ptr(mu_in),
+                                              _ptr(mu_out), _ptr(dL_domega), int(bool(final_t0)))
+    if code == LWACM_EUNSUPPORTED:
+        return False
+    _check(code, "lwacm_adjoint_step2")
+    return True
 
 
 def lwacm_destroy(ctx):
