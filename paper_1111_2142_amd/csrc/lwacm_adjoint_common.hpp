@@ -165,27 +165,28 @@ __device__ __forceinline__ f32x4 adj_point(const float (*Wm)[NS], const float (*
     add_pair<0, 1, 1>(M, 1.0f, m[14], m[15]);
     add_pair<0, 1, -1>(M, 1.0f, m[16], m[17]);
     M.m0 = fmaf(12.0f, own.x, M.m0);  // rest link: m = mu_R(y)
-    // divide the integer weights out (correctly rounded division by 36)
-    const float m0 = div36(M.m0), m1x = div36(M.m1x), m1y = div36(M.m1y), m1z = div36(M.m1z);
-    const float xx = div36(M.xx), yy = div36(M.yy), zz = div36(M.zz);
-    const float xy = div36(M.xy), xz = div36(M.xz), yz = div36(M.yz);
+    // The moments carry the integer weights 36 w_k.  Every use below is
+    // linear in them, so the factor 1/36 is taken out once per result
+    // (div36: correctly rounded, no bias) instead of once per moment.
+    const float m0 = M.m0, m1x = M.m1x, m1y = M.m1y, m1z = M.m1z;
+    const float xx = M.xx, yy = M.yy, zz = M.zz, xy = M.xy, xz = M.xz, yz = M.yz;
 
     const float rho = 1.0f + dr;
     const float B = -1.5f * fmaf(ux, ux, fmaf(uy, uy, uz * uz));
-    const float uM1 = fmaf(ux, m1x, fmaf(uy, m1y, uz * m1z));
+    const float uM1 = div36(fmaf(ux, m1x, fmaf(uy, m1y, uz * m1z)));
     const float M2ux = fmaf(xx, ux, fmaf(xy, uy, xz * uz));
     const float M2uy = fmaf(xy, ux, fmaf(yy, uy, yz * uz));
     const float M2uz = fmaf(xz, ux, fmaf(yz, uy, zz * uz));
     const float uM2u = fmaf(ux, M2ux, fmaf(uy, M2uy, uz * M2uz));
     const float mJu = fmaf(own.y, ux, fmaf(own.z, uy, own.w * uz));
-    float lr = fmaf(m0, 1.0f + B, fmaf(A, uM1, 4.5f * uM2u));
+    float lr = fmaf(div36(m0), 1.0f + B, fmaf(A, uM1, div36(4.5f * uM2u)));
     lr = fmaf(own.y, fmaf(a, ux, p.g[0]), lr);
     lr = fmaf(own.z, fmaf(a, uy, p.g[1]), lr);
     lr = fmaf(own.w, fmaf(a, uz, p.g[2]), lr);
     const float arho = a * rho;
-    const float lux = fmaf(rho, fmaf(A, m1x, fmaf(9.0f, M2ux, -3.0f * ux * m0)), arho * own.y);
-    const float luy = fmaf(rho, fmaf(A, m1y, fmaf(9.0f, M2uy, -3.0f * uy * m0)), arho * own.z);
-    const float luz = fmaf(rho, fmaf(A, m1z, fmaf(9.0f, M2uz, -3.0f * uz * m0)), arho * own.w);
+    const float lux = fmaf(rho, div36(fmaf(A, m1x, fmaf(9.0f, M2ux, -3.0f * ux * m0))), arho * own.y);
+    const float luy = fmaf(rho, div36(fmaf(A, m1y, fmaf(9.0f, M2uy, -3.0f * uy * m0))), arho * own.z);
+    const float luz = fmaf(rho, div36(fmaf(A, m1z, fmaf(9.0f, M2uz, -3.0f * uz * m0))), arho * own.w);
     da = fmaf(rho, fmaf(-3.0f, uM1, mJu), da);
     if (MASK && (bits & kMovingWallFlag)) {
         // moving walls: sum over bounced links of w_k (v_k . 6 rho0 u_w) m_k
@@ -198,11 +199,12 @@ __device__ __forceinline__ f32x4 adj_point(const float (*Wm)[NS], const float (*
 }
 
 // mu of the step before from lambda: the normalisation u = J / rho of that
-// step folded in, (lambda_rho - lambda_u . u / rho, lambda_u / rho).
+// step folded in, (lambda_rho - lambda_u . u / rho, lambda_u / rho).  1/rho
+// is the hardware reciprocal (1 ulp), not a correctly rounded division.
 __device__ __forceinline__ f32x4 fold_normalisation(const f32x4 &lam, float dr, float ux,
                                                     float uy, float uz)
 {
-    const float inv = 1.0f / (1.0f + dr);
+    const float inv = __builtin_amdgcn_rcpf(1.0f + dr);
     const float lu_u = fmaf(lam.y, ux, fmaf(lam.z, uy, lam.w * uz));
     const f32x4 mu = {lam.x - lu_u * inv, lam.y * inv, lam.z * inv, lam.w * inv};
     return mu;
