@@ -257,6 +257,158 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
         finish_previous_sums(r.prev_partials, r.prev_nblocks, r.prev_out, r.prev_out2);
 }
 
+// The same step for problems without walls, with the plane loop rolled
+// (plane_loop: small code, so the instruction cache holds it) and every
+// chunk NZC planes deep: a ragged last chunk is moved down to end at nz, its
+// planes below zs written twice with the same bits and summed once.  Inside
+// the loop every load and store is unconditional and a ring slot is
+// refilled right after its last use, so the loads stay in flight across the
+// back edge.  Node for node the same operations as k_fwd_march (the column
+// helpers are shared), so the same results.
+template <class T, int NZC, bool SR>
+__global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
+                                                               const T *__restrict__ src,
+                                                               T *__restrict__ dst, ReduceArgs r)
+{
+    // two exchange buffers (by iteration parity) with one spare slot each:
+    // idle halo lanes write there instead of branching
+    __shared__ float2 xp[2][4][NSLOT + 1];
+    __shared__ float xd[2][4][NSLOT + 1];
+    constexpr bool MASK = false;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const long long n = p.n;
+    const long long plane = (long long)nx * ny;
+
+    const TileIdx ti = tile_of_block(nx, ny, TX, TY);
+    const int zs = ti.zc * NZC;
+    const int z0 = min(zs, nz - NZC);
+    const int z1 = z0 + NZC;
+
+    const int role = tid < NINT ? INTERIOR : (tid < NINT + kWave ? HALO_Y : HALO_X);
+    int lx, ly;
+    float sgn = 1.0f;
+    bool active = true;
+    if (role == INTERIOR) {
+        lx = tid % TX;
+        ly = tid / TX;
+    } else if (role == HALO_Y) {
+        const bool top = lane >= TX;
+        lx = top ? lane - TX : lane;
+        ly = top ? TY : -1;
+        sgn = top ? -1.0f : 1.0f;
+        active = lane < 2 * TX;
+        if (!active) lx = 0;
+    } else {
+        const bool right = lane >= TY + 2;
+        const int l = right ? lane - (TY + 2) : lane;
+        lx = right ? TX : -1;
+        ly = l - 1;
+        sgn = right ? -1.0f : 1.0f;
+        active = lane < 2 * (TY + 2);
+        if (!active) ly = 0;
+    }
+    const int gx = wrap_index(ti.tile_x * TX + lx, nx);
+    const int gy = wrap_index(ti.tile_y * TY + ly, ny);
+    const unsigned col = (unsigned)(gy * nx + gx);
+    const int slot = (ly + 1) * SX + (lx + 1);
+    const int wslot = active ? slot : NSLOT;
+
+    const float A = p.A;
+    const float a = p.a;
+    constexpr unsigned NB = BufIO<T>::kNodeBytes;
+    const unsigned plane_bytes = (unsigned)(plane * (long long)NB);
+    const unsigned long long sbytes = (unsigned long long)n * NB;
+    const Rsrc rs = make_rsrc(src, sbytes);
+    const Rsrc rd = make_rsrc(dst, sbytes);
+    const unsigned voff = col * NB;
+    auto issue = [&](Ring<T> &rg, int pz) {
+        rg.v = BufIO<T>::load(rs, voff, (unsigned)wrap_index(pz, nz) * plane_bytes);
+    };
+
+    Ring<T> ring[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) issue(ring[j], z0 - 1 + j);
+
+    float mass = 0.0f, energy = 0.0f;
+    constexpr int N = NZC + 2;  // planes z0 - 1 .. z1
+    auto value = [&](const Ring<T> &rg, float &dr, float &ux, float &uy, float &uz) {
+        dr = BufIO<T>::value(rg.v, 0, p.ld_scale[0]);
+        ux = BufIO<T>::value(rg.v, 1, p.ld_scale[1]);
+        uy = BufIO<T>::value(rg.v, 2, p.ld_scale[1]);
+        uz = BufIO<T>::value(rg.v, 3, p.ld_scale[1]);
+    };
+
+    if (role == INTERIOR) {
+        Acc acc[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[j] = Acc{};
+        plane_loop<N>([&](int k, auto kc) {
+            using I = PlaneIter<decltype(kc)::value, N, 3>;
+            constexpr int j = I::j;
+            __builtin_amdgcn_sched_barrier(0);
+            float dr, ux, uy, uz;
+            value(ring[j], dr, ux, uy, uz);
+            Acc &Am = acc[(j + 2) % 3];  // target plane pz - 1 (finalised now)
+            push_column<MASK>(dr, ux, uy, uz, 0, A, a, acc[(j + 1) % 3], acc[j], Am);
+            __builtin_amdgcn_sched_barrier(0);  // the ring slot's last use is above
+            if (I::refill) issue(ring[j], z0 + 2 + k);
+            if (I::phase < 2) return;
+            const Xchg<NSLOT + 1> X{xp[k & 1], xd[k & 1]};
+            put_slot(X, slot, Am);
+            __syncthreads();
+            const int tz = z0 - 2 + k;
+            const NodeOut o = finalize<MASK, NSLOT + 1, SX>(X, slot, Am, p, nullptr, 0);
+            const unsigned so = (unsigned)tz * plane_bytes;
+            if (SR) {  // FP16 storage, stochastic rounding (a template parameter: one path)
+                const U32x4 h = pcg4d((uint32_t)gx, (uint32_t)gy, (uint32_t)tz, p.sr_word);
+                BufIO<T>::store_sr(rd, voff, so, o.D, o.vx, o.vy, o.vz, p.st_scale, h);
+            } else {
+                BufIO<T>::store(rd, voff, so, o.D, o.vx, o.vy, o.vz, p.st_scale);
+            }
+            const bool count = tz >= zs;
+            mass += count ? o.D : 0.0f;
+            energy = count ? fmaf(o.vx, o.vx, fmaf(o.vy, o.vy, fmaf(o.vz, o.vz, energy))) : energy;
+        });
+    } else {
+        float hp[3] = {0.0f, 0.0f, 0.0f}, hz[3] = {0.0f, 0.0f, 0.0f};
+        float hd1[3] = {0.0f, 0.0f, 0.0f}, hd2[3] = {0.0f, 0.0f, 0.0f};
+        const bool isY = role == HALO_Y;
+        plane_loop<N>([&](int k, auto kc) {
+            using I = PlaneIter<decltype(kc)::value, N, 3>;
+            constexpr int j = I::j, j1 = (j + 1) % 3, jm = (j + 2) % 3;
+            __builtin_amdgcn_sched_barrier(0);
+            float dr, ux, uy, uz;
+            value(ring[j], dr, ux, uy, uz);
+            push_halo<MASK>(dr, ux, uy, uz, 0, A, isY, sgn, hp[j1], hz[j1], hp[j], hd1[j], hd2[j],
+                            hp[jm], hz[jm]);
+            __builtin_amdgcn_sched_barrier(0);
+            if (I::refill) issue(ring[j], z0 + 2 + k);
+            if (I::phase < 2) return;
+            put_halo(Xchg<NSLOT + 1>{xp[k & 1], xd[k & 1]}, wslot, isY, sgn, hp[jm], hz[jm],
+                     hd1[jm], hd2[jm]);
+            __syncthreads();
+        });
+    }
+
+    double v[2] = {(double)mass, 0.5 * (double)energy};
+    store_block_partials<2>(v, r.partials, blockIdx.x);
+    if (blockIdx.x == 0 && r.prev_nblocks)
+        finish_previous_sums(r.prev_partials, r.prev_nblocks, r.prev_out, r.prev_out2);
+}
+
+// Chunk depth of the rolled kernel: the problem's, halved while deeper than
+// nz (0: nz < 8, the unrolled kernel runs).
+int rolled_nzc(const ProblemArgs &p)
+{
+    if (p.mask) return 0;
+    int c = p.march_nzc;
+    while (c > 8 && c > p.nz) c /= 2;
+    return c <= p.nz ? c : 0;
+}
+
 // Node classes and solid-upstream bit sets for the bounce-back of the march
 // kernel: class 0 fluid with only fluid upstream nodes, 1 fluid with at
 // least one solid upstream node (bit i set when x - v_i is solid), 2 solid.
@@ -311,6 +463,19 @@ __global__ __launch_bounds__(256) void k_classify(ProblemArgs p, uint8_t *cls, u
     }
 }
 
+template <class T, bool SR>
+void launch_rolled(int c, unsigned nb, hipStream_t s, const ProblemArgs &p, const T *a, T *b,
+                   const ReduceArgs &r)
+{
+    switch (c) {
+    case 8: k_fwd_march_rolled<T, 8, SR><<<nb, NTHREADS, 0, s>>>(p, a, b, r); break;
+    case 16: k_fwd_march_rolled<T, 16, SR><<<nb, NTHREADS, 0, s>>>(p, a, b, r); break;
+    case 32: k_fwd_march_rolled<T, 32, SR><<<nb, NTHREADS, 0, s>>>(p, a, b, r); break;
+    case 64: k_fwd_march_rolled<T, 64, SR><<<nb, NTHREADS, 0, s>>>(p, a, b, r); break;
+    default: k_fwd_march_rolled<T, 128, SR><<<nb, NTHREADS, 0, s>>>(p, a, b, r); break;
+    }
+}
+
 template <class T>
 hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint8_t *cls,
                     const unsigned *bits, const float4 *wallg, const ReduceArgs &r,
@@ -319,18 +484,25 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
     const unsigned nb = march_num_blocks(p);
     const T *a = static_cast<const T *>(src);
     T *b = static_cast<T *>(dst);
-#define LWACM_LAUNCH(Z)                                                                   \
-    if (p.mask)                                                                           \
-        k_fwd_march<T, true, Z><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);    \
-    else                                                                                  \
-        k_fwd_march<T, false, Z><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
+    if (!p.mask) {
+        // no walls: the rolled kernel (nz >= 8), else the unrolled one with a
+        // 32-plane chunk
+        const int c = rolled_nzc(p);
+        if (c == 0) {
+            k_fwd_march<T, false, 32><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
+        } else if (std::is_same<T, __half>::value && p.fp16_sr) {
+            launch_rolled<T, true>(c, nb, s, p, a, b, r);
+        } else {
+            launch_rolled<T, false>(c, nb, s, p, a, b, r);
+        }
+        return hipGetLastError();
+    }
     switch (p.march_nzc) {
-    case 32: LWACM_LAUNCH(32) break;
-    case 64: LWACM_LAUNCH(64) break;
-    case 128: LWACM_LAUNCH(128) break;
+    case 32: k_fwd_march<T, true, 32><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r); break;
+    case 64: k_fwd_march<T, true, 64><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r); break;
+    case 128: k_fwd_march<T, true, 128><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r); break;
     default: return hipErrorInvalidValue;
     }
-#undef LWACM_LAUNCH
     return hipGetLastError();
 }
 
@@ -371,6 +543,10 @@ int march_choose_nzc(const ProblemArgs &p, int ncu)
 unsigned march_num_blocks(const ProblemArgs &p)
 {
     if (!march_supported(p) || p.march_nzc <= 0) return 0;
+    if (!p.mask) {  // the kernel dispatch() launches for problems without walls
+        const int c = rolled_nzc(p);
+        return (unsigned)march_blocks_for(p, c > 0 ? c : 32);
+    }
     return (unsigned)march_blocks_for(p, p.march_nzc);
 }
 
