@@ -257,24 +257,29 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
         finish_previous_sums(r.prev_partials, r.prev_nblocks, r.prev_out, r.prev_out2);
 }
 
-// The same step for problems without walls, with the plane loop rolled
-// (plane_loop: small code, so the instruction cache holds it) and every
-// chunk NZC planes deep: a ragged last chunk is moved down to end at nz, its
-// planes below zs written twice with the same bits and summed once.  Inside
-// the loop every load and store is unconditional and a ring slot is
-// refilled right after its last use, so the loads stay in flight across the
-// back edge.  Node for node the same operations as k_fwd_march (the column
-// helpers are shared), so the same results.
-template <class T, int NZC, bool SR>
+// The same step with the plane loop rolled (plane_loop: small code, so the
+// instruction cache holds it) and every chunk NZC planes deep: a ragged last
+// chunk is moved down to end at nz, its planes below zs written twice with
+// the same bits and summed once.  Inside the loop every load and store is
+// unconditional and a ring slot is refilled right after its last use, so the
+// loads stay in flight across the back edge.  With walls, each node's 32-bit
+// link set is loaded with its state on every plane (bit 0 marks a solid
+// node), and a solid node stores back the value it loaded, so that its store
+// too is unconditional; only the moving-wall sums are loaded conditionally,
+// by the waves next to a moving wall.  Node for node the same operations as
+// k_fwd_march (the column helpers are shared), so the same results.
+template <class T, int NZC, bool SR, bool MASK>
 __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
                                                                const T *__restrict__ src,
-                                                               T *__restrict__ dst, ReduceArgs r)
+                                                               T *__restrict__ dst,
+                                                               const unsigned *__restrict__ bb_bits,
+                                                               const float4 *__restrict__ wallg,
+                                                               ReduceArgs r)
 {
     // two exchange buffers (by iteration parity) with one spare slot each:
     // idle halo lanes write there instead of branching
     __shared__ float2 xp[2][4][NSLOT + 1];
     __shared__ float xd[2][4][NSLOT + 1];
-    constexpr bool MASK = false;
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -324,13 +329,18 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
     const Rsrc rs = make_rsrc(src, sbytes);
     const Rsrc rd = make_rsrc(dst, sbytes);
     const unsigned voff = col * NB;
-    auto issue = [&](Ring<T> &rg, int pz) {
-        rg.v = BufIO<T>::load(rs, voff, (unsigned)wrap_index(pz, nz) * plane_bytes);
+    const Rsrc rbits = make_rsrc(bb_bits, MASK ? (unsigned long long)n * 4u : 0ull);
+    unsigned bw[3] = {0u, 0u, 0u};  // link sets of the ring's planes (MASK)
+    auto issue = [&](int j, Ring<T> &rg, int pz) {
+        const unsigned pw = (unsigned)wrap_index(pz, nz);
+        rg.v = BufIO<T>::load(rs, voff, pw * plane_bytes);
+        if (MASK) bw[j] = __builtin_amdgcn_raw_buffer_load_b32(rbits, col * 4u, pw * (unsigned)(plane * 4), 0);
     };
+    auto class_of = [](unsigned b) { return (b & 1u) ? 2 : (b ? 1 : 0); };
 
     Ring<T> ring[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) issue(ring[j], z0 - 1 + j);
+    for (int j = 0; j < 3; ++j) issue(j, ring[j], z0 - 1 + j);
 
     float mass = 0.0f, energy = 0.0f;
     constexpr int N = NZC + 2;  // planes z0 - 1 .. z1
@@ -345,30 +355,40 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
         Acc acc[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) acc[j] = Acc{};
+        typename BufIO<T>::Raw raw[3];  // loaded values, stored back by solid nodes (MASK)
         plane_loop<N>([&](int k, auto kc) {
             using I = PlaneIter<decltype(kc)::value, N, 3>;
             constexpr int j = I::j;
             __builtin_amdgcn_sched_barrier(0);
             float dr, ux, uy, uz;
             value(ring[j], dr, ux, uy, uz);
+            const unsigned b = bw[j];
+            if (MASK) raw[j] = ring[j].v;
             Acc &Am = acc[(j + 2) % 3];  // target plane pz - 1 (finalised now)
-            push_column<MASK>(dr, ux, uy, uz, 0, A, a, acc[(j + 1) % 3], acc[j], Am);
+            push_column<MASK>(dr, ux, uy, uz, MASK ? class_of(b) : 0, A, a, acc[(j + 1) % 3],
+                              acc[j], Am);
+            if (MASK) acc[j].bits = b;
             __builtin_amdgcn_sched_barrier(0);  // the ring slot's last use is above
-            if (I::refill) issue(ring[j], z0 + 2 + k);
+            if (I::refill) issue(j, ring[j], z0 + 2 + k);
             if (I::phase < 2) return;
             const Xchg<NSLOT + 1> X{xp[k & 1], xd[k & 1]};
             put_slot(X, slot, Am);
             __syncthreads();
             const int tz = z0 - 2 + k;
-            const NodeOut o = finalize<MASK, NSLOT + 1, SX>(X, slot, Am, p, nullptr, 0);
+            const NodeOut o = finalize<MASK, NSLOT + 1, SX>(X, slot, Am, p, wallg,
+                                                            (long long)tz * plane + col);
             const unsigned so = (unsigned)tz * plane_bytes;
+            typename BufIO<T>::Raw out;
             if (SR) {  // FP16 storage, stochastic rounding (a template parameter: one path)
                 const U32x4 h = pcg4d((uint32_t)gx, (uint32_t)gy, (uint32_t)tz, p.sr_word);
-                BufIO<T>::store_sr(rd, voff, so, o.D, o.vx, o.vy, o.vz, p.st_scale, h);
+                out = BufIO<T>::pack_sr(o.D, o.vx, o.vy, o.vz, p.st_scale, h);
             } else {
-                BufIO<T>::store(rd, voff, so, o.D, o.vx, o.vy, o.vz, p.st_scale);
+                out = BufIO<T>::pack(o.D, o.vx, o.vy, o.vz, p.st_scale);
             }
-            const bool count = tz >= zs;
+            const bool solid = MASK && Am.cls >= 2;
+            if (MASK) out = solid ? raw[(j + 2) % 3] : out;
+            BufIO<T>::store_raw(rd, voff, so, out);
+            const bool count = tz >= zs && !solid;
             mass += count ? o.D : 0.0f;
             energy = count ? fmaf(o.vx, o.vx, fmaf(o.vy, o.vy, fmaf(o.vz, o.vz, energy))) : energy;
         });
@@ -382,10 +402,10 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             __builtin_amdgcn_sched_barrier(0);
             float dr, ux, uy, uz;
             value(ring[j], dr, ux, uy, uz);
-            push_halo<MASK>(dr, ux, uy, uz, 0, A, isY, sgn, hp[j1], hz[j1], hp[j], hd1[j], hd2[j],
-                            hp[jm], hz[jm]);
+            push_halo<MASK>(dr, ux, uy, uz, MASK ? class_of(bw[j]) : 0, A, isY, sgn, hp[j1],
+                            hz[j1], hp[j], hd1[j], hd2[j], hp[jm], hz[jm]);
             __builtin_amdgcn_sched_barrier(0);
-            if (I::refill) issue(ring[j], z0 + 2 + k);
+            if (I::refill) issue(j, ring[j], z0 + 2 + k);
             if (I::phase < 2) return;
             put_halo(Xchg<NSLOT + 1>{xp[k & 1], xd[k & 1]}, wslot, isY, sgn, hp[jm], hz[jm],
                      hd1[jm], hd2[jm]);
@@ -403,7 +423,6 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
 // nz (0: nz < 8, the unrolled kernel runs).
 int rolled_nzc(const ProblemArgs &p)
 {
-    if (p.mask) return 0;
     int c = p.march_nzc;
     while (c > 8 && c > p.nz) c /= 2;
     return c <= p.nz ? c : 0;
@@ -411,7 +430,8 @@ int rolled_nzc(const ProblemArgs &p)
 
 // Node classes and solid-upstream bit sets for the bounce-back of the march
 // kernel: class 0 fluid with only fluid upstream nodes, 1 fluid with at
-// least one solid upstream node (bit i set when x - v_i is solid), 2 solid.
+// least one solid upstream node (bit i set when x - v_i is solid), 2 solid
+// (bit set 1: bit 0 alone, so the bit set also tells the class).
 // For a fluid node whose solid upstream nodes include a moving wall, the
 // flag bit is set and wallg holds sum_i 36 w_i (v_i . u_w(x - v_i)) times
 // (1, v_i) over its bounce-back links: the moving-wall term per unit of
@@ -423,7 +443,7 @@ __global__ __launch_bounds__(256) void k_classify(ProblemArgs p, uint8_t *cls, u
          idx += (long long)gridDim.x * blockDim.x) {
         if (p.mask[idx] != 0) {
             cls[idx] = 2;
-            bits[idx] = 0u;
+            bits[idx] = 1u;  // bit 0 (the rest link, never a bounce-back link): solid
             continue;
         }
         const long long t = idx / p.nx;
@@ -463,16 +483,16 @@ __global__ __launch_bounds__(256) void k_classify(ProblemArgs p, uint8_t *cls, u
     }
 }
 
-template <class T, bool SR>
+template <class T, bool SR, bool MASK>
 void launch_rolled(int c, unsigned nb, hipStream_t s, const ProblemArgs &p, const T *a, T *b,
-                   const ReduceArgs &r)
+                   const unsigned *bits, const float4 *wallg, const ReduceArgs &r)
 {
     switch (c) {
-    case 8: k_fwd_march_rolled<T, 8, SR><<<nb, NTHREADS, 0, s>>>(p, a, b, r); break;
-    case 16: k_fwd_march_rolled<T, 16, SR><<<nb, NTHREADS, 0, s>>>(p, a, b, r); break;
-    case 32: k_fwd_march_rolled<T, 32, SR><<<nb, NTHREADS, 0, s>>>(p, a, b, r); break;
-    case 64: k_fwd_march_rolled<T, 64, SR><<<nb, NTHREADS, 0, s>>>(p, a, b, r); break;
-    default: k_fwd_march_rolled<T, 128, SR><<<nb, NTHREADS, 0, s>>>(p, a, b, r); break;
+    case 8: k_fwd_march_rolled<T, 8, SR, MASK><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 16: k_fwd_march_rolled<T, 16, SR, MASK><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 32: k_fwd_march_rolled<T, 32, SR, MASK><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 64: k_fwd_march_rolled<T, 64, SR, MASK><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    default: k_fwd_march_rolled<T, 128, SR, MASK><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
     }
 }
 
@@ -484,24 +504,19 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
     const unsigned nb = march_num_blocks(p);
     const T *a = static_cast<const T *>(src);
     T *b = static_cast<T *>(dst);
-    if (!p.mask) {
-        // no walls: the rolled kernel (nz >= 8), else the unrolled one with a
-        // 32-plane chunk
-        const int c = rolled_nzc(p);
-        if (c == 0) {
+    const int c = rolled_nzc(p);
+    const bool sr = std::is_same<T, __half>::value && p.fp16_sr;
+    if (c == 0) {  // nz < 8: the unrolled kernel with a 32-plane chunk
+        if (p.mask)
+            k_fwd_march<T, true, 32><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
+        else
             k_fwd_march<T, false, 32><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
-        } else if (std::is_same<T, __half>::value && p.fp16_sr) {
-            launch_rolled<T, true>(c, nb, s, p, a, b, r);
-        } else {
-            launch_rolled<T, false>(c, nb, s, p, a, b, r);
-        }
-        return hipGetLastError();
-    }
-    switch (p.march_nzc) {
-    case 32: k_fwd_march<T, true, 32><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r); break;
-    case 64: k_fwd_march<T, true, 64><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r); break;
-    case 128: k_fwd_march<T, true, 128><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r); break;
-    default: return hipErrorInvalidValue;
+    } else if (p.mask) {
+        if (sr) launch_rolled<T, true, true>(c, nb, s, p, a, b, bits, wallg, r);
+        else launch_rolled<T, false, true>(c, nb, s, p, a, b, bits, wallg, r);
+    } else {
+        if (sr) launch_rolled<T, true, false>(c, nb, s, p, a, b, bits, wallg, r);
+        else launch_rolled<T, false, false>(c, nb, s, p, a, b, bits, wallg, r);
     }
     return hipGetLastError();
 }
@@ -543,11 +558,8 @@ int march_choose_nzc(const ProblemArgs &p, int ncu)
 unsigned march_num_blocks(const ProblemArgs &p)
 {
     if (!march_supported(p) || p.march_nzc <= 0) return 0;
-    if (!p.mask) {  // the kernel dispatch() launches for problems without walls
-        const int c = rolled_nzc(p);
-        return (unsigned)march_blocks_for(p, c > 0 ? c : 32);
-    }
-    return (unsigned)march_blocks_for(p, p.march_nzc);
+    const int c = rolled_nzc(p);  // the kernel dispatch() launches
+    return (unsigned)march_blocks_for(p, c > 0 ? c : 32);
 }
 
 hipError_t launch_classify(const ProblemArgs &p, uint8_t *cls, unsigned *bits, float4 *wallg,

@@ -113,12 +113,28 @@ struct BufIO<float> {
     {
         return f == 0 ? v.x : (f == 1 ? v.y : (f == 2 ? v.z : v.w));
     }
-    __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float d,
-                                                 float ux, float uy, float uz, const float (&)[2])
+    // a node's new values in storage format
+    __device__ __forceinline__ static Raw pack(float d, float ux, float uy, float uz,
+                                               const float (&)[2])
     {
         const f32x4 v = {d, ux, uy, uz};
+        return v;
+    }
+    __device__ __forceinline__ static Raw pack_sr(float d, float ux, float uy, float uz,
+                                                  const float (&sc)[2], const U32x4 &)
+    {
+        return pack(d, ux, uy, uz, sc);
+    }
+    __device__ __forceinline__ static void store_raw(Rsrc r, unsigned voff, unsigned soff,
+                                                     const Raw &v)
+    {
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
         store_data_guard();
+    }
+    __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float d,
+                                                 float ux, float uy, float uz, const float (&sc)[2])
+    {
+        store_raw(r, voff, soff, pack(d, ux, uy, uz, sc));
     }
     __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float d,
                                                     float ux, float uy, float uz,
@@ -142,11 +158,31 @@ struct BufIO<__half> {
         const unsigned short h = (unsigned short)((f & 1) ? w >> 16 : w & 0xffffu);
         return __half2float(__ushort_as_half(h)) * inv_scale;
     }
-    __device__ __forceinline__ static void put(Rsrc r, unsigned voff, unsigned soff,
-                                               unsigned short b0, unsigned short b1,
-                                               unsigned short b2, unsigned short b3)
+    __device__ __forceinline__ static Raw bits4(unsigned short b0, unsigned short b1,
+                                                unsigned short b2, unsigned short b3)
     {
         const Raw v = {(unsigned)b0 | ((unsigned)b1 << 16), (unsigned)b2 | ((unsigned)b3 << 16)};
+        return v;
+    }
+    // a node's new values in storage format: scaled deviations, rounded to
+    // nearest or stochastically (random words h)
+    __device__ __forceinline__ static Raw pack(float d, float ux, float uy, float uz,
+                                               const float (&st)[2])
+    {
+        return bits4(__half_as_ushort(__float2half_rn(d * st[0])),
+                     __half_as_ushort(__float2half_rn(ux * st[1])),
+                     __half_as_ushort(__float2half_rn(uy * st[1])),
+                     __half_as_ushort(__float2half_rn(uz * st[1])));
+    }
+    __device__ __forceinline__ static Raw pack_sr(float d, float ux, float uy, float uz,
+                                                  const float (&st)[2], const U32x4 &h)
+    {
+        return bits4(half_bits_sr(d * st[0], h.x), half_bits_sr(ux * st[1], h.y),
+                     half_bits_sr(uy * st[1], h.z), half_bits_sr(uz * st[1], h.w));
+    }
+    __device__ __forceinline__ static void store_raw(Rsrc r, unsigned voff, unsigned soff,
+                                                     const Raw &v)
+    {
         __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
         store_data_guard();
     }
@@ -154,17 +190,13 @@ struct BufIO<__half> {
                                                  float ux, float uy, float uz,
                                                  const float (&st)[2])
     {
-        put(r, voff, soff, __half_as_ushort(__float2half_rn(d * st[0])),
-            __half_as_ushort(__float2half_rn(ux * st[1])),
-            __half_as_ushort(__float2half_rn(uy * st[1])),
-            __half_as_ushort(__float2half_rn(uz * st[1])));
+        store_raw(r, voff, soff, pack(d, ux, uy, uz, st));
     }
     __device__ __forceinline__ static void store_sr(Rsrc r, unsigned voff, unsigned soff, float d,
                                                     float ux, float uy, float uz,
                                                     const float (&st)[2], const U32x4 &h)
     {
-        put(r, voff, soff, half_bits_sr(d * st[0], h.x), half_bits_sr(ux * st[1], h.y),
-            half_bits_sr(uy * st[1], h.z), half_bits_sr(uz * st[1], h.w));
+        store_raw(r, voff, soff, pack_sr(d, ux, uy, uz, st, h));
     }
 };
 
