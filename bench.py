@@ -68,6 +68,29 @@ def _events_time(fn, n, stream):
     return start.elapsed_time(stop) / 1e3  # seconds
 
 
+def _cavity_leg(args, L, wl, dev, stream):
+    """The 192^3 lid-driven cavity: walls on every face, the lid moving.  The
+    masked one-step kernel moves 36 B per node: the state read and written
+    (2 x 16 B) and the node's 32-bit set of solid upstream links."""
+    import torch
+    c4 = wl.CAVITY_192
+    m4 = torch.as_tensor(wl.cavity_mask(c4.nx), device=dev)
+    s4 = L.Solver(L.LWACM_D3Q19, c4.nx, c4.ny, c4.nz, c4.omega, mask=m4,
+                  wall_u=[list(r) for r in wl.wall_table(c4.lid)], device=dev)
+    s4.set_state(torch.zeros((c4.nz, c4.ny, c4.nx), device=dev),
+                 torch.zeros((3, c4.nz, c4.ny, c4.nx), device=dev))
+    s4.step(args.warmup)
+    dt4 = _events_time(s4.step, args.steps, stream)
+    s4.close()
+    fluid4 = (c4.nx - 2) * (c4.ny - 2) * (c4.nz - 2)
+    ms4 = dt4 / args.steps * 1e3
+    print(f"[bench] cavity 192^3: {ms4:.4f} ms/step", file=sys.stderr, flush=True)
+    return {"value": round(fluid4 * args.steps / dt4 / 1e6, 1), "unit": "MLUPS (fluid nodes)",
+            "ms_per_step": round(ms4, 5), "omega": c4.omega, "lid": list(c4.lid),
+            "achieved_GBs": round(36.0 * c4.nx * c4.ny * c4.nz / (ms4 * 1e-3) / 1e9, 1),
+            "basis": "36 B per node: state in and out, 32-bit solid-link set"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +107,8 @@ def main():
     ap.add_argument("--reverse-only", action="store_true",
                     help="time only the reverse (adjoint) step of the 256^3 workload (two per "
                          "launch; --variant 2: one per launch)")
+    ap.add_argument("--cavity-only", action="store_true",
+                    help="time only the 192^3 lid-driven cavity (walls, moving lid)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of 256 MiB (the reference kernel for "
                          "scaling HBM byte counters) and exit")
@@ -113,6 +138,9 @@ def main():
                           "ms_per_launch": dt / args.steps * 1e3,
                           "GBs": nbytes * args.steps / dt / 1e9}), flush=True)
         return
+    if args.cavity_only:
+        print(json.dumps({"cavity_192": _cavity_leg(args, L, wl, dev, stream)}), flush=True)
+        return
     n = args.n
     cfg = wl.TGV3D_256
     drho, u = wl.taylor_green_3d(n, cfg.u0)
@@ -131,6 +159,8 @@ def main():
         s = make(L.LWACM_FP32)
         s.step(2)
         st = s.save_state()
+        s.step(1)
+        st2 = s.save_state()  # the state of the step after st: two distinct inputs
         mu_a = torch.zeros((4, n, n, n), dtype=torch.float32, device=dev)
         mu_b = torch.zeros_like(mu_a)
         lam = torch.zeros_like(mu_a)
@@ -144,7 +174,7 @@ def main():
             a_, b_ = mu_a, mu_b
             if two:
                 for _ in range(k // 2):
-                    if not L.lwacm_adjoint_step2(s.ctx, st, st, a_, b_, dw, False):
+                    if not L.lwacm_adjoint_step2(s.ctx, st2, st, a_, b_, dw, False):
                         raise RuntimeError("two-step reverse kernel declined the 256^3 problem")
                     a_, b_ = b_, a_
             else:
@@ -182,7 +212,7 @@ def main():
     bytes32 = 32.0 * nodes
     achieved = bytes32 / (ms32 * 1e-3) / 1e9
     fused = n == 256 and args.variant in (0, 3) and args.steps % 2 == 0
-    kname = "k_fwd_march2<128>" if fused else "k_fwd_march<float,false,128>"
+    kname = "k_fwd_march2<128>" if fused else "k_fwd_march_rolled<float,128,false,false>"
     per_launch = 2 if fused else 1
     t_launch = ms32 * 1e-3 * per_launch  # seconds per launch of the dominant kernel
     result = {
@@ -241,8 +271,9 @@ def main():
         "ms_per_step": round(ms1, 5),
         "achieved_GBs": round(32.0 * nodes / (ms1 * 1e-3) / 1e9, 1),
         "frac": round(32.0 * nodes / (ms1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "kernel": "k_fwd_march<float,false,128>" if n == 256 else None,
-        "traffic": _measured_traffic("k_fwd_march<float,false,128>") if n == 256 else None}
+        "kernel": "k_fwd_march_rolled<float,128,false,false>" if n == 256 else None,
+        "traffic": _measured_traffic("k_fwd_march_rolled<float,128,false,false>")
+        if n == 256 else None}
 
     # ---- FP16-deviation storage
     s16 = make(L.LWACM_FP16_DEV)
@@ -261,12 +292,16 @@ def main():
                             "ms_per_step": round(ms16, 5), "rounding": "stochastic (pcg4d)",
                             "achieved_GBs": round(16.0 * nodes / dt16 * args.steps / 1e9, 1),
                             "ms_per_step_nearest_rounding": round(dt16n / args.steps * 1e3, 5),
-                            "kernel": "k_fwd_march<__half,false,128>" if n == 256 else None,
-                            "traffic": _measured_traffic("k_fwd_march<__half,false,128>")
+                            "kernel": "k_fwd_march_rolled<__half,128,true,false>"
+                            if n == 256 else None,
+                            "traffic": _measured_traffic("k_fwd_march_rolled<__half,128,true,false>")
                             if n == 256 else None}
 
-    # ---- reverse step at the same size (reads state_t and mu_t, writes mu_{t-1})
+    # ---- reverse step at the same size (reads state_t and mu_t, writes mu_{t-1});
+    # two per launch: the states of two consecutive steps (distinct buffers)
     st = s32.save_state()
+    s32.step(1)
+    st2 = s32.save_state()
     mu_a = torch.zeros((4, n, n, n), dtype=torch.float32, device=dev)
     mu_b = torch.zeros_like(mu_a)
     dw = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -279,7 +314,7 @@ def main():
         a, b = mu_a, mu_b
         if two:
             for _ in range(k // 2):
-                if not L.lwacm_adjoint_step2(s32.ctx, st, st, a, b, dw, False):
+                if not L.lwacm_adjoint_step2(s32.ctx, st2, st, a, b, dw, False):
                     raise RuntimeError("two-step reverse kernel declined the problem")
                 a, b = b, a
         else:
@@ -313,28 +348,12 @@ def main():
                              "traffic": _measured_traffic("k_adj_march<float,false>")
                              if n == 256 else None}}
     s32.close()
-    del mu_a, mu_b, lam, st
+    del mu_a, mu_b, lam, st, st2
     torch.cuda.empty_cache()
     dw.zero_()
 
     # ---- lid-driven cavity 192^3 (mask active, moving lid)
-    c4 = wl.CAVITY_192
-    m4 = torch.as_tensor(wl.cavity_mask(c4.nx), device=dev)
-    s4 = L.Solver(L.LWACM_D3Q19, c4.nx, c4.ny, c4.nz, c4.omega, mask=m4,
-                  wall_u=[list(r) for r in wl.wall_table(c4.lid)], device=dev)
-    s4.set_state(torch.zeros((c4.nz, c4.ny, c4.nx), device=dev),
-                 torch.zeros((3, c4.nz, c4.ny, c4.nx), device=dev))
-    s4.step(args.warmup)
-    dt4 = _events_time(s4.step, args.steps, stream)
-    s4.close()
-    fluid4 = (c4.nx - 2) * (c4.ny - 2) * (c4.nz - 2)
-    ms4 = dt4 / args.steps * 1e3
-    print(f"[bench] cavity 192^3: {ms4:.4f} ms/step", file=sys.stderr, flush=True)
-    result["cavity_192"] = {
-        "value": round(fluid4 * args.steps / dt4 / 1e6, 1), "unit": "MLUPS (fluid nodes)",
-        "ms_per_step": round(ms4, 5), "omega": c4.omega, "lid": list(c4.lid),
-        "achieved_GBs_33B": round(33.0 * c4.nx * c4.ny * c4.nz / (ms4 * 1e-3) / 1e9, 1)}
-    del m4
+    result["cavity_192"] = _cavity_leg(args, L, wl, dev, stream)
 
     # ---- differentiable D2Q9 512^2: reverse / forward at the gradient workload (launch-bound)
     c5 = wl.ADJOINT_512
