@@ -77,6 +77,24 @@ struct Acc {
 
 __device__ __forceinline__ bool has_bit(unsigned bits, int i) { return (bits >> i) & 1u; }
 
+// Bitwise OR of v over the 64 lanes of the wave, returned in a scalar
+// register (the same value in every lane): prefix ORs within each row of 16
+// lanes (row_shr 1, 2, 4, 8), then rows 0 -> 1 and 2 -> 3 (row_bcast:15) and
+// rows 0-1 -> 2-3 (row_bcast:31), so lane 63 holds the OR of all lanes.
+// Lanes shifted in from outside a row read 0.  A branch on the result is a
+// scalar branch that the whole wave takes or skips.
+__device__ __forceinline__ unsigned wave_or(unsigned v)
+{
+    int x = (int)v;
+    x |= __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x |= __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x |= __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x |= __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x |= __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x |= __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return (unsigned)__builtin_amdgcn_readlane(x, 63);
+}
+
 // Global memory goes through buffer resources: one descriptor per state
 // buffer in SGPRs, the column's fixed 32-bit byte offset in a VGPR and the
 // plane's byte offset as the scalar offset, so a load or store costs no
@@ -383,31 +401,50 @@ __device__ __forceinline__ NodeOut finish(const Gathered &g, const Acc &Am, cons
     float Jx = (g.pE - g.pW) + ((g.dNE - g.dNW) + (g.dSE - g.dSW));
     float Jy = (g.pN - g.pS) + ((g.dNE + g.dNW) - (g.dSE + g.dSW));
     float Jz = Am.jz + ((g.zE + g.zW) + (g.zN + g.zS));
-    if (MASK && Am.bits != 0u) {
+    // Bounce-back: a wave next to a wall has a few of the 18 links set in
+    // some of its lanes.  The OR of the link sets over the wave is tested
+    // per link by the scalar unit, so the wave evaluates only the links one
+    // of its lanes needs.  The bounced term is the node's own term for the
+    // opposite link, with v_i . u formed as push_column forms it (same
+    // operands, same order: the same bits up to the sign of a zero).
+    if (MASK && __builtin_amdgcn_ballot_w64(Am.bits > 1u) != 0ull) {
+        const unsigned any = wave_or(Am.bits);
+        {
 #pragma unroll
-        for (int i = 1; i < 19; ++i) {
-            if (has_bit(Am.bits, i)) {
-                const int cx = link_cx(i), cy = link_cy(i), cz = link_cz(i);
-                float c = 0.0f;  // v_i . u, summed in the order push_column uses
-                if (cx != 0) c = cx > 0 ? c + Am.own[3] : c - Am.own[3];
-                if (cy != 0) c = cy > 0 ? c + Am.own[4] : c - Am.own[4];
-                if (cz != 0) c = cz > 0 ? c + Am.own[5] : c - Am.own[5];
-                const float m = fmaf(Am.own[1] * c, c, Am.own[0]);
-                const float s = Lattice<19>::w36(i) * fmaf(Am.own[2], -c, m);
-                D36 += s;
-                Jx = fmaf((float)cx, s, Jx);
-                Jy = fmaf((float)cy, s, Jy);
-                Jz = fmaf((float)cz, s, Jz);
+            for (int i = 1; i < 19; ++i) {
+                if (!((any >> i) & 1u)) continue;  // scalar branch: no lane has link i
+                // an empty statement with side effects keeps the compiler from
+                // evaluating the link unconditionally (select instead of branch)
+                asm volatile("");
+                if (has_bit(Am.bits, i)) {
+                    const int cx = link_cx(i), cy = link_cy(i), cz = link_cz(i);
+                    float c = 0.0f;
+                    bool first = true;
+                    auto add = [&](int k, float u) {
+                        if (k == 0) return;
+                        c = first ? (k > 0 ? u : -u) : (k > 0 ? c + u : c - u);
+                        first = false;
+                    };
+                    add(cx, Am.own[3]);
+                    add(cy, Am.own[4]);
+                    add(cz, Am.own[5]);
+                    const float m = fmaf(Am.own[1] * c, c, Am.own[0]);
+                    const float sv = Lattice<19>::w36(i) * fmaf(Am.own[2], -c, m);
+                    D36 += sv;
+                    if (cx != 0) Jx = cx > 0 ? Jx + sv : Jx - sv;
+                    if (cy != 0) Jy = cy > 0 ? Jy + sv : Jy - sv;
+                    if (cz != 0) Jz = cz > 0 ? Jz + sv : Jz - sv;
+                }
             }
-        }
-        // moving walls (Eq. ACM2.0ccccbb): (1 - a) 6 rho0 times the node's
-        // geometry sums of 36 w_i (1, v_i) (v_i . u_w)
-        if (Am.bits & kMovingWallFlag) {
-            const float4 w = wallg[widx];
-            D36 = fmaf(p.wall_scale, w.x, D36);
-            Jx = fmaf(p.wall_scale, w.y, Jx);
-            Jy = fmaf(p.wall_scale, w.z, Jy);
-            Jz = fmaf(p.wall_scale, w.w, Jz);
+            // moving walls (Eq. ACM2.0ccccbb): (1 - a) 6 rho0 times the node's
+            // geometry sums of 36 w_i (1, v_i) (v_i . u_w)
+            if ((any & kMovingWallFlag) && (Am.bits & kMovingWallFlag)) {
+                const float4 w = wallg[widx];
+                D36 = fmaf(p.wall_scale, w.x, D36);
+                Jx = fmaf(p.wall_scale, w.y, Jx);
+                Jy = fmaf(p.wall_scale, w.z, Jy);
+                Jz = fmaf(p.wall_scale, w.w, Jz);
+            }
         }
     }
     Jx = div36(Jx) + Am.post[0];
