@@ -189,11 +189,12 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 // refill with plane pz + RING (unconditional; past the chunk it
                 // re-reads plane z1, which is cached and never consumed)
                 if (k + RING < NZC + 2) issue(ring[rj], min(pz + RING, z1));
-
-                push_column<MASK>(dr, ux, uy, uz, cls, A, a, A1, A0, Am);
-                // only planes this chunk finalises (z0 <= pz < z1 <= nz)
+                // link sets: only planes this chunk finalises (z0 <= pz < z1 <= nz)
+                unsigned bits = 0u;
                 if (MASK && cls == 1 && pz >= z0 && pz < z1)
-                    A0.bits = bb_bits[(long long)pz * plane + col];
+                    bits = bb_bits[(long long)pz * plane + col];
+
+                push_column<MASK>(dr, ux, uy, uz, cls, bits, A, a, A1, A0, Am);
 
                 if (k < 2) return;  // planes below the chunk are halo only
                 // ---- exchange the partials of plane pz - 1 through LDS
@@ -290,7 +291,6 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
     const TileIdx ti = tile_of_block(nx, ny, TX, TY);
     const int zs = ti.zc * NZC;
     const int z0 = min(zs, nz - NZC);
-    const int z1 = z0 + NZC;
 
     const int role = tid < NINT ? INTERIOR : (tid < NINT + kWave ? HALO_Y : HALO_X);
     int lx, ly;
@@ -365,9 +365,8 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             const unsigned b = bw[j];
             if (MASK) raw[j] = ring[j].v;
             Acc &Am = acc[(j + 2) % 3];  // target plane pz - 1 (finalised now)
-            push_column<MASK>(dr, ux, uy, uz, MASK ? class_of(b) : 0, A, a, acc[(j + 1) % 3],
+            push_column<MASK>(dr, ux, uy, uz, MASK ? class_of(b) : 0, b, A, a, acc[(j + 1) % 3],
                               acc[j], Am);
-            if (MASK) acc[j].bits = b;
             __builtin_amdgcn_sched_barrier(0);  // the ring slot's last use is above
             if (I::refill) issue(j, ring[j], z0 + 2 + k);
             if (I::phase < 2) return;

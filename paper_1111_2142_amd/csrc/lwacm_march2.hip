@@ -175,7 +175,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
         using I = decltype(It);
         __builtin_amdgcn_sched_barrier(0);  // no work of this iteration moves up
         const f32x4 v = ring[I::j].v;
-        push_column<MASK>(v.x, v.y, v.z, v.w, 0, A, a, acc1[(I::j + 1) % 3], acc1[I::j],
+        push_column<MASK>(v.x, v.y, v.z, v.w, 0, 0u, A, a, acc1[(I::j + 1) % 3], acc1[I::j],
                           acc1[(I::j + 2) % 3]);
         refill(k, It);
     };
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
             e1 = count ? fmaf(o.vx, o.vx, fmaf(o.vy, o.vy, fmaf(o.vz, o.vz, e1))) : e1;
         }
         if (tile) {
-            push_column<MASK>(o.D, o.vx, o.vy, o.vz, 0, A, a, acc2[(I::j + 1) % 3], acc2[I::j],
+            push_column<MASK>(o.D, o.vx, o.vy, o.vz, 0, 0u, A, a, acc2[(I::j + 1) % 3], acc2[I::j],
                               acc2[(I::j + 2) % 3]);
             if (I::phase >= 4) put_slot(X2, wslot2, acc2[(I::j + 2) % 3]);
         } else {

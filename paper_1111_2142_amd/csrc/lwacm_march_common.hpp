@@ -70,30 +70,12 @@ struct Acc {
     float ne, nw, se, sw;                  // in-plane diagonals
     float d, jz;                           // own column: rest + (0,0,+-1) links
     float post[3];                         // a rho u of the node itself
-    float own[6];                          // E0, 4.5 rho, A rho, u (bounce-back only)
+    float bb[4];                           // bounced-back terms: 36 w (1, v) sums (MASK)
     unsigned bits;                         // solid upstream links (bounce-back only)
     int cls;                               // 0 fluid, 1 fluid next to a wall, 2 solid
 };
 
 __device__ __forceinline__ bool has_bit(unsigned bits, int i) { return (bits >> i) & 1u; }
-
-// Bitwise OR of v over the 64 lanes of the wave, returned in a scalar
-// register (the same value in every lane): prefix ORs within each row of 16
-// lanes (row_shr 1, 2, 4, 8), then rows 0 -> 1 and 2 -> 3 (row_bcast:15) and
-// rows 0-1 -> 2-3 (row_bcast:31), so lane 63 holds the OR of all lanes.
-// Lanes shifted in from outside a row read 0.  A branch on the result is a
-// scalar branch that the whole wave takes or skips.
-__device__ __forceinline__ unsigned wave_or(unsigned v)
-{
-    int x = (int)v;
-    x |= __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
-    x |= __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
-    x |= __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
-    x |= __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
-    x |= __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
-    x |= __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
-    return (unsigned)__builtin_amdgcn_readlane(x, 63);
-}
 
 // Global memory goes through buffer resources: one descriptor per state
 // buffer in SGPRs, the column's fixed 32-bit byte offset in a VGPR and the
@@ -257,9 +239,72 @@ struct Xchg {
 // m(c) = E0 + 4.5 rho c^2 with E0 = drho - 1.5 rho |u|^2; a solid node pushes
 // zeros.  With MASK, A0 also keeps the class and the coefficients that the
 // bounce-back of its own links needs (its bit set is the caller's).
+// Halfway bounce-back (Eq. ACM2.0cbb): when the upstream node x - v_i of a
+// fluid node is solid (bit i of its link set), link i brings the node's own
+// term for the opposite link -v_i, the term it sends into the wall.  Those
+// terms are the L arguments here (unweighted, as push_column computes them),
+// so the bounced terms are summed when the node is pushed, away from the
+// plane's LDS exchange: bb = sum over the set links of 36 w_i L(-v_i) (1, v_i).
+// Only waves with a lane next to a wall take this path (one scalar branch).
+// It has no further branches: a branch per link or per face kept the
+// compiler from overlapping these sums with the rest of the plane, and cost
+// more than evaluating all 18 links.  Each link is selected per lane by
+// AND-ing the term's bits with a mask made from bit i (all ones or zero).
+__device__ __forceinline__ void push_bounce_back(unsigned bits, float Lpx, float Lmx, float Lpy,
+                                                 float Lmy, float Lpz, float Lmz, float Lpp0,
+                                                 float Lmm0, float Lpm0, float Lmp0, float Lp0p,
+                                                 float Lm0m, float Lp0m, float Lm0p, float L0pp,
+                                                 float L0mm, float L0pm, float L0mp, float bb[4])
+{
+    float sd = 0.0f, sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    if (__builtin_amdgcn_ballot_w64(bits > 1u) != 0ull) {
+        // link (cx, cy, cz) of weight 36 w, bouncing back the term lo of (-cx, -cy, -cz)
+        auto link = [&](auto cxc, auto cyc, auto czc, float lo) {
+            constexpr int cx = decltype(cxc)::value, cy = decltype(cyc)::value;
+            constexpr int cz = decltype(czc)::value;
+            constexpr int i = link_index(cx, cy, cz);
+            constexpr float w = Lattice<19>::w36(i);
+            // bit i spread over the word: 0xffffffff when set, else 0
+            const unsigned m = (unsigned)((int)(bits << (31 - i)) >> 31);
+            const float t = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, lo) & m);
+            // w t is exact (w = 1 or 2), so each fma rounds like adding 36 w_i L
+            sd = fmaf(w, t, sd);
+            if (cx != 0) sx = fmaf(cx * w, t, sx);
+            if (cy != 0) sy = fmaf(cy * w, t, sy);
+            if (cz != 0) sz = fmaf(cz * w, t, sz);
+        };
+        using P = std::integral_constant<int, 1>;
+        using Z = std::integral_constant<int, 0>;
+        using M = std::integral_constant<int, -1>;
+        link(P{}, Z{}, Z{}, Lmx);
+        link(M{}, Z{}, Z{}, Lpx);
+        link(Z{}, P{}, Z{}, Lmy);
+        link(Z{}, M{}, Z{}, Lpy);
+        link(Z{}, Z{}, P{}, Lmz);
+        link(Z{}, Z{}, M{}, Lpz);
+        link(P{}, P{}, Z{}, Lmm0);
+        link(M{}, M{}, Z{}, Lpp0);
+        link(P{}, M{}, Z{}, Lmp0);
+        link(M{}, P{}, Z{}, Lpm0);
+        link(P{}, Z{}, P{}, Lm0m);
+        link(M{}, Z{}, M{}, Lp0p);
+        link(P{}, Z{}, M{}, Lm0p);
+        link(M{}, Z{}, P{}, Lp0m);
+        link(Z{}, P{}, P{}, L0mm);
+        link(Z{}, M{}, M{}, L0pp);
+        link(Z{}, P{}, M{}, L0mp);
+        link(Z{}, M{}, P{}, L0pm);
+    }
+    bb[0] = sd;
+    bb[1] = sx;
+    bb[2] = sy;
+    bb[3] = sz;
+}
+
 template <bool MASK>
 __device__ __forceinline__ void push_column(float dr, float ux, float uy, float uz, int cls,
-                                            float A, float a, Acc &A1, Acc &A0, Acc &Am)
+                                            unsigned bits, float A, float a, Acc &A1, Acc &A0,
+                                            Acc &Am)
 {
     const float rho = 1.0f + dr;
     const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
@@ -317,13 +362,9 @@ __device__ __forceinline__ void push_column(float dr, float ux, float uy, float 
     A0.post[2] = arho * uz;
     if (MASK) {
         A0.cls = cls;
-        A0.bits = 0u;
-        A0.own[0] = E0;
-        A0.own[1] = r45;
-        A0.own[2] = rA;
-        A0.own[3] = ux;
-        A0.own[4] = uy;
-        A0.own[5] = uz;
+        A0.bits = bits;
+        push_bounce_back(bits, Lpx, Lmx, Lpy, Lmy, Lpz, Lmz, Lpp0, Lmm0, Lpm0, Lmp0, Lp0p, Lm0m,
+                         Lp0m, Lm0p, L0pp, L0mm, L0pm, L0mp, A0.bb);
     }
     // links with v_z = -1 finish plane pz - 1
     Am.pe += Lp0m;
@@ -401,50 +442,21 @@ __device__ __forceinline__ NodeOut finish(const Gathered &g, const Acc &Am, cons
     float Jx = (g.pE - g.pW) + ((g.dNE - g.dNW) + (g.dSE - g.dSW));
     float Jy = (g.pN - g.pS) + ((g.dNE + g.dNW) - (g.dSE + g.dSW));
     float Jz = Am.jz + ((g.zE + g.zW) + (g.zN + g.zS));
-    // Bounce-back: a wave next to a wall has a few of the 18 links set in
-    // some of its lanes.  The OR of the link sets over the wave is tested
-    // per link by the scalar unit, so the wave evaluates only the links one
-    // of its lanes needs.  The bounced term is the node's own term for the
-    // opposite link, with v_i . u formed as push_column forms it (same
-    // operands, same order: the same bits up to the sign of a zero).
-    if (MASK && __builtin_amdgcn_ballot_w64(Am.bits > 1u) != 0ull) {
-        const unsigned any = wave_or(Am.bits);
-        {
-#pragma unroll
-            for (int i = 1; i < 19; ++i) {
-                if (!((any >> i) & 1u)) continue;  // scalar branch: no lane has link i
-                // an empty statement with side effects keeps the compiler from
-                // evaluating the link unconditionally (select instead of branch)
-                asm volatile("");
-                if (has_bit(Am.bits, i)) {
-                    const int cx = link_cx(i), cy = link_cy(i), cz = link_cz(i);
-                    float c = 0.0f;
-                    bool first = true;
-                    auto add = [&](int k, float u) {
-                        if (k == 0) return;
-                        c = first ? (k > 0 ? u : -u) : (k > 0 ? c + u : c - u);
-                        first = false;
-                    };
-                    add(cx, Am.own[3]);
-                    add(cy, Am.own[4]);
-                    add(cz, Am.own[5]);
-                    const float m = fmaf(Am.own[1] * c, c, Am.own[0]);
-                    const float sv = Lattice<19>::w36(i) * fmaf(Am.own[2], -c, m);
-                    D36 += sv;
-                    if (cx != 0) Jx = cx > 0 ? Jx + sv : Jx - sv;
-                    if (cy != 0) Jy = cy > 0 ? Jy + sv : Jy - sv;
-                    if (cz != 0) Jz = cz > 0 ? Jz + sv : Jz - sv;
-                }
-            }
-            // moving walls (Eq. ACM2.0ccccbb): (1 - a) 6 rho0 times the node's
-            // geometry sums of 36 w_i (1, v_i) (v_i . u_w)
-            if ((any & kMovingWallFlag) && (Am.bits & kMovingWallFlag)) {
-                const float4 w = wallg[widx];
-                D36 = fmaf(p.wall_scale, w.x, D36);
-                Jx = fmaf(p.wall_scale, w.y, Jx);
-                Jy = fmaf(p.wall_scale, w.z, Jy);
-                Jz = fmaf(p.wall_scale, w.w, Jz);
-            }
+    if (MASK) {
+        // bounced-back terms (summed when the node was pushed; zero elsewhere)
+        D36 += Am.bb[0];
+        Jx += Am.bb[1];
+        Jy += Am.bb[2];
+        Jz += Am.bb[3];
+        // moving walls (Eq. ACM2.0ccccbb): (1 - a) 6 rho0 times the node's
+        // geometry sums of 36 w_i (1, v_i) (v_i . u_w)
+        if (__builtin_amdgcn_ballot_w64((Am.bits & kMovingWallFlag) != 0u) != 0ull &&
+            (Am.bits & kMovingWallFlag)) {
+            const float4 w = wallg[widx];
+            D36 = fmaf(p.wall_scale, w.x, D36);
+            Jx = fmaf(p.wall_scale, w.y, Jx);
+            Jy = fmaf(p.wall_scale, w.z, Jy);
+            Jz = fmaf(p.wall_scale, w.w, Jz);
         }
     }
     Jx = div36(Jx) + Am.post[0];
