@@ -46,6 +46,9 @@ def _load():
               _u8p, _dp, ctypes.c_int, _dp, ctypes.c_double]
     lib.oracle_step.argtypes = common + [_dp, _dp, _dp, _dp]
     lib.oracle_step.restype = ctypes.c_int
+    lib.oracle_step_split.argtypes = common[:5] + [ctypes.c_double] + common[5:] + [_dp, _dp, _dp,
+                                                                                     _dp]
+    lib.oracle_step_split.restype = ctypes.c_int
     lib.oracle_vjp.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_vjp.restype = ctypes.c_int
     lib.oracle_step_nodes.argtypes = common + [_dp, _dp, ctypes.POINTER(ctypes.c_long),
@@ -115,6 +118,7 @@ class Problem:
     wall_u: Optional[np.ndarray] = None   # (n_ids, 3) wall velocities by id
     g: Optional[Tuple[float, ...]] = None  # body acceleration
     rho0: float = 1.0          # mean fluid density at t=0, used by moving walls
+    omega_p: Optional[float] = None  # separate relaxation of the density (None: omega)
 
     @property
     def d(self) -> int:
@@ -151,14 +155,23 @@ def _f64(a, shape):
     return a
 
 
+def _step_call(lib, p: Problem, args, rho_in, u_in, rho_out, u_out):
+    """oracle_step, or oracle_step_split when the problem has its own omega_p."""
+    if p.omega_p is None:
+        return lib.oracle_step(*args, _ptr(rho_in), _ptr(u_in), _ptr(rho_out), _ptr(u_out))
+    split = args[:5] + [float(p.omega_p)] + args[5:]
+    return lib.oracle_step_split(*split, _ptr(rho_in), _ptr(u_in), _ptr(rho_out), _ptr(u_out))
+
+
 def step(p: Problem, rho, u):
-    """One step of Eq. ACM2.0 (with forcing and walls); returns new (rho, u)."""
+    """One step of Eq. ACM2.0 (with forcing, walls and, if given, a separate
+    omega_p for the density); returns new (rho, u)."""
     lib = _load()
     rho = _f64(rho, p.shape)
     u = _f64(u, (p.d,) + p.shape)
     r1 = np.empty_like(rho)
     u1 = np.empty_like(u)
-    rc = lib.oracle_step(*p._args(), _ptr(rho), _ptr(u), _ptr(r1), _ptr(u1))
+    rc = _step_call(lib, p, p._args(), rho, u, r1, u1)
     if rc != 0:
         raise RuntimeError(f"oracle_step failed ({rc})")
     return r1, u1
@@ -169,6 +182,8 @@ def step_nodes(p: Problem, rho, u, idx):
 
     Returns (rho_new[len(idx)], u_new[D, len(idx)]).
     """
+    if p.omega_p is not None:
+        raise NotImplementedError("step_nodes: no separate omega_p")
     lib = _load()
     rho = _f64(rho, p.shape)
     u = _f64(u, (p.d,) + p.shape)
@@ -192,7 +207,7 @@ def run(p: Problem, rho, u, nsteps: int, callback: Optional[Callable] = None):
     b_u = np.empty_like(a_u)
     args = p._args()
     for t in range(nsteps):
-        rc = lib.oracle_step(*args, _ptr(a_r), _ptr(a_u), _ptr(b_r), _ptr(b_u))
+        rc = _step_call(lib, p, args, a_r, a_u, b_r, b_u)
         if rc != 0:
             raise RuntimeError(f"oracle_step failed ({rc})")
         a_r, b_r = b_r, a_r
@@ -246,6 +261,8 @@ def vjp(p: Problem, rho, u, lam_rho1, lam_u1):
 
     Returns (lam_rho0, lam_u0, dL_domega) for output cotangents (lam_rho1, lam_u1).
     """
+    if p.omega_p is not None:
+        raise NotImplementedError("vjp: no separate omega_p")
     lib = _load()
     rho = _f64(rho, p.shape)
     u = _f64(u, (p.d,) + p.shape)

@@ -24,6 +24,12 @@
  *     ACM2.0cccbb2, with the moving-wall correction of Eqs. ACM2.0movebb
  *     and ACM2.0ccccbb, (2/omega - 1) * 2 f^(e,o)(rho0, u_w);
  *   - new moments rho = sum f_i, rho u = sum v_i f_i (Section 2.1);
+ *   - a separate relaxation omega_p for the continuity equation (Section
+ *     "finite-difference formulation", item 3; Appendix E): the density is
+ *     the zeroth moment of the populations of Eq. ACM2.0 evaluated with
+ *     omega_p in place of omega (in the link update, the bounce-back and
+ *     the moving-wall correction alike), the momentum their first moment
+ *     with omega, and u = momentum / density;
  *   - diagnostics: mass sum(rho) and kinetic energy 1/2 sum |u|^2 over
  *     fluid nodes (the energy of Section 3.1.1, in lattice units);
  *   - FP16 storage with stochastic rounding (not part of the paper: a
@@ -288,6 +294,51 @@ int oracle_step(int q, int nx, int ny, int nz, double omega, const uint8_t *mask
                 double r = 0.0, j[3] = {0, 0, 0};
                 for (int i = 0; i < L.q; ++i) {
                     r += f[i];
+                    for (int k = 0; k < 3; ++k) j[k] += L.v[i][k] * f[i];
+                }
+                rho_out[ix] = r;
+                for (int k = 0; k < L.d; ++k) u_out[k * n + ix] = j[k] / r;
+            }
+    return 0;
+}
+
+/* One step with a separate relaxation omega_p for the density (the
+ * continuity equation) and omega for the momentum; omega_p == omega is the
+ * step of oracle_step.  The populations are evaluated twice, once with each
+ * relaxation: rho = sum f_i(omega_p), rho u = sum v_i f_i(omega). */
+int oracle_step_split(int q, int nx, int ny, int nz, double omega, double omega_p,
+                      const uint8_t *mask, const double *wall_u, int n_ids, const double *g_in,
+                      double rho0, const double *rho_in, const double *u_in, double *rho_out,
+                      double *u_out)
+{
+    lattice_t L;
+    if (make_lattice(q, &L)) return -1;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (L.d == 2 && nz != 1)) return -1;
+    if (!(omega_p > 0.0 && omega_p < 2.0)) return -1;
+    long n = (long)nx * ny * nz;
+    double g[3] = {0, 0, 0};
+    if (g_in)
+        for (int k = 0; k < L.d; ++k) g[k] = g_in[k];
+    const double *gp = g_in ? g : NULL;
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long ix = node_index(nx, ny, x, y, z);
+                if (mask && mask[ix] != 0) {
+                    rho_out[ix] = rho_in[ix];
+                    for (int k = 0; k < L.d; ++k) u_out[k * n + ix] = u_in[k * n + ix];
+                    continue;
+                }
+                double f[MAXQ], fp[MAXQ];
+                node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_in,
+                                 u_in, x, y, z, f);
+                node_populations(&L, nx, ny, nz, omega_p, mask, wall_u, n_ids, gp, rho0, rho_in,
+                                 u_in, x, y, z, fp);
+                double r = 0.0, j[3] = {0, 0, 0};
+                for (int i = 0; i < L.q; ++i) {
+                    r += fp[i];
                     for (int k = 0; k < 3; ++k) j[k] += L.v[i][k] * f[i];
                 }
                 rho_out[ix] = r;
