@@ -142,6 +142,22 @@ int lwacm_set_variant(lwacm_ctx *c, int variant);
  * overrides it (tuning, tests).  Results do not depend on the depth. */
 int lwacm_set_march_chunk(lwacm_ctx *c, int planes);
 
+/* Separate relaxation frequency omega_p of the continuity (density) update
+ * (Section "finite-difference formulation", item 3; Appendix E, where the
+ * density update takes b = 2 - 2/omega_p and the momentum update keeps
+ * a = 2 - 2/omega).  The density of a step is the zeroth moment of the
+ * populations of Eq. ACM2.0 evaluated with omega_p: in the link update, the
+ * bounce-back and the moving-wall correction alike; the momentum is their
+ * first moment with omega, and u = momentum / density.  The
+ * pseudo-compressibility term of the continuity equation then scales with
+ * 1/nu(omega_p) (Eq. viscosity2), so nu(omega_p) > nu(omega) reduces the
+ * compressibility error of under-resolved runs.  0 < omega_p < 2, else
+ * LWACM_EINVAL; omega_p == omega (the default after lwacm_init) is the
+ * single-relaxation step.  With omega_p != omega the forward step runs on the
+ * generic kernel (every lattice, walls and force allowed) and the reverse
+ * steps return LWACM_EUNSUPPORTED.  Takes effect from the next lwacm_step. */
+int lwacm_set_omega_p(lwacm_ctx *c, double omega_p);
+
 /* Load the state from FP32 fields (rho - 1 and u, SoA), converting to the
  * storage format, and set rho0 (the mean fluid density used by moving walls,
  * Section 3.2) to the mean of 1 + d_drho over fluid nodes.  Resets the step

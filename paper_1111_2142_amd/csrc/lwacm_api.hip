@@ -20,6 +20,7 @@ struct lwacm_ctx {
     int variant;  // requested LWACM_KERNEL_*
     bool force;
     double omega;
+    double omega_p;  // relaxation of the density update (== omega: single relaxation)
     double a_exact;  // the a used by the kernels (1 - quantised h), as a double
     double rho0;
     void *buf[2];
@@ -51,14 +52,28 @@ int dev_err(hipError_t e)
     return e == hipSuccess ? LWACM_OK : LWACM_EDEVICE;
 }
 
+// h = 2/omega - 1 on a grid fine enough that 1 - h and 3 h are both exact in
+// FP32 (so a + A/3 = 1 holds exactly and the link terms conserve momentum to
+// rounding; a mismatch of ~1e-8 would act like a source term every step).
+// The relative change of the viscosity nu = h/6 is at most 2^-25 / h.
+double quantised_h(double omega)
+{
+    const double h = 2.0 / omega - 1.0;
+    const double quantum = fabs(h) < 0.25 ? ldexp(1.0, -24)
+                           : (fabs(h) < 0.5 ? ldexp(1.0, -23) : ldexp(1.0, -22));
+    return nearbyint(h / quantum) * quantum;
+}
+
 void set_wall_terms(lwacm_ctx *c)
 {
     const float a = c->p.a;
+    const double hp = c->p.Ap / 3.0;  // 2/omega_p - 1 (exact: Ap = 3 hp in FP32)
     for (int m = 0; m < lwacm::kMaxWallIds; ++m)
         for (int k = 0; k < 3; ++k) {
             const double uw = (m < c->n_wall_ids) ? c->wall_u[m][k] : 0.0;
             c->p.wall_da[m][k] = (float)(6.0 * c->rho0 * uw);
             c->p.wall_term[m][k] = (float)((1.0 - a) * 6.0 * c->rho0 * uw);
+            c->p.wall_term_p[m][k] = (float)(hp * 6.0 * c->rho0 * uw);
             c->p.wall_u[m][k] = (float)uw;
         }
     c->p.wall_scale = (float)((1.0 - a) * 6.0 * c->rho0);
@@ -195,19 +210,15 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
     p.ny = ny;
     p.nz = nz;
     p.n = (long long)nx * ny * nz;
-    // h = 1 - a = 2/omega - 1 is put on a grid fine enough that a = 1 - h and
-    // A = 3 h are both exact in FP32, so that a + A/3 = 1 holds exactly and
-    // the link terms conserve momentum to rounding (a mismatch of ~1e-8 would
-    // act like a source term every step).  The relative change of the
-    // viscosity nu = h/6 is at most 2^-25 / h.
+    // a = 1 - h and A = 3 h from the quantised h = 2/omega - 1
     {
-        const double h = 2.0 / omega - 1.0;
-        const double quantum = fabs(h) < 0.25 ? ldexp(1.0, -24)
-                               : (fabs(h) < 0.5 ? ldexp(1.0, -23) : ldexp(1.0, -22));
-        const double hq = nearbyint(h / quantum) * quantum;
+        const double hq = quantised_h(omega);
         p.a = (float)(1.0 - hq);
         p.A = (float)(3.0 * hq);
+        p.Ap = p.A;
+        p.split = 0;
         c->a_exact = 1.0 - hq;
+        c->omega_p = omega;
     }
     p.mask = d_mask;
     if (h_g) {
@@ -324,6 +335,16 @@ int lwacm_set_march_chunk(lwacm_ctx *c, int planes)
         c->p.march_nzc = keep;
         return LWACM_EUNSUPPORTED;
     }
+    return LWACM_OK;
+}
+
+int lwacm_set_omega_p(lwacm_ctx *c, double omega_p)
+{
+    if (!c || !(omega_p > 0.0 && omega_p < 2.0)) return LWACM_EINVAL;
+    c->omega_p = omega_p;
+    c->p.Ap = (float)(3.0 * quantised_h(omega_p));
+    c->p.split = c->p.Ap != c->p.A;
+    set_wall_terms(c);
     return LWACM_OK;
 }
 
@@ -520,6 +541,7 @@ int lwacm_adjoint_step(lwacm_ctx *c, const void *d_state_t, const float *d_mu_in
 {
     if (!c || !d_state_t || !d_mu_in || !d_mu_out || !d_dL_domega || d_mu_in == d_mu_out)
         return LWACM_EINVAL;
+    if (c->p.split) return LWACM_EUNSUPPORTED;  // no reverse step for omega_p != omega
     ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
     r.accumulate = 1;
     r.out_scale = 2.0 / (c->omega * c->omega);  // da/domega for a = 2 - 2/omega
@@ -537,7 +559,7 @@ int lwacm_adjoint_step2(lwacm_ctx *c, const void *d_state_t, const void *d_state
         d_mu_in == d_mu_out)
         return LWACM_EINVAL;
     if ((c->variant != LWACM_KERNEL_AUTO && c->variant != LWACM_KERNEL_MARCH2) ||
-        !lwacm::adj_march2_supported(c->p))
+        !lwacm::adj_march2_supported(c->p) || c->p.split)
         return LWACM_EUNSUPPORTED;
     ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
     r.accumulate = 1;

@@ -100,7 +100,11 @@ __device__ __forceinline__ float vdot(int i, const float (&u)[3])
     return c;
 }
 
-template <int Q, class T, bool MASK, bool FORCE>
+// SPLIT: a separate relaxation omega_p for the density (Section
+// "finite-difference formulation", item 3; Appendix E).  The density sums the
+// same link terms with Ap = 3 (2/omega_p - 1) in place of A (and the moving
+// wall's omega_p term); the momentum keeps A.
+template <int Q, class T, bool MASK, bool FORCE, bool SPLIT>
 __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, const T *__restrict__ src,
                                                                T *__restrict__ dst, ReduceArgs r)
 {
@@ -141,22 +145,30 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
                                          wrap_add(c.y, -link_cy(i), p.ny),
                                          wrap_add(c.z, -link_cz(i), p.nz));
             const float fg = FORCE ? vdot<Q>(i, g3) : 0.0f;
-            float s;
+            float s, sp = 0.0f;  // link term; with SPLIT, its density form
             uint8_t m = 0;
             if (MASK) m = p.mask[up];
             if (MASK && m != 0) {
                 // bounce-back: own term of the opposite link + moving wall
                 const int ib = link_opp(i);
                 const float uw[3] = {p.wall_term[m][0], p.wall_term[m][1], p.wall_term[m][2]};
-                s = link_term_unweighted(drx + fg, rx, vdot<Q>(ib, ux), Bx, p.A) + vdot<Q>(i, uw);
+                const float cb = vdot<Q>(ib, ux);
+                s = link_term_unweighted(drx + fg, rx, cb, Bx, p.A) + vdot<Q>(i, uw);
+                if (SPLIT) {
+                    const float uwp[3] = {p.wall_term_p[m][0], p.wall_term_p[m][1],
+                                          p.wall_term_p[m][2]};
+                    sp = link_term_unweighted(drx + fg, rx, cb, Bx, p.Ap) + vdot<Q>(i, uwp);
+                }
             } else {
                 float dry, uy[3];
                 load_state<D, T>(src, up, p, dry, uy);
                 const float By = -1.5f * (uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2]);
-                s = link_term_unweighted(dry + fg, 1.0f + dry, vdot<Q>(i, uy), By, p.A);
+                const float cy = vdot<Q>(i, uy);
+                s = link_term_unweighted(dry + fg, 1.0f + dry, cy, By, p.A);
+                if (SPLIT) sp = link_term_unweighted(dry + fg, 1.0f + dry, cy, By, p.Ap);
             }
             s *= L::w36(i);
-            D36 += s;
+            D36 += SPLIT ? sp * L::w36(i) : s;
             if (link_cx(i) != 0) J36[0] += link_cx(i) * s;
             if (link_cy(i) != 0) J36[1] += link_cy(i) * s;
             if (link_cz(i) != 0) J36[2] += link_cz(i) * s;
@@ -374,24 +386,33 @@ unsigned grid_for(long long n)
     return (unsigned)(b > (long long)kGenericMaxBlocks ? kGenericMaxBlocks : b);
 }
 
+template <int Q, class T, bool SPLIT>
+hipError_t fwd_dispatch_split(const ProblemArgs &p, bool force, const T *a, T *b,
+                              const ReduceArgs &r, unsigned nb, hipStream_t s)
+{
+    if (p.mask) {
+        if (force)
+            k_fwd_generic<Q, T, true, true, SPLIT><<<nb, kGenericBlock, 0, s>>>(p, a, b, r);
+        else
+            k_fwd_generic<Q, T, true, false, SPLIT><<<nb, kGenericBlock, 0, s>>>(p, a, b, r);
+    } else {
+        if (force)
+            k_fwd_generic<Q, T, false, true, SPLIT><<<nb, kGenericBlock, 0, s>>>(p, a, b, r);
+        else
+            k_fwd_generic<Q, T, false, false, SPLIT><<<nb, kGenericBlock, 0, s>>>(p, a, b, r);
+    }
+    return hipGetLastError();
+}
+
 template <int Q, class T>
 hipError_t fwd_dispatch(const ProblemArgs &p, bool force, const void *src, void *dst,
                         const ReduceArgs &r, unsigned nb, hipStream_t s)
 {
     const T *a = static_cast<const T *>(src);
     T *b = static_cast<T *>(dst);
-    if (p.mask) {
-        if (force)
-            k_fwd_generic<Q, T, true, true><<<nb, kGenericBlock, 0, s>>>(p, a, b, r);
-        else
-            k_fwd_generic<Q, T, true, false><<<nb, kGenericBlock, 0, s>>>(p, a, b, r);
-    } else {
-        if (force)
-            k_fwd_generic<Q, T, false, true><<<nb, kGenericBlock, 0, s>>>(p, a, b, r);
-        else
-            k_fwd_generic<Q, T, false, false><<<nb, kGenericBlock, 0, s>>>(p, a, b, r);
-    }
-    return hipGetLastError();
+    if (p.split)
+        return fwd_dispatch_split<Q, T, true>(p, force, a, b, r, nb, s);
+    return fwd_dispatch_split<Q, T, false>(p, force, a, b, r, nb, s);
 }
 
 template <int Q, class T>

@@ -15,6 +15,12 @@ struct ProblemArgs {
     long long n;             // nodes
     float a;                 // 2 - 2/omega, the post-combine factor of Eq. ACM2.0
     float A;                 // 3 (1 - a) = 3 (2/omega - 1); a + A/3 == 1 exactly in FP32
+    // Separate relaxation omega_p of the density update (the continuity
+    // equation): the density sums the link terms with Ap = 3 (2/omega_p - 1)
+    // and the moving-wall terms wall_term_p; 0: omega_p == omega.
+    int split;
+    float Ap;
+    float wall_term_p[kMaxWallIds][3];  // (2/omega_p - 1) * 6 * rho0 * u_w per wall id
     float g[3];              // body acceleration (Eq. force)
     int has_force;           // g given (forced problems use the generic kernel)
     float wall_term[kMaxWallIds][3];  // (1 - a) * 6 * rho0 * u_w per wall id (Eq. ACM2.0ccccbb)

@@ -525,7 +525,7 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
 bool march_supported(const ProblemArgs &p)
 {
     // 32-bit byte offsets inside a state buffer: n * 16 bytes < 4 GiB
-    return p.Q == 19 && !p.has_force && p.nx >= TX && p.ny >= TY && p.nx % TX == 0 &&
+    return p.Q == 19 && !p.has_force && !p.split && p.nx >= TX && p.ny >= TY && p.nx % TX == 0 &&
            p.ny % TY == 0 && p.nz >= 1 && p.n < (1LL << 28);
 }
 

@@ -51,6 +51,7 @@ def load_library():
         "lwacm_set_fp16_rounding": (i, [_vp, i, ctypes.c_uint32]),
         "lwacm_set_variant": (i, [_vp, i]),
         "lwacm_set_march_chunk": (i, [_vp, i]),
+        "lwacm_set_omega_p": (i, [_vp, ctypes.c_double]),
         "lwacm_set_state": (i, [_vp, _vp, _vp]),
         "lwacm_step": (i, [_vp, i]),
         "lwacm_diagnostics": (i, [_vp, dp, dp]),
@@ -129,6 +130,10 @@ def lwacm_set_fp16_rounding(ctx, mode: int, seed: int = 0):
 
 def lwacm_set_march_chunk(ctx, planes: int):
     _check(load_library().lwacm_set_march_chunk(ctx, planes), "lwacm_set_march_chunk")
+
+
+def lwacm_set_omega_p(ctx, omega_p: float):
+    _check(load_library().lwacm_set_omega_p(ctx, float(omega_p)), "lwacm_set_omega_p")
 
 
 def lwacm_set_variant(ctx, variant: int):
@@ -225,7 +230,8 @@ class Solver:
                  wall_u: Optional[Sequence[Sequence[float]]] = None,
                  g: Optional[Sequence[float]] = None, device="cuda",
                  variant: int = LWACM_KERNEL_AUTO, fp16_scales: Optional[Tuple[int, int]] = None,
-                 fp16_rounding: Optional[Tuple[int, int]] = None):
+                 fp16_rounding: Optional[Tuple[int, int]] = None,
+                 omega_p: Optional[float] = None):
         load_library()
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -251,6 +257,8 @@ class Solver:
             lwacm_set_fp16_scales(self.ctx, *fp16_scales)
         if fp16_rounding is not None:
             lwacm_set_fp16_rounding(self.ctx, *fp16_rounding)
+        if omega_p is not None:
+            lwacm_set_omega_p(self.ctx, omega_p)
         if variant != LWACM_KERNEL_AUTO:
             lwacm_set_variant(self.ctx, variant)
 

@@ -28,14 +28,14 @@ def to_dev(a, dtype=torch.float32):
 
 
 def gpu_run(q, shape, omega, drho, u, steps, storage=0, mask=None, wall_u=None, g=None,
-            variant=0, fp16_scales=None):
+            variant=0, fp16_scales=None, omega_p=None):
     """Run `steps` steps on the GPU; returns (drho, u) float64 numpy, diag, solver."""
     L = need_gpu()
     nz, ny, nx = shape
     s = L.Solver(q, nx, ny, nz, omega, storage=storage,
                  mask=None if mask is None else to_dev(mask, torch.uint8),
                  wall_u=None if wall_u is None else [list(r) for r in wall_u], g=g,
-                 variant=variant, fp16_scales=fp16_scales)
+                 variant=variant, fp16_scales=fp16_scales, omega_p=omega_p)
     s.set_state(to_dev(drho), to_dev(u))
     s.step(steps)
     dr, uu = s.moments()
@@ -43,10 +43,11 @@ def gpu_run(q, shape, omega, drho, u, steps, storage=0, mask=None, wall_u=None, 
     return dr.double().cpu().numpy(), uu.double().cpu().numpy(), s
 
 
-def oracle_run(q, shape, omega, drho, u, steps, mask=None, wall_u=None, g=None, rho0=1.0):
+def oracle_run(q, shape, omega, drho, u, steps, mask=None, wall_u=None, g=None, rho0=1.0,
+               omega_p=None):
     nz, ny, nx = shape
     p = oracle.Problem(q=q, nx=nx, ny=ny, nz=nz, omega=omega, mask=mask, wall_u=wall_u, g=g,
-                       rho0=rho0)
+                       rho0=rho0, omega_p=omega_p)
     r, uu = oracle.run(p, 1.0 + np.asarray(drho, dtype=np.float64), u, steps)
     return r - 1.0, uu
 

@@ -122,6 +122,25 @@ def divergence_free_field(n: int, kmax: int, amplitude: float, seed: int):
     return np.zeros((1, n, n)), u
 
 
+def double_shear_layer(n: int, u0: float, k: float = 80.0, delta: float = 0.05):
+    """The doubly periodic shear layer the paper uses to show the separate
+    omega_p (Section on the Minion & Brown test): on the unit square,
+    u = tanh(k (y - 1/4)) for y <= 1/2 and tanh(k (3/4 - y)) above, v = delta
+    sin(2 pi (x + 1/4)), both scaled by the lattice velocity u0; node i sits at
+    i / n.  rho = 1."""
+    x, y, _ = _grid(n, n, 1)
+    xs, ys = x / n, y / n
+    u = np.zeros((2, 1, n, n))
+    u[0] = u0 * np.where(ys <= 0.5, np.tanh(k * (ys - 0.25)), np.tanh(k * (0.75 - ys)))
+    u[1] = u0 * delta * np.sin(2 * np.pi * (xs + 0.25))
+    return np.zeros((1, n, n)), u
+
+
+def omega_for_viscosity(nu: float) -> float:
+    """omega of the lattice kinematic viscosity nu = (1/omega - 1/2) / 3 (Eq. viscosity2)."""
+    return 1.0 / (3.0 * nu + 0.5)
+
+
 def random_state(shape: Tuple[int, int, int], d: int, seed: int, du: float = 0.05,
                  drho: float = 0.02):
     """Uniform random (drho, u) perturbations of the rest state (for algebraic
