@@ -88,7 +88,35 @@ def _cavity_leg(args, L, wl, dev, stream):
     return {"value": round(fluid4 * args.steps / dt4 / 1e6, 1), "unit": "MLUPS (fluid nodes)",
             "ms_per_step": round(ms4, 5), "omega": c4.omega, "lid": list(c4.lid),
             "achieved_GBs": round(36.0 * c4.nx * c4.ny * c4.nz / (ms4 * 1e-3) / 1e9, 1),
-            "basis": "36 B per node: state in and out, 32-bit solid-link set"}
+            "basis": "36 B per node: state in and out, 32-bit solid-link set",
+            "kernel": "k_fwd_march_rolled<float,64,false,true,false>",
+            "traffic": _measured_traffic("k_fwd_march_rolled<float,64,false,true,false>")}
+
+
+def _split_leg(args, L, wl, dev, stream, drho_t, u_t, n):
+    """The 256^3 Taylor-Green step with a separate omega_p for the density
+    (nu_p = 10 nu): the single-step tile kernel with its eight extra LDS
+    partials per node."""
+    cfg = wl.TGV3D_256
+    nu = (1.0 / cfg.omega - 0.5) / 3.0
+    s6 = L.Solver(L.LWACM_D3Q19, n, n, n, cfg.omega, device=dev,
+                  omega_p=wl.omega_for_viscosity(10.0 * nu))
+    s6.set_state(drho_t, u_t)
+    s6.step(args.warmup)
+    dt6 = _events_time(s6.step, args.steps, stream)
+    s6.close()
+    ms6 = dt6 / args.steps * 1e3
+    nodes = n ** 3
+    print(f"[bench] omega_p split {n}^3: {ms6:.4f} ms/step", file=sys.stderr, flush=True)
+    kname = "k_fwd_march_rolled<float,128,false,false,true>"
+    return {"value": round(nodes * args.steps / dt6 / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(ms6, 5), "nu_p_over_nu": 10.0,
+            "achieved_GBs": round(32.0 * nodes / (ms6 * 1e-3) / 1e9, 1),
+            "frac": round(32.0 * nodes / (ms6 * 1e-3) / 8.0e12, 4),
+            "kernel": kname if n == 256 else None,
+            "traffic": _measured_traffic(kname) if n == 256 else None,
+            "basis": "32 B per update (state read and written); one step per launch: the "
+                     "single-step tile kernel with eight more LDS partials per node"}
 
 
 def main():
@@ -107,6 +135,8 @@ def main():
     ap.add_argument("--reverse-only", action="store_true",
                     help="time only the reverse (adjoint) step of the 256^3 workload (two per "
                          "launch; --variant 2: one per launch)")
+    ap.add_argument("--split-only", action="store_true",
+                    help="time only the 256^3 step with a separate omega_p (nu_p = 10 nu)")
     ap.add_argument("--cavity-only", action="store_true",
                     help="time only the 192^3 lid-driven cavity (walls, moving lid)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -148,6 +178,10 @@ def main():
     u_t = torch.as_tensor(u, dtype=torch.float32, device=dev)
     nodes = n ** 3
     del drho, u
+    if args.split_only:
+        print(json.dumps({"omega_p_split": _split_leg(args, L, wl, dev, stream, drho_t, u_t, n)}),
+              flush=True)
+        return
 
     def make(storage, rounding=L.LWACM_ROUND_STOCHASTIC):
         s = L.Solver(L.LWACM_D3Q19, n, n, n, cfg.omega, storage=storage, device=dev,
@@ -212,7 +246,7 @@ def main():
     bytes32 = 32.0 * nodes
     achieved = bytes32 / (ms32 * 1e-3) / 1e9
     fused = n == 256 and args.variant in (0, 3) and args.steps % 2 == 0
-    kname = "k_fwd_march2<128>" if fused else "k_fwd_march_rolled<float,128,false,false>"
+    kname = "k_fwd_march2<128>" if fused else "k_fwd_march_rolled<float,128,false,false,false>"
     per_launch = 2 if fused else 1
     t_launch = ms32 * 1e-3 * per_launch  # seconds per launch of the dominant kernel
     result = {
@@ -271,8 +305,8 @@ def main():
         "ms_per_step": round(ms1, 5),
         "achieved_GBs": round(32.0 * nodes / (ms1 * 1e-3) / 1e9, 1),
         "frac": round(32.0 * nodes / (ms1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "kernel": "k_fwd_march_rolled<float,128,false,false>" if n == 256 else None,
-        "traffic": _measured_traffic("k_fwd_march_rolled<float,128,false,false>")
+        "kernel": "k_fwd_march_rolled<float,128,false,false,false>" if n == 256 else None,
+        "traffic": _measured_traffic("k_fwd_march_rolled<float,128,false,false,false>")
         if n == 256 else None}
 
     # ---- FP16-deviation storage
@@ -292,9 +326,9 @@ def main():
                             "ms_per_step": round(ms16, 5), "rounding": "stochastic (pcg4d)",
                             "achieved_GBs": round(16.0 * nodes / dt16 * args.steps / 1e9, 1),
                             "ms_per_step_nearest_rounding": round(dt16n / args.steps * 1e3, 5),
-                            "kernel": "k_fwd_march_rolled<__half,128,true,false>"
+                            "kernel": "k_fwd_march_rolled<__half,128,true,false,false>"
                             if n == 256 else None,
-                            "traffic": _measured_traffic("k_fwd_march_rolled<__half,128,true,false>")
+                            "traffic": _measured_traffic("k_fwd_march_rolled<__half,128,true,false,false>")
                             if n == 256 else None}
 
     # ---- reverse step at the same size (reads state_t and mu_t, writes mu_{t-1});
@@ -355,23 +389,8 @@ def main():
     # ---- lid-driven cavity 192^3 (mask active, moving lid)
     result["cavity_192"] = _cavity_leg(args, L, wl, dev, stream)
 
-    # ---- separate omega_p for the density: the same 256^3 step on the generic kernel
-    s6 = L.Solver(L.LWACM_D3Q19, n, n, n, cfg.omega, device=dev,
-                  omega_p=wl.omega_for_viscosity(10.0 * (1.0 / cfg.omega - 0.5) / 3.0))
-    s6.set_state(drho_t, u_t)
-    s6.step(args.warmup)
-    dt6 = _events_time(s6.step, args.steps, stream)
-    s6.close()
-    ms6 = dt6 / args.steps * 1e3
-    print(f"[bench] omega_p split 256^3: {ms6:.4f} ms/step", file=sys.stderr, flush=True)
-    result["omega_p_split"] = {
-        "value": round(nodes * args.steps / dt6 / 1e6, 1), "unit": "MLUPS",
-        "ms_per_step": round(ms6, 5), "nu_p_over_nu": 10.0,
-        "achieved_GBs": round(32.0 * nodes / (ms6 * 1e-3) / 1e9, 1),
-        "frac": round(32.0 * nodes / (ms6 * 1e-3) / 8.0e12, 4),
-        "kernel": "k_fwd_generic<19,float,false,false,true>",
-        "basis": "32 B per update (state read and written); the generic kernel gathers the "
-                 "18 upstream nodes through L1/L2"}
+    # ---- separate omega_p for the density: the same 256^3 step, one step per launch
+    result["omega_p_split"] = _split_leg(args, L, wl, dev, stream, drho_t, u_t, n)
 
     # ---- differentiable D2Q9 512^2: reverse / forward at the gradient workload (launch-bound)
     c5 = wl.ADJOINT_512

@@ -269,7 +269,9 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
 // too is unconditional; only the moving-wall sums are loaded conditionally,
 // by the waves next to a moving wall.  Node for node the same operations as
 // k_fwd_march (the column helpers are shared), so the same results.
-template <class T, int NZC, bool SR, bool MASK>
+// SPLIT: a separate omega_p for the density (no walls): the columns also
+// push q = 36 w (Ap - A) rho (v . u) through eight more LDS arrays.
+template <class T, int NZC, bool SR, bool MASK, bool SPLIT>
 __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
                                                                const T *__restrict__ src,
                                                                T *__restrict__ dst,
@@ -281,6 +283,10 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
     // idle halo lanes write there instead of branching
     __shared__ float2 xp[2][4][NSLOT + 1];
     __shared__ float xd[2][4][NSLOT + 1];
+    constexpr int QS = SPLIT ? NSLOT + 1 : 1;  // q slots (one spare, as above)
+    __shared__ float xq[SPLIT ? 2 : 1][8][QS];
+    static_assert(!(SPLIT && MASK), "the separate omega_p runs without walls");
+    const float dA = p.Ap - p.A;
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -367,15 +373,20 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             Acc &Am = acc[(j + 2) % 3];  // target plane pz - 1 (finalised now)
             push_column<MASK>(dr, ux, uy, uz, MASK ? class_of(b) : 0, b, A, a, acc[(j + 1) % 3],
                               acc[j], Am);
+            if (SPLIT) push_split_column(1.0f + dr, ux, uy, uz, dA, acc[(j + 1) % 3], acc[j], Am);
             __builtin_amdgcn_sched_barrier(0);  // the ring slot's last use is above
             if (I::refill) issue(j, ring[j], z0 + 2 + k);
             if (I::phase < 2) return;
             const Xchg<NSLOT + 1> X{xp[k & 1], xd[k & 1]};
             put_slot(X, slot, Am);
+            if constexpr (SPLIT) put_slot_split(XchgQ<QS>{xq[k & 1]}, slot, Am);
             __syncthreads();
             const int tz = z0 - 2 + k;
-            const NodeOut o = finalize<MASK, NSLOT + 1, SX>(X, slot, Am, p, wallg,
-                                                            (long long)tz * plane + col);
+            float qsum = 0.0f;
+            if constexpr (SPLIT) qsum = Am.qd + gather_split<QS, SX>(XchgQ<QS>{xq[k & 1]}, slot);
+            const NodeOut o = finalize<MASK, NSLOT + 1, SX, SPLIT>(X, slot, Am, p, wallg,
+                                                                   (long long)tz * plane + col,
+                                                                   qsum);
             const unsigned so = (unsigned)tz * plane_bytes;
             typename BufIO<T>::Raw out;
             if (SR) {  // FP16 storage, stochastic rounding (a template parameter: one path)
@@ -394,6 +405,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
     } else {
         float hp[3] = {0.0f, 0.0f, 0.0f}, hz[3] = {0.0f, 0.0f, 0.0f};
         float hd1[3] = {0.0f, 0.0f, 0.0f}, hd2[3] = {0.0f, 0.0f, 0.0f};
+        float hq[3] = {0.0f, 0.0f, 0.0f}, hq1[3] = {0.0f, 0.0f, 0.0f}, hq2[3] = {0.0f, 0.0f, 0.0f};
         const bool isY = role == HALO_Y;
         plane_loop<N>([&](int k, auto kc) {
             using I = PlaneIter<decltype(kc)::value, N, 3>;
@@ -403,11 +415,16 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             value(ring[j], dr, ux, uy, uz);
             push_halo<MASK>(dr, ux, uy, uz, MASK ? class_of(bw[j]) : 0, A, isY, sgn, hp[j1],
                             hz[j1], hp[j], hd1[j], hd2[j], hp[jm], hz[jm]);
+            if (SPLIT)
+                push_split_halo(1.0f + dr, ux, uy, uz, dA, isY, sgn, hq[j1], hq[j], hq1[j], hq2[j],
+                                hq[jm]);
             __builtin_amdgcn_sched_barrier(0);
             if (I::refill) issue(j, ring[j], z0 + 2 + k);
             if (I::phase < 2) return;
             put_halo(Xchg<NSLOT + 1>{xp[k & 1], xd[k & 1]}, wslot, isY, sgn, hp[jm], hz[jm],
                      hd1[jm], hd2[jm]);
+            if constexpr (SPLIT)
+                put_halo_split(XchgQ<QS>{xq[k & 1]}, wslot, isY, sgn, hq[jm], hq1[jm], hq2[jm]);
             __syncthreads();
         });
     }
@@ -482,16 +499,16 @@ __global__ __launch_bounds__(256) void k_classify(ProblemArgs p, uint8_t *cls, u
     }
 }
 
-template <class T, bool SR, bool MASK>
+template <class T, bool SR, bool MASK, bool SPLIT = false>
 void launch_rolled(int c, unsigned nb, hipStream_t s, const ProblemArgs &p, const T *a, T *b,
                    const unsigned *bits, const float4 *wallg, const ReduceArgs &r)
 {
     switch (c) {
-    case 8: k_fwd_march_rolled<T, 8, SR, MASK><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    case 16: k_fwd_march_rolled<T, 16, SR, MASK><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    case 32: k_fwd_march_rolled<T, 32, SR, MASK><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    case 64: k_fwd_march_rolled<T, 64, SR, MASK><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    default: k_fwd_march_rolled<T, 128, SR, MASK><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 8: k_fwd_march_rolled<T, 8, SR, MASK, SPLIT><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 16: k_fwd_march_rolled<T, 16, SR, MASK, SPLIT><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 32: k_fwd_march_rolled<T, 32, SR, MASK, SPLIT><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 64: k_fwd_march_rolled<T, 64, SR, MASK, SPLIT><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    default: k_fwd_march_rolled<T, 128, SR, MASK, SPLIT><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
     }
 }
 
@@ -513,6 +530,9 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
     } else if (p.mask) {
         if (sr) launch_rolled<T, true, true>(c, nb, s, p, a, b, bits, wallg, r);
         else launch_rolled<T, false, true>(c, nb, s, p, a, b, bits, wallg, r);
+    } else if (p.split) {  // separate omega_p (no walls, nz >= 8: march_supported)
+        if (sr) launch_rolled<T, true, false, true>(c, nb, s, p, a, b, bits, wallg, r);
+        else launch_rolled<T, false, false, true>(c, nb, s, p, a, b, bits, wallg, r);
     } else {
         if (sr) launch_rolled<T, true, false>(c, nb, s, p, a, b, bits, wallg, r);
         else launch_rolled<T, false, false>(c, nb, s, p, a, b, bits, wallg, r);
@@ -525,7 +545,9 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
 bool march_supported(const ProblemArgs &p)
 {
     // 32-bit byte offsets inside a state buffer: n * 16 bytes < 4 GiB
-    return p.Q == 19 && !p.has_force && !p.split && p.nx >= TX && p.ny >= TY && p.nx % TX == 0 &&
+    // a separate omega_p only on the rolled kernel without walls
+    const bool split_ok = !p.split || (!p.mask && p.nz >= 8);
+    return p.Q == 19 && !p.has_force && split_ok && p.nx >= TX && p.ny >= TY && p.nx % TX == 0 &&
            p.ny % TY == 0 && p.nz >= 1 && p.n < (1LL << 28);
 }
 

@@ -71,6 +71,9 @@ struct Acc {
     float d, jz;                           // own column: rest + (0,0,+-1) links
     float post[3];                         // a rho u of the node itself
     float bb[4];                           // bounced-back terms: 36 w (1, v) sums (MASK)
+    // separate omega_p (SPLIT): 36 w (Ap - A) rho (v . u) over the same links
+    // as pe .. sw and as the own column's z links
+    float qe, qw, qn, qs, qne, qnw, qse, qsw, qd;
     unsigned bits;                         // solid upstream links (bounce-back only)
     int cls;                               // 0 fluid, 1 fluid next to a wall, 2 solid
 };
@@ -434,9 +437,9 @@ __device__ __forceinline__ Gathered gather(const Xchg<NS> &X, int slot)
 // recomputed from its saved coefficients with the same operations, plus the
 // moving-wall term from the geometry sums wallg[widx]), then the
 // normalisation by 1 + D.
-template <bool MASK>
+template <bool MASK, bool SPLIT = false>
 __device__ __forceinline__ NodeOut finish(const Gathered &g, const Acc &Am, const ProblemArgs &p,
-                                          const float4 *wallg, long long widx)
+                                          const float4 *wallg, long long widx, float qsum = 0.0f)
 {
     float D36 = Am.d + ((g.pE + g.pW) + (g.pN + g.pS)) + ((g.dNE + g.dNW) + (g.dSE + g.dSW));
     float Jx = (g.pE - g.pW) + ((g.dNE - g.dNW) + (g.dSE - g.dSW));
@@ -459,6 +462,8 @@ __device__ __forceinline__ NodeOut finish(const Gathered &g, const Acc &Am, cons
             Jz = fmaf(p.wall_scale, w.w, Jz);
         }
     }
+    // separate omega_p: the density takes its link terms with Ap in place of A
+    if (SPLIT) D36 += qsum;
     Jx = div36(Jx) + Am.post[0];
     Jy = div36(Jy) + Am.post[1];
     Jz = div36(Jz) + Am.post[2];
@@ -471,12 +476,111 @@ __device__ __forceinline__ NodeOut finish(const Gathered &g, const Acc &Am, cons
     return o;
 }
 
-template <bool MASK, int NS, int SXP>
+template <bool MASK, int NS, int SXP, bool SPLIT = false>
 __device__ __forceinline__ NodeOut finalize(const Xchg<NS> &X, int slot, const Acc &Am,
                                             const ProblemArgs &p, const float4 *wallg,
-                                            long long widx)
+                                            long long widx, float qsum = 0.0f)
 {
-    return finish<MASK>(gather<NS, SXP>(X, slot), Am, p, wallg, widx);
+    return finish<MASK, SPLIT>(gather<NS, SXP>(X, slot), Am, p, wallg, widx, qsum);
+}
+
+// ---- separate omega_p for the density (Section "finite-difference
+// formulation", item 3; Appendix E).  The density of the step sums the link
+// terms with Ap = 3 (2/omega_p - 1) in place of A; a link term is linear in A
+// through A rho (v . u), so the density gains, per incoming link,
+// q = 36 w (Ap - A) rho_y (v . u_y).  Columns push q along the links that
+// carry the density partials (pe .. sw, and the own column's z links), in
+// eight LDS arrays of their own: e, w, n, s, ne, nw, se, sw.
+template <int NS>
+struct XchgQ {
+    float (*Q)[NS];
+};
+
+// q of the links pushed by an interior column (the links and targets of
+// push_column); rd = (Ap - A) rho, v . u formed as push_column forms it
+__device__ __forceinline__ void push_split_column(float rho, float ux, float uy, float uz,
+                                                  float dA, Acc &A1, Acc &A0, Acc &Am)
+{
+    const float rd = dA * rho;
+    const float qx = rd * ux, qy = rd * uy, qz = rd * uz;
+    const float qpp0 = rd * (ux + uy), qpm0 = rd * (ux - uy);
+    const float qp0p = rd * (ux + uz), qp0m = rd * (ux - uz);
+    const float q0pp = rd * (uy + uz), q0pm = rd * (uy - uz);
+    // v_z = +1: start plane pz + 1
+    A1.qe = qp0p;
+    A1.qw = -qp0m;
+    A1.qn = q0pp;
+    A1.qs = -q0pm;
+    A1.qd = 2.0f * qz;
+    // v_z = 0: plane pz (the rest link has v . u = 0)
+    A0.qe = fmaf(2.0f, qx, A0.qe);
+    A0.qw = fmaf(-2.0f, qx, A0.qw);
+    A0.qn = fmaf(2.0f, qy, A0.qn);
+    A0.qs = fmaf(-2.0f, qy, A0.qs);
+    A0.qne = qpp0;
+    A0.qnw = -qpm0;
+    A0.qse = qpm0;
+    A0.qsw = -qpp0;
+    // v_z = -1: finish plane pz - 1
+    Am.qe += qp0m;
+    Am.qw -= qp0p;
+    Am.qn += q0pm;
+    Am.qs -= q0pp;
+    Am.qd = fmaf(-2.0f, qz, Am.qd);
+}
+
+// q of the five links a halo column pushes into the tile (push_halo's links)
+__device__ __forceinline__ void push_split_halo(float rho, float ux, float uy, float uz,
+                                                float dA, bool isY, float sgn, float &q1,
+                                                float &q0, float &qd1, float &qd2, float &qm)
+{
+    const float rd = dA * rho;
+    const float ua = isY ? uy : ux;
+    const float ub = isY ? ux : uy;
+    const float cs = sgn * ua;
+    q1 = rd * (cs + uz);
+    q0 = fmaf(2.0f, rd * cs, q0);
+    qd1 = rd * (cs + ub);
+    qd2 = rd * (cs - ub);
+    qm += rd * (cs - uz);
+}
+
+template <int NS>
+__device__ __forceinline__ void put_slot_split(const XchgQ<NS> &X, int slot, const Acc &Am)
+{
+    X.Q[0][slot] = Am.qe;
+    X.Q[1][slot] = Am.qw;
+    X.Q[2][slot] = Am.qn;
+    X.Q[3][slot] = Am.qs;
+    X.Q[4][slot] = Am.qne;
+    X.Q[5][slot] = Am.qnw;
+    X.Q[6][slot] = Am.qse;
+    X.Q[7][slot] = Am.qsw;
+}
+
+// the arrays put_halo writes for the same links
+template <int NS>
+__device__ __forceinline__ void put_halo_split(const XchgQ<NS> &X, int slot, bool isY, float sgn,
+                                               float q, float qd1, float qd2)
+{
+    const int hi = sgn > 0.0f ? 0 : 1;
+    const int ip = isY ? 2 + hi : hi;
+    const int i1 = isY ? 2 * hi : hi;
+    const int i2 = isY ? 2 * hi + 1 : hi + 2;
+    X.Q[ip][slot] = q;
+    X.Q[4 + i1][slot] = qd1;
+    X.Q[4 + i2][slot] = qd2;
+}
+
+// the q a node receives from its eight in-plane neighbours (gather's slots)
+template <int NS, int SXP>
+__device__ __forceinline__ float gather_split(const XchgQ<NS> &X, int slot)
+{
+    const float qE = X.Q[0][slot - 1], qW = X.Q[1][slot + 1];
+    const float qN = X.Q[2][slot - SXP], qS = X.Q[3][slot + SXP];
+    const float qNE = X.Q[4][slot - SXP - 1], qNW = X.Q[5][slot - SXP + 1];
+    const float qSE = X.Q[6][slot + SXP - 1], qSW = X.Q[7][slot + SXP + 1];
+    return ((qE + qW) + (qN + qS)) + ((qNE + qNW) + (qSE + qSW));
 }
 
 // A halo column pushes only the five links that point into the tile: those

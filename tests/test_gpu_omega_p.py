@@ -5,9 +5,12 @@ oracle's split step.
 - The paper's use case: the under-resolved double shear layer (D2Q9 128^2,
   Re = 10^4) with nu_p = 170 nu.
 - D3Q19 with walls (two moving ids) and a body force, FP32 and FP16 storage.
-- Scope: the split runs on the generic kernel only.  The tile kernels are
-  declined, and so are the reverse steps.  omega_p == omega gives back the
-  single-relaxation step bit for bit, on the tile kernels.
+- The single-step D3Q19 tile kernel with the split (no walls, nz >= 8):
+  against the generic kernel and the oracle, FP32 and FP16, ragged and thin
+  grids; chunk depths bitwise equal.
+- Scope: walls, thin grids and the two-step kernel go to the generic kernel
+  (the tile variants are declined), and the reverse steps are declined.
+  omega_p == omega gives back the single-relaxation step bit for bit.
 - The FP64 mass diagnostic of a periodic run stays at its initial value.
 """
 import numpy as np
@@ -79,6 +82,50 @@ def test_d3q19_walls_and_force_match_oracle(storage):
     assert err_r < (1e-4 if storage == 0 else 2e-2)
 
 
+@pytest.mark.parametrize("shape", [(40, 32, 64), (150, 32, 64), (8, 16, 32)])
+@pytest.mark.parametrize("storage", [0, 1])
+def test_tile_kernel_split_matches_generic_and_oracle(shape, storage):
+    banner(f"omega_p tile kernel {shape} storage={storage}")
+    drho, u = wl.random_state(shape, 3, seed=23, du=0.03, drho=0.01)
+    drho = drho.astype(np.float32).astype(np.float64)
+    u = u.astype(np.float32).astype(np.float64)
+    dt, ut, s = gpu_run(19, shape, 1.7, drho, u, 6, storage=storage, omega_p=0.9,
+                        variant=MARCH)
+    s.close()
+    dg, ug, s = gpu_run(19, shape, 1.7, drho, u, 6, storage=storage, omega_p=0.9,
+                        variant=GENERIC)
+    s.close()
+    rdr, ru = oracle_run(19, shape, 1.7, drho, u, 6, omega_p=0.9)
+    err_u, err_r = rel_l2(ut, ru), rel_l2(dt, rdr)
+    banner(f"omega_p tile: rel-L2 u {err_u:.3e}, drho {err_r:.3e}; vs generic "
+           f"{rel_l2(ut, ug):.3e}")
+    if storage == 0:
+        assert rel_l2(ut, ug) < 1e-6 and rel_l2(dt, dg) < 1e-5
+        assert err_u < 1e-5 and err_r < 1e-4
+    else:
+        assert err_u < 1e-3 and err_r < 2e-2
+
+
+@pytest.mark.parametrize("planes", [32, 64, 128])
+def test_tile_kernel_split_chunk_depths_agree_bitwise(planes):
+    L = need_gpu()
+    shape = (150, 32, 64)
+    banner(f"omega_p tile chunk {planes}")
+    drho, u = wl.random_state(shape, 3, seed=24, du=0.03, drho=0.01)
+
+    def run(depth):
+        s = L.Solver(19, 64, 32, 150, 1.6, omega_p=1.2)
+        L.lwacm_set_march_chunk(s.ctx, depth)
+        s.set_state(to_dev(drho), to_dev(u))
+        s.step(5)
+        dr, uu = s.moments()
+        s.close()
+        return dr, uu
+
+    a, b = run(planes), run(32)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
 def test_omega_p_scope():
     L = need_gpu()
     banner("omega_p scope")
@@ -87,10 +134,18 @@ def test_omega_p_scope():
         L.lwacm_set_omega_p(s.ctx, 2.0)
     assert ei.value.code == L.LWACM_EINVAL
     L.lwacm_set_omega_p(s.ctx, 1.1)
-    for v in (MARCH, MARCH2):
+    with pytest.raises(L.LWACMError) as ei:
+        L.lwacm_set_variant(s.ctx, MARCH2)
+    assert ei.value.code == L.LWACM_EUNSUPPORTED
+    L.lwacm_set_variant(s.ctx, MARCH)  # the single-step tile kernel takes it
+    mask = torch.zeros((16, 32, 64), dtype=torch.uint8, device="cuda")
+    mask[0] = 1
+    for shp, msk in (((16, 32, 64), mask), ((7, 32, 64), None)):  # walls; fewer than 8 planes
+        t = L.Solver(19, shp[2], shp[1], shp[0], 1.7, mask=msk, omega_p=1.1)
         with pytest.raises(L.LWACMError) as ei:
-            L.lwacm_set_variant(s.ctx, v)
+            L.lwacm_set_variant(t.ctx, MARCH)
         assert ei.value.code == L.LWACM_EUNSUPPORTED
+        t.close()
     drho, u = wl.random_state((16, 32, 64), 3, seed=20, du=0.02, drho=0.01)
     s.set_state(to_dev(drho), to_dev(u))
     st = s.save_state()
@@ -106,7 +161,7 @@ def test_omega_p_scope():
 
 def test_omega_p_equal_to_omega_is_the_single_relaxation_step():
     """Default, omega_p set to omega, and omega_p set away and back: the
-    same bits (the tile kernels run in all three)."""
+    same bits (the two-step tile kernel runs in all three)."""
     shape = (40, 32, 64)
     banner("omega_p == omega")
     drho, u = wl.random_state(shape, 3, seed=21, du=0.03, drho=0.01)
@@ -130,17 +185,21 @@ def test_omega_p_equal_to_omega_is_the_single_relaxation_step():
 
 
 def test_omega_p_keeps_mass_on_a_periodic_grid():
+    """nu_p ~ 4 nu (omega 1.9, omega_p 1.2): a stable run, its kinetic energy
+    decays.  (omega_p = 0.8 with omega = 1.9 is unstable for this grid-scale
+    random state: the FP64 oracle's energy grows a millionfold in 50 steps.)"""
     shape = (32, 32, 64)
     banner("omega_p mass")
     drho, u = wl.random_state(shape, 3, seed=22, du=0.03, drho=0.01)
     drho = drho - drho.mean()
     L = need_gpu()
-    s = L.Solver(19, 64, 32, 32, 1.9, omega_p=0.8)
+    s = L.Solver(19, 64, 32, 32, 1.9, omega_p=1.2)
     s.set_state(to_dev(drho), to_dev(u))
-    _, _, (m0, _) = s.moments(diagnostics=True)
+    _, _, (m0, e0) = s.moments(diagnostics=True)
     s.step(50)
-    _, _, (m1, _) = s.moments(diagnostics=True)
+    _, _, (m1, e1) = s.moments(diagnostics=True)
     s.close()
     n = float(np.prod(shape))
-    banner(f"omega_p mass: {m0 - n:.3e} -> {m1 - n:.3e}")
+    banner(f"omega_p mass: {m0 - n:.3e} -> {m1 - n:.3e}, energy {e0:.3e} -> {e1:.3e}")
+    assert e1 < 0.1 * e0
     assert abs(m1 - m0) < 1e-9 * n
