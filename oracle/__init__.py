@@ -49,6 +49,8 @@ def _load():
     lib.oracle_step_split.argtypes = common[:5] + [ctypes.c_double] + common[5:] + [_dp, _dp, _dp,
                                                                                      _dp]
     lib.oracle_step_split.restype = ctypes.c_int
+    lib.oracle_step_field.argtypes = common[:8] + [_dp, ctypes.c_double, _dp, _dp, _dp, _dp]
+    lib.oracle_step_field.restype = ctypes.c_int
     lib.oracle_vjp.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_vjp.restype = ctypes.c_int
     lib.oracle_step_nodes.argtypes = common + [_dp, _dp, ctypes.POINTER(ctypes.c_long),
@@ -174,6 +176,23 @@ def step(p: Problem, rho, u):
     rc = _step_call(lib, p, p._args(), rho, u, r1, u1)
     if rc != 0:
         raise RuntimeError(f"oracle_step failed ({rc})")
+    return r1, u1
+
+
+def step_field(p: Problem, rho, u, g_field):
+    """One step with a node-by-node body acceleration g_field (D, nz, ny, nx)
+    (the problem's uniform g and omega_p are not used); returns new (rho, u)."""
+    lib = _load()
+    rho = _f64(rho, p.shape)
+    u = _f64(u, (p.d,) + p.shape)
+    g = _f64(g_field, (p.d,) + p.shape)
+    r1 = np.empty_like(rho)
+    u1 = np.empty_like(u)
+    args = p._args()
+    rc = lib.oracle_step_field(*args[:8], _ptr(g), args[9], _ptr(rho), _ptr(u), _ptr(r1),
+                               _ptr(u1))
+    if rc != 0:
+        raise RuntimeError(f"oracle_step_field failed ({rc})")
     return r1, u1
 
 

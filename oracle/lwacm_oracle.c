@@ -19,7 +19,9 @@
  *     upstream equilibrium plus (2 - 2/omega) times the odd-part difference
  *     between x and the upstream node;
  *   - the forcing step, Eq. force: the odd part evaluated at (rho(x,t), g) is
- *     added to every population;
+ *     added to every population; g uniform, or a field given node by node
+ *     (the space- and time-dependent acceleration of Section "Generalized
+ *     Taylor-Green vortex flow");
  *   - halfway bounce-back for a solid upstream node, Eqs. ACM2.0cbb to
  *     ACM2.0cccbb2, with the moving-wall correction of Eqs. ACM2.0movebb
  *     and ACM2.0ccccbb, (2/omega - 1) * 2 f^(e,o)(rho0, u_w);
@@ -290,6 +292,46 @@ int oracle_step(int q, int nx, int ny, int nz, double omega, const uint8_t *mask
                 }
                 double f[MAXQ];
                 node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_in,
+                                 u_in, x, y, z, f);
+                double r = 0.0, j[3] = {0, 0, 0};
+                for (int i = 0; i < L.q; ++i) {
+                    r += f[i];
+                    for (int k = 0; k < 3; ++k) j[k] += L.v[i][k] * f[i];
+                }
+                rho_out[ix] = r;
+                for (int k = 0; k < L.d; ++k) u_out[k * n + ix] = j[k] / r;
+            }
+    return 0;
+}
+
+/* One step with a body acceleration that varies from node to node (Section
+ * "Generalized Taylor-Green vortex flow": a space- and time-dependent
+ * external acceleration).  g_field holds D fields of n values (SoA): the
+ * acceleration of node x for this step, entering Eq. force with rho(x, t)
+ * as the uniform g does. */
+int oracle_step_field(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
+                      const double *wall_u, int n_ids, const double *g_field, double rho0,
+                      const double *rho_in, const double *u_in, double *rho_out, double *u_out)
+{
+    lattice_t L;
+    if (make_lattice(q, &L)) return -1;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (L.d == 2 && nz != 1) || !g_field) return -1;
+    long n = (long)nx * ny * nz;
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long ix = node_index(nx, ny, x, y, z);
+                if (mask && mask[ix] != 0) {
+                    rho_out[ix] = rho_in[ix];
+                    for (int k = 0; k < L.d; ++k) u_out[k * n + ix] = u_in[k * n + ix];
+                    continue;
+                }
+                double g[3] = {0, 0, 0};
+                for (int k = 0; k < L.d; ++k) g[k] = g_field[k * n + ix];
+                double f[MAXQ];
+                node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, g, rho0, rho_in,
                                  u_in, x, y, z, f);
                 double r = 0.0, j[3] = {0, 0, 0};
                 for (int i = 0; i < L.q; ++i) {

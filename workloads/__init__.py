@@ -136,9 +136,62 @@ def double_shear_layer(n: int, u0: float, k: float = 80.0, delta: float = 0.05):
     return np.zeros((1, n, n)), u
 
 
-def omega_for_viscosity(nu: float) -> float:
-    """omega of the lattice kinematic viscosity nu = (1/omega - 1/2) / 3 (Eq. viscosity2)."""
-    return 1.0 / (3.0 * nu + 0.5)
+class ForcedTaylorGreen:
+    """The generalized Taylor-Green vortex of the paper (its section of that
+    name): a time-periodic flow kept up by an external acceleration, on the
+    periodic square [0, 2 pi]^2 with (u0, v0) = (0.3, 0.6) and nu = 0.1, in
+    diffusive scaling (dx = eps, dt = eps^2, Table "scaling").  Node i sits at
+    i eps, N = 2 pi / eps nodes per side; lattice velocity u = eps u_bar,
+    pressure p_bar = (rho/3 - p0) / eps^2 with p0 the mean, acceleration
+    g = eps^3 g_bar, omega from nu (Eq. viscosity2)."""
+
+    u0, v0, nu = 0.3, 0.6, 0.1
+
+    def __init__(self, m: int):
+        self.eps = np.pi / m          # eps = pi/16, pi/32, pi/64 in the paper's table
+        self.n = 2 * m
+        self.omega = omega_for_viscosity(self.nu)
+        idx = np.arange(self.n) * self.eps
+        self.x, self.y = np.meshgrid(idx, idx, indexing="xy")  # [y, x]
+
+    def steps_to(self, t: float) -> int:
+        return int(round(t / self.eps ** 2))
+
+    def exact(self, t: float):
+        """(u_bar, v_bar, p_bar) of the analytic solution at time t."""
+        a, b = self.x - self.u0 * t, self.y - self.v0 * t
+        u = self.u0 + np.sin(a) * np.cos(b) * np.cos(t)
+        v = self.v0 - np.cos(a) * np.sin(b) * np.cos(t)
+        p = 0.25 * (np.cos(2 * a) + np.cos(2 * b)) * np.cos(t) ** 2
+        return u, v, p
+
+    def initial_state(self):
+        """(drho (1, n, n), u (2, 1, n, n)) in lattice units at t = 0."""
+        ub, vb, pb = self.exact(0.0)
+        drho = (3.0 * self.eps ** 2 * pb)[None]
+        u = np.stack([self.eps * ub, self.eps * vb])[:, None]
+        return drho, u
+
+    def acceleration(self, step: int):
+        """Lattice acceleration field (2, 1, n, n) of the step that starts at
+        t = step eps^2 (Eq. force takes g at the current time level)."""
+        t = step * self.eps ** 2
+        a, b = self.x - self.u0 * t, self.y - self.v0 * t
+        f = 2.0 * self.nu * np.cos(t) - np.sin(t)
+        e3 = self.eps ** 3
+        return np.stack([e3 * np.sin(a) * np.cos(b) * f, -e3 * np.cos(a) * np.sin(b) * f])[:, None]
+
+    def l1_errors(self, step: int, drho, u):
+        """Mean absolute errors of (u_bar, v_bar, p_bar) over the nodes after
+        `step` steps (lattice state drho (1, n, n), u (2, 1, n, n))."""
+        ue, ve, pe = self.exact(step * self.eps ** 2)
+        r = 1.0 + np.asarray(drho, dtype=np.float64)[0]
+        p = r / 3.0
+        pnum = (p - p.mean()) / self.eps ** 2
+        uu = np.asarray(u, dtype=np.float64)
+        return (float(np.abs(uu[0, 0] / self.eps - ue).mean()),
+                float(np.abs(uu[1, 0] / self.eps - ve).mean()),
+                float(np.abs(pnum - pe).mean()))
 
 
 def random_state(shape: Tuple[int, int, int], d: int, seed: int, du: float = 0.05,
