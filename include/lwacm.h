@@ -158,6 +158,19 @@ int lwacm_set_march_chunk(lwacm_ctx *c, int planes);
  * steps return LWACM_EUNSUPPORTED.  Takes effect from the next lwacm_step. */
 int lwacm_set_omega_p(lwacm_ctx *c, double omega_p);
 
+/* Body acceleration given node by node (Eq. force with a space- and
+ * time-dependent g, as in the paper's generalized Taylor-Green vortex, Eq.
+ * external-force).  d_g: D FP32 fields of nx*ny*nz values (SoA, node index as
+ * the state's), caller-owned device memory read by every following step until
+ * the next call; it replaces the uniform g of lwacm_init while set, and NULL
+ * returns to that g (or to no forcing).  The step adds rho(x, t) g(x) to the
+ * momentum of node x (Eq. force, with the density before the step).  A g that
+ * changes in time is set before each lwacm_step(c, 1), with the field of the
+ * step's starting time.  The forward step then runs on the generic kernel;
+ * the reverse steps return LWACM_EUNSUPPORTED while a field is set.
+ * LWACM_EINVAL for a null context. */
+int lwacm_set_force_field(lwacm_ctx *c, const float *d_g);
+
 /* Load the state from FP32 fields (rho - 1 and u, SoA), converting to the
  * storage format, and set rho0 (the mean fluid density used by moving walls,
  * Section 3.2) to the mean of 1 + d_drho over fluid nodes.  Resets the step

@@ -338,6 +338,14 @@ int lwacm_set_march_chunk(lwacm_ctx *c, int planes)
     return LWACM_OK;
 }
 
+int lwacm_set_force_field(lwacm_ctx *c, const float *d_g)
+{
+    if (!c) return LWACM_EINVAL;
+    c->p.g_field = d_g;
+    c->p.has_force = (c->force || d_g) ? 1 : 0;
+    return LWACM_OK;
+}
+
 int lwacm_set_omega_p(lwacm_ctx *c, double omega_p)
 {
     if (!c || !(omega_p > 0.0 && omega_p < 2.0)) return LWACM_EINVAL;
@@ -440,7 +448,8 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
             e = lwacm::launch_fwd_march(c->p, c->storage, src, dst, c->d_cls, c->d_bits,
                                         c->d_wallg, r, c->stream);
         else
-            e = lwacm::launch_fwd_generic(c->p, c->storage, c->force, src, dst, r, nb1, c->stream);
+            e = lwacm::launch_fwd_generic(c->p, c->storage, c->p.has_force != 0, src, dst, r, nb1,
+                                          c->stream);
         if (e != hipSuccess) return LWACM_EDEVICE;
         const unsigned nb = two ? nb2 : nb1;
         npend = 0;
@@ -541,7 +550,8 @@ int lwacm_adjoint_step(lwacm_ctx *c, const void *d_state_t, const float *d_mu_in
 {
     if (!c || !d_state_t || !d_mu_in || !d_mu_out || !d_dL_domega || d_mu_in == d_mu_out)
         return LWACM_EINVAL;
-    if (c->p.split) return LWACM_EUNSUPPORTED;  // no reverse step for omega_p != omega
+    // no reverse step for omega_p != omega, nor for a node-by-node acceleration
+    if (c->p.split || c->p.g_field) return LWACM_EUNSUPPORTED;
     ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
     r.accumulate = 1;
     r.out_scale = 2.0 / (c->omega * c->omega);  // da/domega for a = 2 - 2/omega
@@ -559,7 +569,7 @@ int lwacm_adjoint_step2(lwacm_ctx *c, const void *d_state_t, const void *d_state
         d_mu_in == d_mu_out)
         return LWACM_EINVAL;
     if ((c->variant != LWACM_KERNEL_AUTO && c->variant != LWACM_KERNEL_MARCH2) ||
-        !lwacm::adj_march2_supported(c->p) || c->p.split)
+        !lwacm::adj_march2_supported(c->p) || c->p.split || c->p.g_field)
         return LWACM_EUNSUPPORTED;
     ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
     r.accumulate = 1;

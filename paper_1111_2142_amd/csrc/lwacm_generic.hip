@@ -137,7 +137,8 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
         float g3[3] = {0.0f, 0.0f, 0.0f};
         if (FORCE)
 #pragma unroll
-            for (int k = 0; k < D; ++k) g3[k] = 3.0f * rx * p.g[k];
+            for (int k = 0; k < D; ++k)
+                g3[k] = 3.0f * rx * (p.g_field ? p.g_field[(long long)k * n + idx] : p.g[k]);
         float D36 = 0.0f, J36[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int i = 0; i < Q; ++i) {

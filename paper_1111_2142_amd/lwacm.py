@@ -52,6 +52,7 @@ def load_library():
         "lwacm_set_variant": (i, [_vp, i]),
         "lwacm_set_march_chunk": (i, [_vp, i]),
         "lwacm_set_omega_p": (i, [_vp, ctypes.c_double]),
+        "lwacm_set_force_field": (i, [_vp, _vp]),
         "lwacm_set_state": (i, [_vp, _vp, _vp]),
         "lwacm_step": (i, [_vp, i]),
         "lwacm_diagnostics": (i, [_vp, dp, dp]),
@@ -134,6 +135,12 @@ def lwacm_set_march_chunk(ctx, planes: int):
 
 def lwacm_set_omega_p(ctx, omega_p: float):
     _check(load_library().lwacm_set_omega_p(ctx, float(omega_p)), "lwacm_set_omega_p")
+
+
+def lwacm_set_force_field(ctx, g: Optional[torch.Tensor]):
+    """g: (D, nz, ny, nx) float32 contiguous on the solver's device, or None.
+    The tensor must stay alive while it is set."""
+    _check(load_library().lwacm_set_force_field(ctx, _ptr(g)), "lwacm_set_force_field")
 
 
 def lwacm_set_variant(ctx, variant: int):
@@ -275,6 +282,16 @@ class Solver:
 
     def step(self, n: int = 1):
         lwacm_step(self.ctx, n)
+
+    def set_force_field(self, g: Optional[torch.Tensor]):
+        """Node-by-node acceleration (D, nz, ny, nx) for the following steps, or
+        None; the solver keeps the FP32 copy it passes alive while it is set."""
+        if g is not None:
+            g = g.to(self.device, torch.float32).contiguous()
+            if g.numel() != self.D * self.nx * self.ny * self.nz:
+                raise LWACMError(LWACM_EINVAL, "set_force_field size")
+        self._g_field = g
+        lwacm_set_force_field(self.ctx, g)
 
     def moments(self, diagnostics: bool = False):
         drho = torch.empty(self.shape, dtype=torch.float32, device=self.device)
