@@ -89,8 +89,8 @@ def _cavity_leg(args, L, wl, dev, stream):
             "ms_per_step": round(ms4, 5), "omega": c4.omega, "lid": list(c4.lid),
             "achieved_GBs": round(36.0 * c4.nx * c4.ny * c4.nz / (ms4 * 1e-3) / 1e9, 1),
             "basis": "36 B per node: state in and out, 32-bit solid-link set",
-            "kernel": "k_fwd_march_rolled<float,64,false,true,false>",
-            "traffic": _measured_traffic("k_fwd_march_rolled<float,64,false,true,false>")}
+            "kernel": "k_fwd_march_rolled<float,64,false,true,false,0>",
+            "traffic": _measured_traffic("k_fwd_march_rolled<float,64,false,true,false,0>")}
 
 
 def _split_leg(args, L, wl, dev, stream, drho_t, u_t, n):
@@ -108,7 +108,7 @@ def _split_leg(args, L, wl, dev, stream, drho_t, u_t, n):
     ms6 = dt6 / args.steps * 1e3
     nodes = n ** 3
     print(f"[bench] omega_p split {n}^3: {ms6:.4f} ms/step", file=sys.stderr, flush=True)
-    kname = "k_fwd_march_rolled<float,128,false,false,true>"
+    kname = "k_fwd_march_rolled<float,128,false,false,true,0>"
     return {"value": round(nodes * args.steps / dt6 / 1e6, 1), "unit": "MLUPS",
             "ms_per_step": round(ms6, 5), "nu_p_over_nu": 10.0,
             "achieved_GBs": round(32.0 * nodes / (ms6 * 1e-3) / 1e9, 1),
@@ -121,8 +121,8 @@ def _split_leg(args, L, wl, dev, stream, drho_t, u_t, n):
 
 def _field_leg(args, L, wl, dev, stream, drho_t, u_t, n):
     """The 256^3 Taylor-Green step with a body acceleration given node by node
-    (lwacm_set_force_field): the generic kernel, which also reads the three
-    acceleration fields (44 B per update)."""
+    (lwacm_set_force_field): the single-step tile kernel, which also reads the
+    three acceleration fields (44 B per update)."""
     import torch
     cfg = wl.TGV3D_256
     s7 = L.Solver(L.LWACM_D3Q19, n, n, n, cfg.omega, device=dev)
@@ -141,9 +141,11 @@ def _field_leg(args, L, wl, dev, stream, drho_t, u_t, n):
             "ms_per_step": round(ms7, 5),
             "achieved_GBs": round(44.0 * nodes / (ms7 * 1e-3) / 1e9, 1),
             "frac": round(44.0 * nodes / (ms7 * 1e-3) / 8.0e12, 4),
-            "kernel": "k_fwd_generic<19,float,false,true,false>",
+            "kernel": "k_fwd_march_rolled<float,128,false,false,false,2>" if n == 256 else None,
+            "traffic": _measured_traffic("k_fwd_march_rolled<float,128,false,false,false,2>")
+            if n == 256 else None,
             "basis": "44 B per update (state read and written, three FP32 acceleration "
-                     "fields read); the generic kernel gathers the 18 upstream nodes"}
+                     "fields read); one step per launch on the single-step tile kernel"}
 
 
 def main():
@@ -164,6 +166,8 @@ def main():
                          "launch; --variant 2: one per launch)")
     ap.add_argument("--split-only", action="store_true",
                     help="time only the 256^3 step with a separate omega_p (nu_p = 10 nu)")
+    ap.add_argument("--field-only", action="store_true",
+                    help="time only the 256^3 step with a node-by-node acceleration field")
     ap.add_argument("--cavity-only", action="store_true",
                     help="time only the 192^3 lid-driven cavity (walls, moving lid)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -205,6 +209,10 @@ def main():
     u_t = torch.as_tensor(u, dtype=torch.float32, device=dev)
     nodes = n ** 3
     del drho, u
+    if args.field_only:
+        print(json.dumps({"force_field": _field_leg(args, L, wl, dev, stream, drho_t, u_t, n)}),
+              flush=True)
+        return
     if args.split_only:
         print(json.dumps({"omega_p_split": _split_leg(args, L, wl, dev, stream, drho_t, u_t, n)}),
               flush=True)
@@ -273,7 +281,7 @@ def main():
     bytes32 = 32.0 * nodes
     achieved = bytes32 / (ms32 * 1e-3) / 1e9
     fused = n == 256 and args.variant in (0, 3) and args.steps % 2 == 0
-    kname = "k_fwd_march2<128>" if fused else "k_fwd_march_rolled<float,128,false,false,false>"
+    kname = "k_fwd_march2<128>" if fused else "k_fwd_march_rolled<float,128,false,false,false,0>"
     per_launch = 2 if fused else 1
     t_launch = ms32 * 1e-3 * per_launch  # seconds per launch of the dominant kernel
     result = {
@@ -332,8 +340,8 @@ def main():
         "ms_per_step": round(ms1, 5),
         "achieved_GBs": round(32.0 * nodes / (ms1 * 1e-3) / 1e9, 1),
         "frac": round(32.0 * nodes / (ms1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "kernel": "k_fwd_march_rolled<float,128,false,false,false>" if n == 256 else None,
-        "traffic": _measured_traffic("k_fwd_march_rolled<float,128,false,false,false>")
+        "kernel": "k_fwd_march_rolled<float,128,false,false,false,0>" if n == 256 else None,
+        "traffic": _measured_traffic("k_fwd_march_rolled<float,128,false,false,false,0>")
         if n == 256 else None}
 
     # ---- FP16-deviation storage
@@ -353,9 +361,9 @@ def main():
                             "ms_per_step": round(ms16, 5), "rounding": "stochastic (pcg4d)",
                             "achieved_GBs": round(16.0 * nodes / dt16 * args.steps / 1e9, 1),
                             "ms_per_step_nearest_rounding": round(dt16n / args.steps * 1e3, 5),
-                            "kernel": "k_fwd_march_rolled<__half,128,true,false,false>"
+                            "kernel": "k_fwd_march_rolled<__half,128,true,false,false,0>"
                             if n == 256 else None,
-                            "traffic": _measured_traffic("k_fwd_march_rolled<__half,128,true,false,false>")
+                            "traffic": _measured_traffic("k_fwd_march_rolled<__half,128,true,false,false,0>")
                             if n == 256 else None}
 
     # ---- reverse step at the same size (reads state_t and mu_t, writes mu_{t-1});

@@ -234,21 +234,26 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
     set_scales(c);
     set_wall_terms(c);
 
-    if (lwacm::march_supported(p)) {
+    // the tile kernels' chunk depth and block counts of the unforced problem
+    // (a force, or a field set later, keeps the same tiling)
+    ProblemArgs unforced = p;
+    unforced.has_force = 0;
+    if (lwacm::march_supported(unforced)) {
         int dev = 0, ncu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             ncu = 256;
         p.march_nzc = lwacm::march_choose_nzc(p, ncu);
     }
+    unforced.march_nzc = p.march_nzc;
     size_t nb = lwacm::kGenericMaxBlocks;
-    const size_t mb = lwacm::march_num_blocks(p);
+    const size_t mb = lwacm::march_num_blocks(unforced);
     if (mb > nb) nb = mb;
-    const size_t ab = lwacm::adj_march_num_blocks(p);
+    const size_t ab = lwacm::adj_march_num_blocks(unforced);
     if (ab > nb) nb = ab;
-    const size_t fb = lwacm::march2_num_blocks(p);
+    const size_t fb = lwacm::march2_num_blocks(unforced);
     if (fb > nb) nb = fb;
-    const size_t rb = lwacm::adj_march2_num_blocks(p);
+    const size_t rb = lwacm::adj_march2_num_blocks(unforced);
     if (rb > nb) nb = rb;
     c->n_partial_blocks = nb;
     // four partial sets of 2 doubles per block: a forward launch (one or two

@@ -271,7 +271,11 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
 // k_fwd_march (the column helpers are shared), so the same results.
 // SPLIT: a separate omega_p for the density (no walls): the columns also
 // push q = 36 w (Ap - A) rho (v . u) through eight more LDS arrays.
-template <class T, int NZC, bool SR, bool MASK, bool SPLIT>
+// FRC: body acceleration (Eq. force), 0 none, 1 uniform p.g, 2 node by node
+// from p.g_field (loaded with the state).  The forcing adds rho(x, t) g(x) to
+// the node's momentum; it enters the node's post-combine term a rho u through
+// the addend of its FMA, where it meets a node-dependent product.
+template <class T, int NZC, bool SR, bool MASK, bool SPLIT, int FRC>
 __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
                                                                const T *__restrict__ src,
                                                                T *__restrict__ dst,
@@ -342,11 +346,26 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
         rg.v = BufIO<T>::load(rs, voff, pw * plane_bytes);
         if (MASK) bw[j] = __builtin_amdgcn_raw_buffer_load_b32(rbits, col * 4u, pw * (unsigned)(plane * 4), 0);
     };
+    // node-by-node acceleration (FRC 2): three FP32 fields, one resource each
+    const unsigned long long gbytes = FRC == 2 ? (unsigned long long)n * 4u : 0ull;
+    const Rsrc rgx = make_rsrc(FRC == 2 ? p.g_field : nullptr, gbytes);
+    const Rsrc rgy = make_rsrc(FRC == 2 ? p.g_field + n : nullptr, gbytes);
+    const Rsrc rgz = make_rsrc(FRC == 2 ? p.g_field + 2 * n : nullptr, gbytes);
+    unsigned gq[3][3] = {{0u, 0u, 0u}, {0u, 0u, 0u}, {0u, 0u, 0u}};  // FP32 bits of g
+    auto issue_g = [&](int j, int pz) {
+        const unsigned so = (unsigned)wrap_index(pz, nz) * (unsigned)(plane * 4);
+        gq[j][0] = __builtin_amdgcn_raw_buffer_load_b32(rgx, col * 4u, so, 0);
+        gq[j][1] = __builtin_amdgcn_raw_buffer_load_b32(rgy, col * 4u, so, 0);
+        gq[j][2] = __builtin_amdgcn_raw_buffer_load_b32(rgz, col * 4u, so, 0);
+    };
     auto class_of = [](unsigned b) { return (b & 1u) ? 2 : (b ? 1 : 0); };
 
     Ring<T> ring[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) issue(j, ring[j], z0 - 1 + j);
+    if (FRC == 2 && role == INTERIOR)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) issue_g(j, z0 - 1 + j);
 
     float mass = 0.0f, energy = 0.0f;
     constexpr int N = NZC + 2;  // planes z0 - 1 .. z1
@@ -374,8 +393,20 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             push_column<MASK>(dr, ux, uy, uz, MASK ? class_of(b) : 0, b, A, a, acc[(j + 1) % 3],
                               acc[j], Am);
             if (SPLIT) push_split_column(1.0f + dr, ux, uy, uz, dA, acc[(j + 1) % 3], acc[j], Am);
+            if (FRC) {  // post-combine a rho u plus the forcing rho g
+                const float rho = 1.0f + dr, arho = a * rho;
+                const float gx = FRC == 2 ? __builtin_bit_cast(float, gq[j][0]) : p.g[0];
+                const float gy = FRC == 2 ? __builtin_bit_cast(float, gq[j][1]) : p.g[1];
+                const float gz = FRC == 2 ? __builtin_bit_cast(float, gq[j][2]) : p.g[2];
+                acc[j].post[0] = fmaf(arho, ux, rho * gx);
+                acc[j].post[1] = fmaf(arho, uy, rho * gy);
+                acc[j].post[2] = fmaf(arho, uz, rho * gz);
+            }
             __builtin_amdgcn_sched_barrier(0);  // the ring slot's last use is above
-            if (I::refill) issue(j, ring[j], z0 + 2 + k);
+            if (I::refill) {
+                issue(j, ring[j], z0 + 2 + k);
+                if (FRC == 2) issue_g(j, z0 + 2 + k);
+            }
             if (I::phase < 2) return;
             const Xchg<NSLOT + 1> X{xp[k & 1], xd[k & 1]};
             put_slot(X, slot, Am);
@@ -499,17 +530,28 @@ __global__ __launch_bounds__(256) void k_classify(ProblemArgs p, uint8_t *cls, u
     }
 }
 
-template <class T, bool SR, bool MASK, bool SPLIT = false>
+template <class T, bool SR, bool MASK, bool SPLIT = false, int FRC = 0>
 void launch_rolled(int c, unsigned nb, hipStream_t s, const ProblemArgs &p, const T *a, T *b,
                    const unsigned *bits, const float4 *wallg, const ReduceArgs &r)
 {
     switch (c) {
-    case 8: k_fwd_march_rolled<T, 8, SR, MASK, SPLIT><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    case 16: k_fwd_march_rolled<T, 16, SR, MASK, SPLIT><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    case 32: k_fwd_march_rolled<T, 32, SR, MASK, SPLIT><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    case 64: k_fwd_march_rolled<T, 64, SR, MASK, SPLIT><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    default: k_fwd_march_rolled<T, 128, SR, MASK, SPLIT><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 8: k_fwd_march_rolled<T, 8, SR, MASK, SPLIT, FRC><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 16: k_fwd_march_rolled<T, 16, SR, MASK, SPLIT, FRC><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 32: k_fwd_march_rolled<T, 32, SR, MASK, SPLIT, FRC><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 64: k_fwd_march_rolled<T, 64, SR, MASK, SPLIT, FRC><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    default: k_fwd_march_rolled<T, 128, SR, MASK, SPLIT, FRC><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
     }
+}
+
+// forced problems (march_supported: nz >= 8, no separate omega_p)
+template <class T, bool SR, bool MASK>
+void launch_rolled_forced(int c, unsigned nb, hipStream_t s, const ProblemArgs &p, const T *a,
+                          T *b, const unsigned *bits, const float4 *wallg, const ReduceArgs &r)
+{
+    if (p.g_field)
+        launch_rolled<T, SR, MASK, false, 2>(c, nb, s, p, a, b, bits, wallg, r);
+    else
+        launch_rolled<T, SR, MASK, false, 1>(c, nb, s, p, a, b, bits, wallg, r);
 }
 
 template <class T>
@@ -527,6 +569,14 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
             k_fwd_march<T, true, 32><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
         else
             k_fwd_march<T, false, 32><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
+    } else if (p.has_force) {
+        if (p.mask) {
+            if (sr) launch_rolled_forced<T, true, true>(c, nb, s, p, a, b, bits, wallg, r);
+            else launch_rolled_forced<T, false, true>(c, nb, s, p, a, b, bits, wallg, r);
+        } else {
+            if (sr) launch_rolled_forced<T, true, false>(c, nb, s, p, a, b, bits, wallg, r);
+            else launch_rolled_forced<T, false, false>(c, nb, s, p, a, b, bits, wallg, r);
+        }
     } else if (p.mask) {
         if (sr) launch_rolled<T, true, true>(c, nb, s, p, a, b, bits, wallg, r);
         else launch_rolled<T, false, true>(c, nb, s, p, a, b, bits, wallg, r);
@@ -545,9 +595,11 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
 bool march_supported(const ProblemArgs &p)
 {
     // 32-bit byte offsets inside a state buffer: n * 16 bytes < 4 GiB
-    // a separate omega_p only on the rolled kernel without walls
+    // a separate omega_p only on the rolled kernel without walls; forcing only
+    // on the rolled kernel and not together with a separate omega_p
     const bool split_ok = !p.split || (!p.mask && p.nz >= 8);
-    return p.Q == 19 && !p.has_force && split_ok && p.nx >= TX && p.ny >= TY && p.nx % TX == 0 &&
+    const bool force_ok = !p.has_force || (!p.split && p.nz >= 8);
+    return p.Q == 19 && force_ok && split_ok && p.nx >= TX && p.ny >= TY && p.nx % TX == 0 &&
            p.ny % TY == 0 && p.nz >= 1 && p.n < (1LL << 28);
 }
 

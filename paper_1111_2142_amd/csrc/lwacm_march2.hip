@@ -269,7 +269,8 @@ int march2_nzc(const ProblemArgs &p)
 
 bool march2_supported(const ProblemArgs &p)
 {
-    return march_supported(p) && !p.mask && !p.split && p.march_nzc > 0 && p.nz >= 8;
+    return march_supported(p) && !p.mask && !p.split && !p.has_force && p.march_nzc > 0 &&
+           p.nz >= 8;
 }
 
 unsigned march2_num_blocks(const ProblemArgs &p)

@@ -10,8 +10,10 @@ against the oracle's field-forced step.
   t = 60, a new field before every step): the state against the oracle's,
   and the L1 errors against the analytic solution equal to the oracle's (and
   so near the paper's printed table).
-- Scope: a field routes the step to the generic kernel and declines the
-  reverse steps; clearing it gives back the unforced tile-kernel step.
+- D3Q19 (nz >= 8) runs the single-step tile kernel, which loads the field
+  with the state; against the generic kernel to FP32 rounding.
+- Scope: a field declines the two-step kernel and the reverse steps;
+  clearing it gives back the unforced step bit for bit.
 """
 import numpy as np
 import pytest
@@ -90,6 +92,30 @@ def test_random_field_matches_oracle(q, storage):
     assert err_r < (1e-4 if storage == 0 else 2e-2)
 
 
+@pytest.mark.parametrize("masked", [False, True])
+def test_tile_kernel_field_matches_generic(masked):
+    L = need_gpu()
+    banner(f"force field tile vs generic masked={masked}")
+    shape = (40, 32, 64)
+    drho, u = wl.random_state(shape, 3, seed=35, du=0.03, drho=0.01)
+    rng = np.random.Generator(np.random.PCG64(36))
+    gf = to_dev(1e-4 * rng.standard_normal((3,) + shape))
+    mask = None
+    if masked:
+        mask = (rng.random(shape) < 0.05).astype(np.uint8)
+    out = []
+    for v in (MARCH, 1):
+        s = _solver(L, 19, shape, 1.6, mask=mask)
+        L.lwacm_set_variant(s.ctx, v)
+        s.set_force_field(gf)
+        out.append(_run(s, drho, u, 8))
+        s.close()
+    fl = fluid_of(mask, shape)
+    err = rel_l2(out[0][1][:, fl], out[1][1][:, fl])
+    banner(f"force field tile vs generic: rel-L2 u {err:.3e}")
+    assert err < 1e-6
+
+
 def test_forced_taylor_green_matches_oracle_to_t60():
     L = need_gpu()
     c = wl.ForcedTaylorGreen(32)
@@ -133,8 +159,9 @@ def test_force_field_scope():
     s = _solver(L, 19, shape, 1.7)
     s.set_force_field(torch.zeros((3,) + shape, device="cuda"))
     with pytest.raises(L.LWACMError) as ei:
-        L.lwacm_set_variant(s.ctx, MARCH)
+        L.lwacm_set_variant(s.ctx, 3)  # the two-step kernel
     assert ei.value.code == L.LWACM_EUNSUPPORTED
+    L.lwacm_set_variant(s.ctx, MARCH)  # the single-step tile kernel takes it
     s.set_state(to_dev(drho), to_dev(u))
     st = s.save_state()
     mu = torch.zeros(shape + (4,), device="cuda")

@@ -32,21 +32,41 @@ def test_march_matches_oracle(shape, storage):
     assert rel_l2(dr, rdr) < (1e-4 if storage == 0 else 2e-2)
 
 
-def test_forced_problems_use_the_generic_kernel():
-    """Forcing is applied inside every link term by the generic kernel; the
-    march kernel declines forced problems and AUTO falls back."""
+@pytest.mark.parametrize("masked", [False, True])
+def test_forced_problems_on_the_tile_kernel(masked):
+    """A uniform body acceleration (Eq. force) on the single-step tile kernel:
+    it enters each node's post-combine term (a rho u + rho g in one FMA)
+    instead of every link term as in the generic kernel, so the two agree to
+    FP32 rounding; both match the oracle.  The two-step kernel declines forcing,
+    and so does the tile kernel below 8 planes."""
     L = need_gpu()
     shape = (20, 16, 32)
-    banner("forced march -> generic")
+    banner(f"forced march masked={masked}")
     g = (1e-4, -2e-4, 5e-5)
     s = L.Solver(19, 32, 16, 20, 1.3, g=g)
+    L.lwacm_set_variant(s.ctx, MARCH)
     with pytest.raises(L.LWACMError) as ei:
-        L.lwacm_set_variant(s.ctx, MARCH)
+        L.lwacm_set_variant(s.ctx, 3)
     assert ei.value.code == L.LWACM_EUNSUPPORTED
+    s.close()
+    t = L.Solver(19, 32, 16, 7, 1.3, g=g)
+    with pytest.raises(L.LWACMError):
+        L.lwacm_set_variant(t.ctx, MARCH)
+    t.close()
+    mask = None
+    if masked:
+        mask = np.zeros(shape, dtype=np.uint8)
+        mask[:, 0] = 1
+        mask[:, -1] = 1
     drho, u = wl.random_state(shape, 3, seed=14, du=0.03, drho=0.01)
-    dr, uu, _ = gpu_run(19, shape, 1.3, drho, u, 20, g=g)
-    rdr, ru = oracle_run(19, shape, 1.3, drho, u, 20, g=g)
-    assert rel_l2(uu, ru) < 1e-5
+    dr, uu, _ = gpu_run(19, shape, 1.3, drho, u, 20, g=g, mask=mask, variant=MARCH)
+    dg, ug, _ = gpu_run(19, shape, 1.3, drho, u, 20, g=g, mask=mask, variant=GENERIC)
+    rho0 = 1.0 if mask is None else 1.0 + drho.astype(np.float32)[mask == 0].mean()
+    rdr, ru = oracle_run(19, shape, 1.3, drho.astype(np.float32).astype(np.float64),
+                         u.astype(np.float32).astype(np.float64), 20, g=g, mask=mask, rho0=rho0)
+    fl = fluid_of(mask, shape)
+    assert rel_l2(uu[:, fl], ru[:, fl]) < 1e-5
+    assert rel_l2(uu[:, fl], ug[:, fl]) < 1e-6
 
 
 @pytest.mark.parametrize("n", [32, 64])
