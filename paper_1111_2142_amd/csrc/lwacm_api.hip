@@ -387,7 +387,7 @@ int lwacm_set_state(lwacm_ctx *c, const float *d_drho, const float *d_u)
     set_scales(c);
     hipError_t e = lwacm::launch_set_state(c->p, c->storage, d_drho, d_u, c->buf[c->cur], c->stream);
     if (e != hipSuccess) return LWACM_EDEVICE;
-    // both buffers hold the state: solid nodes are never written by a step
+    // both buffers hold the state: a step leaves solid nodes as they are
     e = hipMemcpyAsync(c->buf[c->cur ^ 1], c->buf[c->cur], state_bytes(c),
                        hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return LWACM_EDEVICE;

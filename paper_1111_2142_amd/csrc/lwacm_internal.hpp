@@ -23,7 +23,7 @@ struct ProblemArgs {
     float wall_term_p[kMaxWallIds][3];  // (2/omega_p - 1) * 6 * rho0 * u_w per wall id
     float g[3];              // body acceleration (Eq. force)
     const float *g_field;    // or, when set, D fields of n accelerations (SoA) node by node
-    int has_force;           // g or g_field given (forced problems use the generic kernel)
+    int has_force;           // g or g_field given (no two-step kernel for forced problems)
     float wall_term[kMaxWallIds][3];  // (1 - a) * 6 * rho0 * u_w per wall id (Eq. ACM2.0ccccbb)
     float wall_da[kMaxWallIds][3];  // 6 * rho0 * u_w: minus d(wall_term)/da
     float wall_u[kMaxWallIds][3];   // wall velocities u_w per wall id (0 for fluid id 0)

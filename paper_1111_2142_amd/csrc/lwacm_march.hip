@@ -23,11 +23,11 @@
 //
 // The receiving column adds the exchanged terms, its own (v_x, v_y) = (0, 0)
 // links and the post-combine term a rho u (Eqs. ACM2.0b), normalises, and
-// stores.  Forced problems (Eq. force) run on the generic kernel, which adds
-// the forcing inside each link term where its FP32 rounding does not bias
-// long runs.  Halfway bounce-back (Eqs. ACM2.0cbb-ACM2.0ccccbb) is applied at
-// the receiving node from a precomputed per-node bit set of solid upstream
-// links; solid nodes push zeros and are never written.
+// stores.  A body acceleration (Eq. force, uniform or node by node) enters
+// that post-combine term as a rho u + rho g in one FMA.  Halfway bounce-back
+// (Eqs. ACM2.0cbb-ACM2.0ccccbb) uses a precomputed per-node bit set of solid
+// upstream links: a node sums its own bounced-back terms when it is pushed,
+// and solid nodes push zeros and keep their state.
 //
 // Link terms are kept unweighted and summed with the exact integer weights
 // 12, 2, 1 (= 36 w_i for rest, axis and diagonal links of D3Q19); the sums
@@ -46,8 +46,9 @@ namespace {
 #endif
 constexpr int TX = 32;                // tile width (x, contiguous in memory)
 constexpr int TY = 16;                // tile height (y)
-// Planes per workgroup: a template parameter (the plane loop is fully
-// unrolled), chosen per problem among kChunkDepths by march_choose_nzc().
+// Planes per workgroup: a template parameter (ring and accumulator indices
+// are compile-time constants), chosen per problem among kChunkDepths by
+// march_choose_nzc().
 constexpr int kChunkDepths[3] = {32, 64, 128};
 // LDS exchange buffers: 2 = one barrier per plane; 1 = half the LDS (more
 // workgroups per CU) at the cost of a second barrier per plane.

@@ -87,7 +87,7 @@ def test_march_masked_cavity_matches_oracle(n):
     m, _ = s.diagnostics()
     nf = int(fl.sum())
     assert abs(m - nf) / nf < 1e-9
-    # solid nodes are never written
+    # solid nodes keep their state
     assert np.all(uu[:, ~fl] == 0) and np.all(dr[~fl] == 0)
 
 
