@@ -51,6 +51,8 @@ def _load():
     lib.oracle_step_split.restype = ctypes.c_int
     lib.oracle_step_field.argtypes = common[:8] + [_dp, ctypes.c_double, _dp, _dp, _dp, _dp]
     lib.oracle_step_field.restype = ctypes.c_int
+    lib.oracle_step_q.argtypes = common + [_dp, _dp, _dp, _dp, _dp]
+    lib.oracle_step_q.restype = ctypes.c_int
     lib.oracle_vjp.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_vjp.restype = ctypes.c_int
     lib.oracle_step_nodes.argtypes = common + [_dp, _dp, ctypes.POINTER(ctypes.c_long),
@@ -193,6 +195,22 @@ def step_field(p: Problem, rho, u, g_field):
                                _ptr(u1))
     if rc != 0:
         raise RuntimeError(f"oracle_step_field failed ({rc})")
+    return r1, u1
+
+
+def step_q(p: Problem, rho, u, qd):
+    """One step with link-wall distances qd (Q, nz, ny, nx): qd[j] at node x is
+    the fraction of the link x -> x + v_j at which the wall cuts it (read where
+    x + v_j is solid); returns new (rho, u)."""
+    lib = _load()
+    rho = _f64(rho, p.shape)
+    u = _f64(u, (p.d,) + p.shape)
+    qd = _f64(qd, (p.q,) + p.shape)
+    r1 = np.empty_like(rho)
+    u1 = np.empty_like(u)
+    rc = lib.oracle_step_q(*p._args(), _ptr(qd), _ptr(rho), _ptr(u), _ptr(r1), _ptr(u1))
+    if rc != 0:
+        raise RuntimeError(f"oracle_step_q failed ({rc})")
     return r1, u1
 
 

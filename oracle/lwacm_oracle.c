@@ -24,7 +24,10 @@
  *     Taylor-Green vortex flow");
  *   - halfway bounce-back for a solid upstream node, Eqs. ACM2.0cbb to
  *     ACM2.0cccbb2, with the moving-wall correction of Eqs. ACM2.0movebb
- *     and ACM2.0ccccbb, (2/omega - 1) * 2 f^(e,o)(rho0, u_w);
+ *     and ACM2.0ccccbb, (2/omega - 1) * 2 f^(e,o)(rho0, u_w); and, with
+ *     link-wall distances q, the interpolated bounce-back of Eq. ACM2.0cc
+ *     with the moving-wall term of Eq. ACM2.0move (factor 2 or 1/q in place
+ *     of 2);
  *   - new moments rho = sum f_i, rho u = sum v_i f_i (Section 2.1);
  *   - a separate relaxation omega_p for the continuity equation (Section
  *     "finite-difference formulation", item 3; Appendix E): the density is
@@ -202,7 +205,8 @@ static void wall_velocity(const double *wall_u, int n_ids, int m, double out[3])
 static void node_populations(const lattice_t *L, int nx, int ny, int nz, double omega,
                              const uint8_t *mask, const double *wall_u, int n_ids,
                              const double g[3], double rho0, const double *rho,
-                             const double *u, int x, int y, int z, double f[MAXQ])
+                             const double *u, int x, int y, int z, double f[MAXQ],
+                             const double *qd)
 {
     long n = (long)nx * ny * nz;
     long ix = node_index(nx, ny, x, y, z);
@@ -226,7 +230,32 @@ static void node_populations(const lattice_t *L, int nx, int ny, int nz, double 
             double uw[3];
             wall_velocity(wall_u, n_ids, mask[iy], uw);
             double fstar = feq(L, ib, rx, ux) - a * feo(L, ib, rx, ux);
-            f[i] = fstar + a * feo(L, i, rx, ux) + (2.0 / omega - 1.0) * 2.0 * feo(L, i, rho0, uw);
+            /* Interpolated bounce-back (Eq. ACM2.0cc) when the wall cuts the
+             * link x -> x + v_ib at the fraction q of its length (qd, link ib
+             * of node x; NULL: q = 1/2, the halfway rule above), and the
+             * moving-wall term scaled as in Eq. ACM2.0move: 2 for q < 1/2,
+             * 1/q for q >= 1/2.  For q < 1/2 the rule also takes the
+             * pre-combined population of the node x - v_ib = x + v_i; when
+             * that node is solid as well, the halfway rule is used. */
+            double wscale = 2.0;
+            if (qd) {
+                double q = qd[(long)ib * n + ix];
+                if (q < 0.5) {
+                    long iz = upstream(L, nx, ny, nz, x, y, z, ib); /* x - v_ib */
+                    if (!mask || mask[iz] == 0) {
+                        double uz[3];
+                        load_u(L, n, iz, u, uz);
+                        double rz = rho[iz];
+                        double fz = feq(L, ib, rz, uz) - a * feo(L, ib, rz, uz);
+                        fstar = 2.0 * q * fstar + (1.0 - 2.0 * q) * fz;
+                    }
+                } else {
+                    double fi = feq(L, i, rx, ux) - a * feo(L, i, rx, ux);
+                    fstar = fstar / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * fi;
+                    wscale = 1.0 / q;
+                }
+            }
+            f[i] = fstar + a * feo(L, i, rx, ux) + (2.0 / omega - 1.0) * wscale * feo(L, i, rho0, uw);
         }
         if (g) f[i] += feo(L, i, rx, g);
     }
@@ -292,7 +321,50 @@ int oracle_step(int q, int nx, int ny, int nz, double omega, const uint8_t *mask
                 }
                 double f[MAXQ];
                 node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_in,
-                                 u_in, x, y, z, f);
+                                 u_in, x, y, z, f, NULL);
+                double r = 0.0, j[3] = {0, 0, 0};
+                for (int i = 0; i < L.q; ++i) {
+                    r += f[i];
+                    for (int k = 0; k < 3; ++k) j[k] += L.v[i][k] * f[i];
+                }
+                rho_out[ix] = r;
+                for (int k = 0; k < L.d; ++k) u_out[k * n + ix] = j[k] / r;
+            }
+    return 0;
+}
+
+/* One step with link-wall distances (interpolated bounce-back, Section
+ * "Moving complex boundaries", Eqs. ACM2.0cc and ACM2.0move).  qd holds q
+ * fields of n values (SoA): qd[j * n + x] is the fraction of the link from
+ * the fluid node x to x + v_j at which the wall cuts it, read where x + v_j
+ * is solid; NULL gives the halfway rule (q = 1/2) of oracle_step. */
+int oracle_step_q(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
+                  const double *wall_u, int n_ids, const double *g_in, double rho0,
+                  const double *qd, const double *rho_in, const double *u_in, double *rho_out,
+                  double *u_out)
+{
+    lattice_t L;
+    if (make_lattice(q, &L)) return -1;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (L.d == 2 && nz != 1)) return -1;
+    long n = (long)nx * ny * nz;
+    double g[3] = {0, 0, 0};
+    if (g_in)
+        for (int k = 0; k < L.d; ++k) g[k] = g_in[k];
+    const double *gp = g_in ? g : NULL;
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long ix = node_index(nx, ny, x, y, z);
+                if (mask && mask[ix] != 0) {
+                    rho_out[ix] = rho_in[ix];
+                    for (int k = 0; k < L.d; ++k) u_out[k * n + ix] = u_in[k * n + ix];
+                    continue;
+                }
+                double f[MAXQ];
+                node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_in,
+                                 u_in, x, y, z, f, qd);
                 double r = 0.0, j[3] = {0, 0, 0};
                 for (int i = 0; i < L.q; ++i) {
                     r += f[i];
@@ -332,7 +404,7 @@ int oracle_step_field(int q, int nx, int ny, int nz, double omega, const uint8_t
                 for (int k = 0; k < L.d; ++k) g[k] = g_field[k * n + ix];
                 double f[MAXQ];
                 node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, g, rho0, rho_in,
-                                 u_in, x, y, z, f);
+                                 u_in, x, y, z, f, NULL);
                 double r = 0.0, j[3] = {0, 0, 0};
                 for (int i = 0; i < L.q; ++i) {
                     r += f[i];
@@ -375,9 +447,9 @@ int oracle_step_split(int q, int nx, int ny, int nz, double omega, double omega_
                 }
                 double f[MAXQ], fp[MAXQ];
                 node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_in,
-                                 u_in, x, y, z, f);
+                                 u_in, x, y, z, f, NULL);
                 node_populations(&L, nx, ny, nz, omega_p, mask, wall_u, n_ids, gp, rho0, rho_in,
-                                 u_in, x, y, z, fp);
+                                 u_in, x, y, z, fp, NULL);
                 double r = 0.0, j[3] = {0, 0, 0};
                 for (int i = 0; i < L.q; ++i) {
                     r += fp[i];
@@ -417,7 +489,7 @@ int oracle_step_nodes(int q, int nx, int ny, int nz, double omega, const uint8_t
         int x = (int)(ix % nx), y = (int)((ix / nx) % ny), z = (int)(ix / ((long)nx * ny));
         double f[MAXQ];
         node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_in, u_in, x,
-                         y, z, f);
+                         y, z, f, NULL);
         double r = 0.0, j[3] = {0, 0, 0};
         for (int i = 0; i < L.q; ++i) {
             r += f[i];
@@ -576,7 +648,7 @@ int oracle_vjp(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
                 if (mask && mask[ix] != 0) continue;
                 double f[MAXQ];
                 node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_t,
-                                 u_t, x, y, z, f);
+                                 u_t, x, y, z, f, NULL);
                 double r = 0.0, j[3] = {0, 0, 0};
                 for (int i = 0; i < L.q; ++i) {
                     r += f[i];
