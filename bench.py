@@ -93,6 +93,34 @@ def _cavity_leg(args, L, wl, dev, stream):
             "traffic": _measured_traffic("k_fwd_march_rolled<float,64,false,true,false,0>")}
 
 
+def _qbb_leg(args, L, wl, dev, stream):
+    """The 192^3 lid-driven cavity with interpolated bounce-back: every wall
+    cuts its links at q = 0.3 (d_q of lwacm_init); the generic kernel."""
+    import torch
+    c4 = wl.CAVITY_192
+    m4 = torch.as_tensor(wl.cavity_mask(c4.nx), device=dev)
+    qd = torch.full((19, c4.nz, c4.ny, c4.nx), 0.3, dtype=torch.float32, device=dev)
+    s8 = L.Solver(L.LWACM_D3Q19, c4.nx, c4.ny, c4.nz, c4.omega, mask=m4,
+                  wall_u=[list(r) for r in wl.wall_table(c4.lid)], device=dev, qd=qd)
+    s8.set_state(torch.zeros((c4.nz, c4.ny, c4.nx), device=dev),
+                 torch.zeros((3, c4.nz, c4.ny, c4.nx), device=dev))
+    s8.step(args.warmup)
+    dt8 = _events_time(s8.step, args.steps, stream)
+    s8.close()
+    del qd, m4
+    torch.cuda.empty_cache()
+    fluid = (c4.nx - 2) * (c4.ny - 2) * (c4.nz - 2)
+    ms8 = dt8 / args.steps * 1e3
+    print(f"[bench] cavity 192^3 interpolated walls: {ms8:.4f} ms/step", file=sys.stderr,
+          flush=True)
+    return {"value": round(fluid * args.steps / dt8 / 1e6, 1), "unit": "MLUPS (fluid nodes)",
+            "ms_per_step": round(ms8, 5), "q": 0.3,
+            "achieved_GBs": round(33.0 * c4.nx * c4.ny * c4.nz / (ms8 * 1e-3) / 1e9, 1),
+            "kernel": "k_fwd_generic<19,float,true,false,false>",
+            "basis": "33 B per node (state in and out, uint8 mask); the generic kernel gathers "
+                     "the 18 upstream nodes and, at the walls, the q values and the second node"}
+
+
 def _split_leg(args, L, wl, dev, stream, drho_t, u_t, n):
     """The 256^3 Taylor-Green step with a separate omega_p for the density
     (nu_p = 10 nu): the single-step tile kernel with its eight extra LDS
@@ -166,6 +194,8 @@ def main():
                          "launch; --variant 2: one per launch)")
     ap.add_argument("--split-only", action="store_true",
                     help="time only the 256^3 step with a separate omega_p (nu_p = 10 nu)")
+    ap.add_argument("--qbb-only", action="store_true",
+                    help="time only the 192^3 cavity with interpolated bounce-back (q = 0.3)")
     ap.add_argument("--field-only", action="store_true",
                     help="time only the 256^3 step with a node-by-node acceleration field")
     ap.add_argument("--cavity-only", action="store_true",
@@ -198,6 +228,10 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": args.steps,
                           "ms_per_launch": dt / args.steps * 1e3,
                           "GBs": nbytes * args.steps / dt / 1e9}), flush=True)
+        return
+    if args.qbb_only:
+        print(json.dumps({"cavity_192_interpolated": _qbb_leg(args, L, wl, dev, stream)}),
+              flush=True)
         return
     if args.cavity_only:
         print(json.dumps({"cavity_192": _cavity_leg(args, L, wl, dev, stream)}), flush=True)
@@ -427,8 +461,11 @@ def main():
     # ---- separate omega_p for the density: the same 256^3 step, one step per launch
     result["omega_p_split"] = _split_leg(args, L, wl, dev, stream, drho_t, u_t, n)
 
-    # ---- node-by-node body acceleration: the same 256^3 step on the generic kernel
+    # ---- node-by-node body acceleration: the same 256^3 step
     result["force_field"] = _field_leg(args, L, wl, dev, stream, drho_t, u_t, n)
+
+    # ---- interpolated bounce-back: the 192^3 cavity with walls at q = 0.3
+    result["cavity_192_interpolated"] = _qbb_leg(args, L, wl, dev, stream)
 
     # ---- differentiable D2Q9 512^2: reverse / forward at the gradient workload (launch-bound)
     c5 = wl.ADJOINT_512

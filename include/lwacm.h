@@ -101,8 +101,20 @@ size_t lwacm_state_bytes(int lattice, int nx, int ny, int nz, int storage);
  *  h_wall_u     host table of n_wall_ids velocities (3 floats each), or NULL
  *               (all walls at rest); copied.  n_wall_ids <= 16.
  *  d_q          link-wall distances for interpolated bounce-back
- *               (Eqs. ACM2.0cc, ACM2.0move): must be NULL (q = 1/2, halfway
- *               walls); non-NULL gives LWACM_EUNSUPPORTED.
+ *               (Section "Moving complex boundaries", Eqs. ACM2.0cc and
+ *               ACM2.0move), or NULL for halfway walls (q = 1/2).  Q FP32
+ *               fields of nx*ny*nz values (SoA, node index as the state's),
+ *               caller-owned device memory kept alive until lwacm_destroy:
+ *               d_q[j*n + x] is the fraction 0 < q <= 1 of the link from the
+ *               fluid node x to x + v_j at which the wall cuts it, read only
+ *               where x + v_j is solid.  j is the library's link index:
+ *                 0 rest, 1 (+x), 2 (-x), 3 (+y), 4 (-y), 5 (+x+y), 6 (-x-y),
+ *                 7 (+x-y), 8 (-x+y), 9 (+z), 10 (+x+z), 11 (-x+z), 12 (+y+z),
+ *                 13 (-y+z), 14 (-z), 15 (-x-z), 16 (+x-z), 17 (-y-z), 18 (+y-z)
+ *               (D2Q9: 0..8).  For q < 1/2 the rule also takes the
+ *               node x - v_j; where that node is solid too, the halfway rule
+ *               is used.  With d_q the forward step runs on the generic kernel
+ *               and the reverse steps return LWACM_EUNSUPPORTED.
  *  h_g          host body acceleration g[3] (Eq. force), or NULL; copied.
  *  stream       HIP stream every call of this context is issued on.
  *
@@ -153,7 +165,8 @@ int lwacm_set_march_chunk(lwacm_ctx *c, int planes);
  * 1/nu(omega_p) (Eq. viscosity2), so nu(omega_p) > nu(omega) reduces the
  * compressibility error of under-resolved runs.  0 < omega_p < 2, else
  * LWACM_EINVAL; omega_p == omega (the default after lwacm_init) is the
- * single-relaxation step.  With omega_p != omega the forward step runs on the
+ * single-relaxation step; omega_p != omega with link-wall distances (d_q)
+ * gives LWACM_EUNSUPPORTED.  With omega_p != omega the forward step runs on the
  * generic kernel (every lattice, walls and force allowed) and the reverse
  * steps return LWACM_EUNSUPPORTED.  Takes effect from the next lwacm_step. */
 int lwacm_set_omega_p(lwacm_ctx *c, double omega_p);

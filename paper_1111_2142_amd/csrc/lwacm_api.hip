@@ -187,7 +187,6 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
     if (!(omega > 0.0 && omega < 2.0)) return LWACM_EINVAL;
     if (!d_state_a || !d_state_b || d_state_a == d_state_b) return LWACM_EINVAL;
     if (h_wall_u && (n_wall_ids < 1 || n_wall_ids > lwacm::kMaxWallIds)) return LWACM_EINVAL;
-    if (d_q) return LWACM_EUNSUPPORTED;
 
     lwacm_ctx *c = new (std::nothrow) lwacm_ctx;
     if (!c) return LWACM_ENOMEM;
@@ -221,6 +220,7 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
         c->omega_p = omega;
     }
     p.mask = d_mask;
+    p.qd = d_q;
     if (h_g) {
         for (int k = 0; k < p.D; ++k) p.g[k] = h_g[k];
         c->force = true;
@@ -354,8 +354,10 @@ int lwacm_set_force_field(lwacm_ctx *c, const float *d_g)
 int lwacm_set_omega_p(lwacm_ctx *c, double omega_p)
 {
     if (!c || !(omega_p > 0.0 && omega_p < 2.0)) return LWACM_EINVAL;
+    const float Ap = (float)(3.0 * quantised_h(omega_p));
+    if (c->p.qd && Ap != c->p.A) return LWACM_EUNSUPPORTED;  // not with interpolated walls
     c->omega_p = omega_p;
-    c->p.Ap = (float)(3.0 * quantised_h(omega_p));
+    c->p.Ap = Ap;
     c->p.split = c->p.Ap != c->p.A;
     set_wall_terms(c);
     return LWACM_OK;
@@ -555,8 +557,9 @@ int lwacm_adjoint_step(lwacm_ctx *c, const void *d_state_t, const float *d_mu_in
 {
     if (!c || !d_state_t || !d_mu_in || !d_mu_out || !d_dL_domega || d_mu_in == d_mu_out)
         return LWACM_EINVAL;
-    // no reverse step for omega_p != omega, nor for a node-by-node acceleration
-    if (c->p.split || c->p.g_field) return LWACM_EUNSUPPORTED;
+    // no reverse step for omega_p != omega, a node-by-node acceleration or
+    // interpolated bounce-back
+    if (c->p.split || c->p.g_field || c->p.qd) return LWACM_EUNSUPPORTED;
     ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
     r.accumulate = 1;
     r.out_scale = 2.0 / (c->omega * c->omega);  // da/domega for a = 2 - 2/omega
@@ -574,7 +577,7 @@ int lwacm_adjoint_step2(lwacm_ctx *c, const void *d_state_t, const void *d_state
         d_mu_in == d_mu_out)
         return LWACM_EINVAL;
     if ((c->variant != LWACM_KERNEL_AUTO && c->variant != LWACM_KERNEL_MARCH2) ||
-        !lwacm::adj_march2_supported(c->p) || c->p.split || c->p.g_field)
+        !lwacm::adj_march2_supported(c->p) || c->p.split || c->p.g_field || c->p.qd)
         return LWACM_EUNSUPPORTED;
     ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
     r.accumulate = 1;

@@ -154,7 +154,33 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
                 const int ib = link_opp(i);
                 const float uw[3] = {p.wall_term[m][0], p.wall_term[m][1], p.wall_term[m][2]};
                 const float cb = vdot<Q>(ib, ux);
-                s = link_term_unweighted(drx + fg, rx, cb, Bx, p.A) + vdot<Q>(i, uw);
+                float sb = link_term_unweighted(drx + fg, rx, cb, Bx, p.A);
+                float wsc = 1.0f;  // scale of the halfway moving-wall term
+                if (p.qd) {
+                    // interpolated bounce-back (Eq. ACM2.0cc): the wall cuts the
+                    // link x -> x + v_ib at the fraction q; the terms are in
+                    // deviation form, whose mixing weights sum to one
+                    const float qv = p.qd[(long long)ib * n + idx];
+                    if (qv < 0.5f) {
+                        const long long dn = node_at(p, wrap_add(c.x, link_cx(i), p.nx),
+                                                     wrap_add(c.y, link_cy(i), p.ny),
+                                                     wrap_add(c.z, link_cz(i), p.nz));
+                        if (p.mask[dn] == 0) {  // x - v_ib fluid (else halfway)
+                            float drz, uz[3];
+                            load_state<D, T>(src, dn, p, drz, uz);
+                            const float Bz = -1.5f * (uz[0] * uz[0] + uz[1] * uz[1] + uz[2] * uz[2]);
+                            const float sz = link_term_unweighted(drz + fg, 1.0f + drz,
+                                                                  vdot<Q>(ib, uz), Bz, p.A);
+                            sb = fmaf(2.0f * qv, sb, (1.0f - 2.0f * qv) * sz);
+                        }
+                    } else {
+                        const float si = link_term_unweighted(drx + fg, rx, vdot<Q>(i, ux), Bx, p.A);
+                        const float h = 0.5f / qv;  // 1 / (2q)
+                        sb = fmaf(h, sb, (1.0f - h) * si);
+                        wsc = h;  // Eq. ACM2.0move: 1/q in place of 2
+                    }
+                }
+                s = fmaf(wsc, vdot<Q>(i, uw), sb);
                 if (SPLIT) {
                     const float uwp[3] = {p.wall_term_p[m][0], p.wall_term_p[m][1],
                                           p.wall_term_p[m][2]};

@@ -34,6 +34,7 @@ struct ProblemArgs {
     int fp16_sr;             // FP16 storage: 1 stochastic rounding of step outputs, 0 nearest
     uint32_t sr_word;        // fourth pcg4d input of this step: t ^ seed
     const uint8_t *mask;     // nullptr: all fluid
+    const float *qd;         // link-wall distances, Q fields of n values (SoA), or nullptr: q = 1/2
     int march_nzc;           // planes per workgroup of the forward tile kernel (0: unused)
 };
 

@@ -21,6 +21,15 @@ LWACM_OK, LWACM_EINVAL, LWACM_ENOMEM, LWACM_EDEVICE, LWACM_ENONFINITE, LWACM_EUN
 LWACM_KERNEL_AUTO, LWACM_KERNEL_GENERIC, LWACM_KERNEL_MARCH, LWACM_KERNEL_MARCH2 = 0, 1, 2, 3
 LWACM_ROUND_NEAREST, LWACM_ROUND_STOCHASTIC = 0, 1
 
+# The library's link order (the index of lwacm_init's link-wall distances d_q):
+# D2Q9 is the first nine links of D3Q19.
+LINK_VELOCITIES = {
+    19: ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (1, 1, 0), (-1, -1, 0),
+         (1, -1, 0), (-1, 1, 0), (0, 0, 1), (1, 0, 1), (-1, 0, 1), (0, 1, 1), (0, -1, 1),
+         (0, 0, -1), (-1, 0, -1), (1, 0, -1), (0, -1, -1), (0, 1, -1)),
+}
+LINK_VELOCITIES[9] = LINK_VELOCITIES[19][:9]
+
 _lib = None
 _vp = ctypes.c_void_p
 
@@ -238,7 +247,7 @@ class Solver:
                  g: Optional[Sequence[float]] = None, device="cuda",
                  variant: int = LWACM_KERNEL_AUTO, fp16_scales: Optional[Tuple[int, int]] = None,
                  fp16_rounding: Optional[Tuple[int, int]] = None,
-                 omega_p: Optional[float] = None):
+                 omega_p: Optional[float] = None, qd: Optional[torch.Tensor] = None):
         load_library()
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -258,8 +267,14 @@ class Solver:
             self.mask = torch.as_tensor(mask, dtype=torch.uint8).to(self.device).contiguous()
             if self.mask.numel() != nx * ny * nz:
                 raise LWACMError(LWACM_EINVAL, "mask size")
+        # link-wall distances (Q, nz, ny, nx) for interpolated bounce-back, kept alive here
+        self.qd = None
+        if qd is not None:
+            self.qd = torch.as_tensor(qd, dtype=torch.float32).to(self.device).contiguous()
+            if self.qd.numel() != lattice * nx * ny * nz:
+                raise LWACMError(LWACM_EINVAL, "qd size")
         self.ctx = lwacm_init(lattice, nx, ny, nz, omega, storage, self._a, self._b, self.mask,
-                              wall_u, g, _stream_handle(self.device))
+                              wall_u, g, _stream_handle(self.device), q=self.qd)
         if fp16_scales is not None:
             lwacm_set_fp16_scales(self.ctx, *fp16_scales)
         if fp16_rounding is not None:

@@ -79,7 +79,6 @@ def test_init_rejects_bad_arguments_before_device_work(lib):
     assert init(b=fake_a) == L.LWACM_EINVAL            # the two buffers must differ
     assert init(lattice=9) == L.LWACM_EINVAL            # nz = 8 with D2Q9
     assert init(storage=3) == L.LWACM_EINVAL
-    assert init(q=ctypes.c_void_p(0x3000)) == L.LWACM_EUNSUPPORTED
     assert ctx.value is None
     assert lib.lwacm_step(None, 1) == L.LWACM_EINVAL
     assert lib.lwacm_step_count(None) == -1
