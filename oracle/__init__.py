@@ -14,7 +14,9 @@ strings the per-step calls together:
 * ``diagnostics``-- mass sum(rho) and energy 1/2 sum|u|^2 over fluid nodes;
 * ``vjp``        -- reverse mode of one step;
 * ``gradient``   -- reverse sweep over n steps with a checkpoint every K
-                    steps and recomputation in between.
+                    steps and recomputation in between;
+* ``thermal_step`` -- one step of the temperature lattice (Eq. ACM2.0t)
+                    advected by a given flow velocity.
 
 Arrays: ``rho`` has shape (nz, ny, nx) (nz = 1 for D2Q9), ``u`` has shape
 (D, nz, ny, nx); float64, C order (x fastest).
@@ -58,6 +60,11 @@ def _load():
     lib.oracle_step_nodes.argtypes = common + [_dp, _dp, ctypes.POINTER(ctypes.c_long),
                                                ctypes.c_long, _dp, _dp]
     lib.oracle_step_nodes.restype = ctypes.c_int
+    lib.oracle_thermal_step.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double, _u8p, _dp,
+                                                            ctypes.c_int, _dp, _dp, _dp]
+    lib.oracle_thermal_step.restype = ctypes.c_int
+    lib.oracle_thermal_equilibrium.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
+    lib.oracle_thermal_equilibrium.restype = ctypes.c_int
     lib.oracle_diagnostics.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        _u8p, _dp, _dp, _dp, _dp]
     lib.oracle_diagnostics.restype = ctypes.c_int
@@ -212,6 +219,38 @@ def step_q(p: Problem, rho, u, qd):
     if rc != 0:
         raise RuntimeError(f"oracle_step_q failed ({rc})")
     return r1, u1
+
+
+def thermal_step(p: Problem, T, u, omega_t: float, wall_T=None):
+    """One step of the temperature lattice (Eq. ACM2.0t) on the problem's
+    lattice, grid and mask, advected by the flow velocity u (D, nz, ny, nx) at
+    the same time; wall_T[m] is the temperature of the walls with mask id m
+    (NaN or ids past the end: adiabatic; None: all adiabatic).  Returns T at
+    the next step."""
+    lib = _load()
+    T = _f64(T, p.shape)
+    u = _f64(u, (p.d,) + p.shape)
+    mask = None if p.mask is None else np.ascontiguousarray(p.mask, dtype=np.uint8)
+    wt = None if wall_T is None else np.ascontiguousarray(wall_T, dtype=np.float64).reshape(-1)
+    out = np.empty_like(T)
+    rc = lib.oracle_thermal_step(p.q, p.nx, p.ny, p.nz, float(omega_t), _ptr(mask, _u8p),
+                                 _ptr(wt), 0 if wt is None else len(wt), _ptr(T), _ptr(u),
+                                 _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"oracle_thermal_step failed ({rc})")
+    return out
+
+
+def thermal_equilibrium(q: int, T: float, u):
+    """(g^(e)_i, g^(e,e)_i), i = 0..q-1, of the temperature lattice at (T, u)."""
+    lib = _load()
+    uu = np.zeros(3)
+    uu[:len(u)] = u
+    g = np.empty(q)
+    ge = np.empty(q)
+    if lib.oracle_thermal_equilibrium(q, float(T), _ptr(uu), _ptr(g), _ptr(ge)) != 0:
+        raise ValueError(f"unknown lattice Q={q}")
+    return g, ge
 
 
 def step_nodes(p: Problem, rho, u, idx):

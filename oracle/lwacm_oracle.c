@@ -43,6 +43,12 @@
  *     neighbouring FP16 magnitudes plus a uniform variate reaches 1; the
  *     variate comes from the pcg4d hash (Jarzynski and Olano, "Hash
  *     Functions for GPU Rendering", JCGT 9(3), 2020) of (x, y, z, t ^ seed);
+ *   - the thermal extension (Appendix "Asymptotic analysis for energy
+ *     equation", Eqs. ACM2.0t and feqe): a temperature lattice on the
+ *     flow's lattice, advected by the flow velocity, with an equilibrium
+ *     whose moments are the ones the appendix states, its even part taken
+ *     literally as the mean at +u and -u, and adiabatic or fixed-temperature
+ *     halfway walls (the oracle's reading; the paper has no thermal wall rule);
  *   - the vector-Jacobian product of one step (reverse mode), obtained by
  *     the chain rule through the same population form.  The paper has no
  *     adjoint; the oracle's reading is "exact derivative of the step above",
@@ -735,5 +741,115 @@ int oracle_vjp(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
     *dL_domega = s * 2.0 / (omega * omega); /* a = 2 - 2/omega, da/domega = 2/omega^2 */
     free(fbar);
     free(da);
+    return 0;
+}
+
+/* ---- thermal LW-ACM: a temperature lattice advected by the flow ----
+ *
+ * Appendix "Asymptotic analysis for energy equation", Eqs. ACM2.0t and
+ * feqe.  The temperature lattice uses the flow's lattice (Q_t = Q); its only
+ * state is T at every node.  The velocity u in its equilibria is the flow
+ * velocity at the same node and time (the flow is not influenced by T).
+ */
+
+/* g_i^(e)(T, u): the function of T and u whose moments are the ones the
+ * appendix requires -- sum_i g = T, sum_i v_i g = T u and
+ * sum_i v_i v_i g = u u + T/3 I -- written with the lattice's weights as
+ * w_i [T (1 + 3 v_i.u) + 4.5 (v_i.u)^2 - 1.5 |u|^2]. */
+static double geq(const lattice_t *L, int i, double T, const double u[3])
+{
+    double c = vdot(L, i, u);
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return L->w[i] * (T * (1.0 + 3.0 * c) + 4.5 * c * c - 1.5 * uu);
+}
+
+/* Even part, Eq. feqe: the mean of g^(e) at +u and at -u. */
+static double gee(const lattice_t *L, int i, double T, const double u[3])
+{
+    double mu[3] = {-u[0], -u[1], -u[2]};
+    return 0.5 * (geq(L, i, T, u) + geq(L, i, T, mu));
+}
+
+/* g^(e)_i(T, u) and g^(e,e)_i(T, u) for i = 0..q-1 (pinned in the tests
+ * against the moments the appendix requires). */
+int oracle_thermal_equilibrium(int q, double T, const double *u_in, double *g_out,
+                               double *gee_out)
+{
+    lattice_t L;
+    if (make_lattice(q, &L)) return -1;
+    double u[3] = {0, 0, 0};
+    for (int k = 0; k < L.d; ++k) u[k] = u_in[k];
+    for (int i = 0; i < L.q; ++i) {
+        g_out[i] = geq(&L, i, T, u);
+        gee_out[i] = gee(&L, i, T, u);
+    }
+    return 0;
+}
+
+/*
+ * One step of the temperature lattice, Eq. ACM2.0t:
+ *   g_i(x, t+1) = g^(e)_i(x - v_i) + (2 - 2/omega_t) (g^(e,e)_i(x) - g^(e,e)_i(x - v_i)),
+ *   T(x, t+1)   = sum_i g_i(x, t+1),
+ * with T(., t) from T_in and u(., t) the flow velocity (D fields, SoA).
+ *
+ * Walls (the paper gives no thermal wall rule; this is the oracle's reading,
+ * built like the flow's halfway rule): where x - v_i is solid, the term
+ * g^(e)_ib(x) - (2 - 2/omega_t) g^(e,e)_ib(x) that x sends along ib = BB(i)
+ * into the wall comes back along i, with its sign kept for an adiabatic wall
+ * (bounce-back: no flux of T through the wall), or with its sign reversed
+ * plus (2/omega_t - 1) * 2 w_i T_w for a wall held at temperature T_w
+ * (anti-bounce-back, the same factor as the flow's moving-wall term); the
+ * own term (2 - 2/omega_t) g^(e,e)_i(x) is added as in the interior.
+ * wall_T[m] is the temperature of the walls with mask id m (0 <= m < n_ids);
+ * NaN, an id >= n_ids or wall_T == NULL mean adiabatic.  Solid nodes keep
+ * their T.
+ */
+int oracle_thermal_step(int q, int nx, int ny, int nz, double omega_t, const uint8_t *mask,
+                        const double *wall_T, int n_ids, const double *T_in, const double *u,
+                        double *T_out)
+{
+    lattice_t L;
+    if (make_lattice(q, &L)) return -1;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (L.d == 2 && nz != 1)) return -1;
+    if (!(omega_t > 0.0 && omega_t < 2.0)) return -1;
+    long n = (long)nx * ny * nz;
+    double k = 2.0 * (omega_t - 1.0) / omega_t;
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long ix = node_index(nx, ny, x, y, z);
+                if (mask && mask[ix] != 0) {
+                    T_out[ix] = T_in[ix];
+                    continue;
+                }
+                double ux[3];
+                load_u(&L, n, ix, u, ux);
+                double Tx = T_in[ix];
+                double sum = 0.0;
+                for (int i = 0; i < L.q; ++i) {
+                    long iy = upstream(&L, nx, ny, nz, x, y, z, i);
+                    double gi;
+                    if (!mask || mask[iy] == 0) {
+                        double uy[3];
+                        load_u(&L, n, iy, u, uy);
+                        double Ty = T_in[iy];
+                        gi = geq(&L, i, Ty, uy) + k * (gee(&L, i, Tx, ux) - gee(&L, i, Ty, uy));
+                    } else {
+                        int ib = L.opp[i];
+                        double sent = geq(&L, ib, Tx, ux) - k * gee(&L, ib, Tx, ux);
+                        double Tw = NAN;
+                        if (wall_T && mask[iy] < n_ids) Tw = wall_T[mask[iy]];
+                        if (isnan(Tw))
+                            gi = sent;
+                        else
+                            gi = -sent + (2.0 / omega_t - 1.0) * 2.0 * L.w[i] * Tw;
+                        gi += k * gee(&L, i, Tx, ux);
+                    }
+                    sum += gi;
+                }
+                T_out[ix] = sum;
+            }
     return 0;
 }

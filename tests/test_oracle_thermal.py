@@ -1,0 +1,167 @@
+"""Pins of the oracle's thermal LW-ACM (Appendix "Asymptotic analysis for
+energy equation", Eqs. ACM2.0t, feqe, AAT2 and diffusivity2).
+
+- The equilibrium has the moments the appendix requires (T, T u and
+  u u + T/3 I); its even part is even in u and keeps the even moments.
+- A Fourier mode in a uniform flow on a periodic grid is multiplied every step
+  by the amplification factor obtained by inserting e^{i k.x} into Eq.
+  ACM2.0t by hand:  lambda(k) = kap + sum_i w_i (1 + 3 v_i.u - kap) e^{-i k.v_i},
+  kap = 2 - 2/omega_t (the u-only terms of g^(e) and g^(e,e) cancel for a
+  uniform u).  Exact to rounding.
+- Long waves diffuse with the paper's alpha = (1/3)(1/omega_t - 1/2)
+  (Eq. diffusivity2) and travel with the flow velocity (Eq. AAT2).
+- The sum of T over the fluid nodes is conserved on a periodic grid and with
+  adiabatic walls, for any flow field.
+- Between two walls held at fixed temperatures (the halfway reading: the wall
+  sits halfway between the last fluid and the first solid layer) the steady
+  state is the exact linear profile, at rest and in plane Couette flow (the
+  thermal Couette problem without viscous heating, Br = 0); a uniform
+  initial state converges to it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Problem
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_equilibrium_moments(q):
+    d, v, w, _ = oracle.lattice_info(q)
+    rng = _rng(1)
+    for _ in range(5):
+        T = rng.uniform(0.2, 1.0)
+        u = rng.uniform(-0.1, 0.1, d)
+        u3 = np.zeros(3)
+        u3[:d] = u
+        g, ge = oracle.thermal_equilibrium(q, T, u)
+        vv = np.einsum("ia,ib->iab", v, v)
+        pi = np.outer(u3, u3) + T / 3.0 * np.diag([1.0] * d + [0.0] * (3 - d))
+        assert abs(g.sum() - T) < 1e-15
+        assert np.abs(v.T @ g - T * u3).max() < 1e-15
+        assert np.abs(np.einsum("iab,i->ab", vv, g) - pi).max() < 1e-15
+        assert abs(ge.sum() - T) < 1e-15
+        assert np.abs(v.T @ ge).max() < 1e-15
+        assert np.abs(np.einsum("iab,i->ab", vv, ge) - pi).max() < 1e-15
+        assert np.array_equal(ge, oracle.thermal_equilibrium(q, T, -u)[1])
+        assert np.abs(ge - 0.5 * (g + oracle.thermal_equilibrium(q, T, -u)[0])).max() < 1e-16
+
+
+def _mode_run(q, shape, kvec, u, omega_t, steps, T0=0.5, A=0.1):
+    d, v, w, _ = oracle.lattice_info(q)
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phase = kvec[0] * x + kvec[1] * y + kvec[2] * z
+    T = T0 + A * np.cos(phase)
+    uf = np.zeros((d,) + shape)
+    for a in range(d):
+        uf[a] = u[a]
+    p = Problem(q, nx, ny, nz)
+    for _ in range(steps):
+        T = oracle.thermal_step(p, T, uf, omega_t)
+    return T, phase, T0, A
+
+
+@pytest.mark.parametrize("q,shape,kvec,u,omega_t", [
+    (9, (1, 16, 24), (2 * np.pi * 3 / 24, 2 * np.pi / 16, 0.0), (0.04, -0.03), 1.3),
+    (9, (1, 12, 12), (2 * np.pi * 2 / 12, 2 * np.pi * 5 / 12, 0.0), (0.0, 0.1), 0.7),
+    (19, (8, 12, 10), (2 * np.pi / 10, 2 * np.pi * 2 / 12, 2 * np.pi * 3 / 8), (0.03, 0.02, -0.05),
+     1.6),
+])
+def test_fourier_mode_in_uniform_flow(q, shape, kvec, u, omega_t):
+    d, v, w, _ = oracle.lattice_info(q)
+    kap = 2.0 - 2.0 / omega_t
+    k3 = np.array(kvec)
+    u3 = np.zeros(3)
+    u3[:d] = u
+    lam = kap + sum(w[i] * (1.0 + 3.0 * (v[i] @ u3) - kap) * np.exp(-1j * (k3 @ v[i]))
+                    for i in range(q))
+    steps = 15
+    T, phase, T0, A = _mode_run(q, shape, kvec, u, omega_t, steps)
+    exact = T0 + A * np.real(lam ** steps * np.exp(1j * phase))
+    assert np.abs(T - exact).max() < 1e-13
+
+
+def test_long_wave_diffuses_with_alpha_and_moves_with_u():
+    """D2Q9, a wave of length 128: at rest its decay rate / k^2 is alpha of
+    Eq. diffusivity2 to O(k^2); in a flow along it the phase speed is u, and
+    the decay rate departs from alpha by O(u^2) only (the O(eps^2) of Eq.
+    AAT2 under diffusive scaling, u = O(eps))."""
+    n, steps = 128, 400
+    kx = 2 * np.pi / n
+    for omega_t, ux in [(1.2, 0.0), (1.8, 0.0), (0.8, 0.0), (1.2, 0.02), (1.8, 0.05)]:
+        T, phase, T0, A = _mode_run(9, (1, 2, n), (kx, 0.0, 0.0), (ux, 0.0), omega_t, steps)
+        amp = 2.0 / T[0, 0].size * np.sum((T[0, 0] - T0) * np.exp(-1j * phase[0, 0])) / A
+        alpha = (1.0 / omega_t - 0.5) / 3.0
+        alpha_meas = -np.log(abs(amp)) / (kx * kx * steps)
+        if ux == 0.0:
+            assert abs(alpha_meas / alpha - 1.0) < 5e-3, (omega_t, alpha_meas, alpha)
+            assert abs(np.angle(amp)) < 1e-12
+        else:
+            assert abs(alpha_meas - alpha) < ux * ux, (omega_t, alpha_meas, alpha)
+            speed = -np.angle(amp) / (kx * steps)
+            assert abs(speed / ux - 1.0) < 5e-3, (omega_t, speed, ux)
+
+
+@pytest.mark.parametrize("q,shape", [(9, (1, 18, 20)), (19, (8, 10, 12))])
+def test_total_temperature_is_conserved(q, shape):
+    d = 2 if q == 9 else 3
+    nz, ny, nx = shape
+    rng = _rng(2)
+    T = rng.uniform(0.3, 1.0, shape)
+    u = 0.05 * rng.standard_normal((d,) + shape)
+    mask = (rng.random(shape) < 0.12).astype(np.uint8)
+    mask[mask == 1] = rng.integers(1, 4, int(mask.sum())).astype(np.uint8)
+    for m in (None, mask):
+        p = Problem(q, nx, ny, nz, mask=m)
+        fl = np.ones(shape, bool) if m is None else (m == 0)
+        total0 = T[fl].sum()
+        t = T
+        for _ in range(20):
+            t = oracle.thermal_step(p, t, u, 1.4)  # all walls adiabatic
+        assert abs(t[fl].sum() / total0 - 1.0) < 1e-13
+        if m is not None:
+            assert np.array_equal(t[~fl], T[~fl])
+
+
+def _channel(q, h, Tb, Tt, U, omega_t, steps, start_exact):
+    d, v, w, _ = oracle.lattice_info(q)
+    ax = 1 if q == 9 else 2
+    shape = (1, h, 4) if q == 9 else (h, 4, 4)
+    nz, ny, nx = shape
+    mask = np.zeros(shape, np.uint8)
+    sl = [slice(None)] * 3
+    sl[2 - ax] = 0
+    mask[tuple(sl)] = 1
+    sl[2 - ax] = h - 1
+    mask[tuple(sl)] = 2
+    coord = np.arange(h, dtype=float)
+    # walls halfway between the last fluid and the first solid layer
+    exact = Tb + (Tt - Tb) * (coord - 0.5) / (h - 2.0)
+    bshape = [1, 1, 1]
+    bshape[2 - ax] = h
+    prof = exact.reshape(bshape) * np.ones(shape)
+    u = np.zeros((d,) + shape)
+    u[0] = (U * (coord - 0.5) / (h - 2.0)).reshape(bshape)
+    T = prof.copy() if start_exact else np.full(shape, 0.5 * (Tb + Tt))
+    p = Problem(q, nx, ny, nz, mask=mask)
+    for _ in range(steps):
+        T = oracle.thermal_step(p, T, u, omega_t, wall_T=[np.nan, Tb, Tt])
+    fl = mask == 0
+    return float(np.abs(T[fl] - prof[fl]).max() / abs(Tt - Tb))
+
+
+@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("U", [0.0, 0.05])
+@pytest.mark.parametrize("omega_t", [0.9, 1.5])
+def test_linear_profile_between_fixed_temperature_walls_is_steady(q, U, omega_t):
+    assert _channel(q, 10, 1.0, 0.2, U, omega_t, 40, True) < 1e-13
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_thermal_couette_without_heating_converges_to_linear_profile(q):
+    assert _channel(q, 10, 1.0, 0.2, 0.05, 1.5, 1500, False) < 1e-9
