@@ -117,6 +117,7 @@ def _qbb_leg(args, L, wl, dev, stream):
             "ms_per_step": round(ms8, 5), "q": 0.3,
             "achieved_GBs": round(33.0 * c4.nx * c4.ny * c4.nz / (ms8 * 1e-3) / 1e9, 1),
             "kernel": "k_fwd_generic<19,float,true,false,false>",
+            "traffic": _measured_traffic("k_fwd_generic<19,float,true,false,false>"),
             "basis": "33 B per node (state in and out, uint8 mask); the generic kernel gathers "
                      "the 18 upstream nodes and, at the walls, the q values and the second node"}
 
