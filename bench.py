@@ -177,6 +177,42 @@ def _field_leg(args, L, wl, dev, stream, drho_t, u_t, n):
                      "fields read); one step per launch on the single-step tile kernel"}
 
 
+def _thermal_leg(args, L, wl, dev, stream, drho_t, u_t, n):
+    """The 256^3 Taylor-Green step with a temperature field advected by the
+    flow (lwacm_set_thermal, omega_t = 1.4): each step is the temperature
+    tile kernel (reads T and the flow state, writes T: 24 B per node) followed by
+    the single-step flow kernel.  The step time added by the temperature is
+    the difference to the same steps without it (an underestimate of the
+    kernel's own time: the flow kernel that follows finds part of the state
+    it reads still cached); the kernel's own duration is in its profile."""
+    import torch
+    cfg = wl.TGV3D_256
+    times = []
+    for thermal in (False, True):
+        s9 = L.Solver(L.LWACM_D3Q19, n, n, n, cfg.omega, device=dev, variant=2)
+        s9.set_state(drho_t, u_t)
+        if thermal:
+            s9.set_thermal(1.4, 0.5 + 0.5 * torch.rand((n, n, n), device=dev))
+        s9.step(args.warmup)
+        times.append(_events_time(s9.step, args.steps, stream))
+        s9.close()
+    torch.cuda.empty_cache()
+    ms_flow, ms_both = (t / args.steps * 1e3 for t in times)
+    ms_t = ms_both - ms_flow
+    nodes = n ** 3
+    print(f"[bench] thermal {n}^3: {ms_both:.4f} ms/step with T, {ms_flow:.4f} without",
+          file=sys.stderr, flush=True)
+    return {"value": round(nodes * args.steps / times[1] / 1e6, 1),
+            "unit": "MLUPS (flow and temperature)", "ms_per_step": round(ms_both, 5),
+            "ms_flow_only": round(ms_flow, 5), "ms_added_by_temperature": round(ms_t, 5),
+            "GBs_at_added_time": round(24.0 * nodes / (ms_t * 1e-3) / 1e9, 1) if ms_t > 0
+            else None,
+            "kernel": "k_thermal_march<false>" if n % 32 == 0 else "k_thermal_step<19,false>",
+            "traffic": _measured_traffic("k_thermal_march<false>") if n == 256 else None,
+            "basis": "24 B per node for the temperature kernel (FP32 flow state and T read, "
+                     "T written); the flow step is the single-step tile kernel"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +235,8 @@ def main():
                     help="time only the 192^3 cavity with interpolated bounce-back (q = 0.3)")
     ap.add_argument("--field-only", action="store_true",
                     help="time only the 256^3 step with a node-by-node acceleration field")
+    ap.add_argument("--thermal-only", action="store_true",
+                    help="time only the 256^3 step with a temperature field")
     ap.add_argument("--cavity-only", action="store_true",
                     help="time only the 192^3 lid-driven cavity (walls, moving lid)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -246,6 +284,10 @@ def main():
     del drho, u
     if args.field_only:
         print(json.dumps({"force_field": _field_leg(args, L, wl, dev, stream, drho_t, u_t, n)}),
+              flush=True)
+        return
+    if args.thermal_only:
+        print(json.dumps({"thermal": _thermal_leg(args, L, wl, dev, stream, drho_t, u_t, n)}),
               flush=True)
         return
     if args.split_only:
@@ -464,6 +506,9 @@ def main():
 
     # ---- node-by-node body acceleration: the same 256^3 step
     result["force_field"] = _field_leg(args, L, wl, dev, stream, drho_t, u_t, n)
+
+    # ---- temperature advected by the flow: the same 256^3 step plus the temperature kernel
+    result["thermal"] = _thermal_leg(args, L, wl, dev, stream, drho_t, u_t, n)
 
     # ---- interpolated bounce-back: the 192^3 cavity with walls at q = 0.3
     result["cavity_192_interpolated"] = _qbb_leg(args, L, wl, dev, stream)

@@ -167,8 +167,10 @@ int lwacm_set_march_chunk(lwacm_ctx *c, int planes);
  * LWACM_EINVAL; omega_p == omega (the default after lwacm_init) is the
  * single-relaxation step; omega_p != omega with link-wall distances (d_q)
  * gives LWACM_EUNSUPPORTED.  With omega_p != omega the forward step runs on the
- * generic kernel (every lattice, walls and force allowed) and the reverse
- * steps return LWACM_EUNSUPPORTED.  Takes effect from the next lwacm_step. */
+ * single-step tile kernel (D3Q19 without walls, nz >= 8) or else on the
+ * generic kernel (every lattice, walls and force allowed), never on the
+ * two-step kernel, and the reverse steps return LWACM_EUNSUPPORTED.  Takes
+ * effect from the next lwacm_step. */
 int lwacm_set_omega_p(lwacm_ctx *c, double omega_p);
 
 /* Body acceleration given node by node (Eq. force with a space- and
@@ -179,10 +181,47 @@ int lwacm_set_omega_p(lwacm_ctx *c, double omega_p);
  * returns to that g (or to no forcing).  The step adds rho(x, t) g(x) to the
  * momentum of node x (Eq. force, with the density before the step).  A g that
  * changes in time is set before each lwacm_step(c, 1), with the field of the
- * step's starting time.  The forward step then runs on the generic kernel;
- * the reverse steps return LWACM_EUNSUPPORTED while a field is set.
- * LWACM_EINVAL for a null context. */
+ * step's starting time.  The forward step then runs on the single-step tile
+ * kernel (D3Q19, nz >= 8, omega_p == omega) or else on the generic kernel,
+ * never on the two-step kernel; the reverse steps return LWACM_EUNSUPPORTED
+ * while a field is set.  LWACM_EINVAL for a null context. */
 int lwacm_set_force_field(lwacm_ctx *c, const float *d_g);
+
+/* Temperature advected by the flow: the thermal LW-ACM (Appendix
+ * "Asymptotic analysis for energy equation", Eq. ACM2.0t with the even part
+ * of Eq. feqe) on the flow's lattice.  Its only state is T per node; its
+ * equilibrium w_i [T (1 + 3 v_i.u) + 9/2 (v_i.u)^2 - 3/2 |u|^2] has the
+ * moments the appendix requires (T, T u, u u + T/3 I), u being the flow
+ * velocity at the same node and time; T diffuses with
+ * alpha = (1/omega_t - 1/2) / 3 (Eq. diffusivity2) and does not act on the
+ * flow.  From this call on every lwacm_step also advances T by one step per
+ * flow step, reading the flow state of the step's starting time.
+ *   omega_t   relaxation frequency, 0 < omega_t < 2 (stable for
+ *             1 <= omega_t < 2 as the appendix notes).
+ *   d_T_a, d_T_b  two distinct caller-owned device buffers of nx*ny*nz FP32
+ *             values (node index as the state's), kept alive while the
+ *             temperature is on; d_T_a holds T now.  Steps write them in
+ *             turn: lwacm_temperature names the one holding the current T.
+ *             Both NULL: the temperature is switched off.
+ *   h_wall_T  host table of n_wall_T temperatures by mask id (copied), or
+ *             NULL with n_wall_T = 0.  A fluid node next to a solid node
+ *             with id m sends back the term it sends into the wall: with the
+ *             same sign where h_wall_T[m] is NaN, m >= n_wall_T or the table
+ *             is NULL (adiabatic wall), or with the opposite sign plus
+ *             (2/omega_t - 1) 2 w_i h_wall_T[m] (wall at that temperature,
+ *             halfway between the fluid and the solid node).  The paper
+ *             gives no thermal wall rule; this halfway reading keeps a linear
+ *             profile between two such walls exactly steady.  n_wall_T <= 16.
+ *             Solid nodes keep their T.
+ * LWACM_EINVAL for bad arguments, LWACM_EUNSUPPORTED with FP16 storage or
+ * with the two-step kernel requested (the two-step kernel is not used while
+ * the temperature is on).  The reverse steps cover the flow only. */
+int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
+                      const float *h_wall_T, int n_wall_T);
+
+/* Device pointer of the buffer that holds T at the current step (one of the
+ * two given to lwacm_set_thermal).  LWACM_EINVAL when the temperature is off. */
+int lwacm_temperature(lwacm_ctx *c, float **d_T);
 
 /* Load the state from FP32 fields (rho - 1 and u, SoA), converting to the
  * storage format, and set rho0 (the mean fluid density used by moving walls,

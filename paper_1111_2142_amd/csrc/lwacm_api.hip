@@ -9,6 +9,7 @@
 
 #include "lwacm.h"
 #include "lwacm_internal.hpp"
+#include "lwacm_thermal.hpp"
 
 using lwacm::ProblemArgs;
 using lwacm::ReduceArgs;
@@ -43,6 +44,11 @@ struct lwacm_ctx {
     long long steps;
     bool diag_valid;
     unsigned long long n_fluid;
+    // temperature lattice (lwacm_set_thermal): two caller-owned buffers
+    bool thermal;
+    float *T_buf[2];
+    int tcur;
+    lwacm::ThermalArgs targs;
 };
 
 namespace {
@@ -126,7 +132,7 @@ bool use_march(const lwacm_ctx *c)
 bool use_march2(const lwacm_ctx *c)
 {
     if (c->variant != LWACM_KERNEL_AUTO && c->variant != LWACM_KERNEL_MARCH2) return false;
-    return c->storage == LWACM_FP32 && lwacm::march2_supported(c->p);
+    return c->storage == LWACM_FP32 && !c->thermal && lwacm::march2_supported(c->p);
 }
 
 double *hist_slot(lwacm_ctx *c, long long step)
@@ -363,6 +369,43 @@ int lwacm_set_omega_p(lwacm_ctx *c, double omega_p)
     return LWACM_OK;
 }
 
+int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
+                      const float *h_wall_T, int n_wall_T)
+{
+    if (!c) return LWACM_EINVAL;
+    if (!d_T_a && !d_T_b) {
+        c->thermal = false;
+        return LWACM_OK;
+    }
+    if (!d_T_a || !d_T_b || d_T_a == d_T_b || !(omega_t > 0.0 && omega_t < 2.0))
+        return LWACM_EINVAL;
+    if (n_wall_T < 0 || n_wall_T > lwacm::kMaxThermalWallIds || (n_wall_T > 0 && !h_wall_T))
+        return LWACM_EINVAL;
+    if (c->storage != LWACM_FP32 || c->variant == LWACM_KERNEL_MARCH2) return LWACM_EUNSUPPORTED;
+    lwacm::ThermalArgs &t = c->targs;
+    t.Q = c->p.Q;
+    t.nx = c->p.nx;
+    t.ny = c->p.ny;
+    t.nz = c->p.nz;
+    t.kap = (float)(2.0 - 2.0 / omega_t);
+    t.h = (float)(2.0 / omega_t - 1.0);
+    t.mask = c->p.mask;
+    for (int m = 0; m < lwacm::kMaxThermalWallIds; ++m)
+        t.wall_T[m] = m < n_wall_T ? h_wall_T[m] : __builtin_nanf("");
+    c->T_buf[0] = d_T_a;
+    c->T_buf[1] = d_T_b;
+    c->tcur = 0;
+    c->thermal = true;
+    return LWACM_OK;
+}
+
+int lwacm_temperature(lwacm_ctx *c, float **d_T)
+{
+    if (!c || !d_T || !c->thermal) return LWACM_EINVAL;
+    *d_T = c->T_buf[c->tcur];
+    return LWACM_OK;
+}
+
 int lwacm_set_variant(lwacm_ctx *c, int variant)
 {
     if (!c) return LWACM_EINVAL;
@@ -371,7 +414,8 @@ int lwacm_set_variant(lwacm_ctx *c, int variant)
         return LWACM_OK;
     }
     if (variant == LWACM_KERNEL_MARCH2) {
-        if (c->storage != LWACM_FP32 || !lwacm::march2_supported(c->p)) return LWACM_EUNSUPPORTED;
+        if (c->storage != LWACM_FP32 || c->thermal || !lwacm::march2_supported(c->p))
+            return LWACM_EUNSUPPORTED;
         c->variant = variant;
         return LWACM_OK;
     }
@@ -448,6 +492,16 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
         void *dst = c->buf[c->cur ^ 1];
         c->p.sr_word = (uint32_t)(c->steps + 1) ^ c->sr_seed;
         hipError_t e;
+        if (c->thermal) {
+            // T advances with the flow velocity of the same time: it reads the
+            // state this step's flow kernel reads, before that kernel runs
+            lwacm::ThermalArgs t = c->targs;
+            t.state = static_cast<const float *>(src);
+            t.T_in = c->T_buf[c->tcur];
+            t.T_out = c->T_buf[c->tcur ^ 1];
+            if (lwacm::launch_thermal_step(t, c->stream) != hipSuccess) return LWACM_EDEVICE;
+            c->tcur ^= 1;
+        }
         if (two)
             e = lwacm::launch_fwd_march2(c->p, static_cast<const float *>(src),
                                          static_cast<float *>(dst), r, c->stream);

@@ -1,0 +1,26 @@
+// lwacm_thermal.hpp -- arguments and launch of the temperature-lattice step
+// (thermal LW-ACM, Eq. ACM2.0t with the even part of Eq. feqe).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lwacm {
+
+constexpr int kMaxThermalWallIds = 16;
+
+struct ThermalArgs {
+    int Q, nx, ny, nz;
+    float kap;            // 2 - 2/omega_t: weight of the even-part difference
+    float h;              // 1 - kap = 2/omega_t - 1
+    const float *state;   // flow state at the step's time, FP32 (D + 1 floats per node)
+    const float *T_in;    // T at the step's time
+    float *T_out;         // T one step later
+    const uint8_t *mask;  // 0 fluid, m >= 1 solid with wall id m; null: no walls
+    float wall_T[kMaxThermalWallIds];  // temperature of wall id m; NaN: adiabatic
+};
+
+hipError_t launch_thermal_step(const ThermalArgs &t, hipStream_t stream);
+
+}  // namespace lwacm

@@ -62,6 +62,8 @@ def load_library():
         "lwacm_set_march_chunk": (i, [_vp, i]),
         "lwacm_set_omega_p": (i, [_vp, ctypes.c_double]),
         "lwacm_set_force_field": (i, [_vp, _vp]),
+        "lwacm_set_thermal": (i, [_vp, d, _vp, _vp, _vp, i]),
+        "lwacm_temperature": (i, [_vp, ctypes.POINTER(_vp)]),
         "lwacm_set_state": (i, [_vp, _vp, _vp]),
         "lwacm_step": (i, [_vp, i]),
         "lwacm_diagnostics": (i, [_vp, dp, dp]),
@@ -150,6 +152,27 @@ def lwacm_set_force_field(ctx, g: Optional[torch.Tensor]):
     """g: (D, nz, ny, nx) float32 contiguous on the solver's device, or None.
     The tensor must stay alive while it is set."""
     _check(load_library().lwacm_set_force_field(ctx, _ptr(g)), "lwacm_set_force_field")
+
+
+def lwacm_set_thermal(ctx, omega_t: float, T_a: Optional[torch.Tensor],
+                      T_b: Optional[torch.Tensor], wall_T: Optional[Sequence[float]] = None):
+    """T_a, T_b: two (nz, ny, nx) float32 contiguous tensors on the solver's
+    device (T_a holds T now), kept alive while set; both None switch the
+    temperature off.  wall_T[m]: temperature of the walls with mask id m
+    (NaN: adiabatic)."""
+    arr, n = None, 0
+    if wall_T is not None:
+        n = len(wall_T)
+        arr = (ctypes.c_float * max(n, 1))(*[float(v) for v in wall_T])
+    _check(load_library().lwacm_set_thermal(ctx, float(omega_t), _ptr(T_a), _ptr(T_b), arr, n),
+           "lwacm_set_thermal")
+
+
+def lwacm_temperature(ctx) -> int:
+    """Device address of the buffer holding the current T."""
+    out = _vp()
+    _check(load_library().lwacm_temperature(ctx, ctypes.byref(out)), "lwacm_temperature")
+    return out.value
 
 
 def lwacm_set_variant(ctx, variant: int):
@@ -307,6 +330,31 @@ class Solver:
                 raise LWACMError(LWACM_EINVAL, "set_force_field size")
         self._g_field = g
         lwacm_set_force_field(self.ctx, g)
+
+    def set_thermal(self, omega_t: float, T: Optional[torch.Tensor],
+                    wall_T: Optional[Sequence[float]] = None):
+        """Advance a temperature field T (nz, ny, nx) with every following step
+        (thermal LW-ACM, relaxation omega_t); None switches it off.  The solver
+        owns the two FP32 buffers it passes to the library."""
+        if T is None:
+            lwacm_set_thermal(self.ctx, 1.0, None, None)
+            self._T = None
+            return
+        T = T.to(self.device, torch.float32).contiguous()
+        if T.numel() != self.nx * self.ny * self.nz:
+            raise LWACMError(LWACM_EINVAL, "set_thermal size")
+        a = T.clone().reshape(self.shape)
+        b = torch.empty_like(a)
+        lwacm_set_thermal(self.ctx, omega_t, a, b, wall_T)
+        self._T = (a, b)
+
+    def temperature(self) -> torch.Tensor:
+        """A copy of T at the current step, (nz, ny, nx) float32."""
+        if getattr(self, "_T", None) is None:
+            raise LWACMError(LWACM_EINVAL, "temperature: no temperature field")
+        addr = lwacm_temperature(self.ctx)
+        cur = self._T[0] if addr == self._T[0].data_ptr() else self._T[1]
+        return cur.clone()
 
     def moments(self, diagnostics: bool = False):
         drho = torch.empty(self.shape, dtype=torch.float32, device=self.device)

@@ -1,0 +1,174 @@
+"""The temperature lattice of the thermal LW-ACM (lwacm_set_thermal;
+Eq. ACM2.0t with the even part of Eq. feqe) against the oracle's
+thermal_step, run in lockstep with the flow.
+
+- Random flow states, random T and walls of three kinds (two held at fixed
+  temperatures, one adiabatic), D2Q9 and D3Q19, several steps: T on the fluid
+  nodes to the FP32 bar; the flow is the oracle's as well.
+- The 256^3 Taylor-Green flow with a random T field, one step on the full
+  grid against the oracle at every node; the total of T over 20 steps
+  conserved to FP32 rounding (periodic grid).
+- Thermal Couette flow without heating: the exact linear profile between the
+  two fixed-temperature walls stays steady.
+- The temperature does not change the flow (bitwise equal to the same steps
+  without it); scope: FP16 storage and the two-step kernel decline it;
+  switching it off is allowed.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+from gpu_helpers import banner, fluid_of, need_gpu, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+MARCH, MARCH2 = 2, 3
+WALL_T = [np.nan, 0.2, np.nan, 0.9]  # ids 1 and 3 fixed, id 2 adiabatic
+
+
+def _walls(shape, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mask = (rng.random(shape) < 0.1).astype(np.uint8)
+    mask[mask == 1] = rng.integers(1, 4, int(mask.sum())).astype(np.uint8)
+    return mask
+
+
+@pytest.mark.parametrize("q,masked,shape", [(9, False, (1, 40, 48)), (9, True, (1, 40, 48)),
+                                             (19, False, (12, 32, 32)), (19, True, (40, 32, 64)),
+                                             (19, True, (10, 20, 24))])
+def test_random_fields_match_oracle(q, masked, shape):
+    """D3Q19 shapes with nx % 32 == 0 and ny % 16 == 0 run the tile kernel
+    (one z chunk, and two chunks with a tail); (10, 20, 24) the gather kernel."""
+    L = need_gpu()
+    banner(f"thermal random q={q} masked={masked} shape={shape}")
+    nz, ny, nx = shape
+    d = 2 if q == 9 else 3
+    drho, u = wl.random_state(shape, d, seed=51, du=0.03, drho=0.01)
+    drho = drho.astype(np.float32).astype(np.float64)
+    u = u.astype(np.float32).astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(52))
+    T = rng.uniform(0.2, 1.0, shape).astype(np.float32).astype(np.float64)
+    mask = _walls(shape, 53) if masked else None
+    table = np.zeros((4, 3))
+    s = L.Solver(q, nx, ny, nz, 1.6, mask=None if mask is None else to_dev(mask, torch.uint8),
+                 wall_u=[list(r) for r in table])
+    s.set_state(to_dev(drho), to_dev(u))
+    s.set_thermal(1.3, to_dev(T), wall_T=WALL_T)
+    steps = 6
+    s.step(steps)
+    Tg = s.temperature().double().cpu().numpy()
+    dr, uu = s.moments()
+    uu = uu.double().cpu().numpy()
+    s.close()
+    rho0 = 1.0 + (drho if mask is None else drho[mask == 0]).astype(np.float32).mean()
+    p = oracle.Problem(q, nx, ny, nz, omega=1.6, mask=mask, wall_u=table, rho0=rho0)
+    r, ru, rT = 1.0 + drho, u, T
+    for _ in range(steps):
+        rT = oracle.thermal_step(p, rT, ru, 1.3, wall_T=WALL_T)
+        r, ru = oracle.step(p, r, ru)
+    fl = fluid_of(mask, shape)
+    err_T = rel_l2(Tg[fl], rT[fl])
+    err_max = float(np.abs(Tg[fl] - rT[fl]).max())
+    banner(f"thermal random: rel-L2 T {err_T:.3e}, max |dT| {err_max:.3e}, "
+           f"rel-L2 u {rel_l2(uu[:, fl], ru[:, fl]):.3e}")
+    assert err_T < 1e-6 and err_max < 1e-5
+    assert rel_l2(uu[:, fl], ru[:, fl]) < 1e-5
+    if mask is not None:
+        assert np.array_equal(Tg[~fl], T[~fl])
+
+
+def test_full_size_step_matches_oracle_and_conserves_total():
+    L = need_gpu()
+    cfg = wl.TGV3D_256
+    n = cfg.nx
+    banner(f"thermal 256^3 one step vs oracle, then 20 steps total")
+    drho, u = wl.taylor_green_3d(n, cfg.u0)
+    drho = drho.astype(np.float32).astype(np.float64)
+    u = u.astype(np.float32).astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(54))
+    T = rng.uniform(0.2, 1.0, (n, n, n)).astype(np.float32)
+    s = L.Solver(19, n, n, n, cfg.omega)
+    s.set_state(to_dev(drho), to_dev(u))
+    s.set_thermal(1.4, to_dev(T))
+    s.step(1)
+    Tg = s.temperature().double().cpu().numpy()
+    p = oracle.Problem(19, n, n, n, omega=cfg.omega)
+    rT = oracle.thermal_step(p, T.astype(np.float64), u, 1.4)
+    err_max = float(np.abs(Tg - rT).max())
+    banner(f"thermal 256^3: max |dT| {err_max:.3e}")
+    assert err_max < 1e-6
+    total0 = float(T.astype(np.float64).sum())
+    s.step(19)
+    total = float(s.temperature().double().sum().item())
+    s.close()
+    banner(f"thermal 256^3: total T drift over 20 steps {abs(total / total0 - 1):.3e}")
+    assert abs(total / total0 - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_linear_profile_between_fixed_temperature_walls_stays(q):
+    L = need_gpu()
+    banner(f"thermal Couette q={q}")
+    h, U, Tb, Tt = 18, 0.02, 1.0, 0.2
+    ax = 1 if q == 9 else 2
+    shape = (1, h, 64) if q == 9 else (h, 16, 64)
+    nz, ny, nx = shape
+    d = 2 if q == 9 else 3
+    mask = np.zeros(shape, np.uint8)
+    sl = [slice(None)] * 3
+    sl[2 - ax] = 0
+    mask[tuple(sl)] = 1
+    sl[2 - ax] = h - 1
+    mask[tuple(sl)] = 2
+    coord = np.arange(h, dtype=float)
+    bshape = [1, 1, 1]
+    bshape[2 - ax] = h
+    prof = (Tb + (Tt - Tb) * (coord - 0.5) / (h - 2.0)).reshape(bshape) * np.ones(shape)
+    u = np.zeros((d,) + shape)
+    u[0] = (U * (coord - 0.5) / (h - 2.0)).reshape(bshape)
+    s = L.Solver(q, nx, ny, nz, 1.5, mask=to_dev(mask, torch.uint8),
+                 wall_u=[[0, 0, 0], [0, 0, 0], [U, 0, 0]])
+    s.set_state(to_dev(np.zeros(shape)), to_dev(u))
+    s.set_thermal(1.5, to_dev(prof), wall_T=[np.nan, Tb, Tt])
+    s.step(300)
+    Tg = s.temperature().double().cpu().numpy()
+    s.close()
+    fl = mask == 0
+    err = float(np.abs(Tg[fl] - prof[fl]).max() / abs(Tt - Tb))
+    banner(f"thermal Couette: max error / dT {err:.3e}")
+    assert err < 2e-5
+
+
+def test_temperature_leaves_the_flow_alone_and_scope():
+    L = need_gpu()
+    banner("thermal scope")
+    shape = (16, 32, 64)
+    nz, ny, nx = shape
+    drho, u = wl.random_state(shape, 3, seed=55, du=0.02, drho=0.01)
+    ref = L.Solver(19, nx, ny, nz, 1.7, variant=MARCH)
+    ref.set_state(to_dev(drho), to_dev(u))
+    ref.step(5)
+    r_ref = [t.cpu().numpy() for t in ref.moments()]
+    ref.close()
+    s = L.Solver(19, nx, ny, nz, 1.7)
+    T0 = torch.rand(shape, device="cuda")
+    s.set_thermal(1.2, T0)
+    with pytest.raises(L.LWACMError) as ei:
+        L.lwacm_set_variant(s.ctx, MARCH2)
+    assert ei.value.code == L.LWACM_EUNSUPPORTED
+    s.set_state(to_dev(drho), to_dev(u))
+    s.step(5)
+    r = [t.cpu().numpy() for t in s.moments()]
+    assert all(np.array_equal(a, b) for a, b in zip(r, r_ref))
+    s.set_thermal(1.0, None)
+    with pytest.raises(L.LWACMError):
+        s.temperature()
+    L.lwacm_set_variant(s.ctx, MARCH2)
+    s.close()
+    h = L.Solver(19, nx, ny, nz, 1.7, storage=1)
+    with pytest.raises(L.LWACMError) as ei:
+        h.set_thermal(1.2, T0)
+    assert ei.value.code == L.LWACM_EUNSUPPORTED
+    h.close()
