@@ -65,6 +65,9 @@ def _load():
     lib.oracle_thermal_step.restype = ctypes.c_int
     lib.oracle_thermal_equilibrium.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
     lib.oracle_thermal_equilibrium.restype = ctypes.c_int
+    lib.oracle_wall_force.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double, _u8p, _dp, _dp, _dp,
+                                                          ctypes.c_int, _dp, _dp]
+    lib.oracle_wall_force.restype = ctypes.c_int
     lib.oracle_diagnostics.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        _u8p, _dp, _dp, _dp, _dp]
     lib.oracle_diagnostics.restype = ctypes.c_int
@@ -239,6 +242,26 @@ def thermal_step(p: Problem, T, u, omega_t: float, wall_T=None):
     if rc != 0:
         raise RuntimeError(f"oracle_thermal_step failed ({rc})")
     return out
+
+
+def wall_force(p: Problem, rho, u, wall_id: int, center=(0.0, 0.0, 0.0), qd=None):
+    """Force and torque on the walls with mask id ``wall_id`` by momentum
+    exchange (Eqs. MEA3-MEA5) at the state (rho, u); qd as in step_q.
+    Returns (F[3], T[3]) in lattice units, torque about ``center`` (node
+    coordinates x, y, z)."""
+    lib = _load()
+    rho = _f64(rho, p.shape)
+    u = _f64(u, (p.d,) + p.shape)
+    mask = np.ascontiguousarray(p.mask, dtype=np.uint8)
+    q = None if qd is None else _f64(qd, (p.q,) + p.shape)
+    c = np.zeros(3)
+    c[:len(center)] = center
+    out = np.empty(6)
+    rc = lib.oracle_wall_force(p.q, p.nx, p.ny, p.nz, float(p.omega), _ptr(mask, _u8p), _ptr(q),
+                               _ptr(rho), _ptr(u), int(wall_id), _ptr(c), _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"oracle_wall_force failed ({rc})")
+    return out[:3].copy(), out[3:].copy()
 
 
 def thermal_equilibrium(q: int, T: float, u):

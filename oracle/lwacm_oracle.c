@@ -43,6 +43,8 @@
  *     neighbouring FP16 magnitudes plus a uniform variate reaches 1; the
  *     variate comes from the pcg4d hash (Jarzynski and Olano, "Hash
  *     Functions for GPU Rendering", JCGT 9(3), 2020) of (x, y, z, t ^ seed);
+ *   - force and torque on a wall by momentum exchange (Eqs. MEA3, MEA4,
+ *     MEA5), for halfway and interpolated walls at rest;
  *   - the thermal extension (Appendix "Asymptotic analysis for energy
  *     equation", Eqs. ACM2.0t and feqe): a temperature lattice on the
  *     flow's lattice, advected by the flow velocity, with an equilibrium
@@ -850,6 +852,73 @@ int oracle_thermal_step(int q, int nx, int ny, int nz, double omega_t, const uin
                     sum += gi;
                 }
                 T_out[ix] = sum;
+            }
+    return 0;
+}
+
+/*
+ * Force and torque on the walls with mask id wall_id by momentum exchange
+ * (Section "Moving complex boundaries", Eqs. MEA3, MEA4 and MEA5), from the
+ * state (rho, u) at time t.  For every link j from a fluid node x to a solid
+ * node x + v_j of that id,
+ *   p_j = v_j [f*_j(x, t) + f**_BB(j)(x, t+1)],
+ * f*_j = f^(e)_j - (2 - 2/omega) f^(e,o)_j at x (the population x sends into
+ * the wall) and f**_BB(j) the population the wall returns along BB(j) before
+ * post-combining: f*_j itself for the halfway rule, the interpolation of Eq.
+ * ACM2.0cc with qd[j * n + x] when qd is given (the same rule as
+ * oracle_step_q).  The paper restricts the formula to bodies at rest; the
+ * returned population here excludes the wall-motion term.
+ * F = sum p_j, T = sum (x - x_c) x p_j, x being the node the link starts from
+ * (coordinates are node indices); out = (F_x, F_y, F_z, T_x, T_y, T_z).
+ */
+int oracle_wall_force(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
+                      const double *qd, const double *rho, const double *u, int wall_id,
+                      const double xc[3], double out[6])
+{
+    lattice_t L;
+    if (make_lattice(q, &L)) return -1;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (L.d == 2 && nz != 1) || !mask || wall_id < 1) return -1;
+    long n = (long)nx * ny * nz;
+    double a = 2.0 * (omega - 1.0) / omega;
+    for (int k = 0; k < 6; ++k) out[k] = 0.0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long ix = node_index(nx, ny, x, y, z);
+                if (mask[ix] != 0) continue;
+                double ux[3];
+                load_u(&L, n, ix, u, ux);
+                double rx = rho[ix];
+                for (int j = 0; j < L.q; ++j) {
+                    /* x + v_j is x - v_BB(j) */
+                    int i = L.opp[j];
+                    long iw = upstream(&L, nx, ny, nz, x, y, z, i);
+                    if (mask[iw] != wall_id) continue;
+                    double fs = feq(&L, j, rx, ux) - a * feo(&L, j, rx, ux);
+                    double fb = fs;
+                    if (qd) {
+                        double qq = qd[(long)j * n + ix];
+                        if (qq < 0.5) {
+                            long iz = upstream(&L, nx, ny, nz, x, y, z, j); /* x - v_j */
+                            if (mask[iz] == 0) {
+                                double uz[3];
+                                load_u(&L, n, iz, u, uz);
+                                double fz = feq(&L, j, rho[iz], uz) - a * feo(&L, j, rho[iz], uz);
+                                fb = 2.0 * qq * fs + (1.0 - 2.0 * qq) * fz;
+                            }
+                        } else {
+                            double fi = feq(&L, i, rx, ux) - a * feo(&L, i, rx, ux);
+                            fb = fs / (2.0 * qq) + (1.0 - 1.0 / (2.0 * qq)) * fi;
+                        }
+                    }
+                    double p[3];
+                    for (int k = 0; k < 3; ++k) p[k] = L.v[j][k] * (fs + fb);
+                    double r[3] = {x - xc[0], y - xc[1], z - xc[2]};
+                    for (int k = 0; k < 3; ++k) out[k] += p[k];
+                    out[3] += r[1] * p[2] - r[2] * p[1];
+                    out[4] += r[2] * p[0] - r[0] * p[2];
+                    out[5] += r[0] * p[1] - r[1] * p[0];
+                }
             }
     return 0;
 }
