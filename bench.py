@@ -81,14 +81,28 @@ def _cavity_leg(args, L, wl, dev, stream):
                  torch.zeros((3, c4.nz, c4.ny, c4.nx), device=dev))
     s4.step(args.warmup)
     dt4 = _events_time(s4.step, args.steps, stream)
+    # momentum-exchange force and torque on the walls at rest (mask id 1;
+    # lwacm_wall_force): one pass over the grid and a fixed-order FP64 sum,
+    # host-synchronised
+    import time
+    c = (c4.nx - 1) / 2.0
+    s4.wall_force(1, (c, c, c))
+    t0 = time.perf_counter()
+    for _ in range(10):
+        f_w, t_w = s4.wall_force(1, (c, c, c))
+    ms_force = (time.perf_counter() - t0) / 10 * 1e3
     s4.close()
     fluid4 = (c4.nx - 2) * (c4.ny - 2) * (c4.nz - 2)
     ms4 = dt4 / args.steps * 1e3
-    print(f"[bench] cavity 192^3: {ms4:.4f} ms/step", file=sys.stderr, flush=True)
+    print(f"[bench] cavity 192^3: {ms4:.4f} ms/step; wall force {ms_force:.3f} ms per call",
+          file=sys.stderr, flush=True)
     return {"value": round(fluid4 * args.steps / dt4 / 1e6, 1), "unit": "MLUPS (fluid nodes)",
             "ms_per_step": round(ms4, 5), "omega": c4.omega, "lid": list(c4.lid),
             "achieved_GBs": round(36.0 * c4.nx * c4.ny * c4.nz / (ms4 * 1e-3) / 1e9, 1),
             "basis": "36 B per node: state in and out, 32-bit solid-link set",
+            "wall_force_ms": round(ms_force, 4),
+            "walls_at_rest_force": [round(v, 8) for v in f_w],
+            "walls_at_rest_torque": [round(v, 8) for v in t_w],
             "kernel": "k_fwd_march_rolled<float,64,false,true,false,0>",
             "traffic": _measured_traffic("k_fwd_march_rolled<float,64,false,true,false,0>")}
 

@@ -219,6 +219,27 @@ int lwacm_set_force_field(lwacm_ctx *c, const float *d_g);
 int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
                       const float *h_wall_T, int n_wall_T);
 
+/* Force and torque that the fluid exerts on the walls with mask id wall_id,
+ * by momentum exchange (Section "Moving complex boundaries", Eqs. MEA3, MEA4
+ * and MEA5), from the current state.  Every link j from a fluid node x to a
+ * solid node x + v_j of that id contributes
+ *   p_j = v_j [f*_j(x) + f**_BB(j)(x)],
+ * f*_j the pre-combined population x sends into the wall and f**_BB(j) the
+ * one the wall returns before post-combining: f*_j itself for halfway walls,
+ * the interpolation of Eq. ACM2.0cc when lwacm_init was given d_q (bodies at
+ * rest: no wall-motion term).  F = sum p_j, T = sum (x - x_c) x p_j, x the node
+ * the link starts from, in lattice units (node coordinates; the hydrostatic
+ * part rho/3 per wall node is included; the diffusive-scaling forms MEA6 and
+ * MEA7 are the caller's).  Summed in FP64 in a fixed order.
+ *   wall_id   1..255: the mask id of the body.
+ *   h_center  host double[3], the point x_c (NULL: the origin).
+ *   h_out     host double[6]: F_x, F_y, F_z, T_x, T_y, T_z (D2Q9: F_z = T_x =
+ *             T_y = 0).
+ * Synchronises the context's stream.  Allocates a small device buffer on its
+ * first call.  LWACM_EINVAL without a mask or for a bad id or pointer,
+ * LWACM_EUNSUPPORTED with FP16 storage. */
+int lwacm_wall_force(lwacm_ctx *c, int wall_id, const double *h_center, double *h_out);
+
 /* Device pointer of the buffer that holds T at the current step (one of the
  * two given to lwacm_set_thermal).  LWACM_EINVAL when the temperature is off. */
 int lwacm_temperature(lwacm_ctx *c, float **d_T);

@@ -10,6 +10,7 @@
 #include "lwacm.h"
 #include "lwacm_internal.hpp"
 #include "lwacm_thermal.hpp"
+#include "lwacm_force.hpp"
 
 using lwacm::ProblemArgs;
 using lwacm::ReduceArgs;
@@ -49,6 +50,7 @@ struct lwacm_ctx {
     float *T_buf[2];
     int tcur;
     lwacm::ThermalArgs targs;
+    double *d_force;  // wall-force partials and result (allocated on first use)
 };
 
 namespace {
@@ -149,6 +151,8 @@ void free_scratch(lwacm_ctx *c)
     if (c->d_cls) (void)hipFree(c->d_cls);
     if (c->d_bits) (void)hipFree(c->d_bits);
     if (c->d_wallg) (void)hipFree(c->d_wallg);
+    if (c->d_force) (void)hipFree(c->d_force);
+    c->d_force = nullptr;
     c->d_cls = nullptr;
     c->d_bits = nullptr;
     c->d_wallg = nullptr;
@@ -397,6 +401,39 @@ int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
     c->tcur = 0;
     c->thermal = true;
     return LWACM_OK;
+}
+
+int lwacm_wall_force(lwacm_ctx *c, int wall_id, const double *h_center, double *h_out)
+{
+    if (!c || !h_out || !c->p.mask || wall_id < 1 || wall_id > 255) return LWACM_EINVAL;
+    if (c->storage != LWACM_FP32) return LWACM_EUNSUPPORTED;
+    if (!c->d_force) {
+        if (hipMalloc(&c->d_force, sizeof(double) * 6 * (lwacm::kForceMaxBlocks + 1)) != hipSuccess) {
+            c->d_force = nullptr;
+            return LWACM_ENOMEM;
+        }
+    }
+    lwacm::ForceArgs f;
+    f.Q = c->p.Q;
+    f.nx = c->p.nx;
+    f.ny = c->p.ny;
+    f.nz = c->p.nz;
+    f.A = c->p.A;
+    f.state = static_cast<const float *>(c->buf[c->cur]);
+    f.mask = c->p.mask;
+    f.qd = c->p.qd;
+    f.wall_id = wall_id;
+    for (int k = 0; k < 3; ++k) f.xc[k] = h_center ? h_center[k] : 0.0;
+    f.partials = c->d_force + 6;
+    f.out = c->d_force;
+    const long long n = (long long)c->p.nx * c->p.ny * c->p.nz;
+    long long nb = (n + lwacm::kForceBlock - 1) / lwacm::kForceBlock;
+    if (nb > (long long)lwacm::kForceMaxBlocks) nb = lwacm::kForceMaxBlocks;
+    if (lwacm::launch_wall_force(f, (unsigned)nb, c->stream) != hipSuccess) return LWACM_EDEVICE;
+    if (hipMemcpyAsync(h_out, c->d_force, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+        hipSuccess)
+        return LWACM_EDEVICE;
+    return dev_err(hipStreamSynchronize(c->stream));
 }
 
 int lwacm_temperature(lwacm_ctx *c, float **d_T)

@@ -64,6 +64,7 @@ def load_library():
         "lwacm_set_force_field": (i, [_vp, _vp]),
         "lwacm_set_thermal": (i, [_vp, d, _vp, _vp, _vp, i]),
         "lwacm_temperature": (i, [_vp, ctypes.POINTER(_vp)]),
+        "lwacm_wall_force": (i, [_vp, i, dp, dp]),
         "lwacm_set_state": (i, [_vp, _vp, _vp]),
         "lwacm_step": (i, [_vp, i]),
         "lwacm_diagnostics": (i, [_vp, dp, dp]),
@@ -173,6 +174,15 @@ def lwacm_temperature(ctx) -> int:
     out = _vp()
     _check(load_library().lwacm_temperature(ctx, ctypes.byref(out)), "lwacm_temperature")
     return out.value
+
+
+def lwacm_wall_force(ctx, wall_id: int, center=(0.0, 0.0, 0.0)):
+    """(F[3], T[3]) on the walls with mask id ``wall_id`` (momentum exchange),
+    torque about ``center`` (node coordinates x, y, z)."""
+    c = (ctypes.c_double * 3)(*[float(v) for v in (list(center) + [0.0, 0.0, 0.0])[:3]])
+    out = (ctypes.c_double * 6)()
+    _check(load_library().lwacm_wall_force(ctx, int(wall_id), c, out), "lwacm_wall_force")
+    return list(out[:3]), list(out[3:])
 
 
 def lwacm_set_variant(ctx, variant: int):
@@ -347,6 +357,10 @@ class Solver:
         b = torch.empty_like(a)
         lwacm_set_thermal(self.ctx, omega_t, a, b, wall_T)
         self._T = (a, b)
+
+    def wall_force(self, wall_id: int, center=(0.0, 0.0, 0.0)):
+        """Force and torque (lattice units) on the walls with mask id wall_id."""
+        return lwacm_wall_force(self.ctx, wall_id, center)
 
     def temperature(self) -> torch.Tensor:
         """A copy of T at the current step, (nz, ny, nx) float32."""
