@@ -32,6 +32,7 @@
  *    beyond the call unless stated.
  *  - Errors: calls return LWACM_OK (0) or a negative code; no C++
  *    exception crosses the ABI.  A failed launch returns LWACM_EDEVICE.
+ *    The one positive code, LWACM_WOMEGA, is a success with a warning.
  *    lwacm_strerror() names every code.
  */
 #ifndef LWACM_H
@@ -56,7 +57,12 @@ enum {
     LWACM_ENOMEM = -2,      /* the library could not allocate its scratch */
     LWACM_EDEVICE = -3,     /* a HIP call or kernel launch failed */
     LWACM_ENONFINITE = -4,  /* mass or kinetic energy is not finite (blow-up) */
-    LWACM_EUNSUPPORTED = -5 /* valid request this build does not implement */
+    LWACM_EUNSUPPORTED = -5, /* valid request this build does not implement */
+    /* Success with a warning: a relaxation frequency (omega, omega_p or
+     * omega_t) below 1.  The paper finds the method stable for 1 <= omega < 2
+     * (Section "Physical and lattice units", after Eq. viscosity2); smaller values are accepted and the
+     * call has taken effect. */
+    LWACM_WOMEGA = 1
 };
 
 /* Rounding of step outputs into FP16 storage (lwacm_set_fp16_rounding). */
@@ -85,8 +91,11 @@ size_t lwacm_state_bytes(int lattice, int nx, int ny, int nz, int storage);
  *
  *  lattice      LWACM_D2Q9 or LWACM_D3Q19 (Appendix A).
  *  nx, ny, nz   grid size, each >= 1; nz must be 1 for D2Q9.
- *  omega        0 < omega < 2 (the paper finds LW-ACM stable for
- *               1 <= omega < 2; smaller values are accepted).
+ *  omega        0 < omega < 2, else LWACM_EINVAL.  The paper finds LW-ACM
+ *               stable for 1 <= omega < 2; 0 < omega < 1 is accepted and
+ *               the call returns LWACM_WOMEGA (a success) instead of
+ *               LWACM_OK.  The kernels use a = 1 - h and A = 3 h with
+ *               h = 2/omega - 1 rounded as lwacm_coefficients states.
  *  storage      LWACM_FP32 or LWACM_FP16_DEV.
  *  d_state_a/b  two caller-owned device buffers of lwacm_state_bytes() bytes
  *               (the two toggled arrays); kept until lwacm_destroy.  The
@@ -118,12 +127,23 @@ size_t lwacm_state_bytes(int lattice, int nx, int ny, int nz, int storage);
  *  h_g          host body acceleration g[3] (Eq. force), or NULL; copied.
  *  stream       HIP stream every call of this context is issued on.
  *
- * On success *out holds the context; on failure *out is NULL.  The call
- * synchronises the stream once (mask validation).
+ * On success (LWACM_OK or LWACM_WOMEGA) *out holds the context; on failure
+ * *out is NULL.  The call synchronises the stream once (mask validation).
  */
 int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omega, int storage,
                void *d_state_a, void *d_state_b, const uint8_t *d_mask, const float *h_wall_u,
                int n_wall_ids, const float *d_q, const float *h_g, hipStream_t stream);
+
+/* The FP32 coefficients the kernels use for omega (host only, no device
+ * work): a = 2 - 2/omega, the post-combine factor of Eq. ACM2.0, and
+ * A = 3 (2/omega - 1), the odd-part factor of the pre-combined link term
+ * (Eqs. ACM2.0b).  Both come from h = 2/omega - 1 rounded to a multiple of
+ * the finest power of two q for which 1 - h and 3 h are both FP32 numbers,
+ * so a = 1 - h and A = 3 h exactly and a + A/3 = 1 (a uniform state is then a
+ * fixed point of the FP32 step); h moves by at most q/2 (at most 2^-23 for
+ * 1 <= omega < 2).  Returns LWACM_EINVAL for a null pointer or omega outside
+ * (0, 2), LWACM_WOMEGA for omega < 1, else LWACM_OK. */
+int lwacm_coefficients(double omega, float *a, float *A);
 
 /* FP16 storage scales: stored value = field * 2^k (k_rho for rho - 1, k_u for
  * u).  0 <= k <= 24.  Takes effect at the next lwacm_set_state. */
@@ -164,8 +184,8 @@ int lwacm_set_march_chunk(lwacm_ctx *c, int planes);
  * pseudo-compressibility term of the continuity equation then scales with
  * 1/nu(omega_p) (Eq. viscosity2), so nu(omega_p) > nu(omega) reduces the
  * compressibility error of under-resolved runs.  0 < omega_p < 2, else
- * LWACM_EINVAL; omega_p == omega (the default after lwacm_init) is the
- * single-relaxation step; omega_p != omega with link-wall distances (d_q)
+ * LWACM_EINVAL (omega_p < 1: LWACM_WOMEGA, a success); omega_p == omega
+ * (the default after lwacm_init) is the single-relaxation step; omega_p != omega with link-wall distances (d_q)
  * gives LWACM_EUNSUPPORTED.  With omega_p != omega the forward step runs on the
  * single-step tile kernel (D3Q19 without walls, nz >= 8) or else on the
  * generic kernel (every lattice, walls and force allowed), never on the
@@ -197,7 +217,8 @@ int lwacm_set_force_field(lwacm_ctx *c, const float *d_g);
  * flow.  From this call on every lwacm_step also advances T by one step per
  * flow step, reading the flow state of the step's starting time.
  *   omega_t   relaxation frequency, 0 < omega_t < 2 (stable for
- *             1 <= omega_t < 2 as the appendix notes).
+ *             1 <= omega_t < 2 as the appendix notes; omega_t < 1 returns
+ *             LWACM_WOMEGA, a success).
  *   d_T_a, d_T_b  two distinct caller-owned device buffers of nx*ny*nz FP32
  *             values (node index as the state's), kept alive while the
  *             temperature is on; d_T_a holds T now.  Steps write them in
@@ -237,7 +258,8 @@ int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
  *             T_y = 0).
  * Synchronises the context's stream.  Allocates a small device buffer on its
  * first call.  LWACM_EINVAL without a mask or for a bad id or pointer,
- * LWACM_EUNSUPPORTED with FP16 storage. */
+ * LWACM_EUNSUPPORTED with FP16 storage or for an id with a non-zero wall
+ * velocity (the paper states the exchange for bodies at rest). */
 int lwacm_wall_force(lwacm_ctx *c, int wall_id, const double *h_center, double *h_out);
 
 /* Device pointer of the buffer that holds T at the current step (one of the
@@ -335,6 +357,7 @@ int lwacm_adjoint_step2(lwacm_ctx *c, const void *d_state_t, const void *d_state
 
 /* Release the library's scratch.  Caller buffers are untouched. */
 void lwacm_destroy(lwacm_ctx *c);
+
 
 /* Static text for an error code. */
 const char *lwacm_strerror(int code);

@@ -38,6 +38,7 @@ class _Run(torch.autograd.Function):
         ctx.nsteps, ctx.K = nsteps, K
         ctx.omega_is_tensor = torch.is_tensor(omega)
         ctx.omega_shape = omega.shape if torch.is_tensor(omega) else None
+        ctx.omega_dtype = omega.dtype if torch.is_tensor(omega) else None
         return drho_T, u_T
 
     @staticmethod
@@ -80,7 +81,8 @@ class _Run(torch.autograd.Function):
         grad_u0 = mu[1:].clone()
         grad_omega = None
         if ctx.omega_is_tensor:
-            grad_omega = dw.to(torch.float32).reshape(ctx.omega_shape)
+            # accumulated in FP64 on the device; handed back in omega's own dtype
+            grad_omega = dw.to(ctx.omega_dtype).reshape(ctx.omega_shape)
         solver.close()
         ctx.solver = None
         return (grad_drho0, grad_u0, grad_omega, None, None, None, None, None, None, None, None)
@@ -94,7 +96,12 @@ def lwacm_run(drho0: torch.Tensor, u0: torch.Tensor, omega, nsteps: int, lattice
 
     ``drho0`` has shape (nz, ny, nx), ``u0`` shape (D, nz, ny, nx) (float32,
     on the GPU); ``omega`` is a float or a 0-dim tensor (then it receives
-    dL/domega).  Gradients reach ``drho0``, ``u0`` and ``omega``.
+    dL/domega in its own dtype).  Gradients reach ``drho0``, ``u0`` and
+    ``omega``.  With moving walls, the density rho0 of the wall term (Eq.
+    ACM2.0ccccbb: the mean fluid density, computed once from the initial state)
+    is a constant of the problem, as the paper holds it: dL/d(drho0) is the
+    derivative through the steps with rho0 fixed, and carries no term from
+    rho0's own dependence on drho0.
     """
     if nsteps < 0 or K < 1:
         raise ValueError("nsteps must be >= 0 and K >= 1")

@@ -60,16 +60,23 @@ int dev_err(hipError_t e)
     return e == hipSuccess ? LWACM_OK : LWACM_EDEVICE;
 }
 
-// h = 2/omega - 1 on a grid fine enough that 1 - h and 3 h are both exact in
-// FP32 (so a + A/3 = 1 holds exactly and the link terms conserve momentum to
+// h = 2/omega - 1 rounded to a multiple of the finest power of two q for
+// which 1 - h and 3 h are both FP32 numbers, so that a = 1 - h and A = 3 h
+// hold exactly and a + A/3 = 1 (the link terms then conserve momentum to
 // rounding; a mismatch of ~1e-8 would act like a source term every step).
-// The relative change of the viscosity nu = h/6 is at most 2^-25 / h.
+// The quantum follows the FP32 spacing of 3 h and of 1 - h: 2^-24 or 2^-23
+// for 1 <= omega < 2, coarser for omega < 1 where h > 1.  h moves by at most
+// q / 2, a relative change of nu = h/6 of at most q / (2 h).
 double quantised_h(double omega)
 {
     const double h = 2.0 / omega - 1.0;
-    const double quantum = fabs(h) < 0.25 ? ldexp(1.0, -24)
-                           : (fabs(h) < 0.5 ? ldexp(1.0, -23) : ldexp(1.0, -22));
-    return nearbyint(h / quantum) * quantum;
+    for (int e = -40; e <= 8; ++e) {
+        const double q = ldexp(1.0, e);
+        const double hq = nearbyint(h / q) * q;
+        if ((double)(float)(1.0 - hq) == 1.0 - hq && (double)(float)(3.0 * hq) == 3.0 * hq)
+            return hq;
+    }
+    return h;  // not reached for 0 < omega < 2
 }
 
 void set_wall_terms(lwacm_ctx *c)
@@ -183,6 +190,9 @@ const char *lwacm_strerror(int code)
     case LWACM_EDEVICE: return "HIP runtime or kernel launch error";
     case LWACM_ENONFINITE: return "non-finite mass or kinetic energy (unstable run)";
     case LWACM_EUNSUPPORTED: return "not supported by this build";
+    case LWACM_WOMEGA:
+        return "success, with a warning: relaxation frequency below 1 (the method is stable "
+               "for 1 <= omega < 2)";
     default: return "unknown error code";
     }
 }
@@ -319,7 +329,16 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
         return LWACM_EDEVICE;
     }
     *out = c;
-    return LWACM_OK;
+    return omega < 1.0 ? LWACM_WOMEGA : LWACM_OK;
+}
+
+int lwacm_coefficients(double omega, float *a, float *A)
+{
+    if (!a || !A || !(omega > 0.0 && omega < 2.0)) return LWACM_EINVAL;
+    const double hq = quantised_h(omega);
+    *a = (float)(1.0 - hq);
+    *A = (float)(3.0 * hq);
+    return omega < 1.0 ? LWACM_WOMEGA : LWACM_OK;
 }
 
 int lwacm_set_fp16_scales(lwacm_ctx *c, int k_rho, int k_u)
@@ -370,7 +389,7 @@ int lwacm_set_omega_p(lwacm_ctx *c, double omega_p)
     c->p.Ap = Ap;
     c->p.split = c->p.Ap != c->p.A;
     set_wall_terms(c);
-    return LWACM_OK;
+    return omega_p < 1.0 ? LWACM_WOMEGA : LWACM_OK;
 }
 
 int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
@@ -400,13 +419,17 @@ int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
     c->T_buf[1] = d_T_b;
     c->tcur = 0;
     c->thermal = true;
-    return LWACM_OK;
+    return omega_t < 1.0 ? LWACM_WOMEGA : LWACM_OK;
 }
 
 int lwacm_wall_force(lwacm_ctx *c, int wall_id, const double *h_center, double *h_out)
 {
     if (!c || !h_out || !c->p.mask || wall_id < 1 || wall_id > 255) return LWACM_EINVAL;
     if (c->storage != LWACM_FP32) return LWACM_EUNSUPPORTED;
+    // momentum exchange as the paper states it covers bodies at rest
+    if (wall_id < c->n_wall_ids)
+        for (int k = 0; k < 3; ++k)
+            if (c->wall_u[wall_id][k] != 0.0f) return LWACM_EUNSUPPORTED;
     if (!c->d_force) {
         if (hipMalloc(&c->d_force, sizeof(double) * 6 * (lwacm::kForceMaxBlocks + 1)) != hipSuccess) {
             c->d_force = nullptr;

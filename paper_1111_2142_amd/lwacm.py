@@ -7,6 +7,7 @@ fallback: without the built library every call raises.
 """
 import ctypes
 import os
+import warnings
 from typing import Optional, Sequence, Tuple
 
 import torch
@@ -18,6 +19,7 @@ LWACM_D2Q9, LWACM_D3Q19 = 9, 19
 LWACM_FP32, LWACM_FP16_DEV = 0, 1
 LWACM_OK, LWACM_EINVAL, LWACM_ENOMEM, LWACM_EDEVICE, LWACM_ENONFINITE, LWACM_EUNSUPPORTED = (
     0, -1, -2, -3, -4, -5)
+LWACM_WOMEGA = 1  # success with a warning: a relaxation frequency below 1
 LWACM_KERNEL_AUTO, LWACM_KERNEL_GENERIC, LWACM_KERNEL_MARCH, LWACM_KERNEL_MARCH2 = 0, 1, 2, 3
 LWACM_ROUND_NEAREST, LWACM_ROUND_STOCHASTIC = 0, 1
 
@@ -78,6 +80,8 @@ def load_library():
         "lwacm_adjoint_step": (i, [_vp, _vp, _vp, _vp, _vp, i]),
         "lwacm_adjoint_step2": (i, [_vp, _vp, _vp, _vp, _vp, _vp, i]),
         "lwacm_destroy": (None, [_vp]),
+        "lwacm_coefficients": (i, [d, ctypes.POINTER(ctypes.c_float),
+                                   ctypes.POINTER(ctypes.c_float)]),
         "lwacm_strerror": (ctypes.c_char_p, [i]),
     }
     for name, (res, args) in sig.items():
@@ -88,7 +92,15 @@ def load_library():
     return lib
 
 
+class LWACMOmegaWarning(UserWarning):
+    """A relaxation frequency below 1: accepted, outside the range 1 <= omega < 2
+    where the paper finds the method stable."""
+
+
 def _check(code: int, where: str):
+    if code == LWACM_WOMEGA:
+        warnings.warn(f"{where}: {lwacm_strerror(code)}", LWACMOmegaWarning, stacklevel=3)
+        return
     if code != LWACM_OK:
         raise LWACMError(code, where)
 
@@ -264,6 +276,15 @@ def lwacm_adjoint_step2(ctx, state_t: torch.Tensor, state_tm1: torch.Tensor, mu_
 def lwacm_destroy(ctx):
     if ctx:
         load_library().lwacm_destroy(ctx)
+
+
+def lwacm_coefficients(omega: float) -> Tuple[float, float]:
+    """(a, A): the FP32 coefficients the kernels use for omega (host only)."""
+    a, A = ctypes.c_float(), ctypes.c_float()
+    _check(load_library().lwacm_coefficients(float(omega), ctypes.byref(a), ctypes.byref(A)),
+           "lwacm_coefficients")
+    return a.value, A.value
+
 
 
 # ------------------------------------------------------------- Solver
