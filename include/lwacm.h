@@ -58,6 +58,7 @@ enum {
     LWACM_EDEVICE = -3,     /* a HIP call or kernel launch failed */
     LWACM_ENONFINITE = -4,  /* mass or kinetic energy is not finite (blow-up) */
     LWACM_EUNSUPPORTED = -5, /* valid request this build does not implement */
+    LWACM_ESCRATCH = -6,     /* lwacm_step_static: problem beyond its fixed scratch */
     /* Success with a warning: a relaxation frequency (omega, omega_p or
      * omega_t) below 1.  The paper finds the method stable for 1 <= omega < 2
      * (Section "Physical and lattice units", after Eq. viscosity2); smaller values are accepted and the
@@ -358,6 +359,46 @@ int lwacm_adjoint_step2(lwacm_ctx *c, const void *d_state_t, const void *d_state
 /* Release the library's scratch.  Caller buffers are untouched. */
 void lwacm_destroy(lwacm_ctx *c);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): nsteps
+ * forward steps of a periodic problem without walls or forcing in FP32
+ * storage, with no context and no allocation.  The result is bitwise that of
+ *     lwacm_init(lattice, nx, ny, nz, omega, LWACM_FP32, a, b, NULL, NULL, 0,
+ *                NULL, NULL, stream), state in a, lwacm_step(ctx, nsteps)
+ * (same kernels, same two-steps-per-launch pairing), including the FP64
+ * mass and energy of the last step.
+ *   lattice, nx, ny, nz, omega   as for lwacm_init (omega < 1 gives
+ *               LWACM_WOMEGA after the steps ran).
+ *   d_state_a   caller-owned device buffer of lwacm_state_bytes(..., LWACM_FP32)
+ *               bytes holding the state, node-interleaved: rho - 1, u_x, u_y
+ *               (, u_z) of node i at floats (D+1)*i ..
+ *   d_state_b   a second buffer of the same size (distinct).  The steps
+ *               toggle the two buffers once per launch (a launch runs one or
+ *               two steps), so which of them ends with the result depends
+ *               on the kernels: *h_state_out names it.
+ *   d_diag      device double[2], or NULL: receives, once the call's work
+ *               has run, the mass deviation sum(rho - 1) and the kinetic
+ *               energy 1/2 sum|u|^2 of the last step's output (FP64,
+ *               fixed-order sums; mass = nodes + d_diag[0]).
+ *   h_state_out host pointer that receives d_state_a or d_state_b: the
+ *               buffer holding the state after the last step (d_state_a when
+ *               nsteps == 0).  The other one holds an earlier state.  May be
+ *               NULL.
+ *   stream      HIP stream of every launch; the call is asynchronous.
+ * Scratch: the per-block partial sums live in a fixed device array of
+ * 8 * 8192 + 2 doubles (about 512 KiB) that each GPU holds for the life of
+ * the process; problems whose kernels need more than 8192 blocks get
+ * LWACM_ESCRATCH before anything is launched (the D3Q19 tile kernels use
+ * (nx/32)(ny/16)ceil(nz/depth) blocks: 256^3 needs 256).  Every call on a
+ * GPU shares that GPU's array and leaves its last contents there; calls
+ * that overlap in time on one GPU (other streams or threads) race on it and
+ * must be serialised by the caller.  Nothing in it needs to start at zero.
+ * LWACM_EINVAL for bad sizes, omega or buffers.
+ */
+int lwacm_step_static(int lattice, int nx, int ny, int nz, double omega, float *d_state_a,
+                      float *d_state_b, int nsteps, double *d_diag, float **h_state_out,
+                      hipStream_t stream);
 
 /* Static text for an error code. */
 const char *lwacm_strerror(int code);

@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "lwacm.h"
@@ -170,6 +171,41 @@ void free_scratch(lwacm_ctx *c)
 
 }  // namespace
 
+// Fixed scratch of lwacm_step_static: the per-block FP64 partial sums of the
+// forward steps (four sets of two doubles per block: a launch of one or two
+// steps and the launch before it whose second passes it finishes) and two
+// doubles for the mass and energy when the caller passes no d_diag.  Each
+// device holds its own copy for the life of the process; host code reaches
+// it only through the address hipGetSymbolAddress returns on that device.
+constexpr size_t kStaticMaxBlocks = 8192;
+constexpr size_t kStaticScratchDoubles = 8 * kStaticMaxBlocks + 2;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+
+constexpr int kStaticMaxDevices = 64;
+std::mutex g_static_mu;
+double *g_static_scratch[kStaticMaxDevices];
+
+// Device address of this device's copy of `scratch`, looked up once per device.
+int static_scratch(double **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LWACM_EDEVICE;
+    if (dev < 0 || dev >= kStaticMaxDevices) return LWACM_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return LWACM_EDEVICE;
+        g_static_scratch[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_static_scratch[dev];
+    return LWACM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t lwacm_state_bytes(int lattice, int nx, int ny, int nz, int storage)
@@ -190,6 +226,7 @@ const char *lwacm_strerror(int code)
     case LWACM_EDEVICE: return "HIP runtime or kernel launch error";
     case LWACM_ENONFINITE: return "non-finite mass or kinetic energy (unstable run)";
     case LWACM_EUNSUPPORTED: return "not supported by this build";
+    case LWACM_ESCRATCH: return "problem too large for the fixed scratch of lwacm_step_static";
     case LWACM_WOMEGA:
         return "success, with a warning: relaxation frequency below 1 (the method is stable "
                "for 1 <= omega < 2)";
@@ -706,6 +743,66 @@ void lwacm_destroy(lwacm_ctx *c)
     if (!c) return;
     free_scratch(c);
     delete c;
+}
+
+int lwacm_step_static(int lattice, int nx, int ny, int nz, double omega, float *d_state_a,
+                      float *d_state_b, int nsteps, double *d_diag, float **h_state_out,
+                      hipStream_t stream)
+{
+    if (lwacm_state_bytes(lattice, nx, ny, nz, LWACM_FP32) == 0 || nsteps < 0) return LWACM_EINVAL;
+    if (!(omega > 0.0 && omega < 2.0)) return LWACM_EINVAL;
+    if (!d_state_a || !d_state_b || d_state_a == d_state_b) return LWACM_EINVAL;
+    // a context on the stack: the problem of lwacm_init without mask, walls
+    // or force, in FP32 storage, with the kernels lwacm_step chooses for it
+    lwacm_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.lattice = lattice;
+    c.storage = LWACM_FP32;
+    c.variant = LWACM_KERNEL_AUTO;
+    c.omega = omega;
+    c.omega_p = omega;
+    c.rho0 = 1.0;
+    c.buf[0] = d_state_a;
+    c.buf[1] = d_state_b;
+    c.stream = stream;
+    ProblemArgs &p = c.p;
+    p.Q = lattice;
+    p.D = lattice == LWACM_D2Q9 ? 2 : 3;
+    p.nx = nx;
+    p.ny = ny;
+    p.nz = nz;
+    p.n = (long long)nx * ny * nz;
+    const double hq = quantised_h(omega);
+    p.a = (float)(1.0 - hq);
+    p.A = (float)(3.0 * hq);
+    p.Ap = p.A;
+    c.a_exact = 1.0 - hq;
+    set_scales(&c);
+    set_wall_terms(&c);
+    if (lwacm::march_supported(p)) {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 256;
+        p.march_nzc = lwacm::march_choose_nzc(p, ncu);
+    }
+    // the partial sets of the kernels lwacm_step may launch must fit the scratch
+    size_t nb = lwacm::generic_grid(p.n);
+    const size_t mb = lwacm::march_num_blocks(p);
+    if (mb > nb) nb = mb;
+    const size_t fb = lwacm::march2_num_blocks(p);
+    if (fb > nb) nb = fb;
+    if (nb > kStaticMaxBlocks) return LWACM_ESCRATCH;
+    double *base = nullptr;
+    const int rc = static_scratch(&base);
+    if (rc != LWACM_OK) return rc;
+    c.d_partials = base;
+    c.n_partial_blocks = nb;
+    c.d_diag = d_diag ? d_diag : base + 8 * kStaticMaxBlocks;
+    c.n_fluid = (unsigned long long)p.n;
+    const int code = lwacm_step(&c, nsteps);
+    if (code == LWACM_OK && h_state_out) *h_state_out = static_cast<float *>(c.buf[c.cur]);
+    return (code == LWACM_OK && omega < 1.0) ? LWACM_WOMEGA : code;
 }
 
 }  // extern "C"

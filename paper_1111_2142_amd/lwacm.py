@@ -19,6 +19,7 @@ LWACM_D2Q9, LWACM_D3Q19 = 9, 19
 LWACM_FP32, LWACM_FP16_DEV = 0, 1
 LWACM_OK, LWACM_EINVAL, LWACM_ENOMEM, LWACM_EDEVICE, LWACM_ENONFINITE, LWACM_EUNSUPPORTED = (
     0, -1, -2, -3, -4, -5)
+LWACM_ESCRATCH = -6
 LWACM_WOMEGA = 1  # success with a warning: a relaxation frequency below 1
 LWACM_KERNEL_AUTO, LWACM_KERNEL_GENERIC, LWACM_KERNEL_MARCH, LWACM_KERNEL_MARCH2 = 0, 1, 2, 3
 LWACM_ROUND_NEAREST, LWACM_ROUND_STOCHASTIC = 0, 1
@@ -82,6 +83,7 @@ def load_library():
         "lwacm_destroy": (None, [_vp]),
         "lwacm_coefficients": (i, [d, ctypes.POINTER(ctypes.c_float),
                                    ctypes.POINTER(ctypes.c_float)]),
+        "lwacm_step_static": (i, [i, i, i, i, d, _vp, _vp, i, _vp, ctypes.POINTER(_vp), _vp]),
         "lwacm_strerror": (ctypes.c_char_p, [i]),
     }
     for name, (res, args) in sig.items():
@@ -285,6 +287,22 @@ def lwacm_coefficients(omega: float) -> Tuple[float, float]:
            "lwacm_coefficients")
     return a.value, A.value
 
+
+def lwacm_step_static(lattice: int, nx: int, ny: int, nz: int, omega: float,
+                      state_a: torch.Tensor, state_b: torch.Tensor, nsteps: int,
+                      diag: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """nsteps periodic FP32 steps with no context and no allocation; the state
+    (node-interleaved FP32) starts in state_a.  Returns whichever of state_a
+    and state_b holds the state after the last step.  diag: optional device
+    float64 tensor of 2 elements (mass deviation, energy)."""
+    if stream is None:
+        stream = _stream_handle(state_a.device)
+    out = _vp()
+    _check(load_library().lwacm_step_static(lattice, nx, ny, nz, float(omega), _ptr(state_a),
+                                            _ptr(state_b), int(nsteps), _ptr(diag),
+                                            ctypes.byref(out), stream),
+           "lwacm_step_static")
+    return state_a if out.value == state_a.data_ptr() else state_b
 
 
 # ------------------------------------------------------------- Solver

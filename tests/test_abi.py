@@ -51,11 +51,11 @@ def test_state_bytes(lib):
 def test_strerror_names_every_code(lib):
     from paper_1111_2142_amd import lwacm as L
     seen = set()
-    for code in list(range(0, -6, -1)) + [L.LWACM_WOMEGA]:
+    for code in list(range(0, -7, -1)) + [L.LWACM_WOMEGA]:
         s = L.lwacm_strerror(code)
         assert s and s != "unknown error code"
         seen.add(s)
-    assert len(seen) == 7
+    assert len(seen) == 8
     assert L.lwacm_strerror(-99) == "unknown error code"
 
 
@@ -82,6 +82,16 @@ def test_coefficients_make_a_plus_A_over_3_exactly_one(lib):
     assert lib.lwacm_coefficients(2.0, ctypes.byref(ctypes.c_float()),
                                   ctypes.byref(ctypes.c_float())) == L.LWACM_EINVAL
     assert lib.lwacm_coefficients(1.5, None, None) == L.LWACM_EINVAL
+
+
+def test_step_static_rejects_bad_arguments_before_device_work(lib):
+    from paper_1111_2142_amd import lwacm as L
+    fa, fb = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    assert lib.lwacm_step_static(19, 8, 8, 8, 2.0, fa, fb, 1, None, None, None) == L.LWACM_EINVAL
+    assert lib.lwacm_step_static(19, 8, 8, 8, 1.5, None, fb, 1, None, None, None) == L.LWACM_EINVAL
+    assert lib.lwacm_step_static(19, 8, 8, 8, 1.5, fa, fa, 1, None, None, None) == L.LWACM_EINVAL
+    assert lib.lwacm_step_static(9, 8, 8, 2, 1.5, fa, fb, 1, None, None, None) == L.LWACM_EINVAL
+    assert lib.lwacm_step_static(19, 8, 8, 8, 1.5, fa, fb, -1, None, None, None) == L.LWACM_EINVAL
 
 
 def test_init_rejects_bad_arguments_before_device_work(lib):
