@@ -281,3 +281,31 @@ def test_gradient_with_zero_steps_is_identity():
     _, u_T = lwacm_run(to_dev(drho), u0_t, 1.6, 0, 9, K=4)
     (u_T * to_dev(u_tgt)).sum().backward()
     assert np.allclose(u0_t.grad.cpu().numpy(), u_tgt.astype(np.float32), rtol=0, atol=1e-7)
+
+
+def test_gradient_512_full_length_matches_stored_oracle(golden_dir):
+    """The differentiable 512x512 workload at its configured length: 2000
+    steps, a checkpoint every 100 (seeded k <= 8 fields, omega 1.6).  GPU
+    gradient with respect to u0, rho0 - 1 and omega against the FP64 oracle's
+    reverse sweep stored by tests/golden/make_c5_gradient_reference.py."""
+    import os
+    c = wl.ADJOINT_512
+    ref = np.load(os.path.join(golden_dir, "c5_gradient_512_steps2000_K100.npz"))
+    banner("gradient 512x512, 2000 steps, K = 100")
+    L = need_gpu()
+    from paper_1111_2142_amd.autograd import lwacm_run
+    drho, u0, u_tgt = _loss_setup(c.nx, 8)
+    d_t = to_dev(drho).requires_grad_(True)
+    u_t = to_dev(u0).requires_grad_(True)
+    om = torch.tensor(c.omega, dtype=torch.float64, requires_grad=True)
+    _, u_T = lwacm_run(d_t, u_t, om, c.steps, L.LWACM_D2Q9, K=100)
+    loss = ((u_T.double() - to_dev(u_tgt, torch.float64)) ** 2).sum()
+    loss.backward()
+    e_u = rel_l2(u_t.grad.double().cpu().numpy(), ref["du0"])
+    e_r = rel_l2(d_t.grad.double().cpu().numpy(), ref["ddrho0"])
+    gw, gw_o = float(om.grad), float(ref["domega"])
+    banner(f"gradient 512 (2000 steps): loss {loss.item():.9e} vs {float(ref['loss']):.9e}, "
+           f"rel-L2 du0 {e_u:.3e}, drho0 {e_r:.3e}, domega {gw:.9e} vs {gw_o:.9e}")
+    assert abs(loss.item() - float(ref["loss"])) < 1e-5 * float(ref["loss"])
+    assert e_u < 1e-4 and e_r < 1e-4
+    assert abs(gw - gw_o) < 1e-4 * abs(gw_o)
