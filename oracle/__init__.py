@@ -16,7 +16,9 @@ strings the per-step calls together:
 * ``gradient``   -- reverse sweep over n steps with a checkpoint every K
                     steps and recomputation in between;
 * ``thermal_step`` -- one step of the temperature lattice (Eq. ACM2.0t)
-                    advected by a given flow velocity.
+                    advected by a given flow velocity;
+* ``step_q``     -- one step with link-wall distances (interpolated
+                    bounce-back) and, optionally, wall velocities per link.
 
 Arrays: ``rho`` has shape (nz, ny, nx) (nz = 1 for D2Q9), ``u`` has shape
 (D, nz, ny, nx); float64, C order (x fastest).
@@ -55,6 +57,8 @@ def _load():
     lib.oracle_step_field.restype = ctypes.c_int
     lib.oracle_step_q.argtypes = common + [_dp, _dp, _dp, _dp, _dp]
     lib.oracle_step_q.restype = ctypes.c_int
+    lib.oracle_step_qw.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp]
+    lib.oracle_step_qw.restype = ctypes.c_int
     lib.oracle_vjp.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_vjp.restype = ctypes.c_int
     lib.oracle_step_nodes.argtypes = common + [_dp, _dp, ctypes.POINTER(ctypes.c_long),
@@ -208,17 +212,21 @@ def step_field(p: Problem, rho, u, g_field):
     return r1, u1
 
 
-def step_q(p: Problem, rho, u, qd):
+def step_q(p: Problem, rho, u, qd, uwl=None):
     """One step with link-wall distances qd (Q, nz, ny, nx): qd[j] at node x is
     the fraction of the link x -> x + v_j at which the wall cuts it (read where
-    x + v_j is solid); returns new (rho, u)."""
+    x + v_j is solid; None: q = 1/2).  uwl (Q, D, nz, ny, nx), if given, is the
+    velocity of the wall where that link crosses it, in place of the per-id
+    table.  Returns new (rho, u)."""
     lib = _load()
     rho = _f64(rho, p.shape)
     u = _f64(u, (p.d,) + p.shape)
-    qd = _f64(qd, (p.q,) + p.shape)
+    qd = None if qd is None else _f64(qd, (p.q,) + p.shape)
+    uwl = None if uwl is None else _f64(uwl, (p.q, p.d) + p.shape)
     r1 = np.empty_like(rho)
     u1 = np.empty_like(u)
-    rc = lib.oracle_step_q(*p._args(), _ptr(qd), _ptr(rho), _ptr(u), _ptr(r1), _ptr(u1))
+    rc = lib.oracle_step_qw(*p._args(), _ptr(qd), _ptr(uwl), _ptr(rho), _ptr(u), _ptr(r1),
+                            _ptr(u1))
     if rc != 0:
         raise RuntimeError(f"oracle_step_q failed ({rc})")
     return r1, u1

@@ -214,7 +214,7 @@ static void node_populations(const lattice_t *L, int nx, int ny, int nz, double 
                              const uint8_t *mask, const double *wall_u, int n_ids,
                              const double g[3], double rho0, const double *rho,
                              const double *u, int x, int y, int z, double f[MAXQ],
-                             const double *qd)
+                             const double *qd, const double *uwl)
 {
     long n = (long)nx * ny * nz;
     long ix = node_index(nx, ny, x, y, z);
@@ -236,7 +236,15 @@ static void node_populations(const lattice_t *L, int nx, int ny, int nz, double 
              * motion (Eq. ACM2.0ccccbb). */
             int ib = L->opp[i];
             double uw[3];
-            wall_velocity(wall_u, n_ids, mask[iy], uw);
+            if (uwl) {
+                /* the velocity of the wall where the link x -> x + v_ib
+                 * crosses it, given per link (a wall whose velocity varies
+                 * along it, e.g. a rotating cylinder) */
+                uw[0] = uw[1] = uw[2] = 0.0;
+                for (int k = 0; k < L->d; ++k) uw[k] = uwl[((long)ib * L->d + k) * n + ix];
+            } else {
+                wall_velocity(wall_u, n_ids, mask[iy], uw);
+            }
             double fstar = feq(L, ib, rx, ux) - a * feo(L, ib, rx, ux);
             /* Interpolated bounce-back (Eq. ACM2.0cc) when the wall cuts the
              * link x -> x + v_ib at the fraction q of its length (qd, link ib
@@ -329,7 +337,7 @@ int oracle_step(int q, int nx, int ny, int nz, double omega, const uint8_t *mask
                 }
                 double f[MAXQ];
                 node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_in,
-                                 u_in, x, y, z, f, NULL);
+                                 u_in, x, y, z, f, NULL, NULL);
                 double r = 0.0, j[3] = {0, 0, 0};
                 for (int i = 0; i < L.q; ++i) {
                     r += f[i];
@@ -345,11 +353,16 @@ int oracle_step(int q, int nx, int ny, int nz, double omega, const uint8_t *mask
  * "Moving complex boundaries", Eqs. ACM2.0cc and ACM2.0move).  qd holds q
  * fields of n values (SoA): qd[j * n + x] is the fraction of the link from
  * the fluid node x to x + v_j at which the wall cuts it, read where x + v_j
- * is solid; NULL gives the halfway rule (q = 1/2) of oracle_step. */
-int oracle_step_q(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
-                  const double *wall_u, int n_ids, const double *g_in, double rho0,
-                  const double *qd, const double *rho_in, const double *u_in, double *rho_out,
-                  double *u_out)
+ * is solid; NULL gives the halfway rule (q = 1/2) of oracle_step.  uwl, if
+ * not NULL, gives the wall velocity link by link in place of the per-id
+ * table: D * q fields of n values, uwl[(j * D + k) * n + x] the component k
+ * of the velocity of the wall where the link x -> x + v_j crosses it (read
+ * where x + v_j is solid).  It enters the moving-wall term of Eq. ACM2.0move
+ * as the table's velocity does. */
+int oracle_step_qw(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
+                   const double *wall_u, int n_ids, const double *g_in, double rho0,
+                   const double *qd, const double *uwl, const double *rho_in,
+                   const double *u_in, double *rho_out, double *u_out)
 {
     lattice_t L;
     if (make_lattice(q, &L)) return -1;
@@ -372,7 +385,7 @@ int oracle_step_q(int q, int nx, int ny, int nz, double omega, const uint8_t *ma
                 }
                 double f[MAXQ];
                 node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_in,
-                                 u_in, x, y, z, f, qd);
+                                 u_in, x, y, z, f, qd, uwl);
                 double r = 0.0, j[3] = {0, 0, 0};
                 for (int i = 0; i < L.q; ++i) {
                     r += f[i];
@@ -382,6 +395,16 @@ int oracle_step_q(int q, int nx, int ny, int nz, double omega, const uint8_t *ma
                 for (int k = 0; k < L.d; ++k) u_out[k * n + ix] = j[k] / r;
             }
     return 0;
+}
+
+/* oracle_step_qw with the wall velocities of the per-id table. */
+int oracle_step_q(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
+                  const double *wall_u, int n_ids, const double *g_in, double rho0,
+                  const double *qd, const double *rho_in, const double *u_in, double *rho_out,
+                  double *u_out)
+{
+    return oracle_step_qw(q, nx, ny, nz, omega, mask, wall_u, n_ids, g_in, rho0, qd, NULL,
+                          rho_in, u_in, rho_out, u_out);
 }
 
 /* One step with a body acceleration that varies from node to node (Section
@@ -412,7 +435,7 @@ int oracle_step_field(int q, int nx, int ny, int nz, double omega, const uint8_t
                 for (int k = 0; k < L.d; ++k) g[k] = g_field[k * n + ix];
                 double f[MAXQ];
                 node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, g, rho0, rho_in,
-                                 u_in, x, y, z, f, NULL);
+                                 u_in, x, y, z, f, NULL, NULL);
                 double r = 0.0, j[3] = {0, 0, 0};
                 for (int i = 0; i < L.q; ++i) {
                     r += f[i];
@@ -455,9 +478,9 @@ int oracle_step_split(int q, int nx, int ny, int nz, double omega, double omega_
                 }
                 double f[MAXQ], fp[MAXQ];
                 node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_in,
-                                 u_in, x, y, z, f, NULL);
+                                 u_in, x, y, z, f, NULL, NULL);
                 node_populations(&L, nx, ny, nz, omega_p, mask, wall_u, n_ids, gp, rho0, rho_in,
-                                 u_in, x, y, z, fp, NULL);
+                                 u_in, x, y, z, fp, NULL, NULL);
                 double r = 0.0, j[3] = {0, 0, 0};
                 for (int i = 0; i < L.q; ++i) {
                     r += fp[i];
@@ -497,7 +520,7 @@ int oracle_step_nodes(int q, int nx, int ny, int nz, double omega, const uint8_t
         int x = (int)(ix % nx), y = (int)((ix / nx) % ny), z = (int)(ix / ((long)nx * ny));
         double f[MAXQ];
         node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_in, u_in, x,
-                         y, z, f, NULL);
+                         y, z, f, NULL, NULL);
         double r = 0.0, j[3] = {0, 0, 0};
         for (int i = 0; i < L.q; ++i) {
             r += f[i];
@@ -656,7 +679,7 @@ int oracle_vjp(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
                 if (mask && mask[ix] != 0) continue;
                 double f[MAXQ];
                 node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, gp, rho0, rho_t,
-                                 u_t, x, y, z, f, NULL);
+                                 u_t, x, y, z, f, NULL, NULL);
                 double r = 0.0, j[3] = {0, 0, 0};
                 for (int i = 0; i < L.q; ++i) {
                     r += f[i];

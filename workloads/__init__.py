@@ -194,6 +194,80 @@ class ForcedTaylorGreen:
                 float(np.abs(pnum - pe).mean()))
 
 
+class CircularCouette:
+    """Flow between two concentric cylinders on a D2Q9 grid (the paper's
+    Section "Circular Couette flow"): the inner cylinder (radius r_i) at rest,
+    the outer one (radius r_e) turning at angular velocity 1/r_e, so its wall
+    moves at speed 1; nu = 0.07 in physical units; diffusive scaling with grid
+    spacing eps = Ma (lattice velocity = eps x physical velocity, lattice time
+    step eps^2).
+
+    Geometry only: node (i, j) sits at the physical point
+    X = (i + 1/2 - n/2) eps, Y = (j + 1/2 - n/2) eps, so the common axis lies
+    between nodes; nodes with r <= r_i are solid with mask id 1 (at rest),
+    nodes with r >= r_e solid with id 2 (turning), the rest fluid.  For every
+    fluid node x and link v_j with x + v_j solid, q_j(x) is the fraction of
+    the link at which it meets the circle (the root in (0, 1] of
+    |x + t v_j eps| = r), and uw_j(x) the wall velocity at that point in
+    lattice units: eps / r_e (-P_y, P_x) on the outer cylinder, 0 on the
+    inner one.
+    """
+
+    NU = 0.07
+
+    def __init__(self, eps: float, r_i: float = 0.5, r_e: float = 1.0):
+        self.eps, self.r_i, self.r_e = float(eps), float(r_i), float(r_e)
+        self.n = 2 * int(np.ceil(self.r_e / self.eps + 2.0))
+        n = self.n
+        c = (np.arange(n, dtype=np.float64) + 0.5 - n / 2.0) * self.eps
+        self.X, self.Y = np.meshgrid(c, c, indexing="xy")  # (ny, nx)
+        self.R = np.hypot(self.X, self.Y)
+        mask = np.zeros((1, n, n), dtype=np.uint8)
+        mask[0][self.R <= self.r_i] = 1
+        mask[0][self.R >= self.r_e] = 2
+        self.mask = mask
+        self.fluid = mask[0] == 0
+        # diffusive scaling: lattice viscosity = physical viscosity
+        self.omega = 1.0 / (3.0 * self.NU + 0.5)
+        self.C = 1.0 / (self.r_e / self.r_i - self.r_i / self.r_e)
+        self.center = ((n - 1) / 2.0, (n - 1) / 2.0, 0.0)  # node coordinates of the axis
+
+    def steps_to(self, t: float) -> int:
+        return int(round(t / self.eps ** 2))
+
+    def links(self, velocities):
+        """(qd, uwl) for the given link velocities (sequence of (vx, vy[, vz])):
+        qd (Q, 1, n, n) and uwl (Q, 2, 1, n, n); 0 where the link stays in
+        the fluid."""
+        n, eps = self.n, self.eps
+        Q = len(velocities)
+        qd = np.zeros((Q, 1, n, n))
+        uwl = np.zeros((Q, 2, 1, n, n))
+        fy, fx = np.nonzero(self.fluid)
+        for j, v in enumerate(velocities):
+            vx, vy = int(v[0]), int(v[1])
+            if vx == 0 and vy == 0:
+                continue
+            tx, ty = fx + vx, fy + vy
+            solid = self.mask[0, ty, tx]
+            sel = solid != 0
+            x0, y0 = self.X[fy[sel], fx[sel]], self.Y[fy[sel], fx[sel]]
+            r = np.where(solid[sel] == 1, self.r_i, self.r_e)
+            a = (vx * vx + vy * vy) * eps * eps
+            b = 2.0 * eps * (x0 * vx + y0 * vy)
+            cc = x0 * x0 + y0 * y0 - r * r
+            disc = np.sqrt(b * b - 4.0 * a * cc)
+            # inner cylinder: the link enters the circle (smaller root);
+            # outer cylinder: it leaves the disc r < r_e (larger root)
+            t = np.where(solid[sel] == 1, (-b - disc) / (2.0 * a), (-b + disc) / (2.0 * a))
+            qd[j, 0, fy[sel], fx[sel]] = t
+            px, py = x0 + t * vx * eps, y0 + t * vy * eps
+            om = np.where(solid[sel] == 2, eps / self.r_e, 0.0)
+            uwl[j, 0, 0, fy[sel], fx[sel]] = -om * py
+            uwl[j, 1, 0, fy[sel], fx[sel]] = om * px
+        return qd, uwl
+
+
 def random_state(shape: Tuple[int, int, int], d: int, seed: int, du: float = 0.05,
                  drho: float = 0.02):
     """Uniform random (drho, u) perturbations of the rest state (for algebraic
