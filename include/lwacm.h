@@ -186,10 +186,11 @@ int lwacm_set_march_chunk(lwacm_ctx *c, int planes);
  * 1/nu(omega_p) (Eq. viscosity2), so nu(omega_p) > nu(omega) reduces the
  * compressibility error of under-resolved runs.  0 < omega_p < 2, else
  * LWACM_EINVAL (omega_p < 1: LWACM_WOMEGA, a success); omega_p == omega
- * (the default after lwacm_init) is the single-relaxation step; omega_p != omega with link-wall distances (d_q)
- * gives LWACM_EUNSUPPORTED.  With omega_p != omega the forward step runs on the
- * single-step tile kernel (D3Q19 without walls, nz >= 8) or else on the
- * generic kernel (every lattice, walls and force allowed), never on the
+ * (the default after lwacm_init) is the single-relaxation step; omega_p !=
+ * omega with link-wall distances (d_q) or with wall velocities given link by
+ * link gives LWACM_EUNSUPPORTED.  With omega_p != omega the forward step runs
+ * on the single-step tile kernel (D3Q19 without walls, nz >= 8) or else on
+ * the generic kernel (every lattice, walls and force allowed), never on the
  * two-step kernel, and the reverse steps return LWACM_EUNSUPPORTED.  Takes
  * effect from the next lwacm_step. */
 int lwacm_set_omega_p(lwacm_ctx *c, double omega_p);
@@ -207,6 +208,24 @@ int lwacm_set_omega_p(lwacm_ctx *c, double omega_p);
  * never on the two-step kernel; the reverse steps return LWACM_EUNSUPPORTED
  * while a field is set.  LWACM_EINVAL for a null context. */
 int lwacm_set_force_field(lwacm_ctx *c, const float *d_g);
+
+/* Wall velocities given link by link, for walls whose velocity varies along
+ * them (a rotating cylinder: the paper's circular Couette flow, Section
+ * "Circular Couette flow"), in the moving-wall term of Eq. ACM2.0ccccbb
+ * (halfway walls) or Eq. ACM2.0move (with lwacm_init's d_q).
+ *   d_uw  D * Q FP32 fields of nx*ny*nz values (SoA, node index as the
+ *         state's), caller-owned device memory read by every following step
+ *         while set: d_uw[(j * D + k) * n + x] is component k of the velocity
+ *         of the wall where the link from the fluid node x to x + v_j (the
+ *         library's link order, as for d_q) crosses it, in lattice units;
+ *         read only where x + v_j is solid.  It replaces the per-id table of
+ *         lwacm_init for every wall while set; NULL returns to the table.
+ * The forward step then runs on the generic kernel; the reverse steps return
+ * LWACM_EUNSUPPORTED while it is set.  lwacm_wall_force leaves wall motion
+ * out (bodies at rest), so the links into the wall it is asked about must
+ * carry zero velocity.  LWACM_EINVAL without a mask; LWACM_EUNSUPPORTED with
+ * a separate omega_p. */
+int lwacm_set_wall_velocity_links(lwacm_ctx *c, const float *d_uw);
 
 /* Temperature advected by the flow: the thermal LW-ACM (Appendix
  * "Asymptotic analysis for energy equation", Eq. ACM2.0t with the even part

@@ -421,12 +421,21 @@ int lwacm_set_omega_p(lwacm_ctx *c, double omega_p)
 {
     if (!c || !(omega_p > 0.0 && omega_p < 2.0)) return LWACM_EINVAL;
     const float Ap = (float)(3.0 * quantised_h(omega_p));
-    if (c->p.qd && Ap != c->p.A) return LWACM_EUNSUPPORTED;  // not with interpolated walls
+    // not with interpolated walls or wall velocities given link by link
+    if ((c->p.qd || c->p.uwl) && Ap != c->p.A) return LWACM_EUNSUPPORTED;
     c->omega_p = omega_p;
     c->p.Ap = Ap;
     c->p.split = c->p.Ap != c->p.A;
     set_wall_terms(c);
     return omega_p < 1.0 ? LWACM_WOMEGA : LWACM_OK;
+}
+
+int lwacm_set_wall_velocity_links(lwacm_ctx *c, const float *d_uw)
+{
+    if (!c || (d_uw && !c->p.mask)) return LWACM_EINVAL;
+    if (d_uw && c->p.split) return LWACM_EUNSUPPORTED;  // not with a separate omega_p
+    c->p.uwl = d_uw;
+    return LWACM_OK;
 }
 
 int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
@@ -710,7 +719,7 @@ int lwacm_adjoint_step(lwacm_ctx *c, const void *d_state_t, const float *d_mu_in
         return LWACM_EINVAL;
     // no reverse step for omega_p != omega, a node-by-node acceleration or
     // interpolated bounce-back
-    if (c->p.split || c->p.g_field || c->p.qd) return LWACM_EUNSUPPORTED;
+    if (c->p.split || c->p.g_field || c->p.qd || c->p.uwl) return LWACM_EUNSUPPORTED;
     ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
     r.accumulate = 1;
     r.out_scale = 2.0 / (c->omega * c->omega);  // da/domega for a = 2 - 2/omega
@@ -728,7 +737,7 @@ int lwacm_adjoint_step2(lwacm_ctx *c, const void *d_state_t, const void *d_state
         d_mu_in == d_mu_out)
         return LWACM_EINVAL;
     if ((c->variant != LWACM_KERNEL_AUTO && c->variant != LWACM_KERNEL_MARCH2) ||
-        !lwacm::adj_march2_supported(c->p) || c->p.split || c->p.g_field || c->p.qd)
+        !lwacm::adj_march2_supported(c->p) || c->p.split || c->p.g_field || c->p.qd || c->p.uwl)
         return LWACM_EUNSUPPORTED;
     ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
     r.accumulate = 1;

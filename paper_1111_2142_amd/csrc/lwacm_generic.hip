@@ -152,7 +152,13 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
             if (MASK && m != 0) {
                 // bounce-back: own term of the opposite link + moving wall
                 const int ib = link_opp(i);
-                const float uw[3] = {p.wall_term[m][0], p.wall_term[m][1], p.wall_term[m][2]};
+                float uw[3] = {p.wall_term[m][0], p.wall_term[m][1], p.wall_term[m][2]};
+                if (p.uwl) {
+                    // the wall's velocity where the link x -> x + v_ib crosses it
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        uw[k] = p.wall_scale * p.uwl[((long long)ib * D + k) * n + idx];
+                }
                 const float cb = vdot<Q>(ib, ux);
                 float sb = link_term_unweighted(drx + fg, rx, cb, Bx, p.A);
                 float wsc = 1.0f;  // scale of the halfway moving-wall term

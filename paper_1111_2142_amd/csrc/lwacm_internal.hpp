@@ -35,6 +35,9 @@ struct ProblemArgs {
     uint32_t sr_word;        // fourth pcg4d input of this step: t ^ seed
     const uint8_t *mask;     // nullptr: all fluid
     const float *qd;         // link-wall distances, Q fields of n values (SoA), or nullptr: q = 1/2
+    // wall velocities link by link (Q * D fields of n values: component k of
+    // link j at (j * D + k) * n + x), or nullptr: the per-id table
+    const float *uwl;
     int march_nzc;           // planes per workgroup of the forward tile kernel (0: unused)
 };
 

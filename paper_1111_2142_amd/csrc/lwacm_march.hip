@@ -600,7 +600,7 @@ bool march_supported(const ProblemArgs &p)
     // on the rolled kernel and not together with a separate omega_p
     const bool split_ok = !p.split || (!p.mask && p.nz >= 8);
     const bool force_ok = !p.has_force || (!p.split && p.nz >= 8);
-    return p.Q == 19 && force_ok && split_ok && !p.qd && p.nx >= TX && p.ny >= TY && p.nx % TX == 0 &&
+    return p.Q == 19 && force_ok && split_ok && !p.qd && !p.uwl && p.nx >= TX && p.ny >= TY && p.nx % TX == 0 &&
            p.ny % TY == 0 && p.nz >= 1 && p.n < (1LL << 28);
 }
 

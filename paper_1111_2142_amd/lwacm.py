@@ -66,6 +66,7 @@ def load_library():
         "lwacm_set_omega_p": (i, [_vp, ctypes.c_double]),
         "lwacm_set_force_field": (i, [_vp, _vp]),
         "lwacm_set_thermal": (i, [_vp, d, _vp, _vp, _vp, i]),
+        "lwacm_set_wall_velocity_links": (i, [_vp, _vp]),
         "lwacm_temperature": (i, [_vp, ctypes.POINTER(_vp)]),
         "lwacm_wall_force": (i, [_vp, i, dp, dp]),
         "lwacm_set_state": (i, [_vp, _vp, _vp]),
@@ -167,6 +168,13 @@ def lwacm_set_force_field(ctx, g: Optional[torch.Tensor]):
     """g: (D, nz, ny, nx) float32 contiguous on the solver's device, or None.
     The tensor must stay alive while it is set."""
     _check(load_library().lwacm_set_force_field(ctx, _ptr(g)), "lwacm_set_force_field")
+
+
+def lwacm_set_wall_velocity_links(ctx, uw: Optional[torch.Tensor]):
+    """uw: (Q, D, nz, ny, nx) float32 contiguous on the solver's device (the
+    library's link order), or None.  The tensor must stay alive while set."""
+    _check(load_library().lwacm_set_wall_velocity_links(ctx, _ptr(uw)),
+           "lwacm_set_wall_velocity_links")
 
 
 def lwacm_set_thermal(ctx, omega_t: float, T_a: Optional[torch.Tensor],
@@ -379,6 +387,17 @@ class Solver:
                 raise LWACMError(LWACM_EINVAL, "set_force_field size")
         self._g_field = g
         lwacm_set_force_field(self.ctx, g)
+
+    def set_wall_velocity_links(self, uw: Optional[torch.Tensor]):
+        """Wall velocities link by link (Q, D, nz, ny, nx) in the library's
+        link order, or None (the per-id table); the solver keeps the FP32 copy
+        it passes alive while set."""
+        if uw is not None:
+            uw = uw.to(self.device, torch.float32).contiguous()
+            if uw.numel() != self.lattice * self.D * self.nx * self.ny * self.nz:
+                raise LWACMError(LWACM_EINVAL, "set_wall_velocity_links size")
+        self._uwl = uw
+        lwacm_set_wall_velocity_links(self.ctx, uw)
 
     def set_thermal(self, omega_t: float, T: Optional[torch.Tensor],
                     wall_T: Optional[Sequence[float]] = None):
