@@ -31,7 +31,9 @@ from typing import Callable, Optional, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIBPATH = os.path.join(_HERE, "liblwacm_oracle.so")
+# LWACM_ORACLE_LIB selects another build of the same source (the sanitizer
+# build of tests/test_sanitizers.py)
+_LIBPATH = os.environ.get("LWACM_ORACLE_LIB") or os.path.join(_HERE, "liblwacm_oracle.so")
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)

@@ -11,15 +11,20 @@ SRC = os.path.join(HERE, "lwacm_oracle.c")
 LIB = os.path.join(HERE, "liblwacm_oracle.so")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", tmp, SRC, "-lm"]
+def build(verbose: bool = False, out: str = LIB, sanitize: bool = False) -> str:
+    """Compile the oracle to ``out``; ``sanitize`` adds AddressSanitizer and
+    UndefinedBehaviorSanitizer (host code only; load it with the sanitizer
+    runtimes preloaded, see tests/test_sanitizers.py)."""
+    tmp = out + ".tmp"
+    flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
+    cmd = ["gcc"] + flags + ["-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+                             "-o", tmp, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

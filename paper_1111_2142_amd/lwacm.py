@@ -13,7 +13,9 @@ from typing import Optional, Sequence, Tuple
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIBRARY_PATH = os.path.join(_HERE, "liblwacm.so")
+# LWACM_LIBRARY selects another build of the same sources (the host-sanitizer
+# build of tests/test_sanitizers.py); there is no other implementation
+LIBRARY_PATH = os.environ.get("LWACM_LIBRARY") or os.path.join(_HERE, "liblwacm.so")
 
 LWACM_D2Q9, LWACM_D3Q19 = 9, 19
 LWACM_FP32, LWACM_FP16_DEV = 0, 1
