@@ -123,8 +123,13 @@ size_t lwacm_state_bytes(int lattice, int nx, int ny, int nz, int storage);
  *                 13 (-y+z), 14 (-z), 15 (-x-z), 16 (+x-z), 17 (-y-z), 18 (+y-z)
  *               (D2Q9: 0..8).  For q < 1/2 the rule also takes the
  *               node x - v_j; where that node is solid too, the halfway rule
- *               is used.  With d_q the forward step runs on the generic kernel
- *               and the reverse steps return LWACM_EUNSUPPORTED.
+ *               is used.  D3Q19 problems the tile kernels take run there
+ *               (halfway terms plus a per-step correction of the fluid nodes
+ *               next to a wall, made by a small kernel over those nodes);
+ *               for them d_q is read once, here, like the mask: change
+ *               neither afterwards.  Other problems run on the generic kernel,
+ *               which reads d_q at every step.  The reverse steps return
+ *               LWACM_EUNSUPPORTED.
  *  h_g          host body acceleration g[3] (Eq. force), or NULL; copied.
  *  stream       HIP stream every call of this context is issued on.
  *
@@ -220,7 +225,9 @@ int lwacm_set_force_field(lwacm_ctx *c, const float *d_g);
  *         library's link order, as for d_q) crosses it, in lattice units;
  *         read only where x + v_j is solid.  It replaces the per-id table of
  *         lwacm_init for every wall while set; NULL returns to the table.
- * The forward step then runs on the generic kernel; the reverse steps return
+ * The forward step then runs on the D3Q19 tile kernels with the per-step
+ * wall correction (as with d_q; the call synchronises the stream once to
+ * set it up) or else on the generic kernel; the reverse steps return
  * LWACM_EUNSUPPORTED while it is set.  lwacm_wall_force leaves wall motion
  * out (bodies at rest), so the links into the wall it is asked about must
  * carry zero velocity.  LWACM_EINVAL without a mask; LWACM_EUNSUPPORTED with
@@ -276,8 +283,10 @@ int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
  *   h_center  host double[3], the point x_c (NULL: the origin).
  *   h_out     host double[6]: F_x, F_y, F_z, T_x, T_y, T_z (D2Q9: F_z = T_x =
  *             T_y = 0).
- * Synchronises the context's stream.  Allocates a small device buffer on its
- * first call.  LWACM_EINVAL without a mask or for a bad id or pointer,
+ * Synchronises the context's stream.  On its first call it allocates a small
+ * device buffer and six pinned host doubles, and lists the fluid nodes next
+ * to a wall (one pass over the mask, in node order); every call then visits
+ * only those nodes.  LWACM_EINVAL without a mask or for a bad id or pointer,
  * LWACM_EUNSUPPORTED with FP16 storage or for an id with a non-zero wall
  * velocity (the paper states the exchange for bodies at rest). */
 int lwacm_wall_force(lwacm_ctx *c, int wall_id, const double *h_center, double *h_out);

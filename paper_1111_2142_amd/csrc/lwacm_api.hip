@@ -12,6 +12,7 @@
 #include "lwacm_internal.hpp"
 #include "lwacm_thermal.hpp"
 #include "lwacm_force.hpp"
+#include "lwacm_walls.hpp"
 
 using lwacm::ProblemArgs;
 using lwacm::ReduceArgs;
@@ -51,7 +52,16 @@ struct lwacm_ctx {
     float *T_buf[2];
     int tcur;
     lwacm::ThermalArgs targs;
-    double *d_force;  // wall-force partials and result (allocated on first use)
+    double *d_force;  // wall-force partials (allocated on first use)
+    double *h_force;  // pinned host memory the wall-force sum kernel writes its six results to
+    // fluid nodes next to a wall, in node order (built on first use)
+    unsigned *d_wlist;
+    unsigned n_wlist;
+    bool wlist_built;
+    float4 *d_corr;   // per-step wall correction of the tile kernels (interpolated walls)
+    float *d_wqc;     // packed q of the listed nodes' wall links (18 per node, link-major)
+    unsigned *d_wsec; // per listed node: links whose q < 1/2 rule takes the second node
+    unsigned *d_wbits; // per listed node: its solid upstream links
 };
 
 namespace {
@@ -160,6 +170,20 @@ void free_scratch(lwacm_ctx *c)
     if (c->d_bits) (void)hipFree(c->d_bits);
     if (c->d_wallg) (void)hipFree(c->d_wallg);
     if (c->d_force) (void)hipFree(c->d_force);
+    if (c->h_force) (void)hipHostFree(c->h_force);
+    c->h_force = nullptr;
+    if (c->d_wlist) (void)hipFree(c->d_wlist);
+    if (c->d_corr) (void)hipFree(c->d_corr);
+    if (c->d_wqc) (void)hipFree(c->d_wqc);
+    if (c->d_wsec) (void)hipFree(c->d_wsec);
+    if (c->d_wbits) (void)hipFree(c->d_wbits);
+    c->d_wbits = nullptr;
+    c->d_wqc = nullptr;
+    c->d_wsec = nullptr;
+    c->d_wlist = nullptr;
+    c->d_corr = nullptr;
+    c->p.corr = nullptr;
+    c->wlist_built = false;
     c->d_force = nullptr;
     c->d_cls = nullptr;
     c->d_bits = nullptr;
@@ -167,6 +191,97 @@ void free_scratch(lwacm_ctx *c)
     c->d_partials = nullptr;
     c->d_diag = c->d_scratch = nullptr;
     c->d_scan = nullptr;
+}
+
+// The list of fluid nodes next to a wall (lwacm_walls.hip), built once:
+// counts per block, their scan, the total read back (one synchronisation),
+// then the scatter.  Masked problems with fewer than 2^32 nodes.
+int ensure_wall_list(lwacm_ctx *c)
+{
+    if (c->wlist_built) return LWACM_OK;
+    if (!c->p.mask || c->p.n >= (1LL << 32)) return LWACM_EUNSUPPORTED;
+    const size_t nb = lwacm::wall_list_count_blocks(c->p.n);
+    unsigned *counts = nullptr;
+    unsigned long long *d_total = nullptr, total = 0;
+    hipError_t e = hipMalloc(&counts, nb * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMalloc(&d_total, sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        if (counts) (void)hipFree(counts);
+        return LWACM_ENOMEM;
+    }
+    e = lwacm::launch_wall_list_count(c->p, counts, d_total, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&total, d_total, sizeof(total), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMalloc(&c->d_wlist, (total ? total : 1) * sizeof(unsigned));
+    if (e == hipSuccess) e = lwacm::launch_wall_list_scatter(c->p, counts, c->d_wlist, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(counts);
+    (void)hipFree(d_total);
+    if (e != hipSuccess) {
+        if (c->d_wlist) (void)hipFree(c->d_wlist);
+        c->d_wlist = nullptr;
+        return LWACM_EDEVICE;
+    }
+    c->n_wlist = (unsigned)total;
+    c->wlist_built = true;
+    return LWACM_OK;
+}
+
+// Interpolated walls or link velocities on the D3Q19 tile kernels: the wall
+// list and one float4 per node for the per-step correction.  Returns OK and
+// leaves p.corr unset where the tile kernels cannot take the problem (the
+// generic kernel then runs it).
+int enable_wall_correction(lwacm_ctx *c)
+{
+    ProblemArgs g = c->p;  // the tile kernels' own conditions, walls aside
+    g.qd = nullptr;
+    g.uwl = nullptr;
+    g.corr = nullptr;
+    if (!c->p.mask || !c->d_bits || !lwacm::march_supported(g)) return LWACM_OK;
+    const int rc = ensure_wall_list(c);
+    if (rc != LWACM_OK) return rc == LWACM_EUNSUPPORTED ? LWACM_OK : rc;
+    // the correction kernel addresses the packed q (18 per listed node) and
+    // the link velocities (57 fields) with 32-bit byte offsets
+    if (72ull * c->n_wlist >= (1ull << 32) || (c->p.uwl && 228ull * c->p.n >= (1ull << 32)))
+        return LWACM_OK;
+    if (!c->d_corr) {
+        const size_t nl = c->n_wlist ? c->n_wlist : 1;
+        if (hipMalloc(&c->d_corr, (size_t)c->p.n * sizeof(float4)) != hipSuccess ||
+            hipMalloc(&c->d_wqc, 18 * nl * sizeof(float)) != hipSuccess ||
+            hipMalloc(&c->d_wsec, nl * sizeof(unsigned)) != hipSuccess ||
+            hipMalloc(&c->d_wbits, nl * sizeof(unsigned)) != hipSuccess) {
+            if (c->d_corr) (void)hipFree(c->d_corr);
+            if (c->d_wqc) (void)hipFree(c->d_wqc);
+            if (c->d_wsec) (void)hipFree(c->d_wsec);
+            c->d_corr = nullptr;
+            c->d_wqc = nullptr;
+            c->d_wsec = nullptr;
+            c->d_wbits = nullptr;
+            return LWACM_ENOMEM;
+        }
+        // q, the second-node choice and the link sets are fixed with the
+        // walls: packed once
+        if (lwacm::launch_wall_pack(c->p, c->d_wlist, c->n_wlist, c->d_wqc, c->d_wsec,
+                                    c->d_wbits, c->stream) != hipSuccess)
+            return LWACM_EDEVICE;
+    }
+    c->p.corr = c->d_corr;
+    return LWACM_OK;
+}
+
+lwacm::WallLinks wall_links(const lwacm_ctx *c)
+{
+    lwacm::WallLinks w;
+    w.list = c->d_wlist;
+    w.nlist = c->n_wlist;
+    w.bits = c->d_wbits;
+    w.qc = c->d_wqc;
+    w.second = c->d_wsec;
+    w.table_moving = 0;
+    for (int m = 1; m < c->n_wall_ids; ++m)
+        for (int k = 0; k < 3; ++k) w.table_moving |= c->wall_u[m][k] != 0.0f;
+    return w;
 }
 
 }  // namespace
@@ -295,6 +410,7 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
     // (a force, or a field set later, keeps the same tiling)
     ProblemArgs unforced = p;
     unforced.has_force = 0;
+    unforced.qd = nullptr;  // interpolated walls run on the tiles with the wall correction
     if (lwacm::march_supported(unforced)) {
         int dev = 0, ncu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -344,7 +460,8 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
             }
             c->n_fluid = scan[1];
         }
-        if (e == hipSuccess && (lwacm::march_supported(p) || lwacm::adj_march_supported(p))) {
+        if (e == hipSuccess &&
+            (lwacm::march_supported(unforced) || lwacm::adj_march_supported(unforced))) {
             bool moving = false;
             for (int m = 1; m < lwacm::kMaxWallIds; ++m)
                 for (int k = 0; k < 3; ++k) moving = moving || p.wall_u[m][k] != 0.0f;
@@ -364,6 +481,14 @@ int lwacm_init(lwacm_ctx **out, int lattice, int nx, int ny, int nz, double omeg
         free_scratch(c);
         delete c;
         return LWACM_EDEVICE;
+    }
+    if (d_q && d_mask) {
+        const int rc = enable_wall_correction(c);
+        if (rc != LWACM_OK) {
+            free_scratch(c);
+            delete c;
+            return rc;
+        }
     }
     *out = c;
     return omega < 1.0 ? LWACM_WOMEGA : LWACM_OK;
@@ -435,6 +560,14 @@ int lwacm_set_wall_velocity_links(lwacm_ctx *c, const float *d_uw)
     if (!c || (d_uw && !c->p.mask)) return LWACM_EINVAL;
     if (d_uw && c->p.split) return LWACM_EUNSUPPORTED;  // not with a separate omega_p
     c->p.uwl = d_uw;
+    if (d_uw) {
+        if (228ull * c->p.n >= (1ull << 32)) {  // beyond the correction kernel's offsets
+            c->p.corr = nullptr;
+            return LWACM_OK;
+        }
+        return enable_wall_correction(c);
+    }
+    if (!c->p.qd) c->p.corr = nullptr;  // back to the halfway rule and the id table
     return LWACM_OK;
 }
 
@@ -477,8 +610,12 @@ int lwacm_wall_force(lwacm_ctx *c, int wall_id, const double *h_center, double *
         for (int k = 0; k < 3; ++k)
             if (c->wall_u[wall_id][k] != 0.0f) return LWACM_EUNSUPPORTED;
     if (!c->d_force) {
-        if (hipMalloc(&c->d_force, sizeof(double) * 6 * (lwacm::kForceMaxBlocks + 1)) != hipSuccess) {
+        // the result goes straight to pinned host memory: no copy after the sum
+        if (hipMalloc(&c->d_force, sizeof(double) * 6 * (lwacm::kForceMaxBlocks + 1)) != hipSuccess ||
+            hipHostMalloc(&c->h_force, 6 * sizeof(double), hipHostMallocMapped) != hipSuccess) {
+            if (c->d_force) (void)hipFree(c->d_force);
             c->d_force = nullptr;
+            c->h_force = nullptr;
             return LWACM_ENOMEM;
         }
     }
@@ -494,15 +631,29 @@ int lwacm_wall_force(lwacm_ctx *c, int wall_id, const double *h_center, double *
     f.wall_id = wall_id;
     for (int k = 0; k < 3; ++k) f.xc[k] = h_center ? h_center[k] : 0.0;
     f.partials = c->d_force + 6;
-    f.out = c->d_force;
-    const long long n = (long long)c->p.nx * c->p.ny * c->p.nz;
-    long long nb = (n + lwacm::kForceBlock - 1) / lwacm::kForceBlock;
+    double *d_out = nullptr;
+    if (hipHostGetDevicePointer((void **)&d_out, c->h_force, 0) != hipSuccess || !d_out)
+        return LWACM_EDEVICE;
+    f.out = d_out;
+    f.list = nullptr;
+    f.nlist = 0;
+    long long items = (long long)c->p.nx * c->p.ny * c->p.nz;
+    const int lrc = ensure_wall_list(c);
+    if (lrc == LWACM_OK) {
+        // only the fluid nodes next to a wall carry links into one
+        f.list = c->d_wlist;
+        f.nlist = c->n_wlist;
+        items = c->n_wlist;
+    } else if (lrc != LWACM_EUNSUPPORTED) {
+        return lrc;
+    }
+    long long nb = (items + lwacm::kForceBlock - 1) / lwacm::kForceBlock;
+    if (nb < 1) nb = 1;
     if (nb > (long long)lwacm::kForceMaxBlocks) nb = lwacm::kForceMaxBlocks;
     if (lwacm::launch_wall_force(f, (unsigned)nb, c->stream) != hipSuccess) return LWACM_EDEVICE;
-    if (hipMemcpyAsync(h_out, c->d_force, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
-        hipSuccess)
-        return LWACM_EDEVICE;
-    return dev_err(hipStreamSynchronize(c->stream));
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return LWACM_EDEVICE;
+    for (int k = 0; k < 6; ++k) h_out[k] = c->h_force[k];
+    return LWACM_OK;
 }
 
 int lwacm_temperature(lwacm_ctx *c, float **d_T)
@@ -608,6 +759,10 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
             if (lwacm::launch_thermal_step(t, c->stream) != hipSuccess) return LWACM_EDEVICE;
             c->tcur ^= 1;
         }
+        if (march && !two && c->p.corr &&
+            lwacm::launch_wall_correction(c->p, c->storage, src, wall_links(c), c->d_corr,
+                                          c->stream) != hipSuccess)
+            return LWACM_EDEVICE;
         if (two)
             e = lwacm::launch_fwd_march2(c->p, static_cast<const float *>(src),
                                          static_cast<float *>(dst), r, c->stream);

@@ -20,9 +20,12 @@ struct ForceArgs {
     double xc[3];          // torque centre (node coordinates)
     double *partials;      // [6 * nblocks]
     double *out;           // [6]: F, T
+    const unsigned *list;  // fluid nodes next to a wall (node order), or null: scan every node
+    unsigned nlist;
 };
 
-// Launches the per-node pass over nblocks blocks and the fixed-order sum.
+// Launches the pass over the listed nodes (or over every node when list is
+// null) on nblocks blocks and the fixed-order sum.
 hipError_t launch_wall_force(const ForceArgs &f, unsigned nblocks, hipStream_t stream);
 
 }  // namespace lwacm

@@ -38,6 +38,11 @@ struct ProblemArgs {
     // wall velocities link by link (Q * D fields of n values: component k of
     // link j at (j * D + k) * n + x), or nullptr: the per-id table
     const float *uwl;
+    // D3Q19 tile kernels with interpolated walls or link velocities: per node
+    // next to a wall, the step's correction to the halfway terms (wall motion
+    // included) in units of 36 w, added before normalisation; nullptr: the
+    // halfway rule with the per-id moving-wall sums
+    const float4 *corr;
     int march_nzc;           // planes per workgroup of the forward tile kernel (0: unused)
 };
 

@@ -360,10 +360,18 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
         gq[j][2] = __builtin_amdgcn_raw_buffer_load_b32(rgz, col * 4u, so, 0);
     };
     auto class_of = [](unsigned b) { return (b & 1u) ? 2 : (b ? 1 : 0); };
+    // per-step wall correction (interpolated walls, link velocities): one
+    // float4 per node next to a wall, loaded at the top of the iteration that
+    // finalises its plane so that its latency hides behind the plane's work
+    const bool corr = MASK && p.corr != nullptr;
+    const Rsrc rcorr = make_rsrc(corr ? (const void *)p.corr : nullptr,
+                                 corr ? (unsigned long long)n * 16u : 0ull);
 
     Ring<T> ring[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) issue(j, ring[j], z0 - 1 + j);
+    // corrections of the ring's planes (slot = the plane's ring slot)
+    f32x4 cwr[3] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
     if (FRC == 2 && role == INTERIOR)
 #pragma unroll
         for (int j = 0; j < 3; ++j) issue_g(j, z0 - 1 + j);
@@ -391,6 +399,8 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             const unsigned b = bw[j];
             if (MASK) raw[j] = ring[j].v;
             Acc &Am = acc[(j + 2) % 3];  // target plane pz - 1 (finalised now)
+            // the correction of plane pz - 1, loaded two iterations ago
+            const f32x4 cw = cwr[(j + 2) % 3];
             push_column<MASK>(dr, ux, uy, uz, MASK ? class_of(b) : 0, b, A, a, acc[(j + 1) % 3],
                               acc[j], Am);
             if (SPLIT) push_split_column(1.0f + dr, ux, uy, uz, dA, acc[(j + 1) % 3], acc[j], Am);
@@ -402,6 +412,21 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
                 acc[j].post[0] = fmaf(arho, ux, rho * gx);
                 acc[j].post[1] = fmaf(arho, uy, rho * gy);
                 acc[j].post[2] = fmaf(arho, uz, rho * gz);
+            }
+            if constexpr (MASK) {
+                // the correction of plane pz + 1 (its link set is in the ring
+                // already), finalised two iterations from now: issued before
+                // this iteration's ring refill, so waiting for it then waits
+                // for no load that is not due by then.  Lanes away from the
+                // walls ask for an offset past the end of the buffer: zeros,
+                // no memory access.
+                const unsigned b1 = bw[(j + 1) % 3];
+                cwr[(j + 1) % 3] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                if (corr && __builtin_amdgcn_ballot_w64(b1 > 1u) != 0ull) {
+                    const unsigned node = (unsigned)wrap_index(z0 + k, nz) * (unsigned)plane + col;
+                    cwr[(j + 1) % 3] =
+                        BufIO<float>::load(rcorr, b1 > 1u ? node * 16u : 0xfffffff0u, 0u);
+                }
             }
             __builtin_amdgcn_sched_barrier(0);  // the ring slot's last use is above
             if (I::refill) {
@@ -418,7 +443,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             if constexpr (SPLIT) qsum = Am.qd + gather_split<QS, SX>(XchgQ<QS>{xq[k & 1]}, slot);
             const NodeOut o = finalize<MASK, NSLOT + 1, SX, SPLIT>(X, slot, Am, p, wallg,
                                                                    (long long)tz * plane + col,
-                                                                   qsum);
+                                                                   qsum, corr ? &cw : nullptr);
             const unsigned so = (unsigned)tz * plane_bytes;
             typename BufIO<T>::Raw out;
             if (SR) {  // FP16 storage, stochastic rounding (a template parameter: one path)
@@ -597,10 +622,12 @@ bool march_supported(const ProblemArgs &p)
 {
     // 32-bit byte offsets inside a state buffer: n * 16 bytes < 4 GiB
     // a separate omega_p only on the rolled kernel without walls; forcing only
-    // on the rolled kernel and not together with a separate omega_p
+    // on the rolled kernel and not together with a separate omega_p;
+    // interpolated walls and link-by-link wall velocities only with the
+    // per-step wall correction (p.corr)
     const bool split_ok = !p.split || (!p.mask && p.nz >= 8);
     const bool force_ok = !p.has_force || (!p.split && p.nz >= 8);
-    return p.Q == 19 && force_ok && split_ok && !p.qd && !p.uwl && p.nx >= TX && p.ny >= TY && p.nx % TX == 0 &&
+    return p.Q == 19 && force_ok && split_ok && ((!p.qd && !p.uwl) || p.corr) && p.nx >= TX && p.ny >= TY && p.nx % TX == 0 &&
            p.ny % TY == 0 && p.nz >= 1 && p.n < (1LL << 28);
 }
 

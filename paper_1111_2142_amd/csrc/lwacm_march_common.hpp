@@ -439,7 +439,8 @@ __device__ __forceinline__ Gathered gather(const Xchg<NS> &X, int slot)
 // normalisation by 1 + D.
 template <bool MASK, bool SPLIT = false>
 __device__ __forceinline__ NodeOut finish(const Gathered &g, const Acc &Am, const ProblemArgs &p,
-                                          const float4 *wallg, long long widx, float qsum = 0.0f)
+                                          const float4 *wallg, long long widx, float qsum = 0.0f,
+                                          const f32x4 *cw = nullptr)
 {
     float D36 = Am.d + ((g.pE + g.pW) + (g.pN + g.pS)) + ((g.dNE + g.dNW) + (g.dSE + g.dSW));
     float Jx = (g.pE - g.pW) + ((g.dNE - g.dNW) + (g.dSE - g.dSW));
@@ -451,10 +452,27 @@ __device__ __forceinline__ NodeOut finish(const Gathered &g, const Acc &Am, cons
         Jx += Am.bb[1];
         Jy += Am.bb[2];
         Jz += Am.bb[3];
-        // moving walls (Eq. ACM2.0ccccbb): (1 - a) 6 rho0 times the node's
-        // geometry sums of 36 w_i (1, v_i) (v_i . u_w)
-        if (__builtin_amdgcn_ballot_w64((Am.bits & kMovingWallFlag) != 0u) != 0ull &&
-            (Am.bits & kMovingWallFlag)) {
+        if (p.corr) {
+            // interpolated walls or link velocities (Eqs. ACM2.0cc, ACM2.0move):
+            // this step's correction of every node next to a wall, wall
+            // motion included (made by the wall-correction kernel); cw is
+            // the value the caller loaded ahead (zero away from the walls)
+            if (cw) {
+                D36 += cw->x;
+                Jx += cw->y;
+                Jy += cw->z;
+                Jz += cw->w;
+            } else if (__builtin_amdgcn_ballot_w64(Am.bits > 1u) != 0ull && Am.bits > 1u) {
+                const float4 w = p.corr[widx];
+                D36 += w.x;
+                Jx += w.y;
+                Jy += w.z;
+                Jz += w.w;
+            }
+        } else if (__builtin_amdgcn_ballot_w64((Am.bits & kMovingWallFlag) != 0u) != 0ull &&
+                   (Am.bits & kMovingWallFlag)) {
+            // moving walls (Eq. ACM2.0ccccbb): (1 - a) 6 rho0 times the node's
+            // geometry sums of 36 w_i (1, v_i) (v_i . u_w)
             const float4 w = wallg[widx];
             D36 = fmaf(p.wall_scale, w.x, D36);
             Jx = fmaf(p.wall_scale, w.y, Jx);
@@ -479,9 +497,10 @@ __device__ __forceinline__ NodeOut finish(const Gathered &g, const Acc &Am, cons
 template <bool MASK, int NS, int SXP, bool SPLIT = false>
 __device__ __forceinline__ NodeOut finalize(const Xchg<NS> &X, int slot, const Acc &Am,
                                             const ProblemArgs &p, const float4 *wallg,
-                                            long long widx, float qsum = 0.0f)
+                                            long long widx, float qsum = 0.0f,
+                                            const f32x4 *cw = nullptr)
 {
-    return finish<MASK, SPLIT>(gather<NS, SXP>(X, slot), Am, p, wallg, widx, qsum);
+    return finish<MASK, SPLIT>(gather<NS, SXP>(X, slot), Am, p, wallg, widx, qsum, cw);
 }
 
 // ---- separate omega_p for the density (Section "finite-difference

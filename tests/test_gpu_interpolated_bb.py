@@ -7,8 +7,9 @@ Eqs. ACM2.0cc and ACM2.0move) against the oracle's step_q.
   FP32 and FP16 storage, to the parity bars.
 - Plane Couette flow between off-lattice walls (q = 0.3 and 0.7): the GPU's
   steady state is the exact linear profile to FP32 accuracy.
-- Scope: the tile kernels and the reverse steps decline d_q, and so does a
-  separate omega_p.
+- Scope: the reverse steps, the two-step kernel and a separate omega_p
+  decline d_q (the single-step D3Q19 tile kernels take it through the
+  per-step wall correction: tests/test_gpu_wall_correction.py).
 """
 import numpy as np
 import pytest
@@ -55,14 +56,21 @@ def _gpu(L, q, shape, omega, drho, u, steps, mask, table, qd, storage=0, variant
 
 @pytest.mark.parametrize("q,shape", [(9, (1, 40, 48)), (19, (12, 32, 32))])
 def test_q_one_half_is_the_halfway_step(q, shape):
+    """On the generic kernel q = 1/2 gives the halfway step bit for bit; on the
+    D3Q19 tile kernel (halfway terms plus the per-step wall correction, whose
+    interpolation part is then zero) it agrees with it to FP32 rounding."""
     L = need_gpu()
     banner(f"interpolated bb q=1/2 q={q}")
     d = 2 if q == 9 else 3
     mask, _, table = _walls(q, shape, 41)
     drho, u = wl.random_state(shape, d, seed=42, du=0.03, drho=0.01)
     a = _gpu(L, q, shape, 1.5, drho, u, 5, mask, table, None, variant=GENERIC)
-    b = _gpu(L, q, shape, 1.5, drho, u, 5, mask, table, np.full((q,) + shape, 0.5))
+    half = np.full((q,) + shape, 0.5)
+    b = _gpu(L, q, shape, 1.5, drho, u, 5, mask, table, half, variant=GENERIC)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    if q == 19:
+        c = _gpu(L, q, shape, 1.5, drho, u, 5, mask, table, half)
+        assert np.abs(c[1] - a[1]).max() < 1e-8 and np.abs(c[0] - a[0]).max() < 1e-7
 
 
 @pytest.mark.parametrize("q,storage", [(9, 0), (19, 0), (19, 1)])
@@ -133,8 +141,9 @@ def test_interpolated_bb_scope():
     mask, qd, table = _walls(19, shape, 45)
     s = L.Solver(19, 64, 32, 16, 1.6, mask=to_dev(mask, torch.uint8),
                  wall_u=[list(r) for r in table], qd=to_dev(qd))
+    L.lwacm_set_variant(s.ctx, MARCH)  # the tile kernels take d_q (wall correction)
     with pytest.raises(L.LWACMError) as ei:
-        L.lwacm_set_variant(s.ctx, MARCH)
+        L.lwacm_set_variant(s.ctx, 3)  # not the two-step kernel (walls)
     assert ei.value.code == L.LWACM_EUNSUPPORTED
     with pytest.raises(L.LWACMError) as ei:
         L.lwacm_set_omega_p(s.ctx, 1.1)
