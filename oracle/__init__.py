@@ -61,6 +61,8 @@ def _load():
     lib.oracle_step_q.restype = ctypes.c_int
     lib.oracle_step_qw.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_step_qw.restype = ctypes.c_int
+    lib.oracle_step_si.argtypes = common[:9] + [_dp, ctypes.c_double, _dp, _dp, _dp, _dp]
+    lib.oracle_step_si.restype = ctypes.c_int
     lib.oracle_vjp.argtypes = common + [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_vjp.restype = ctypes.c_int
     lib.oracle_step_nodes.argtypes = common + [_dp, _dp, ctypes.POINTER(ctypes.c_long),
@@ -211,6 +213,24 @@ def step_field(p: Problem, rho, u, g_field):
                                _ptr(u1))
     if rc != 0:
         raise RuntimeError(f"oracle_step_field failed ({rc})")
+    return r1, u1
+
+
+def step_si(p: Problem, rho, u, g_field=None):
+    """One step with the semi-implicit pressure update (Eq. FDcompact_si): the
+    explicit step's velocity, then the density from the old density and the
+    new velocity.  g_field (D, nz, ny, nx) replaces the problem's uniform g
+    when given.  Returns new (rho, u)."""
+    lib = _load()
+    rho = _f64(rho, p.shape)
+    u = _f64(u, (p.d,) + p.shape)
+    gf = None if g_field is None else _f64(g_field, (p.d,) + p.shape)
+    r1 = np.empty_like(rho)
+    u1 = np.empty_like(u)
+    a = p._args()
+    rc = lib.oracle_step_si(*a[:9], _ptr(gf), a[9], _ptr(rho), _ptr(u), _ptr(r1), _ptr(u1))
+    if rc != 0:
+        raise RuntimeError(f"oracle_step_si failed ({rc})")
     return r1, u1
 
 

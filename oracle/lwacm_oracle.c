@@ -447,6 +447,46 @@ int oracle_step_field(int q, int nx, int ny, int nz, double omega, const uint8_t
     return 0;
 }
 
+/* One step with the semi-implicit pressure update (Section "The main
+ * algorithm: Finite difference formulation", item 2, Eq. FDcompact_si): the
+ * velocity of the step comes from the explicit update as in oracle_step (or
+ * oracle_step_field when g_field is given); the density (pressure p = rho/3)
+ * is then the zeroth moment of the Eq. ACM2.0 populations evaluated with the
+ * already updated velocity field and the old density, f_p(u+, v+, p): the
+ * same function of the stencil's values, with u+ in place of u.  Forcing
+ * adds nothing to the density (its odd part sums to zero over the links).
+ * Solid nodes keep their values. */
+int oracle_step_si(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
+                   const double *wall_u, int n_ids, const double *g_in, const double *g_field,
+                   double rho0, const double *rho_in, const double *u_in, double *rho_out,
+                   double *u_out)
+{
+    lattice_t L;
+    if (make_lattice(q, &L)) return -1;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (L.d == 2 && nz != 1)) return -1;
+    int rc = g_field ? oracle_step_field(q, nx, ny, nz, omega, mask, wall_u, n_ids, g_field, rho0,
+                                         rho_in, u_in, rho_out, u_out)
+                     : oracle_step(q, nx, ny, nz, omega, mask, wall_u, n_ids, g_in, rho0, rho_in,
+                                   u_in, rho_out, u_out);
+    if (rc) return rc;
+    /* the pressure from the old density and the new velocity: reads rho_in
+     * and u_out only, so rho_out can be written in place */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long ix = node_index(nx, ny, x, y, z);
+                if (mask && mask[ix] != 0) continue;
+                double f[MAXQ];
+                node_populations(&L, nx, ny, nz, omega, mask, wall_u, n_ids, NULL, rho0, rho_in,
+                                 u_out, x, y, z, f, NULL, NULL);
+                double r = 0.0;
+                for (int i = 0; i < L.q; ++i) r += f[i];
+                rho_out[ix] = r;
+            }
+    return 0;
+}
+
 /* One step with a separate relaxation omega_p for the density (the
  * continuity equation) and omega for the momentum; omega_p == omega is the
  * step of oracle_step.  The populations are evaluated twice, once with each
