@@ -214,6 +214,19 @@ int lwacm_set_omega_p(lwacm_ctx *c, double omega_p);
  * while a field is set.  LWACM_EINVAL for a null context. */
 int lwacm_set_force_field(lwacm_ctx *c, const float *d_g);
 
+/* Semi-implicit pressure update (Section "The main algorithm: Finite
+ * difference formulation", item 2, Eq. FDcompact_si): on != 0 makes every
+ * following step compute the velocity as the explicit step does and then the
+ * pressure (density) from the already updated velocity field with the old
+ * density, f_p(u+, v+, p): the zeroth moment of the Eq. ACM2.0 populations
+ * evaluated with u+ in place of u (walls included; the forcing adds nothing
+ * to it).  A second pass over the grid on the generic kernel; the mass and
+ * energy of the step are those of the final state.  LWACM_EUNSUPPORTED with
+ * FP16 storage, a separate omega_p, link-wall distances, link velocities or
+ * a tile-kernel variant; the reverse steps return LWACM_EUNSUPPORTED while it
+ * is on.  on == 0 returns to the explicit step. */
+int lwacm_set_semi_implicit(lwacm_ctx *c, int on);
+
 /* Wall velocities given link by link, for walls whose velocity varies along
  * them (a rotating cylinder: the paper's circular Couette flow, Section
  * "Circular Couette flow"), in the moving-wall term of Eq. ACM2.0ccccbb

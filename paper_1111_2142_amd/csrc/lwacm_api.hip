@@ -62,6 +62,7 @@ struct lwacm_ctx {
     float *d_wqc;     // packed q of the listed nodes' wall links (18 per node, link-major)
     unsigned *d_wsec; // per listed node: links whose q < 1/2 rule takes the second node
     unsigned *d_wbits; // per listed node: its solid upstream links
+    bool semi_implicit;  // pressure from the updated velocity (Eq. FDcompact_si)
 };
 
 namespace {
@@ -144,7 +145,7 @@ size_t state_bytes(const lwacm_ctx *c)
 
 bool use_march(const lwacm_ctx *c)
 {
-    if (c->variant == LWACM_KERNEL_GENERIC) return false;
+    if (c->variant == LWACM_KERNEL_GENERIC || c->semi_implicit) return false;
     return lwacm::march_supported(c->p);
 }
 
@@ -546,8 +547,9 @@ int lwacm_set_omega_p(lwacm_ctx *c, double omega_p)
 {
     if (!c || !(omega_p > 0.0 && omega_p < 2.0)) return LWACM_EINVAL;
     const float Ap = (float)(3.0 * quantised_h(omega_p));
-    // not with interpolated walls or wall velocities given link by link
-    if ((c->p.qd || c->p.uwl) && Ap != c->p.A) return LWACM_EUNSUPPORTED;
+    // not with interpolated walls, wall velocities given link by link or the
+    // semi-implicit pressure update
+    if ((c->p.qd || c->p.uwl || c->semi_implicit) && Ap != c->p.A) return LWACM_EUNSUPPORTED;
     c->omega_p = omega_p;
     c->p.Ap = Ap;
     c->p.split = c->p.Ap != c->p.A;
@@ -555,10 +557,20 @@ int lwacm_set_omega_p(lwacm_ctx *c, double omega_p)
     return omega_p < 1.0 ? LWACM_WOMEGA : LWACM_OK;
 }
 
+int lwacm_set_semi_implicit(lwacm_ctx *c, int on)
+{
+    if (!c) return LWACM_EINVAL;
+    if (on && (c->storage != LWACM_FP32 || c->p.split || c->p.qd || c->p.uwl ||
+               c->variant == LWACM_KERNEL_MARCH || c->variant == LWACM_KERNEL_MARCH2))
+        return LWACM_EUNSUPPORTED;
+    c->semi_implicit = on != 0;
+    return LWACM_OK;
+}
+
 int lwacm_set_wall_velocity_links(lwacm_ctx *c, const float *d_uw)
 {
     if (!c || (d_uw && !c->p.mask)) return LWACM_EINVAL;
-    if (d_uw && c->p.split) return LWACM_EUNSUPPORTED;  // not with a separate omega_p
+    if (d_uw && (c->p.split || c->semi_implicit)) return LWACM_EUNSUPPORTED;
     c->p.uwl = d_uw;
     if (d_uw) {
         if (228ull * c->p.n >= (1ull << 32)) {  // beyond the correction kernel's offsets
@@ -671,13 +683,14 @@ int lwacm_set_variant(lwacm_ctx *c, int variant)
         return LWACM_OK;
     }
     if (variant == LWACM_KERNEL_MARCH2) {
-        if (c->storage != LWACM_FP32 || c->thermal || !lwacm::march2_supported(c->p))
+        if (c->storage != LWACM_FP32 || c->thermal || c->semi_implicit ||
+            !lwacm::march2_supported(c->p))
             return LWACM_EUNSUPPORTED;
         c->variant = variant;
         return LWACM_OK;
     }
     if (variant == LWACM_KERNEL_MARCH) {
-        if (!lwacm::march_supported(c->p)) return LWACM_EUNSUPPORTED;
+        if (c->semi_implicit || !lwacm::march_supported(c->p)) return LWACM_EUNSUPPORTED;
         c->variant = variant;
         return LWACM_OK;
     }
@@ -772,6 +785,14 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
         else
             e = lwacm::launch_fwd_generic(c->p, c->storage, c->p.has_force != 0, src, dst, r, nb1,
                                           c->stream);
+        if (e == hipSuccess && c->semi_implicit) {
+            // the density again, from the old density and the new velocity;
+            // its sums replace the explicit pass's in the same partial set
+            ReduceArgs r2 = reduce_args(c, r.out, r.out2);
+            r2.partials = r.partials;
+            e = lwacm::launch_density_si(c->p, static_cast<const float *>(src),
+                                         static_cast<float *>(dst), r2, nb1, c->stream);
+        }
         if (e != hipSuccess) return LWACM_EDEVICE;
         const unsigned nb = two ? nb2 : nb1;
         npend = 0;
@@ -874,7 +895,8 @@ int lwacm_adjoint_step(lwacm_ctx *c, const void *d_state_t, const float *d_mu_in
         return LWACM_EINVAL;
     // no reverse step for omega_p != omega, a node-by-node acceleration or
     // interpolated bounce-back
-    if (c->p.split || c->p.g_field || c->p.qd || c->p.uwl) return LWACM_EUNSUPPORTED;
+    if (c->p.split || c->p.g_field || c->p.qd || c->p.uwl || c->semi_implicit)
+        return LWACM_EUNSUPPORTED;
     ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
     r.accumulate = 1;
     r.out_scale = 2.0 / (c->omega * c->omega);  // da/domega for a = 2 - 2/omega
@@ -892,7 +914,8 @@ int lwacm_adjoint_step2(lwacm_ctx *c, const void *d_state_t, const void *d_state
         d_mu_in == d_mu_out)
         return LWACM_EINVAL;
     if ((c->variant != LWACM_KERNEL_AUTO && c->variant != LWACM_KERNEL_MARCH2) ||
-        !lwacm::adj_march2_supported(c->p) || c->p.split || c->p.g_field || c->p.qd || c->p.uwl)
+        !lwacm::adj_march2_supported(c->p) || c->p.split || c->p.g_field || c->p.qd || c->p.uwl ||
+        c->semi_implicit)
         return LWACM_EUNSUPPORTED;
     ReduceArgs r = reduce_args(c, d_dL_domega, nullptr);
     r.accumulate = 1;

@@ -238,6 +238,71 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
         finish_previous_sums(r.prev_partials, r.prev_nblocks, r.prev_out, r.prev_out2);
 }
 
+// Semi-implicit pressure update (Section "The main algorithm: Finite
+// difference formulation", item 2, Eq. FDcompact_si), second pass of a step:
+// the density of the step is the zeroth moment of the Eq. ACM2.0 populations
+// evaluated with the old density (src) and the velocity the explicit pass
+// has just written (dst); it replaces that pass's density in dst.  Other
+// threads read only the velocity of dst, so writing the density field in
+// place is safe (a node's density value loaded with its velocity goes
+// unused).  Forcing adds nothing to the density.  FP32 storage.
+template <int Q, bool MASK>
+__global__ __launch_bounds__(kGenericBlock) void k_density_si(ProblemArgs p,
+                                                              const float *__restrict__ src,
+                                                              float *dst, ReduceArgs r)
+{
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    const long long n = p.n;
+    double acc[2] = {0.0, 0.0};
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        if (MASK && p.mask[idx] != 0) continue;
+        const Coord c = decompose(idx, p.nx, p.ny);
+        float drx, ux[3], dnew, unew[3];
+        load_state<D, float>(src, idx, p, drx, ux);
+        load_state<D, float>(dst, idx, p, dnew, unew);
+        (void)dnew;
+        (void)ux;
+        const float rx = 1.0f + drx;
+        const float Bx = -1.5f * (unew[0] * unew[0] + unew[1] * unew[1] + unew[2] * unew[2]);
+        float D36 = 0.0f;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const long long up = node_at(p, wrap_add(c.x, -link_cx(i), p.nx),
+                                         wrap_add(c.y, -link_cy(i), p.ny),
+                                         wrap_add(c.z, -link_cz(i), p.nz));
+            float s;
+            uint8_t m = 0;
+            if (MASK) m = p.mask[up];
+            if (MASK && m != 0) {
+                // halfway bounce-back and the wall motion's share of the density
+                const int ib = link_opp(i);
+                const float uw[3] = {p.wall_term[m][0], p.wall_term[m][1], p.wall_term[m][2]};
+                s = link_term_unweighted(drx, rx, vdot<Q>(ib, unew), Bx, p.A) + vdot<Q>(i, uw);
+            } else {
+                float dry, uy_old[3];
+                load_state<D, float>(src, up, p, dry, uy_old);
+                (void)uy_old;
+                float dyn, uy[3];
+                load_state<D, float>(dst, up, p, dyn, uy);
+                (void)dyn;
+                const float By = -1.5f * (uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2]);
+                s = link_term_unweighted(dry, 1.0f + dry, vdot<Q>(i, uy), By, p.A);
+            }
+            D36 = fmaf(L::w36(i), s, D36);
+        }
+        const float Dsum = div36(D36);
+        dst[(long long)(D + 1) * idx] = Dsum;
+        float e = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) e = fmaf(unew[k], unew[k], e);
+        acc[0] += (double)Dsum;
+        acc[1] += 0.5 * (double)e;
+    }
+    store_block_partials<2>(acc, r.partials, blockIdx.x);
+}
+
 template <int Q, class T, bool MASK>
 __global__ __launch_bounds__(kGenericBlock) void k_adj_generic(ProblemArgs p, const T *__restrict__ state,
                                                                const float *__restrict__ mu_in,
@@ -496,6 +561,23 @@ hipError_t launch_reduce(const ReduceArgs &r, int nv, unsigned nblocks, hipStrea
         k_reduce_partials<1><<<1, kReduceThreads, 0, s>>>(r, nblocks);
     else
         k_reduce_partials<2><<<1, kReduceThreads, 0, s>>>(r, nblocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_si(const ProblemArgs &p, const float *src, float *dst,
+                             const ReduceArgs &r, unsigned nb, hipStream_t s)
+{
+    if (p.Q == 9) {
+        if (p.mask)
+            k_density_si<9, true><<<nb, kGenericBlock, 0, s>>>(p, src, dst, r);
+        else
+            k_density_si<9, false><<<nb, kGenericBlock, 0, s>>>(p, src, dst, r);
+    } else {
+        if (p.mask)
+            k_density_si<19, true><<<nb, kGenericBlock, 0, s>>>(p, src, dst, r);
+        else
+            k_density_si<19, false><<<nb, kGenericBlock, 0, s>>>(p, src, dst, r);
+    }
     return hipGetLastError();
 }
 

@@ -80,6 +80,10 @@ hipError_t launch_reduce(const ReduceArgs &r, int nv, unsigned nblocks, hipStrea
 hipError_t launch_fwd_generic(const ProblemArgs &p, int storage, bool force, const void *src,
                               void *dst, const ReduceArgs &r, unsigned nblocks,
                               hipStream_t stream);
+// Second pass of a semi-implicit step (FP32 storage): the density from the
+// old density (src) and the new velocity (dst), written into dst.
+hipError_t launch_density_si(const ProblemArgs &p, const float *src, float *dst,
+                             const ReduceArgs &r, unsigned nblocks, hipStream_t stream);
 hipError_t launch_adj_generic(const ProblemArgs &p, int storage, const void *state,
                               const float *mu_in, float *mu_out, int final_t0,
                               const ReduceArgs &r, unsigned nblocks, hipStream_t stream);

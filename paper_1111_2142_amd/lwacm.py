@@ -69,6 +69,7 @@ def load_library():
         "lwacm_set_force_field": (i, [_vp, _vp]),
         "lwacm_set_thermal": (i, [_vp, d, _vp, _vp, _vp, i]),
         "lwacm_set_wall_velocity_links": (i, [_vp, _vp]),
+        "lwacm_set_semi_implicit": (i, [_vp, i]),
         "lwacm_temperature": (i, [_vp, ctypes.POINTER(_vp)]),
         "lwacm_wall_force": (i, [_vp, i, dp, dp]),
         "lwacm_set_state": (i, [_vp, _vp, _vp]),
@@ -170,6 +171,10 @@ def lwacm_set_force_field(ctx, g: Optional[torch.Tensor]):
     """g: (D, nz, ny, nx) float32 contiguous on the solver's device, or None.
     The tensor must stay alive while it is set."""
     _check(load_library().lwacm_set_force_field(ctx, _ptr(g)), "lwacm_set_force_field")
+
+
+def lwacm_set_semi_implicit(ctx, on: bool):
+    _check(load_library().lwacm_set_semi_implicit(ctx, int(bool(on))), "lwacm_set_semi_implicit")
 
 
 def lwacm_set_wall_velocity_links(ctx, uw: Optional[torch.Tensor]):
