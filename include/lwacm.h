@@ -321,7 +321,11 @@ int lwacm_set_state(lwacm_ctx *c, const float *d_drho, const float *d_u);
  * reproducible); see lwacm_diagnostics.  Where LWACM_KERNEL_MARCH2 applies,
  * pairs of steps run as one launch (an odd count starts with a single step);
  * the state, the diagnostics and the history are the same as with single
- * steps.  Asynchronous. */
+ * steps.  D2Q9 problems in FP32 storage without a diagnostics history,
+ * link-wall distances, link velocities, a separate omega_p, a force field, a
+ * temperature or the semi-implicit update run up to 8 steps per launch in
+ * LDS (variant AUTO): the state is bitwise that of single steps, the mass and
+ * energy equal to FP64 rounding.  Asynchronous. */
 int lwacm_step(lwacm_ctx *c, int nsteps);
 
 /* Mass and energy of the state after the most recent lwacm_step (host

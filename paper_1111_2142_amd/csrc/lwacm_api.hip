@@ -143,6 +143,15 @@ size_t state_bytes(const lwacm_ctx *c)
     return (size_t)(c->p.D + 1) * (size_t)c->p.n * (c->storage == LWACM_FP32 ? 4 : 2);
 }
 
+// Several D2Q9 steps per launch in LDS (lwacm_d2q9_multi.hip): FP32, no
+// history (it sums only a launch's last step), variant AUTO.
+bool use_multi(const lwacm_ctx *c)
+{
+    return c->variant == LWACM_KERNEL_AUTO && c->storage == LWACM_FP32 && !c->thermal &&
+           !c->semi_implicit && !c->d_hist && lwacm::d2q9_multi_supported(c->p) &&
+           lwacm::d2q9_multi_num_blocks(c->p) <= c->n_partial_blocks;
+}
+
 bool use_march(const lwacm_ctx *c)
 {
     if (c->variant == LWACM_KERNEL_GENERIC || c->semi_implicit) return false;
@@ -728,7 +737,10 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
     if (!c || nsteps < 0) return LWACM_EINVAL;
     const bool march = use_march(c);
     const bool fuse = march && use_march2(c);
-    const unsigned nb1 = march ? lwacm::march_num_blocks(c->p) : lwacm::generic_grid(c->p.n);
+    const bool multi = !march && use_multi(c);
+    const unsigned nb1 = march ? lwacm::march_num_blocks(c->p)
+                               : (multi ? lwacm::d2q9_multi_num_blocks(c->p)
+                                        : lwacm::generic_grid(c->p.n));
     const unsigned nb2 = fuse ? lwacm::march2_num_blocks(c->p) : 0u;
     const size_t set = 2 * c->n_partial_blocks;  // doubles per partial set
     // Steps whose partials are stored but not yet added up (oldest first): the
@@ -740,8 +752,11 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
     int npend = 0;
     int s = 0;
     for (int launch = 0; s < nsteps; ++launch) {
-        // an odd step count starts with one single step, then pairs
+        // an odd step count starts with one single step, then pairs; the
+        // multi-step D2Q9 kernel takes up to kMultiSteps steps at a time
         const bool two = fuse && (nsteps - s) % 2 == 0;
+        const int kk = multi ? (nsteps - s < lwacm::kMultiSteps ? nsteps - s : lwacm::kMultiSteps)
+                             : (two ? 2 : 1);
         double *part = c->d_partials + 2 * set * (size_t)(launch & 1);
         ReduceArgs r = reduce_args(c, c->d_diag, hist_slot(c, c->steps + 1));
         r.partials = part;
@@ -782,6 +797,9 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
         else if (march)
             e = lwacm::launch_fwd_march(c->p, c->storage, src, dst, c->d_cls, c->d_bits,
                                         c->d_wallg, r, c->stream);
+        else if (multi)
+            e = lwacm::launch_fwd_d2q9_multi(c->p, static_cast<const float *>(src),
+                                             static_cast<float *>(dst), kk, r, c->stream);
         else
             e = lwacm::launch_fwd_generic(c->p, c->storage, c->p.has_force != 0, src, dst, r, nb1,
                                           c->stream);
@@ -799,8 +817,8 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
         pend[npend++] = {r.partials, r.out, r.out2, nb};
         if (two) pend[npend++] = {r.partials_b, c->d_diag, hist_slot(c, c->steps + 2), nb};
         c->cur ^= 1;
-        c->steps += two ? 2 : 1;
-        s += two ? 2 : 1;
+        c->steps += kk;
+        s += kk;
         c->diag_valid = true;
     }
     // the last launch's sums: mass/energy and history complete when the call's work is

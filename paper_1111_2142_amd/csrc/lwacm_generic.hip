@@ -15,6 +15,7 @@
 #include <type_traits>
 
 #include "lwacm_device.hpp"
+#include "lwacm_generic_update.hpp"
 #include "lwacm_internal.hpp"
 
 namespace lwacm {
@@ -90,20 +91,6 @@ __device__ __forceinline__ void store_mu(float *mu, long long idx, float r, cons
     }
 }
 
-template <int Q>
-__device__ __forceinline__ float vdot(int i, const float (&u)[3])
-{
-    float c = 0.0f;
-    if (link_cx(i) != 0) c = (link_cx(i) > 0) ? c + u[0] : c - u[0];
-    if (link_cy(i) != 0) c = (link_cy(i) > 0) ? c + u[1] : c - u[1];
-    if (Q == 19 && link_cz(i) != 0) c = (link_cz(i) > 0) ? c + u[2] : c - u[2];
-    return c;
-}
-
-// SPLIT: a separate relaxation omega_p for the density (Section
-// "finite-difference formulation", item 3; Appendix E).  The density sums the
-// same link terms with Ap = 3 (2/omega_p - 1) in place of A (and the moving
-// wall's omega_p term); the momentum keeps A.
 template <int Q, class T, bool MASK, bool FORCE, bool SPLIT>
 __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, const T *__restrict__ src,
                                                                T *__restrict__ dst, ReduceArgs r)
@@ -127,102 +114,17 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
             continue;
         }
         const Coord c = decompose(idx, p.nx, p.ny);
-        const float rx = 1.0f + drx;
-        const float Bx = -1.5f * (ux[0] * ux[0] + ux[1] * ux[1] + ux[2] * ux[2]);
-        // Forcing (Eq. force) adds the odd part 3 w_i rho_x (v_i . g) to every
-        // population.  It enters each link term through the addend of its FMA,
-        // where it meets an exact, node-dependent product; added to the final
-        // sum instead, the same small constant would round the same way every
-        // step and bias long runs.
-        float g3[3] = {0.0f, 0.0f, 0.0f};
-        if (FORCE)
-#pragma unroll
-            for (int k = 0; k < D; ++k)
-                g3[k] = 3.0f * rx * (p.g_field ? p.g_field[(long long)k * n + idx] : p.g[k]);
-        float D36 = 0.0f, J36[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const long long up = node_at(p, wrap_add(c.x, -link_cx(i), p.nx),
-                                         wrap_add(c.y, -link_cy(i), p.ny),
-                                         wrap_add(c.z, -link_cz(i), p.nz));
-            const float fg = FORCE ? vdot<Q>(i, g3) : 0.0f;
-            float s, sp = 0.0f;  // link term; with SPLIT, its density form
-            uint8_t m = 0;
-            if (MASK) m = p.mask[up];
-            if (MASK && m != 0) {
-                // bounce-back: own term of the opposite link + moving wall
-                const int ib = link_opp(i);
-                float uw[3] = {p.wall_term[m][0], p.wall_term[m][1], p.wall_term[m][2]};
-                if (p.uwl) {
-                    // the wall's velocity where the link x -> x + v_ib crosses it
-#pragma unroll
-                    for (int k = 0; k < D; ++k)
-                        uw[k] = p.wall_scale * p.uwl[((long long)ib * D + k) * n + idx];
-                }
-                const float cb = vdot<Q>(ib, ux);
-                float sb = link_term_unweighted(drx + fg, rx, cb, Bx, p.A);
-                float wsc = 1.0f;  // scale of the halfway moving-wall term
-                if (p.qd) {
-                    // interpolated bounce-back (Eq. ACM2.0cc): the wall cuts the
-                    // link x -> x + v_ib at the fraction q; the terms are in
-                    // deviation form, whose mixing weights sum to one
-                    const float qv = p.qd[(long long)ib * n + idx];
-                    if (qv < 0.5f) {
-                        const long long dn = node_at(p, wrap_add(c.x, link_cx(i), p.nx),
-                                                     wrap_add(c.y, link_cy(i), p.ny),
-                                                     wrap_add(c.z, link_cz(i), p.nz));
-                        if (p.mask[dn] == 0) {  // x - v_ib fluid (else halfway)
-                            float drz, uz[3];
-                            load_state<D, T>(src, dn, p, drz, uz);
-                            const float Bz = -1.5f * (uz[0] * uz[0] + uz[1] * uz[1] + uz[2] * uz[2]);
-                            const float sz = link_term_unweighted(drz + fg, 1.0f + drz,
-                                                                  vdot<Q>(ib, uz), Bz, p.A);
-                            sb = fmaf(2.0f * qv, sb, (1.0f - 2.0f * qv) * sz);
-                        }
-                    } else {
-                        const float si = link_term_unweighted(drx + fg, rx, vdot<Q>(i, ux), Bx, p.A);
-                        const float h = 0.5f / qv;  // 1 / (2q)
-                        sb = fmaf(h, sb, (1.0f - h) * si);
-                        wsc = h;  // Eq. ACM2.0move: 1/q in place of 2
-                    }
-                }
-                s = fmaf(wsc, vdot<Q>(i, uw), sb);
-                if (SPLIT) {
-                    const float uwp[3] = {p.wall_term_p[m][0], p.wall_term_p[m][1],
-                                          p.wall_term_p[m][2]};
-                    sp = link_term_unweighted(drx + fg, rx, cb, Bx, p.Ap) + vdot<Q>(i, uwp);
-                }
-            } else {
-                float dry, uy[3];
-                load_state<D, T>(src, up, p, dry, uy);
-                const float By = -1.5f * (uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2]);
-                const float cy = vdot<Q>(i, uy);
-                s = link_term_unweighted(dry + fg, 1.0f + dry, cy, By, p.A);
-                if (SPLIT) sp = link_term_unweighted(dry + fg, 1.0f + dry, cy, By, p.Ap);
-            }
-            s *= L::w36(i);
-            D36 += SPLIT ? sp * L::w36(i) : s;
-            if (link_cx(i) != 0) J36[0] += link_cx(i) * s;
-            if (link_cy(i) != 0) J36[1] += link_cy(i) * s;
-            if (link_cz(i) != 0) J36[2] += link_cz(i) * s;
-        }
-        const float Dsum = div36(D36);
-        // post-combine: sum_i v_i a f^(e,o)_i(x) = a rho_x u_x
-        float J[3];
-#pragma unroll
-        for (int k = 0; k < D; ++k) J[k] = fmaf(p.a * rx, ux[k], div36(J36[k]));
-        // u = J / (1 + D) evaluated as J - J * (D / (1 + D)): the rounding of
-        // 1 + D then only touches the small correction term, which keeps the
-        // FP32 error from accumulating over long runs.
-        const float q = normalisation_factor(Dsum);
-        float e = 0.0f;
-        float out[D + 1];
-        out[0] = Dsum;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            out[k + 1] = fmaf(-J[k], q, J[k]);
-            e = fmaf(out[k + 1], out[k + 1], e);
-        }
+        auto at = [&](int dx, int dy, int dz) {
+            return node_at(p, wrap_add(c.x, dx, p.nx), wrap_add(c.y, dy, p.ny),
+                           wrap_add(c.z, dz, p.nz));
+        };
+        auto fmask = [&](int dx, int dy, int dz) -> uint8_t { return p.mask[at(dx, dy, dz)]; };
+        auto fstate = [&](int dx, int dy, int dz, float &dr, float (&u)[3], float &B) {
+            load_state<D, T>(src, at(dx, dy, dz), p, dr, u);
+            B = node_B(u);
+        };
+        float out[D + 1], e;
+        link_update<Q, MASK, FORCE, SPLIT>(p, idx, drx, ux, node_B(ux), fmask, fstate, out, e);
         if (std::is_same<T, __half>::value && p.fp16_sr) {
             const U32x4 h = pcg4d((uint32_t)c.x, (uint32_t)c.y, (uint32_t)c.z, p.sr_word);
             const uint32_t rw[4] = {h.x, h.y, h.z, h.w};
@@ -230,7 +132,7 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
         } else {
             NodeState<T, D + 1>::store(dst, idx, out, p.st_scale);
         }
-        acc[0] += (double)Dsum;
+        acc[0] += (double)out[0];
         acc[1] += 0.5 * (double)e;
     }
     store_block_partials<2>(acc, r.partials, blockIdx.x);

@@ -139,6 +139,16 @@ unsigned march2_num_blocks(const ProblemArgs &p);
 hipError_t launch_fwd_march2(const ProblemArgs &p, const float *src, float *dst,
                              const ReduceArgs &r, hipStream_t stream);
 
+// Several D2Q9 steps per launch (FP32 storage; no link-wall distances, link
+// velocities, omega_p or force field): 32 x 32 output tiles, up to
+// kMultiSteps steps per launch in LDS, one partial pair per tile.
+constexpr int kMultiTile = 32;
+constexpr int kMultiSteps = 8;
+bool d2q9_multi_supported(const ProblemArgs &p);
+unsigned d2q9_multi_num_blocks(const ProblemArgs &p);
+hipError_t launch_fwd_d2q9_multi(const ProblemArgs &p, const float *src, float *dst, int ksteps,
+                                 const ReduceArgs &r, hipStream_t stream);
+
 // Number of blocks the generic grid-stride kernels use for n nodes.
 unsigned generic_grid(long long n);
 
