@@ -89,8 +89,8 @@ def _load():
     lib.oracle_store_fp16_sr.argtypes = [ctypes.c_int] * 4 + [ctypes.c_uint32] * 2 + \
         [ctypes.c_int] * 2 + [_dp, _dp]
     lib.oracle_store_fp16_sr.restype = ctypes.c_int
-    lib.oracle_pcg4d.argtypes = [u32p, u32p]
-    lib.oracle_pcg4d.restype = None
+    lib.oracle_sr_words.argtypes = [ctypes.c_uint32, ctypes.c_uint32, u32p]
+    lib.oracle_sr_words.restype = None
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     lib.oracle_set_num_threads.restype = None
     lib.oracle_num_threads.argtypes = []
@@ -346,12 +346,12 @@ def run(p: Problem, rho, u, nsteps: int, callback: Optional[Callable] = None):
     return a_r, a_u
 
 
-def pcg4d(words):
-    """The four 32-bit words of the pcg4d hash of four 32-bit words."""
-    a = np.ascontiguousarray(np.asarray(words, dtype=np.uint32).reshape(4))
+def sr_words(idx: int, w: int):
+    """The four field words of node idx at step word w = t ^ seed: (a, b,
+    a << 13, b << 13) with (a, b) the pcg2d hash of (idx, w)."""
     out = np.zeros(4, dtype=np.uint32)
-    u32p = ctypes.POINTER(ctypes.c_uint32)
-    _load().oracle_pcg4d(a.ctypes.data_as(u32p), out.ctypes.data_as(u32p))
+    _load().oracle_sr_words(int(idx) & 0xFFFFFFFF, int(w) & 0xFFFFFFFF,
+                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
     return out
 
 

@@ -40,9 +40,10 @@
  *   - FP16 storage with stochastic rounding (not part of the paper: a
  *     storage format of the GPU library): the real value is rounded up to
  *     the next FP16 magnitude when its fractional position between the two
- *     neighbouring FP16 magnitudes plus a uniform variate reaches 1; the
- *     variate comes from the pcg4d hash (Jarzynski and Olano, "Hash
- *     Functions for GPU Rendering", JCGT 9(3), 2020) of (x, y, z, t ^ seed);
+ *     neighbouring FP16 magnitudes, cut to 13 bits, plus a uniform 13-bit
+ *     variate reaches 1; the variate comes from the pcg2d hash (Jarzynski
+ *     and Olano, "Hash Functions for GPU Rendering", JCGT 9(3), 2020) of
+ *     (node index, t ^ seed);
  *   - force and torque on a wall by momentum exchange (Eqs. MEA3, MEA4,
  *     MEA5), for halfway and interpolated walls at rest;
  *   - the thermal extension (Appendix "Asymptotic analysis for energy
@@ -574,54 +575,70 @@ int oracle_step_nodes(int q, int nx, int ny, int nz, double omega, const uint8_t
 
 /* ---- FP16 storage with stochastic rounding ---- */
 
-/* pcg4d of Jarzynski and Olano (JCGT 2020): a linear congruential step on
- * each word, two rounds of cross-word multiply-adds with an xor-shift by 16
- * between them.  All arithmetic is modulo 2^32. */
-static void pcg4d(uint32_t v[4])
+/* pcg2d of Jarzynski and Olano (JCGT 2020): a linear congruential step on
+ * each of the two words, then two rounds of "each word adds the other times
+ * the LCG multiplier" followed by an xor-shift by 16.  All arithmetic is
+ * modulo 2^32.  The map is a bijection of the 64-bit input, so distinct
+ * (node, step) counters give distinct output pairs. */
+static void pcg2d(uint32_t v[2])
 {
-    for (int k = 0; k < 4; ++k) v[k] = v[k] * 1664525u + 1013904223u;
-    v[0] += v[1] * v[3];
-    v[1] += v[2] * v[0];
-    v[2] += v[0] * v[1];
-    v[3] += v[1] * v[2];
-    for (int k = 0; k < 4; ++k) v[k] ^= v[k] >> 16;
-    v[0] += v[1] * v[3];
-    v[1] += v[2] * v[0];
-    v[2] += v[0] * v[1];
-    v[3] += v[1] * v[2];
+    v[0] = v[0] * 1664525u + 1013904223u;
+    v[1] = v[1] * 1664525u + 1013904223u;
+    for (int round = 0; round < 2; ++round) {
+        v[0] += v[1] * 1664525u;
+        v[1] += v[0] * 1664525u;
+        v[0] ^= v[0] >> 16;
+        v[1] ^= v[1] >> 16;
+    }
+}
+
+/* The random words of the fields of node idx at step word w = t ^ seed:
+ * (a, b) = pcg2d(idx, w) and field f draws from word f of
+ * (a, b, a << 13, b << 13); the rounding reads only a word's top 13 bits,
+ * so the four fields take disjoint bits of a and b. */
+static void sr_words(uint32_t idx, uint32_t w, uint32_t out[4])
+{
+    uint32_t v[2] = {idx, w};
+    pcg2d(v);
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[0] << 13;
+    out[3] = v[1] << 13;
 }
 
 /* Stochastic rounding of the real y to an IEEE half value with random word r.
  * Between the neighbouring half magnitudes lo <= |y| < lo + s (spacing s =
  * 2^(e - 10) for |y| in [2^e, 2^(e+1)), e >= -14; s = 2^-24 below 2^-14),
- * |y| goes to lo + s when (|y| - lo)/s + U >= 1, with U = (r >> 19) / 2^13 in
- * the normal range and U = (r >> 8) / 2^24 in the subnormal range.
- * Magnitudes above the largest half, 65504, become infinite. */
+ * write (|y| - lo)/s = F / 2^13 + rest with F an integer in [0, 2^13) and
+ * 0 <= rest < 2^-13 (rest is 0 in the normal range, where an FP32 value has
+ * 13 bits below the half spacing); |y| goes to lo + s when
+ * F + (r >> 19) >= 2^13.  The variate thus has 13 bits in both ranges and
+ * the position is cut to 13 bits: the rounding of gfx950's stochastic
+ * FP32 -> FP16 conversion.  Magnitudes above the largest half, 65504,
+ * become infinite. */
 double oracle_round_fp16_sr(double y, uint32_t r)
 {
     double a = fabs(y);
     if (a == 0.0 || isnan(a)) return y;
-    double sp, U;
+    double sp;
     if (a < ldexp(1.0, -14)) {
         sp = ldexp(1.0, -24);
-        U = (double)(r >> 8) * ldexp(1.0, -24);
     } else {
         int e;
         frexp(a, &e); /* a = m 2^e, m in [1/2, 1): a lies in [2^(e-1), 2^e) */
         sp = ldexp(1.0, e - 1 - 10);
-        U = (double)(r >> 19) * ldexp(1.0, -13);
     }
     double lo = floor(a / sp) * sp;
-    double frac = (a - lo) / sp;
-    double res = (frac + U >= 1.0) ? lo + sp : lo;
+    double F = floor((a - lo) / sp * 8192.0);
+    double res = (F + (double)(r >> 19) >= 8192.0) ? lo + sp : lo;
     if (res > 65504.0) res = INFINITY;
     return copysign(res, y);
 }
 
 /* Round a state the way the FP16 storage stores the output of step t:
  * rho - 1 scaled by 2^k_rho and each u component scaled by 2^k_u are rounded
- * stochastically, field f of node (x, y, z) with word f of
- * pcg4d(x, y, z, t ^ seed), and scaled back.  In place. */
+ * stochastically, field f of node idx = (z ny + y) nx + x with word f of
+ * sr_words(idx, t ^ seed), and scaled back.  In place. */
 int oracle_store_fp16_sr(int q, int nx, int ny, int nz, uint32_t t, uint32_t seed, int k_rho,
                          int k_u, double *rho, double *u)
 {
@@ -633,8 +650,8 @@ int oracle_store_fp16_sr(int q, int nx, int ny, int nz, uint32_t t, uint32_t see
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long ix = node_index(nx, ny, x, y, z);
-                uint32_t h[4] = {(uint32_t)x, (uint32_t)y, (uint32_t)z, t ^ seed};
-                pcg4d(h);
+                uint32_t h[4];
+                sr_words((uint32_t)ix, t ^ seed, h);
                 rho[ix] = 1.0 + oracle_round_fp16_sr((rho[ix] - 1.0) * s_rho, h[0]) / s_rho;
                 for (int k = 0; k < L.d; ++k)
                     u[k * n + ix] = oracle_round_fp16_sr(u[k * n + ix] * s_u, h[k + 1]) / s_u;
@@ -642,12 +659,11 @@ int oracle_store_fp16_sr(int q, int nx, int ny, int nz, uint32_t t, uint32_t see
     return 0;
 }
 
-/* The four words of pcg4d(v) (for the tests of the generator itself). */
-void oracle_pcg4d(const uint32_t *in, uint32_t *out)
+/* The four field words of node idx at step word w (for the tests of the
+ * generator itself). */
+void oracle_sr_words(uint32_t idx, uint32_t w, uint32_t *out)
 {
-    uint32_t v[4] = {in[0], in[1], in[2], in[3]};
-    pcg4d(v);
-    for (int k = 0; k < 4; ++k) out[k] = v[k];
+    sr_words(idx, w, out);
 }
 
 /* Mass sum(rho) and energy 1/2 sum |u|^2 over fluid nodes. */

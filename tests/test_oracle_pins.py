@@ -488,16 +488,23 @@ def _half_neighbours(y):
 
 
 def test_round_fp16_sr_threshold_convention():
-    """|y| goes up when frac + U >= 1: U from the top 13 bits of the word in
-    the normal range, from the top 24 bits in the subnormal range."""
-    y = 1.0 + 2.0 ** -10 * 3 / 8            # spacing 2^-10 at 1, frac = 3/8
+    """|y| goes up when F + (r >> 19) >= 2^13, F the first 13 bits of its
+    position between the two neighbouring halves, in the normal and the
+    subnormal range alike."""
+    y = 1.0 + 2.0 ** -10 * 3 / 8            # spacing 2^-10 at 1, position 3/8
     lo, hi = 1.0, 1.0 + 2.0 ** -10
     assert oracle.round_fp16_sr(y, (5119 << 19) | 0x7FFFF) == lo
     assert oracle.round_fp16_sr(y, 5120 << 19) == hi
     assert oracle.round_fp16_sr(-y, 5120 << 19) == -hi
-    s = 2.0 ** -24                          # subnormal spacing, frac = 1/4
+    s = 2.0 ** -24                          # subnormal spacing, position 1/4
     assert oracle.round_fp16_sr(s / 4, ((3 << 22) - 1) << 8) == 0.0
     assert oracle.round_fp16_sr(s / 4, (3 << 22) << 8) == s
+    # a position past 13 bits is cut: 1/4 + 2^-20 still needs r >> 19 >= 6144
+    assert oracle.round_fp16_sr(s * (0.25 + 2.0 ** -20), (6143 << 19) | 0x7FFFF) == 0.0
+    assert oracle.round_fp16_sr(s * (0.25 + 2.0 ** -20), 6144 << 19) == s
+    # below the smallest subnormal: position m / 2^-24, cut to 13 bits
+    assert oracle.round_fp16_sr(s * 2.0 ** -14, 0xFFFFFFFF) == 0.0
+    assert oracle.round_fp16_sr(s * 2.0 ** -13, 0xFFFFFFFF) == s
     # the largest half is 65504, the next magnitude (65536) overflows
     assert oracle.round_fp16_sr(65510.0, 0) == 65504.0
     assert oracle.round_fp16_sr(65510.0, 0xFFFFFFFF) == np.inf
@@ -534,24 +541,27 @@ def test_round_fp16_sr_is_unbiased():
         assert abs(got.mean() - y) < 5 * sigma + (hi - lo) * 2.0 ** -13, y
 
 
-def test_pcg4d_words_are_uniform_and_balanced():
-    """Each output word of pcg4d over a grid of counters: its top 13 bits fill
-    64 bins evenly (chi-square) and every bit is set half of the time."""
-    counts = np.zeros((4, 64))
-    ones = np.zeros((4, 32))
-    m = 0
+def test_sr_words_are_uniform_and_balanced():
+    """The four field words of the nodes of a grid at three steps: the top 13
+    bits of each (the bits the rounding reads) fill 64 bins evenly
+    (chi-square), each of those bits is set half of the time, and the four
+    fields of a node are uncorrelated."""
+    m = 3 * 4096
+    w = np.zeros((m, 4), dtype=np.uint32)
+    k = 0
     for t in (1, 2, 1000):
-        for z in range(2):
-            for y in range(16):
-                for x in range(128):
-                    w = oracle.pcg4d([x, y, z, t])
-                    counts[np.arange(4), (w >> 26).astype(int)] += 1
-                    ones += (w[:, None] >> np.arange(32, dtype=np.uint32)) & 1
-                    m += 1
+        for idx in range(4096):
+            w[k] = oracle.sr_words(idx, t)
+            k += 1
+    top = (w >> 19).astype(np.int64)        # 13-bit variates
+    counts = np.stack([np.bincount(top[:, f] >> 7, minlength=64) for f in range(4)])
     expect = m / 64
     chi2 = ((counts - expect) ** 2 / expect).sum(axis=1)
     assert np.all(chi2 < 120), chi2        # 63 degrees of freedom: mean 63, sd 11
+    ones = ((top[:, :, None] >> np.arange(13)) & 1).sum(axis=0)
     assert np.all(np.abs(ones - m / 2) < 5 * np.sqrt(m / 4)), ones
+    c = np.corrcoef(top.T.astype(np.float64))
+    assert np.all(np.abs(c[np.triu_indices(4, 1)]) < 5 / np.sqrt(m)), c
 
 
 def test_fp16_storage_rounding_preserves_slow_decay():
