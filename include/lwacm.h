@@ -157,12 +157,14 @@ int lwacm_set_fp16_scales(lwacm_ctx *c, int k_rho, int k_u);
 
 /* Rounding of step outputs for FP16 storage.  LWACM_ROUND_STOCHASTIC (the
  * default, seed 0) rounds |v * 2^k| up to the next FP16 magnitude when
- * frac + U >= 1, frac being its position between the two neighbouring FP16
- * magnitudes and U uniform in [0, 1) from the top 13 bits (top 24 bits in the
- * FP16 subnormal range) of one 32-bit word of the pcg4d hash (Jarzynski and
- * Olano, JCGT 2020) of (x, y, z, t ^ seed): word 0 for rho - 1, words 1..D
- * for u, t the index of the step that produces the state.  The stored value
- * is then unbiased, so velocity changes smaller than an FP16 spacing
+ * F + R >= 2^13, F being the first 13 bits of its position between the two
+ * neighbouring FP16 magnitudes and R the top 13 bits of a random word (the
+ * rounding of gfx950's stochastic conversion).  The words of node idx =
+ * (z ny + y) nx + x are (a, b, a << 13, b << 13) for rho - 1, u_x, u_y, u_z,
+ * with (a, b) the pcg2d hash (Jarzynski and Olano, JCGT 2020) of
+ * (idx, t ^ seed), t the index of the step that produces the state.  The
+ * stored value is then unbiased (to 2^-13 of a spacing), so velocity changes
+ * smaller than an FP16 spacing
  * (1e-6 per step against 1e-5 spacing in the 256^3 Taylor-Green flow) are
  * kept on average instead of being rounded away, and a recomputed step
  * draws the same bits.  LWACM_ROUND_NEAREST rounds to nearest even.

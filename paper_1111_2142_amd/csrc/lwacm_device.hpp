@@ -117,57 +117,53 @@ __device__ __forceinline__ float normalisation_factor(float D)
 }
 
 // ------------------------------------------- stochastic FP16 rounding
-// Counter-based random bits: the pcg4d hash of Jarzynski and Olano, "Hash
-// Functions for GPU Rendering", JCGT 9(3), 2020.  Four 32-bit words in, four
-// out; the step stores field f of node (x, y, z) at step t with word f of
-// pcg4d(x, y, z, t ^ seed), so every run and every recomputation of a step
-// draws the same bits.
+// Counter-based random bits: the pcg2d hash of Jarzynski and Olano, "Hash
+// Functions for GPU Rendering", JCGT 9(3), 2020: an LCG step on each of two
+// words, then two rounds of "each word adds the other times the LCG
+// multiplier" and an xor-shift by 16 (six 32-bit multiplies).  A bijection of
+// its 64-bit input, so the counter (node index, t ^ seed) gives every node of
+// every step its own pair (a, b).  Field f of the node's stored state is
+// rounded with the top 13 bits of word f of (a, b, a << 13, b << 13):
+// disjoint bits of the pair, and a recomputed step draws the same bits.
 struct U32x4 {
     uint32_t x, y, z, w;
 };
 
-__device__ __forceinline__ U32x4 pcg4d(uint32_t x, uint32_t y, uint32_t z, uint32_t w)
+__device__ __forceinline__ U32x4 sr_words(uint32_t idx, uint32_t step_word)
 {
-    U32x4 v = {x * 1664525u + 1013904223u, y * 1664525u + 1013904223u,
-               z * 1664525u + 1013904223u, w * 1664525u + 1013904223u};
-    v.x += v.y * v.w;
-    v.y += v.z * v.x;
-    v.z += v.x * v.y;
-    v.w += v.y * v.z;
-    v.x ^= v.x >> 16;
-    v.y ^= v.y >> 16;
-    v.z ^= v.z >> 16;
-    v.w ^= v.w >> 16;
-    v.x += v.y * v.w;
-    v.y += v.z * v.x;
-    v.z += v.x * v.y;
-    v.w += v.y * v.z;
-    return v;
+    uint32_t a = idx * 1664525u + 1013904223u;
+    uint32_t b = step_word * 1664525u + 1013904223u;
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+        a += b * 1664525u;
+        b += a * 1664525u;
+        a ^= a >> 16;
+        b ^= b >> 16;
+    }
+    return U32x4{a, b, a << 13, b << 13};
 }
 
-// FP32 -> FP16 bits with stochastic rounding: |y| lies between two adjacent
-// FP16 magnitudes lo <= |y| < hi and is rounded to hi when
-// frac + U >= 1, frac = (|y| - lo) / (hi - lo), U uniform from the random
-// word r (its top 13 bits in the normal range, where FP32 carries 13 more
-// mantissa bits than FP16; its top 24 bits in the subnormal range, where the
-// FP16 spacing is 2^-24).  The expected stored value is y itself, so updates
-// smaller than one FP16 spacing are not lost; round to nearest would drop them.
+// FP32 -> FP16 with stochastic rounding, two values into one packed word
+// (lo in bits 0..15, hi in 16..31): gfx950's v_cvt_sr_f16_f32.  |y| lies
+// between two adjacent FP16 magnitudes and goes to the upper one when
+// F + (r >> 19) >= 2^13, F the first 13 bits of its position between them
+// (in the normal range all of it: FP32 keeps 13 bits below the FP16 spacing).
+// The expected stored value is y to 2^-13 of a spacing, so updates smaller
+// than one FP16 spacing are not lost; round to nearest would drop them.
+// Magnitudes past 65504 that round up become infinite.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t half2_bits_sr(float lo, uint32_t rlo, float hi, uint32_t rhi)
+{
+    half2_t v = {(_Float16)0.0f, (_Float16)0.0f};
+    v = __builtin_amdgcn_cvt_sr_f16_f32(v, lo, rlo, false);
+    v = __builtin_amdgcn_cvt_sr_f16_f32(v, hi, rhi, true);
+    return __builtin_bit_cast(uint32_t, v);
+}
+
 __device__ __forceinline__ unsigned short half_bits_sr(float y, uint32_t r)
 {
-    const uint32_t b = __float_as_uint(y);
-    uint32_t mag = b & 0x7fffffffu;
-    if (mag >= 0x38800000u) {  // |y| >= 2^-14
-        // adding U * 2^13 to the 13 discarded bits carries exactly when frac + U >= 1
-        mag = (mag + (r >> 19)) & ~0x1fffu;
-    } else {
-        const float m = __uint_as_float(mag) * 16777216.0f;  // |y| / 2^-24, exact
-        const float lo = floorf(m);
-        const float u = (float)(r >> 8) * 5.9604644775390625e-8f;  // (r >> 8) * 2^-24
-        const float up = (u >= 1.0f - (m - lo)) ? 1.0f : 0.0f;
-        mag = __float_as_uint((lo + up) * 5.9604644775390625e-8f);
-    }
-    // the value is now an FP16 number (or beyond the FP16 range: converts to inf)
-    return __half_as_ushort(__float2half_rn(__uint_as_float(mag | (b & 0x80000000u))));
+    return (unsigned short)(half2_bits_sr(y, r, 0.0f, 0u) & 0xffffu);
 }
 
 // Wait states after a buffer store whose offset comes from an SGPR.  This
@@ -221,7 +217,7 @@ struct NodeState<float, NF> {
         }
     }
     __device__ __forceinline__ static void store_sr(float *s, long long idx, const float (&v)[NF],
-                                                    const float (&sc)[2], const uint32_t (&)[4])
+                                                    const float (&sc)[2], const U32x4 &)
     {
         store(s, idx, v, sc);
     }
@@ -269,12 +265,19 @@ struct NodeState<__half, NF> {
         put(s, idx, b);
     }
     __device__ __forceinline__ static void store_sr(__half *s, long long idx, const float (&v)[NF],
-                                                    const float (&st)[2], const uint32_t (&r)[4])
+                                                    const float (&st)[2], const U32x4 &r)
     {
-        unsigned short b[NF];
+        if constexpr (NF == 4) {
+            reinterpret_cast<uint2 *>(s)[idx] =
+                make_uint2(half2_bits_sr(v[0] * st[0], r.x, v[1] * st[1], r.y),
+                           half2_bits_sr(v[2] * st[1], r.z, v[3] * st[1], r.w));
+        } else {
+            const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+            unsigned short b[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) b[f] = half_bits_sr(v[f] * st[f > 0], r[f]);
-        put(s, idx, b);
+            for (int f = 0; f < NF; ++f) b[f] = half_bits_sr(v[f] * st[f > 0], rw[f]);
+            put(s, idx, b);
+        }
     }
 };
 

@@ -126,9 +126,8 @@ __global__ __launch_bounds__(kGenericBlock) void k_fwd_generic(ProblemArgs p, co
         float out[D + 1], e;
         link_update<Q, MASK, FORCE, SPLIT>(p, idx, drx, ux, node_B(ux), fmask, fstate, out, e);
         if (std::is_same<T, __half>::value && p.fp16_sr) {
-            const U32x4 h = pcg4d((uint32_t)c.x, (uint32_t)c.y, (uint32_t)c.z, p.sr_word);
-            const uint32_t rw[4] = {h.x, h.y, h.z, h.w};
-            NodeState<T, D + 1>::store_sr(dst, idx, out, p.st_scale, rw);
+            NodeState<T, D + 1>::store_sr(dst, idx, out, p.st_scale,
+                                          sr_words((uint32_t)idx, p.sr_word));
         } else {
             NodeState<T, D + 1>::store(dst, idx, out, p.st_scale);
         }

@@ -32,7 +32,7 @@ struct ProblemArgs {
     float ld_scale[2];       // storage -> value: 2^-k (rho - 1, u); 1 for FP32
     float st_scale[2];       // value -> storage: 2^k
     int fp16_sr;             // FP16 storage: 1 stochastic rounding of step outputs, 0 nearest
-    uint32_t sr_word;        // fourth pcg4d input of this step: t ^ seed
+    uint32_t sr_word;        // second pcg2d input of this step: t ^ seed
     const uint8_t *mask;     // nullptr: all fluid
     const float *qd;         // link-wall distances, Q fields of n values (SoA), or nullptr: q = 1/2
     // wall velocities link by link (Q * D fields of n values: component k of

@@ -211,7 +211,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 if (!MASK || Am.cls < 2) {
                     const unsigned so = (unsigned)tz * plane_bytes;
                     if (std::is_same<T, __half>::value && p.fp16_sr) {
-                        const U32x4 h = pcg4d((uint32_t)gx, (uint32_t)gy, (uint32_t)tz, p.sr_word);
+                        const U32x4 h = sr_words((uint32_t)((long long)tz * plane + col), p.sr_word);
                         BufIO<T>::store_sr(rd, voff, so, D, vx, vy, vz, p.st_scale, h);
                     } else {
                         BufIO<T>::store(rd, voff, so, D, vx, vy, vz, p.st_scale);
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             const unsigned so = (unsigned)tz * plane_bytes;
             typename BufIO<T>::Raw out;
             if (SR) {  // FP16 storage, stochastic rounding (a template parameter: one path)
-                const U32x4 h = pcg4d((uint32_t)gx, (uint32_t)gy, (uint32_t)tz, p.sr_word);
+                const U32x4 h = sr_words((uint32_t)((long long)tz * plane + col), p.sr_word);
                 out = BufIO<T>::pack_sr(o.D, o.vx, o.vy, o.vz, p.st_scale, h);
             } else {
                 out = BufIO<T>::pack(o.D, o.vx, o.vy, o.vz, p.st_scale);

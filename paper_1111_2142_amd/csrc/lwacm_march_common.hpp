@@ -97,6 +97,11 @@ __device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned long long b
                                              (int)(unsigned)bytes, 0x00020000);
 }
 
+// Cache-policy bits of the state's buffer loads and stores (gfx950: bit 0
+// sc0, bit 1 nt, bit 4 sc1).
+constexpr int kStateLoadAux = 0;
+constexpr int kStateStoreAux = 0;
+
 template <class T>
 struct BufIO;
 
@@ -109,7 +114,7 @@ struct BufIO<float> {
     static constexpr unsigned kNodeBytes = 16;
     __device__ __forceinline__ static Raw load(Rsrc r, unsigned voff, unsigned soff)
     {
-        return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+        return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, kStateLoadAux));
     }
     // field f (0: rho - 1, 1..3: u) of a loaded node
     __device__ __forceinline__ static float value(const Raw &v, int f, float)
@@ -131,7 +136,7 @@ struct BufIO<float> {
     __device__ __forceinline__ static void store_raw(Rsrc r, unsigned voff, unsigned soff,
                                                      const Raw &v)
     {
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, kStateStoreAux);
         store_data_guard();
     }
     __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float d,
@@ -153,7 +158,7 @@ struct BufIO<__half> {
     static constexpr unsigned kNodeBytes = 8;
     __device__ __forceinline__ static Raw load(Rsrc r, unsigned voff, unsigned soff)
     {
-        return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kStateLoadAux);
     }
     __device__ __forceinline__ static float value(const Raw &v, int f, float inv_scale)
     {
@@ -180,13 +185,14 @@ struct BufIO<__half> {
     __device__ __forceinline__ static Raw pack_sr(float d, float ux, float uy, float uz,
                                                   const float (&st)[2], const U32x4 &h)
     {
-        return bits4(half_bits_sr(d * st[0], h.x), half_bits_sr(ux * st[1], h.y),
-                     half_bits_sr(uy * st[1], h.z), half_bits_sr(uz * st[1], h.w));
+        const Raw v = {half2_bits_sr(d * st[0], h.x, ux * st[1], h.y),
+                       half2_bits_sr(uy * st[1], h.z, uz * st[1], h.w)};
+        return v;
     }
     __device__ __forceinline__ static void store_raw(Rsrc r, unsigned voff, unsigned soff,
                                                      const Raw &v)
     {
-        __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, kStateStoreAux);
         store_data_guard();
     }
     __device__ __forceinline__ static void store(Rsrc r, unsigned voff, unsigned soff, float d,
