@@ -793,7 +793,8 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
             return LWACM_EDEVICE;
         if (two)
             e = lwacm::launch_fwd_march2(c->p, static_cast<const float *>(src),
-                                         static_cast<float *>(dst), r, c->stream);
+                                         static_cast<float *>(dst), c->d_bits, c->d_wallg, r,
+                                         c->stream);
         else if (march)
             e = lwacm::launch_fwd_march(c->p, c->storage, src, dst, c->d_cls, c->d_bits,
                                         c->d_wallg, r, c->stream);

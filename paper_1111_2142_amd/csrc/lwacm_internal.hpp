@@ -130,14 +130,16 @@ hipError_t launch_adj_march2(const ProblemArgs &p, int storage, const void *stat
                              const void *state_tm1, const float *mu_in, float *mu_out,
                              int final_t0, const ReduceArgs &r, hipStream_t stream);
 // Two D3Q19 forward steps per launch on FP32 state (same tiles as the
-// single-step kernel, its chunk depth halved while deeper than nz;
-// unmasked problems without body force, nz >= 8).  Stores the first step's
+// single-step kernel, its chunk depth halved while deeper than nz; halfway
+// walls (bb_bits and wallg from k_classify), no body force, no separate
+// omega_p, no per-step wall correction, nz >= 8).  Stores the first step's
 // partials in r.partials and the second step's in r.partials_b (2 doubles
 // per block each); finishes up to two deferred sums of earlier steps.
 bool march2_supported(const ProblemArgs &p);
 unsigned march2_num_blocks(const ProblemArgs &p);
 hipError_t launch_fwd_march2(const ProblemArgs &p, const float *src, float *dst,
-                             const ReduceArgs &r, hipStream_t stream);
+                             const unsigned *bb_bits, const float4 *wallg, const ReduceArgs &r,
+                             hipStream_t stream);
 
 // Several D2Q9 steps per launch (FP32 storage; no link-wall distances, link
 // velocities, omega_p or force field): 32 x 32 output tiles, up to

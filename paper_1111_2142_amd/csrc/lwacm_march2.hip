@@ -26,6 +26,13 @@
 // same order, as in the single-step kernel (the column helpers are shared),
 // so two steps of this kernel are bitwise equal to two single steps, and the
 // per-block mass and energy partials of both steps are the same numbers.
+//
+// Walls (MASK): halfway bounce-back and moving walls as in the single-step
+// kernel.  Every column loads its node's link set with the node's state; the
+// first step's nodes (tile and first ring) sum their bounced-back terms when
+// pushed and take the moving-wall term from the geometry sums, and the
+// second step uses the link set and class that the first step's push kept.
+// A solid node pushes nothing in either step and is written back unchanged.
 #include "lwacm_march_common.hpp"
 
 namespace lwacm {
@@ -78,10 +85,13 @@ __device__ __forceinline__ void finish_previous_sums2(const ReduceArgs &r)
     }
 }
 
-template <int NZC>
+template <int NZC, bool MASK>
 __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
                                                          const float *__restrict__ src,
-                                                         float *__restrict__ dst, ReduceArgs r)
+                                                         float *__restrict__ dst,
+                                                         const unsigned *__restrict__ bb_bits,
+                                                         const float4 *__restrict__ wallg,
+                                                         ReduceArgs r)
 {
     // one spare slot per array: idle lanes write there instead of branching
     __shared__ float2 xp1[4][NS1 + 1];
@@ -90,7 +100,6 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
     __shared__ float xd2[4][NS2 + 1];
     const Xchg<NS1 + 1> X1{xp1, xd1};
     const Xchg<NS2 + 1> X2{xp2, xd2};
-    constexpr bool MASK = false;
 
     const int tid = threadIdx.x;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
@@ -135,13 +144,23 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
     const Rsrc rs = make_rsrc(src, sbytes);
     const Rsrc rd = make_rsrc(dst, sbytes);
     const unsigned voff = col * NB;
-    auto issue = [&](Ring<float> &rg, int pz) {
-        rg.v = BufIO<float>::load(rs, voff, (unsigned)wrapz(pz) * plane_bytes);
+    // link sets of the ring's planes (MASK): bit i set when x - v_i is solid,
+    // bit 0 alone for a solid node, plus the moving-wall flag
+    const Rsrc rbits = make_rsrc(bb_bits, MASK ? (unsigned long long)n * 4u : 0ull);
+    unsigned bw[RING] = {0u, 0u, 0u};
+    auto issue = [&](int j, Ring<float> &rg, int pz) {
+        const unsigned pw = (unsigned)wrapz(pz);
+        rg.v = BufIO<float>::load(rs, voff, pw * plane_bytes);
+        if (MASK)
+            bw[j] = __builtin_amdgcn_raw_buffer_load_b32(rbits, col * 4u, pw * (unsigned)(plane * 4),
+                                                         0);
     };
+    auto class_of = [](unsigned b) { return (b & 1u) ? 2 : (b ? 1 : 0); };
 
     Ring<float> ring[RING];
 #pragma unroll
-    for (int j = 0; j < RING; ++j) issue(ring[j], z0 - 2 + j);
+    for (int j = 0; j < RING; ++j) issue(j, ring[j], z0 - 2 + j);
+    f32x4 raw[RING];  // the tile's loaded values, written back by solid nodes (MASK)
 
     float m1 = 0.0f, e1 = 0.0f, m2 = 0.0f, e2 = 0.0f;
     constexpr int N = NZC + 4;  // planes z0 - 2 .. z1 + 1
@@ -168,15 +187,17 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
     auto refill = [&](int k, auto It) {
         using I = decltype(It);
         __builtin_amdgcn_sched_barrier(0);
-        if (I::refill) issue(ring[I::j], z0 - 2 + k + RING);
+        if (I::refill) issue(I::j, ring[I::j], z0 - 2 + k + RING);
     };
     // Step t pushes of the plane loaded for iteration k (pz = z0 - 2 + k).
-    auto first_push = [&](int k, auto It) {
+    auto first_push = [&](int k, auto It, bool tile) {
         using I = decltype(It);
         __builtin_amdgcn_sched_barrier(0);  // no work of this iteration moves up
         const f32x4 v = ring[I::j].v;
-        push_column<MASK>(v.x, v.y, v.z, v.w, 0, 0u, A, a, acc1[(I::j + 1) % 3], acc1[I::j],
-                          acc1[(I::j + 2) % 3]);
+        const unsigned b = bw[I::j];
+        if (MASK && tile) raw[I::j] = v;
+        push_column<MASK>(v.x, v.y, v.z, v.w, MASK ? class_of(b) : 0, b, A, a,
+                          acc1[(I::j + 1) % 3], acc1[I::j], acc1[(I::j + 2) % 3]);
         refill(k, It);
     };
     // Step t + 1 at plane tq = pz - 1 (z0 - 1 .. z1) and its step-(t + 2)
@@ -187,19 +208,23 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
         put_slot(X1, wslot1, Am);
         __syncthreads();
         const int tq = z0 - 3 + k;
-        const NodeOut o = finalize<MASK, NS1 + 1, SX1>(X1, slot1, Am, p, nullptr, 0);
+        const NodeOut o = finalize<MASK, NS1 + 1, SX1>(X1, slot1, Am, p, wallg,
+                                                       (long long)wrapz(tq) * plane + col);
+        // the node's class and link set at plane tq, kept by its first push
+        const int cls = MASK ? Am.cls : 0;
+        const unsigned bits = MASK ? Am.bits : 0u;
         if (tile) {
-            const bool count = tq >= zs && tq < z1;
+            const bool count = tq >= zs && tq < z1 && cls < 2;
             m1 += count ? o.D : 0.0f;
             e1 = count ? fmaf(o.vx, o.vx, fmaf(o.vy, o.vy, fmaf(o.vz, o.vz, e1))) : e1;
         }
         if (tile) {
-            push_column<MASK>(o.D, o.vx, o.vy, o.vz, 0, 0u, A, a, acc2[(I::j + 1) % 3], acc2[I::j],
-                              acc2[(I::j + 2) % 3]);
+            push_column<MASK>(o.D, o.vx, o.vy, o.vz, cls, bits, A, a, acc2[(I::j + 1) % 3],
+                              acc2[I::j], acc2[(I::j + 2) % 3]);
             if (I::phase >= 4) put_slot(X2, wslot2, acc2[(I::j + 2) % 3]);
         } else {
             constexpr int j = I::j, j1 = (j + 1) % 3, jm = (j + 2) % 3;
-            push_halo<MASK>(o.D, o.vx, o.vy, o.vz, 0, A, isY2, sgn2, hp[j1], hz[j1], hp[j],
+            push_halo<MASK>(o.D, o.vx, o.vy, o.vz, cls, A, isY2, sgn2, hp[j1], hz[j1], hp[j],
                             hd1[j], hd2[j], hp[jm], hz[jm]);
             if (I::phase >= 4) put_halo(X2, wslot2, isY2, sgn2, hp[jm], hz[jm], hd1[jm], hd2[jm]);
         }
@@ -209,24 +234,27 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
     if (tid < NINT) {
         plane_loop<N>([&](int k, auto kc) {
             using I = PlaneIter<decltype(kc)::value, N, RING>;
-            first_push(k, I{});
+            first_push(k, I{}, true);
             if (I::phase < 2) return;
             middle(k, I{}, true);
             if (I::phase < 4) return;
             // ---- step t + 2 at plane tz = pz - 2 (z0 .. z1 - 1)
             const int tz = z0 - 4 + k;
-            const NodeOut o2 = finalize<MASK, NS2 + 1, SX2>(X2, slot2, acc2[(I::j + 2) % 3], p,
-                                                            nullptr, 0);
-            BufIO<float>::store(rd, voff, (unsigned)tz * plane_bytes, o2.D, o2.vx, o2.vy, o2.vz,
-                                p.st_scale);
-            const bool count = tz >= zs;
+            const Acc &A2 = acc2[(I::j + 2) % 3];
+            const NodeOut o2 = finalize<MASK, NS2 + 1, SX2>(X2, slot2, A2, p, wallg,
+                                                            (long long)tz * plane + col);
+            f32x4 out = BufIO<float>::pack(o2.D, o2.vx, o2.vy, o2.vz, p.st_scale);
+            const bool solid = MASK && A2.cls >= 2;
+            if (MASK) out = solid ? raw[(I::j + 1) % 3] : out;  // plane tz's loaded values
+            BufIO<float>::store_raw(rd, voff, (unsigned)tz * plane_bytes, out);
+            const bool count = tz >= zs && !solid;
             m2 += count ? o2.D : 0.0f;
             e2 = count ? fmaf(o2.vx, o2.vx, fmaf(o2.vy, o2.vy, fmaf(o2.vz, o2.vz, e2))) : e2;
         });
     } else if (tid < HALO0) {
         plane_loop<N>([&](int k, auto kc) {
             using I = PlaneIter<decltype(kc)::value, N, RING>;
-            first_push(k, I{});
+            first_push(k, I{}, false);
             if (I::phase < 2) return;
             middle(k, I{}, false);
         });
@@ -236,8 +264,8 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
             constexpr int j = I::j, j1 = (j + 1) % 3, jm = (j + 2) % 3;
             __builtin_amdgcn_sched_barrier(0);
             const f32x4 v = ring[j].v;
-            push_halo<MASK>(v.x, v.y, v.z, v.w, 0, A, isY, sgn, hp[j1], hz[j1], hp[j], hd1[j],
-                            hd2[j], hp[jm], hz[jm]);
+            push_halo<MASK>(v.x, v.y, v.z, v.w, MASK ? class_of(bw[j]) : 0, A, isY, sgn, hp[j1],
+                            hz[j1], hp[j], hd1[j], hd2[j], hp[jm], hz[jm]);
             refill(k, I{});
             if (I::phase < 2) return;
             put_halo(X1, wslot1, isY, sgn, hp[jm], hz[jm], hd1[jm], hd2[jm]);
@@ -269,8 +297,10 @@ int march2_nzc(const ProblemArgs &p)
 
 bool march2_supported(const ProblemArgs &p)
 {
-    return march_supported(p) && !p.mask && !p.split && !p.has_force && p.march_nzc > 0 &&
-           p.nz >= 8;
+    // halfway walls (moving or not) allowed; the per-step wall correction of
+    // interpolated walls and link velocities needs one launch per step
+    return march_supported(p) && !p.corr && !p.qd && !p.uwl && !p.split && !p.has_force &&
+           p.march_nzc > 0 && p.nz >= 8;
 }
 
 unsigned march2_num_blocks(const ProblemArgs &p)
@@ -280,20 +310,33 @@ unsigned march2_num_blocks(const ProblemArgs &p)
     return (unsigned)((long long)(p.nx / TX) * (p.ny / TY) * ((p.nz + c - 1) / c));
 }
 
-hipError_t launch_fwd_march2(const ProblemArgs &p, const float *src, float *dst,
-                             const ReduceArgs &r, hipStream_t s)
+template <bool MASK>
+hipError_t launch_march2_t(const ProblemArgs &p, const float *src, float *dst,
+                           const unsigned *bb_bits, const float4 *wallg, const ReduceArgs &r,
+                           hipStream_t s)
 {
-    if (!march2_supported(p) || !r.partials_b) return hipErrorNotSupported;
     const unsigned nb = march2_num_blocks(p);
     switch (march2_nzc(p)) {
-    case 8: k_fwd_march2<8><<<nb, NTHREADS, 0, s>>>(p, src, dst, r); break;
-    case 16: k_fwd_march2<16><<<nb, NTHREADS, 0, s>>>(p, src, dst, r); break;
-    case 32: k_fwd_march2<32><<<nb, NTHREADS, 0, s>>>(p, src, dst, r); break;
-    case 64: k_fwd_march2<64><<<nb, NTHREADS, 0, s>>>(p, src, dst, r); break;
-    case 128: k_fwd_march2<128><<<nb, NTHREADS, 0, s>>>(p, src, dst, r); break;
+    case 8: k_fwd_march2<8, MASK><<<nb, NTHREADS, 0, s>>>(p, src, dst, bb_bits, wallg, r); break;
+    case 16: k_fwd_march2<16, MASK><<<nb, NTHREADS, 0, s>>>(p, src, dst, bb_bits, wallg, r); break;
+    case 32: k_fwd_march2<32, MASK><<<nb, NTHREADS, 0, s>>>(p, src, dst, bb_bits, wallg, r); break;
+    case 64: k_fwd_march2<64, MASK><<<nb, NTHREADS, 0, s>>>(p, src, dst, bb_bits, wallg, r); break;
+    case 128:
+        k_fwd_march2<128, MASK><<<nb, NTHREADS, 0, s>>>(p, src, dst, bb_bits, wallg, r);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_fwd_march2(const ProblemArgs &p, const float *src, float *dst,
+                             const unsigned *bb_bits, const float4 *wallg, const ReduceArgs &r,
+                             hipStream_t s)
+{
+    if (!march2_supported(p) || !r.partials_b) return hipErrorNotSupported;
+    if (p.mask && !bb_bits) return hipErrorInvalidValue;  // the link sets come from k_classify
+    return p.mask ? launch_march2_t<true>(p, src, dst, bb_bits, wallg, r, s)
+                  : launch_march2_t<false>(p, src, dst, nullptr, nullptr, r, s);
 }
 
 }  // namespace lwacm
