@@ -103,15 +103,16 @@ def _cavity_leg(args, L, wl, dev, stream):
             "wall_force_ms": round(ms_force, 4),
             "walls_at_rest_force": [round(v, 8) for v in f_w],
             "walls_at_rest_torque": [round(v, 8) for v in t_w],
-            "kernel": "k_fwd_march_rolled<float,64,false,true,false,0>",
-            "traffic": _measured_traffic("k_fwd_march_rolled<float,64,false,true,false,0>")}
+            "kernel": "k_fwd_march2<64,true>",
+            "traffic": _measured_traffic("k_fwd_march2<64,true>")}
 
 
 def _qbb_leg(args, L, wl, dev, stream):
     """The 192^3 lid-driven cavity with interpolated bounce-back: every wall
     cuts its links at q = 0.3 (d_q of lwacm_init).  Each step is the wall
-    correction over the fluid nodes next to a wall (k_wall_correction) and
-    the masked single-step tile kernel, which adds it to its halfway terms."""
+    correction over the fluid nodes next to a wall (k_wall_correction: the
+    whole wall term of each) and the masked single-step tile kernel, which
+    adds it in place of its own bounce-back sums."""
     import torch
     c4 = wl.CAVITY_192
     m4 = torch.as_tensor(wl.cavity_mask(c4.nx), device=dev)
@@ -132,8 +133,8 @@ def _qbb_leg(args, L, wl, dev, stream):
     return {"value": round(fluid * args.steps / dt8 / 1e6, 1), "unit": "MLUPS (fluid nodes)",
             "ms_per_step": round(ms8, 5), "q": 0.3,
             "achieved_GBs": round(33.0 * c4.nx * c4.ny * c4.nz / (ms8 * 1e-3) / 1e9, 1),
-            "kernel": "k_fwd_march_rolled<float,64,false,true,false,0> + k_wall_correction<float>",
-            "traffic": _measured_traffic("k_fwd_march_rolled<float,64,false,true,false,0>"),
+            "kernel": "k_fwd_march_rolled<float,64,false,true,false,0,true> + k_wall_correction<float>",
+            "traffic": _measured_traffic("k_fwd_march_rolled<float,64,false,true,false,0,true>"),
             "basis": "33 B per node (state in and out, uint8 mask), the figure of the halfway "
                      "cavity; the wall correction reads the state, q and the second node of "
                      "the fluid nodes next to a wall and writes one float4 for each"}
@@ -154,7 +155,7 @@ def _split_leg(args, L, wl, dev, stream, drho_t, u_t, n):
     ms6 = dt6 / args.steps * 1e3
     nodes = n ** 3
     print(f"[bench] omega_p split {n}^3: {ms6:.4f} ms/step", file=sys.stderr, flush=True)
-    kname = "k_fwd_march_rolled<float,128,false,false,true,0>"
+    kname = "k_fwd_march_rolled<float,128,false,false,true,0,false>"
     return {"value": round(nodes * args.steps / dt6 / 1e6, 1), "unit": "MLUPS",
             "ms_per_step": round(ms6, 5), "nu_p_over_nu": 10.0,
             "achieved_GBs": round(32.0 * nodes / (ms6 * 1e-3) / 1e9, 1),
@@ -187,8 +188,8 @@ def _field_leg(args, L, wl, dev, stream, drho_t, u_t, n):
             "ms_per_step": round(ms7, 5),
             "achieved_GBs": round(44.0 * nodes / (ms7 * 1e-3) / 1e9, 1),
             "frac": round(44.0 * nodes / (ms7 * 1e-3) / 8.0e12, 4),
-            "kernel": "k_fwd_march_rolled<float,128,false,false,false,2>" if n == 256 else None,
-            "traffic": _measured_traffic("k_fwd_march_rolled<float,128,false,false,false,2>")
+            "kernel": "k_fwd_march_rolled<float,128,false,false,false,2,false>" if n == 256 else None,
+            "traffic": _measured_traffic("k_fwd_march_rolled<float,128,false,false,false,2,false>")
             if n == 256 else None,
             "basis": "44 B per update (state read and written, three FP32 acceleration "
                      "fields read); one step per launch on the single-step tile kernel"}
@@ -408,7 +409,7 @@ def main():
           f"energy {energy:.6e}", file=sys.stderr, flush=True)
 
     fused = n == 256 and args.variant in (0, 3) and args.steps % 2 == 0
-    kname = "k_fwd_march2<128>" if fused else "k_fwd_march_rolled<float,128,false,false,false,0>"
+    kname = "k_fwd_march2<128,false>" if fused else "k_fwd_march_rolled<float,128,false,false,false,0,false>"
     per_launch = 2 if fused else 1
     vi = _measured(kname, "valu_insts_per_launch") if n == 256 else None
     traffic = _measured_traffic(kname) if n == 256 else None
@@ -495,8 +496,8 @@ def main():
         "ms_per_step": round(ms1, 5),
         "achieved_GBs": round(32.0 * nodes / (ms1 * 1e-3) / 1e9, 1),
         "frac": round(32.0 * nodes / (ms1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "kernel": "k_fwd_march_rolled<float,128,false,false,false,0>" if n == 256 else None,
-        "traffic": _measured_traffic("k_fwd_march_rolled<float,128,false,false,false,0>")
+        "kernel": "k_fwd_march_rolled<float,128,false,false,false,0,false>" if n == 256 else None,
+        "traffic": _measured_traffic("k_fwd_march_rolled<float,128,false,false,false,0,false>")
         if n == 256 else None}
 
     # ---- FP16-deviation storage
@@ -516,9 +517,9 @@ def main():
                             "ms_per_step": round(ms16, 5), "rounding": "stochastic (pcg2d words, hardware conversion)",
                             "achieved_GBs": round(16.0 * nodes / dt16 * args.steps / 1e9, 1),
                             "ms_per_step_nearest_rounding": round(dt16n / args.steps * 1e3, 5),
-                            "kernel": "k_fwd_march_rolled<__half,128,true,false,false,0>"
+                            "kernel": "k_fwd_march_rolled<__half,128,true,false,false,0,false>"
                             if n == 256 else None,
-                            "traffic": _measured_traffic("k_fwd_march_rolled<__half,128,true,false,false,0>")
+                            "traffic": _measured_traffic("k_fwd_march_rolled<__half,128,true,false,false,0,false>")
                             if n == 256 else None}
 
     # ---- reverse step at the same size (reads state_t and mu_t, writes mu_{t-1});

@@ -195,7 +195,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
                 if (MASK && cls == 1 && pz >= z0 && pz < z1)
                     bits = bb_bits[(long long)pz * plane + col];
 
-                push_column<MASK>(dr, ux, uy, uz, cls, bits, A, a, A1, A0, Am);
+                push_column<MASK>(dr, ux, uy, uz, cls, bits, A, a, A1, A0, Am, p.corr == nullptr);
 
                 if (k < 2) return;  // planes below the chunk are halo only
                 // ---- exchange the partials of plane pz - 1 through LDS
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
 // from p.g_field (loaded with the state).  The forcing adds rho(x, t) g(x) to
 // the node's momentum; it enters the node's post-combine term a rho u through
 // the addend of its FMA, where it meets a node-dependent product.
-template <class T, int NZC, bool SR, bool MASK, bool SPLIT, int FRC>
+template <class T, int NZC, bool SR, bool MASK, bool SPLIT, int FRC, bool CORR>
 __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
                                                                const T *__restrict__ src,
                                                                T *__restrict__ dst,
@@ -363,7 +363,10 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
     // per-step wall correction (interpolated walls, link velocities): one
     // float4 per node next to a wall, loaded at the top of the iteration that
     // finalises its plane so that its latency hides behind the plane's work
-    const bool corr = MASK && p.corr != nullptr;
+    // CORR: interpolated walls or link velocities, the wall term from the
+    // per-step correction (p.corr) in place of the bounce-back sums
+    static_assert(!CORR || MASK, "the wall correction needs walls");
+    constexpr bool corr = CORR;
     const Rsrc rcorr = make_rsrc(corr ? (const void *)p.corr : nullptr,
                                  corr ? (unsigned long long)n * 16u : 0ull);
 
@@ -389,7 +392,6 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
         Acc acc[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) acc[j] = Acc{};
-        typename BufIO<T>::Raw raw[3];  // loaded values, stored back by solid nodes (MASK)
         plane_loop<N>([&](int k, auto kc) {
             using I = PlaneIter<decltype(kc)::value, N, 3>;
             constexpr int j = I::j;
@@ -397,12 +399,11 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             float dr, ux, uy, uz;
             value(ring[j], dr, ux, uy, uz);
             const unsigned b = bw[j];
-            if (MASK) raw[j] = ring[j].v;
             Acc &Am = acc[(j + 2) % 3];  // target plane pz - 1 (finalised now)
-            // the correction of plane pz - 1, loaded two iterations ago
+            // the correction of plane pz - 1, loaded in the previous iteration
             const f32x4 cw = cwr[(j + 2) % 3];
             push_column<MASK>(dr, ux, uy, uz, MASK ? class_of(b) : 0, b, A, a, acc[(j + 1) % 3],
-                              acc[j], Am);
+                              acc[j], Am, !corr);
             if (SPLIT) push_split_column(1.0f + dr, ux, uy, uz, dA, acc[(j + 1) % 3], acc[j], Am);
             if (FRC) {  // post-combine a rho u plus the forcing rho g
                 const float rho = 1.0f + dr, arho = a * rho;
@@ -413,19 +414,17 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
                 acc[j].post[1] = fmaf(arho, uy, rho * gy);
                 acc[j].post[2] = fmaf(arho, uz, rho * gz);
             }
-            if constexpr (MASK) {
-                // the correction of plane pz + 1 (its link set is in the ring
-                // already), finalised two iterations from now: issued before
+            if constexpr (CORR) {
+                // the correction of plane pz (its link set is this
+                // iteration's), finalised in the next iteration: issued before
                 // this iteration's ring refill, so waiting for it then waits
-                // for no load that is not due by then.  Lanes away from the
-                // walls ask for an offset past the end of the buffer: zeros,
-                // no memory access.
-                const unsigned b1 = bw[(j + 1) % 3];
-                cwr[(j + 1) % 3] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-                if (corr && __builtin_amdgcn_ballot_w64(b1 > 1u) != 0ull) {
-                    const unsigned node = (unsigned)wrap_index(z0 + k, nz) * (unsigned)plane + col;
-                    cwr[(j + 1) % 3] =
-                        BufIO<float>::load(rcorr, b1 > 1u ? node * 16u : 0xfffffff0u, 0u);
+                // for no load that is not due by then.  Two slots of cwr are
+                // live at a time.  Lanes away from the walls ask for an offset
+                // past the end of the buffer: zeros, no memory access.
+                cwr[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                if (__builtin_amdgcn_ballot_w64(b > 1u) != 0ull) {
+                    const unsigned node = (unsigned)wrap_index(z0 - 1 + k, nz) * (unsigned)plane + col;
+                    cwr[j] = BufIO<float>::load(rcorr, b > 1u ? node * 16u : 0xfffffff0u, 0u);
                 }
             }
             __builtin_amdgcn_sched_barrier(0);  // the ring slot's last use is above
@@ -453,8 +452,16 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
                 out = BufIO<T>::pack(o.D, o.vx, o.vy, o.vz, p.st_scale);
             }
             const bool solid = MASK && Am.cls >= 2;
-            if (MASK) out = solid ? raw[(j + 2) % 3] : out;
-            BufIO<T>::store_raw(rd, voff, so, out);
+            if (MASK) {
+                // a solid node keeps its state, which both buffers hold
+                // (lwacm_set_state and lwacm_load_state write both): its
+                // store goes past the end of the buffer (n * NB <= 2^32 - 16
+                // bytes), where the hardware drops it; the store itself stays
+                // unconditional
+                BufIO<T>::store_raw(rd, solid ? 0xfffffff0u : voff + so, 0u, out);
+            } else {
+                BufIO<T>::store_raw(rd, voff, so, out);
+            }
             const bool count = tz >= zs && !solid;
             mass += count ? o.D : 0.0f;
             energy = count ? fmaf(o.vx, o.vx, fmaf(o.vy, o.vy, fmaf(o.vz, o.vz, energy))) : energy;
@@ -556,28 +563,42 @@ __global__ __launch_bounds__(256) void k_classify(ProblemArgs p, uint8_t *cls, u
     }
 }
 
-template <class T, bool SR, bool MASK, bool SPLIT = false, int FRC = 0>
+template <class T, bool SR, bool MASK, bool SPLIT = false, int FRC = 0, bool CORR = false>
 void launch_rolled(int c, unsigned nb, hipStream_t s, const ProblemArgs &p, const T *a, T *b,
                    const unsigned *bits, const float4 *wallg, const ReduceArgs &r)
 {
     switch (c) {
-    case 8: k_fwd_march_rolled<T, 8, SR, MASK, SPLIT, FRC><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    case 16: k_fwd_march_rolled<T, 16, SR, MASK, SPLIT, FRC><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    case 32: k_fwd_march_rolled<T, 32, SR, MASK, SPLIT, FRC><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    case 64: k_fwd_march_rolled<T, 64, SR, MASK, SPLIT, FRC><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    default: k_fwd_march_rolled<T, 128, SR, MASK, SPLIT, FRC><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 8: k_fwd_march_rolled<T, 8, SR, MASK, SPLIT, FRC, CORR><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 16: k_fwd_march_rolled<T, 16, SR, MASK, SPLIT, FRC, CORR><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 32: k_fwd_march_rolled<T, 32, SR, MASK, SPLIT, FRC, CORR><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 64: k_fwd_march_rolled<T, 64, SR, MASK, SPLIT, FRC, CORR><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    default: k_fwd_march_rolled<T, 128, SR, MASK, SPLIT, FRC, CORR><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
     }
 }
 
 // forced problems (march_supported: nz >= 8, no separate omega_p)
-template <class T, bool SR, bool MASK>
+template <class T, bool SR, bool MASK, bool CORR = false>
 void launch_rolled_forced(int c, unsigned nb, hipStream_t s, const ProblemArgs &p, const T *a,
                           T *b, const unsigned *bits, const float4 *wallg, const ReduceArgs &r)
 {
     if (p.g_field)
-        launch_rolled<T, SR, MASK, false, 2>(c, nb, s, p, a, b, bits, wallg, r);
+        launch_rolled<T, SR, MASK, false, 2, CORR>(c, nb, s, p, a, b, bits, wallg, r);
     else
-        launch_rolled<T, SR, MASK, false, 1>(c, nb, s, p, a, b, bits, wallg, r);
+        launch_rolled<T, SR, MASK, false, 1, CORR>(c, nb, s, p, a, b, bits, wallg, r);
+}
+
+// walls: halfway bounce-back in the kernel, or the per-step wall correction
+template <class T, bool SR>
+void launch_rolled_walls(int c, unsigned nb, hipStream_t s, const ProblemArgs &p, const T *a,
+                         T *b, const unsigned *bits, const float4 *wallg, const ReduceArgs &r)
+{
+    if (p.has_force) {
+        if (p.corr) launch_rolled_forced<T, SR, true, true>(c, nb, s, p, a, b, bits, wallg, r);
+        else launch_rolled_forced<T, SR, true, false>(c, nb, s, p, a, b, bits, wallg, r);
+    } else {
+        if (p.corr) launch_rolled<T, SR, true, false, 0, true>(c, nb, s, p, a, b, bits, wallg, r);
+        else launch_rolled<T, SR, true>(c, nb, s, p, a, b, bits, wallg, r);
+    }
 }
 
 template <class T>
@@ -595,17 +616,12 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
             k_fwd_march<T, true, 32><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
         else
             k_fwd_march<T, false, 32><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
-    } else if (p.has_force) {
-        if (p.mask) {
-            if (sr) launch_rolled_forced<T, true, true>(c, nb, s, p, a, b, bits, wallg, r);
-            else launch_rolled_forced<T, false, true>(c, nb, s, p, a, b, bits, wallg, r);
-        } else {
-            if (sr) launch_rolled_forced<T, true, false>(c, nb, s, p, a, b, bits, wallg, r);
-            else launch_rolled_forced<T, false, false>(c, nb, s, p, a, b, bits, wallg, r);
-        }
     } else if (p.mask) {
-        if (sr) launch_rolled<T, true, true>(c, nb, s, p, a, b, bits, wallg, r);
-        else launch_rolled<T, false, true>(c, nb, s, p, a, b, bits, wallg, r);
+        if (sr) launch_rolled_walls<T, true>(c, nb, s, p, a, b, bits, wallg, r);
+        else launch_rolled_walls<T, false>(c, nb, s, p, a, b, bits, wallg, r);
+    } else if (p.has_force) {
+        if (sr) launch_rolled_forced<T, true, false>(c, nb, s, p, a, b, bits, wallg, r);
+        else launch_rolled_forced<T, false, false>(c, nb, s, p, a, b, bits, wallg, r);
     } else if (p.split) {  // separate omega_p (no walls, nz >= 8: march_supported)
         if (sr) launch_rolled<T, true, false, true>(c, nb, s, p, a, b, bits, wallg, r);
         else launch_rolled<T, false, false, true>(c, nb, s, p, a, b, bits, wallg, r);

@@ -32,7 +32,8 @@
 // first step's nodes (tile and first ring) sum their bounced-back terms when
 // pushed and take the moving-wall term from the geometry sums, and the
 // second step uses the link set and class that the first step's push kept.
-// A solid node pushes nothing in either step and is written back unchanged.
+// A solid node pushes nothing in either step and is not written: both state
+// buffers hold its unchanged values.
 #include "lwacm_march_common.hpp"
 
 namespace lwacm {
@@ -160,7 +161,6 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
     Ring<float> ring[RING];
 #pragma unroll
     for (int j = 0; j < RING; ++j) issue(j, ring[j], z0 - 2 + j);
-    f32x4 raw[RING];  // the tile's loaded values, written back by solid nodes (MASK)
 
     float m1 = 0.0f, e1 = 0.0f, m2 = 0.0f, e2 = 0.0f;
     constexpr int N = NZC + 4;  // planes z0 - 2 .. z1 + 1
@@ -190,12 +190,11 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
         if (I::refill) issue(I::j, ring[I::j], z0 - 2 + k + RING);
     };
     // Step t pushes of the plane loaded for iteration k (pz = z0 - 2 + k).
-    auto first_push = [&](int k, auto It, bool tile) {
+    auto first_push = [&](int k, auto It) {
         using I = decltype(It);
         __builtin_amdgcn_sched_barrier(0);  // no work of this iteration moves up
         const f32x4 v = ring[I::j].v;
         const unsigned b = bw[I::j];
-        if (MASK && tile) raw[I::j] = v;
         push_column<MASK>(v.x, v.y, v.z, v.w, MASK ? class_of(b) : 0, b, A, a,
                           acc1[(I::j + 1) % 3], acc1[I::j], acc1[(I::j + 2) % 3]);
         refill(k, It);
@@ -234,7 +233,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
     if (tid < NINT) {
         plane_loop<N>([&](int k, auto kc) {
             using I = PlaneIter<decltype(kc)::value, N, RING>;
-            first_push(k, I{}, true);
+            first_push(k, I{});
             if (I::phase < 2) return;
             middle(k, I{}, true);
             if (I::phase < 4) return;
@@ -243,10 +242,14 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
             const Acc &A2 = acc2[(I::j + 2) % 3];
             const NodeOut o2 = finalize<MASK, NS2 + 1, SX2>(X2, slot2, A2, p, wallg,
                                                             (long long)tz * plane + col);
-            f32x4 out = BufIO<float>::pack(o2.D, o2.vx, o2.vy, o2.vz, p.st_scale);
+            const f32x4 out = BufIO<float>::pack(o2.D, o2.vx, o2.vy, o2.vz, p.st_scale);
             const bool solid = MASK && A2.cls >= 2;
-            if (MASK) out = solid ? raw[(I::j + 1) % 3] : out;  // plane tz's loaded values
-            BufIO<float>::store_raw(rd, voff, (unsigned)tz * plane_bytes, out);
+            const unsigned so = (unsigned)tz * plane_bytes;
+            if (MASK)  // a solid node's store is dropped past the buffer's end: both buffers
+                       // hold its state (see the single-step kernel)
+                BufIO<float>::store_raw(rd, solid ? 0xfffffff0u : voff + so, 0u, out);
+            else
+                BufIO<float>::store_raw(rd, voff, so, out);
             const bool count = tz >= zs && !solid;
             m2 += count ? o2.D : 0.0f;
             e2 = count ? fmaf(o2.vx, o2.vx, fmaf(o2.vy, o2.vy, fmaf(o2.vz, o2.vz, e2))) : e2;
@@ -254,7 +257,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march2(ProblemArgs p,
     } else if (tid < HALO0) {
         plane_loop<N>([&](int k, auto kc) {
             using I = PlaneIter<decltype(kc)::value, N, RING>;
-            first_push(k, I{}, false);
+            first_push(k, I{});
             if (I::phase < 2) return;
             middle(k, I{}, false);
         });

@@ -310,10 +310,13 @@ __device__ __forceinline__ void push_bounce_back(unsigned bits, float Lpx, float
     bb[3] = sz;
 }
 
+// bounce: sum the halfway bounced-back terms here; false where a per-step
+// wall correction brings the whole wall term instead (interpolated walls,
+// link velocities).
 template <bool MASK>
 __device__ __forceinline__ void push_column(float dr, float ux, float uy, float uz, int cls,
                                             unsigned bits, float A, float a, Acc &A1, Acc &A0,
-                                            Acc &Am)
+                                            Acc &Am, bool bounce = true)
 {
     const float rho = 1.0f + dr;
     const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
@@ -372,8 +375,8 @@ __device__ __forceinline__ void push_column(float dr, float ux, float uy, float 
     if (MASK) {
         A0.cls = cls;
         A0.bits = bits;
-        push_bounce_back(bits, Lpx, Lmx, Lpy, Lmy, Lpz, Lmz, Lpp0, Lmm0, Lpm0, Lmp0, Lp0p, Lm0m,
-                         Lp0m, Lm0p, L0pp, L0mm, L0pm, L0mp, A0.bb);
+        push_bounce_back(bounce ? bits : 0u, Lpx, Lmx, Lpy, Lmy, Lpz, Lmz, Lpp0, Lmm0, Lpm0, Lmp0,
+                         Lp0p, Lm0m, Lp0m, Lm0p, L0pp, L0mm, L0pm, L0mp, A0.bb);
     }
     // links with v_z = -1 finish plane pz - 1
     Am.pe += Lp0m;
@@ -460,9 +463,10 @@ __device__ __forceinline__ NodeOut finish(const Gathered &g, const Acc &Am, cons
         Jz += Am.bb[3];
         if (p.corr) {
             // interpolated walls or link velocities (Eqs. ACM2.0cc, ACM2.0move):
-            // this step's correction of every node next to a wall, wall
-            // motion included (made by the wall-correction kernel); cw is
-            // the value the caller loaded ahead (zero away from the walls)
+            // this step's whole wall term of every node next to a wall, wall
+            // motion included, made by the wall-correction kernel (the push
+            // summed no bounced-back terms: bb is zero); cw is the value the
+            // caller loaded ahead (zero away from the walls)
             if (cw) {
                 D36 += cw->x;
                 Jx += cw->y;

@@ -13,18 +13,17 @@
 //
 // Correction.  The link data that stay fixed with the walls (q of each wall
 // link, and whether the q < 1/2 rule finds a fluid second node) are packed
-// once per context, link-major, so a step reads them contiguously.  The
-// tile kernel returns, for every incoming link i whose
-// upstream node x - v_i is solid, the node's own term of the opposite link
-// ib (the halfway rule, Eq. ACM2.0ccbb).  The interpolated rule replaces
-// that term by 2q L_ib(x) + (1 - 2q) L_ib(x - v_ib) (q < 1/2, where x - v_ib
-// is fluid) or L_ib(x)/(2q) + (1 - 1/(2q)) L_i(x) (q >= 1/2), and scales the
-// moving-wall term (2/omega - 1) 2 f^(e,o)(rho0, u_w) by 1/(2q) for q >= 1/2
-// (Eq. ACM2.0move).  Per node this kernel sums, with the integer weights
-// 36 w_i, the difference to the halfway term plus the whole moving-wall term
-// into (1, v_i): one float4 the tile kernel adds before normalisation.  The
-// forcing term cancels in the difference (both mixtures have weights that
-// sum to one).
+// once per context, link-major, so a step reads them contiguously.  For
+// every incoming link i whose upstream node x - v_i is solid, the halfway
+// rule (Eq. ACM2.0ccbb) returns the node's own term of the opposite link ib;
+// the interpolated rule replaces it by 2q L_ib(x) + (1 - 2q) L_ib(x - v_ib)
+// (q < 1/2, where x - v_ib is fluid) or L_ib(x)/(2q) + (1 - 1/(2q)) L_i(x)
+// (q >= 1/2), and scales the moving-wall term (2/omega - 1) 2 f^(e,o)(rho0,
+// u_w) by 1/(2q) for q >= 1/2 (Eq. ACM2.0move).  Per node this kernel sums
+// these terms, moving wall included, with the integer weights 36 w_i into
+// (1, v_i): one float4 that the tile kernel adds before normalisation in
+// place of its own bounce-back sums, which it skips for such problems.  The
+// forcing term is not in it: the tile kernel adds rho g as a whole.
 #include "lwacm_device.hpp"
 #include "lwacm_internal.hpp"
 #include "lwacm_march_common.hpp"
@@ -318,8 +317,7 @@ __global__ __launch_bounds__(256) void k_wall_correction(ProblemArgs p, const T 
                 for (int cc = 0; cc < 3; ++cc) uw[cc] = p.wall_term[m][cc];
             }
             const float w36 = (i <= 4 || i == 9 || i == 14) ? 2.0f : 1.0f;
-            const float d = set ? w36 * fmaf(wsc, cx * uw[0] + cy * uw[1] + cz * uw[2], sb - hw)
-                                : 0.0f;
+            const float d = set ? w36 * fmaf(wsc, cx * uw[0] + cy * uw[1] + cz * uw[2], sb) : 0.0f;
             c0 += d;
             c1 = fmaf((float)cx, d, c1);
             c2 = fmaf((float)cy, d, c2);
