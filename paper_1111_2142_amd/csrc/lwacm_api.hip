@@ -777,9 +777,19 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
         void *dst = c->buf[c->cur ^ 1];
         c->p.sr_word = (uint32_t)(c->steps + 1) ^ c->sr_seed;
         hipError_t e;
-        if (c->thermal) {
-            // T advances with the flow velocity of the same time: it reads the
-            // state this step's flow kernel reads, before that kernel runs
+        // T advances with the flow velocity of the same time: in the flow's own
+        // tile kernel where it can, else by a kernel of its own that reads the
+        // state this step's flow kernel reads, before that kernel runs
+        ProblemArgs pl = c->p;
+        const bool tfuse = c->thermal && march && !two && c->storage == LWACM_FP32 &&
+                           lwacm::march_thermal_supported(c->p);
+        if (tfuse) {
+            pl.T_in = c->T_buf[c->tcur];
+            pl.T_out = c->T_buf[c->tcur ^ 1];
+            pl.t_h = c->targs.h;
+            pl.t_kap = c->targs.kap;
+            c->tcur ^= 1;
+        } else if (c->thermal) {
             lwacm::ThermalArgs t = c->targs;
             t.state = static_cast<const float *>(src);
             t.T_in = c->T_buf[c->tcur];
@@ -796,7 +806,7 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
                                          static_cast<float *>(dst), c->d_bits, c->d_wallg, r,
                                          c->stream);
         else if (march)
-            e = lwacm::launch_fwd_march(c->p, c->storage, src, dst, c->d_cls, c->d_bits,
+            e = lwacm::launch_fwd_march(pl, c->storage, src, dst, c->d_cls, c->d_bits,
                                         c->d_wallg, r, c->stream);
         else if (multi)
             e = lwacm::launch_fwd_d2q9_multi(c->p, static_cast<const float *>(src),

@@ -39,11 +39,18 @@ struct ProblemArgs {
     // link j at (j * D + k) * n + x), or nullptr: the per-id table
     const float *uwl;
     // D3Q19 tile kernels with interpolated walls or link velocities: per node
-    // next to a wall, the step's correction to the halfway terms (wall motion
-    // included) in units of 36 w, added before normalisation; nullptr: the
-    // halfway rule with the per-id moving-wall sums
+    // next to a wall, the step's whole wall term (interpolated or halfway
+    // terms of its wall links, wall motion included) in units of 36 w, added
+    // before normalisation; nullptr: the halfway rule with the per-id
+    // moving-wall sums
     const float4 *corr;
     int march_nzc;           // planes per workgroup of the forward tile kernel (0: unused)
+    // the temperature step fused into the single-step tile kernel (thermal
+    // problems, march_thermal_supported): T at the step's time and one step
+    // later, h = 2/omega_t - 1 and kap = 2 - 2/omega_t; T_in null: no fusion
+    const float *T_in;
+    float *T_out;
+    float t_h, t_kap;
 };
 
 // Scratch and destination of the fixed-order grid reductions: a kernel stores
@@ -116,6 +123,9 @@ hipError_t launch_adj_march(const ProblemArgs &p, int storage, const void *state
                             const float *mu_in, float *mu_out, const unsigned *bits,
                             const float4 *wallg, int final_t0, const ReduceArgs &r,
                             hipStream_t stream);
+// D3Q19 single-step tile kernel with the temperature step in the same pass
+// (p.T_in, p.T_out): FP32 state, no walls, force, omega_p or wall correction.
+bool march_thermal_supported(const ProblemArgs &p);
 hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, void *dst,
                             const uint8_t *cls, const unsigned *bits, const float4 *wallg,
                             const ReduceArgs &r, hipStream_t stream);

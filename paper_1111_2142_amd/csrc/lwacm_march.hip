@@ -276,7 +276,11 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
 // from p.g_field (loaded with the state).  The forcing adds rho(x, t) g(x) to
 // the node's momentum; it enters the node's post-combine term a rho u through
 // the addend of its FMA, where it meets a node-dependent product.
-template <class T, int NZC, bool SR, bool MASK, bool SPLIT, int FRC, bool CORR>
+// THERM: the temperature lattice's step (Eq. ACM2.0t) in the same pass, from
+// the same step-t velocities: each column also loads its T (p.T_in) with the
+// state, pushes the temperature terms through the omega_p arrays and writes
+// the new T (p.T_out): 4 + 4 bytes more per node instead of a pass of its own.
+template <class T, int NZC, bool SR, bool MASK, bool SPLIT, int FRC, bool CORR, bool THERM>
 __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
                                                                const T *__restrict__ src,
                                                                T *__restrict__ dst,
@@ -288,9 +292,12 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
     // idle halo lanes write there instead of branching
     __shared__ float2 xp[2][4][NSLOT + 1];
     __shared__ float xd[2][4][NSLOT + 1];
-    constexpr int QS = SPLIT ? NSLOT + 1 : 1;  // q slots (one spare, as above)
-    __shared__ float xq[SPLIT ? 2 : 1][8][QS];
+    constexpr bool QX = SPLIT || THERM;          // the q arrays are used
+    constexpr int QS = QX ? NSLOT + 1 : 1;       // q slots (one spare, as above)
+    __shared__ float xq[QX ? 2 : 1][8][QS];
     static_assert(!(SPLIT && MASK), "the separate omega_p runs without walls");
+    static_assert(!THERM || (!MASK && !SPLIT && FRC == 0 && std::is_same<T, float>::value),
+                  "the fused temperature step: FP32 state, no walls, force or omega_p");
     const float dA = p.Ap - p.A;
 
     const int tid = threadIdx.x;
@@ -342,10 +349,15 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
     const unsigned voff = col * NB;
     const Rsrc rbits = make_rsrc(bb_bits, MASK ? (unsigned long long)n * 4u : 0ull);
     unsigned bw[3] = {0u, 0u, 0u};  // link sets of the ring's planes (MASK)
+    // temperature in and out (THERM), and the T of the ring's planes
+    const Rsrc rTi = make_rsrc(THERM ? p.T_in : nullptr, THERM ? (unsigned long long)n * 4u : 0ull);
+    const Rsrc rTo = make_rsrc(THERM ? p.T_out : nullptr, THERM ? (unsigned long long)n * 4u : 0ull);
+    unsigned tw[3] = {0u, 0u, 0u};
     auto issue = [&](int j, Ring<T> &rg, int pz) {
         const unsigned pw = (unsigned)wrap_index(pz, nz);
         rg.v = BufIO<T>::load(rs, voff, pw * plane_bytes);
         if (MASK) bw[j] = __builtin_amdgcn_raw_buffer_load_b32(rbits, col * 4u, pw * (unsigned)(plane * 4), 0);
+        if (THERM) tw[j] = __builtin_amdgcn_raw_buffer_load_b32(rTi, col * 4u, pw * (unsigned)(plane * 4), 0);
     };
     // node-by-node acceleration (FRC 2): three FP32 fields, one resource each
     const unsigned long long gbytes = FRC == 2 ? (unsigned long long)n * 4u : 0ull;
@@ -405,6 +417,9 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             push_column<MASK>(dr, ux, uy, uz, MASK ? class_of(b) : 0, b, A, a, acc[(j + 1) % 3],
                               acc[j], Am, !corr);
             if (SPLIT) push_split_column(1.0f + dr, ux, uy, uz, dA, acc[(j + 1) % 3], acc[j], Am);
+            if (THERM)
+                push_temp_column(__builtin_bit_cast(float, tw[j]), ux, uy, uz, p.t_h,
+                                 acc[(j + 1) % 3], acc[j], Am);
             if (FRC) {  // post-combine a rho u plus the forcing rho g
                 const float rho = 1.0f + dr, arho = a * rho;
                 const float gx = FRC == 2 ? __builtin_bit_cast(float, gq[j][0]) : p.g[0];
@@ -435,7 +450,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             if (I::phase < 2) return;
             const Xchg<NSLOT + 1> X{xp[k & 1], xd[k & 1]};
             put_slot(X, slot, Am);
-            if constexpr (SPLIT) put_slot_split(XchgQ<QS>{xq[k & 1]}, slot, Am);
+            if constexpr (QX) put_slot_split(XchgQ<QS>{xq[k & 1]}, slot, Am);
             __syncthreads();
             const int tz = z0 - 2 + k;
             float qsum = 0.0f;
@@ -462,6 +477,15 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             } else {
                 BufIO<T>::store_raw(rd, voff, so, out);
             }
+            if constexpr (THERM) {
+                // T(x, t + 1) = (2 - 2/omega_t) T(x) + the incoming terms / 36
+                const float Tsum = Am.qd + gather_split<QS, SX>(XchgQ<QS>{xq[k & 1]}, slot);
+                const float Tn = fmaf(p.t_kap, Am.tx, div36(Tsum));
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, Tn), rTo,
+                                                      col * 4u, (unsigned)tz * (unsigned)(plane * 4),
+                                                      0);
+                store_data_guard();
+            }
             const bool count = tz >= zs && !solid;
             mass += count ? o.D : 0.0f;
             energy = count ? fmaf(o.vx, o.vx, fmaf(o.vy, o.vy, fmaf(o.vz, o.vz, energy))) : energy;
@@ -482,12 +506,15 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
             if (SPLIT)
                 push_split_halo(1.0f + dr, ux, uy, uz, dA, isY, sgn, hq[j1], hq[j], hq1[j], hq2[j],
                                 hq[jm]);
+            if (THERM)
+                push_temp_halo(__builtin_bit_cast(float, tw[j]), ux, uy, uz, p.t_h, isY, sgn, hq[j1],
+                               hq[j], hq1[j], hq2[j], hq[jm]);
             __builtin_amdgcn_sched_barrier(0);
             if (I::refill) issue(j, ring[j], z0 + 2 + k);
             if (I::phase < 2) return;
             put_halo(Xchg<NSLOT + 1>{xp[k & 1], xd[k & 1]}, wslot, isY, sgn, hp[jm], hz[jm],
                      hd1[jm], hd2[jm]);
-            if constexpr (SPLIT)
+            if constexpr (QX)
                 put_halo_split(XchgQ<QS>{xq[k & 1]}, wslot, isY, sgn, hq[jm], hq1[jm], hq2[jm]);
             __syncthreads();
         });
@@ -563,16 +590,17 @@ __global__ __launch_bounds__(256) void k_classify(ProblemArgs p, uint8_t *cls, u
     }
 }
 
-template <class T, bool SR, bool MASK, bool SPLIT = false, int FRC = 0, bool CORR = false>
+template <class T, bool SR, bool MASK, bool SPLIT = false, int FRC = 0, bool CORR = false,
+          bool THERM = false>
 void launch_rolled(int c, unsigned nb, hipStream_t s, const ProblemArgs &p, const T *a, T *b,
                    const unsigned *bits, const float4 *wallg, const ReduceArgs &r)
 {
     switch (c) {
-    case 8: k_fwd_march_rolled<T, 8, SR, MASK, SPLIT, FRC, CORR><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    case 16: k_fwd_march_rolled<T, 16, SR, MASK, SPLIT, FRC, CORR><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    case 32: k_fwd_march_rolled<T, 32, SR, MASK, SPLIT, FRC, CORR><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    case 64: k_fwd_march_rolled<T, 64, SR, MASK, SPLIT, FRC, CORR><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
-    default: k_fwd_march_rolled<T, 128, SR, MASK, SPLIT, FRC, CORR><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 8: k_fwd_march_rolled<T, 8, SR, MASK, SPLIT, FRC, CORR, THERM><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 16: k_fwd_march_rolled<T, 16, SR, MASK, SPLIT, FRC, CORR, THERM><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 32: k_fwd_march_rolled<T, 32, SR, MASK, SPLIT, FRC, CORR, THERM><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    case 64: k_fwd_march_rolled<T, 64, SR, MASK, SPLIT, FRC, CORR, THERM><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
+    default: k_fwd_march_rolled<T, 128, SR, MASK, SPLIT, FRC, CORR, THERM><<<nb, NTHREADS, 0, s>>>(p, a, b, bits, wallg, r); break;
     }
 }
 
@@ -611,6 +639,13 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
     T *b = static_cast<T *>(dst);
     const int c = rolled_nzc(p);
     const bool sr = std::is_same<T, __half>::value && p.fp16_sr;
+    if constexpr (std::is_same<T, float>::value) {
+        if (p.T_in) {  // with the temperature step (march_thermal_supported)
+            launch_rolled<float, false, false, false, 0, false, true>(c, nb, s, p, a, b, bits, wallg,
+                                                                     r);
+            return hipGetLastError();
+        }
+    }
     if (c == 0) {  // nz < 8: the unrolled kernel with a 32-plane chunk
         if (p.mask)
             k_fwd_march<T, true, 32><<<nb, NTHREADS, 0, s>>>(p, a, b, cls, bits, wallg, r);
@@ -688,11 +723,19 @@ hipError_t launch_classify(const ProblemArgs &p, uint8_t *cls, unsigned *bits, f
     return hipGetLastError();
 }
 
+bool march_thermal_supported(const ProblemArgs &p)
+{
+    return march_supported(p) && !p.mask && !p.split && !p.has_force && !p.corr && !p.qd &&
+           !p.uwl && rolled_nzc(p) > 0;
+}
+
 hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, void *dst,
                             const uint8_t *cls, const unsigned *bits, const float4 *wallg,
                             const ReduceArgs &r, hipStream_t s)
 {
     if (!march_supported(p) || (p.mask && (!cls || !bits))) return hipErrorNotSupported;
+    if (p.T_in && (storage != 0 || !p.T_out || !march_thermal_supported(p)))
+        return hipErrorNotSupported;
     return storage ? dispatch<__half>(p, src, dst, cls, bits, wallg, r, s)
                    : dispatch<float>(p, src, dst, cls, bits, wallg, r, s);
 }

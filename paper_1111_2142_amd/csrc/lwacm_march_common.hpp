@@ -73,7 +73,9 @@ struct Acc {
     float bb[4];                           // bounced-back terms: 36 w (1, v) sums (MASK)
     // separate omega_p (SPLIT): 36 w (Ap - A) rho (v . u) over the same links
     // as pe .. sw and as the own column's z links
+    // (or, for the fused temperature step, the temperature terms over them)
     float qe, qw, qn, qs, qne, qnw, qse, qsw, qd;
+    float tx;                              // the node's own T (fused temperature step)
     unsigned bits;                         // solid upstream links (bounce-back only)
     int cls;                               // 0 fluid, 1 fluid next to a wall, 2 solid
 };
@@ -572,6 +574,82 @@ __device__ __forceinline__ void push_split_halo(float rho, float ux, float uy, f
     qd1 = rd * (cs + ub);
     qd2 = rd * (cs - ub);
     qm += rd * (cs - uz);
+}
+
+// ---- temperature lattice fused into the single-step kernel (thermal
+// LW-ACM, Eq. ACM2.0t with the even part of Eq. feqe, on the flow's
+// lattice): the term a node with temperature T and velocity u sends along
+// link v is w [h (T + 9/2 c^2 - 3/2 |u|^2) + 3 T c], c = v . u,
+// h = 2/omega_t - 1, and the node's new T is (2 - 2/omega_t) T(x) plus the
+// sum of the incoming terms.  The terms travel along the links that carry
+// the density partials, in the omega_p arrays (q fields, XchgQ), which a
+// problem with a temperature does not use.  Opposite links share the even
+// part, as in push_column.
+__device__ __forceinline__ void push_temp_column(float T, float ux, float uy, float uz, float h,
+                                                 Acc &A1, Acc &A0, Acc &Am)
+{
+    const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+    const float AT = h * fmaf(-1.5f, usq, T);
+    const float H = 4.5f * h, T3 = 3.0f * T;
+    auto pair = [&](float c, float &lp, float &lm) {
+        const float m = fmaf(H * c, c, AT);
+        lp = fmaf(T3, c, m);
+        lm = fmaf(T3, -c, m);
+    };
+    float Tpx, Tmx, Tpy, Tmy, Tpz, Tmz;
+    float Tpp0, Tmm0, Tpm0, Tmp0, Tp0p, Tm0m, Tp0m, Tm0p, T0pp, T0mm, T0pm, T0mp;
+    pair(ux, Tpx, Tmx);
+    pair(uy, Tpy, Tmy);
+    pair(uz, Tpz, Tmz);
+    pair(ux + uy, Tpp0, Tmm0);
+    pair(ux - uy, Tpm0, Tmp0);
+    pair(ux + uz, Tp0p, Tm0m);
+    pair(ux - uz, Tp0m, Tm0p);
+    pair(uy + uz, T0pp, T0mm);
+    pair(uy - uz, T0pm, T0mp);
+    // v_z = +1: plane pz + 1
+    A1.qe = Tp0p;
+    A1.qw = Tm0p;
+    A1.qn = T0pp;
+    A1.qs = T0mp;
+    A1.qd = 2.0f * Tpz;
+    // v_z = 0: plane pz, with the rest link (c = 0: the term AT, weight 12)
+    A0.qe = fmaf(2.0f, Tpx, A0.qe);
+    A0.qw = fmaf(2.0f, Tmx, A0.qw);
+    A0.qn = fmaf(2.0f, Tpy, A0.qn);
+    A0.qs = fmaf(2.0f, Tmy, A0.qs);
+    A0.qne = Tpp0;
+    A0.qnw = Tmp0;
+    A0.qse = Tpm0;
+    A0.qsw = Tmm0;
+    A0.qd = fmaf(12.0f, AT, A0.qd);
+    A0.tx = T;
+    // v_z = -1: plane pz - 1
+    Am.qe += Tp0m;
+    Am.qw += Tm0m;
+    Am.qn += T0pm;
+    Am.qs += T0mm;
+    Am.qd = fmaf(2.0f, Tmz, Am.qd);
+}
+
+// the five temperature terms a halo column pushes into the tile (the links of
+// push_halo; the same operations as push_temp_column's pairs)
+__device__ __forceinline__ void push_temp_halo(float T, float ux, float uy, float uz, float h,
+                                               bool isY, float sgn, float &q1, float &q0,
+                                               float &qd1, float &qd2, float &qm)
+{
+    const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+    const float AT = h * fmaf(-1.5f, usq, T);
+    const float H = 4.5f * h, T3 = 3.0f * T;
+    auto lt = [&](float c) { return fmaf(T3, c, fmaf(H * c, c, AT)); };
+    const float ua = isY ? uy : ux;
+    const float ub = isY ? ux : uy;
+    const float cs = sgn * ua;
+    q1 = lt(cs + uz);
+    q0 = fmaf(2.0f, lt(cs), q0);
+    qd1 = lt(cs + ub);
+    qd2 = lt(cs - ub);
+    qm += lt(cs - uz);
 }
 
 template <int NS>

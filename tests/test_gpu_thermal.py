@@ -13,6 +13,9 @@ thermal_step, run in lockstep with the flow.
 - The temperature does not change the flow (bitwise equal to the same steps
   without it); scope: FP16 storage and the two-step kernel decline it;
   switching it off is allowed.
+- Unmasked D3Q19 tile shapes run the temperature step inside the flow's
+  single-step kernel: against the temperature kernel of its own (generic
+  variant) and the oracle.
 """
 import numpy as np
 import pytest
@@ -77,6 +80,40 @@ def test_random_fields_match_oracle(q, masked, shape):
     assert rel_l2(uu[:, fl], ru[:, fl]) < 1e-5
     if mask is not None:
         assert np.array_equal(Tg[~fl], T[~fl])
+
+
+@pytest.mark.parametrize("shape", [(40, 32, 64), (8, 16, 32)])
+def test_fused_temperature_step_matches_the_separate_kernel(shape):
+    """Unmasked D3Q19 tile shapes carry the temperature step inside the
+    single-step flow kernel; the generic variant runs the temperature kernel
+    of its own and the gather flow kernel.  Ten steps: T and u agree to FP32
+    rounding (the sums run in another order), and T matches the oracle."""
+    L = need_gpu()
+    banner(f"thermal fused vs separate {shape}")
+    nz, ny, nx = shape
+    drho, u = wl.random_state(shape, 3, seed=61, du=0.03, drho=0.01)
+    drho = drho.astype(np.float32).astype(np.float64)
+    u = u.astype(np.float32).astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(62))
+    T = rng.uniform(0.2, 1.0, shape).astype(np.float32).astype(np.float64)
+    out = []
+    for variant in (MARCH, 1):
+        s = L.Solver(19, nx, ny, nz, 1.6, variant=variant)
+        s.set_state(to_dev(drho), to_dev(u))
+        s.set_thermal(1.3, to_dev(T))
+        s.step(10)
+        out.append((s.temperature().double().cpu().numpy(), s.moments()[1].double().cpu().numpy()))
+        s.close()
+    (Tf, uf), (Ts, us) = out
+    e_T, e_u = rel_l2(Tf, Ts), rel_l2(uf, us)
+    p = oracle.Problem(19, nx, ny, nz, omega=1.6)
+    r, ru, rT = 1.0 + drho, u, T
+    for _ in range(10):
+        rT = oracle.thermal_step(p, rT, ru, 1.3)
+        r, ru = oracle.step(p, r, ru)
+    e_o = rel_l2(Tf, rT)
+    banner(f"thermal fused vs separate: rel-L2 T {e_T:.3e}, u {e_u:.3e}; vs oracle T {e_o:.3e}")
+    assert e_T < 1e-6 and e_u < 1e-6 and e_o < 1e-6
 
 
 def test_full_size_step_matches_oracle_and_conserves_total():
