@@ -68,6 +68,43 @@ def _events_time(fn, n, stream):
     return start.elapsed_time(stop) / 1e3  # seconds
 
 
+def _stream_reference(dev):
+    """GB/s of bench_stream_ref.hip's copy (bytes read + written), read and
+    write of 1 GiB, each under the cache policies 0 (default), 2 (nt), 16
+    (sc1), 18 (nt, sc1) and two grid sizes; the best of each kind beside
+    torch's own device copy."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "bench_stream_ref.so"))
+    lib.stream_ref_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_uint, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_float)]
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.zeros_like(src)
+    torch.cuda.synchronize()
+    out = {}
+    for kind, name, moved in ((0, "copy", 2 * nbytes), (1, "read", nbytes), (2, "write", nbytes)):
+        for pol in (0, 2, 16, 18):
+            for grid in (2048, 8192):
+                ms = ctypes.c_float(0.0)
+                rc = lib.stream_ref_run(kind, pol, dst.data_ptr(), src.data_ptr(), nbytes, grid,
+                                        20, ctypes.byref(ms))
+                if rc != 0:
+                    raise RuntimeError(f"stream_ref_run({kind}, {pol}, {grid}) = {rc}")
+                out[f"{name}_p{pol}_g{grid}"] = round(moved / (ms.value * 1e-3) / 1e9, 1)
+    for _ in range(3):
+        dst.copy_(src)
+    t = _events_time(lambda k: [dst.copy_(src) for _ in range(k)], 20,
+                     torch.cuda.current_stream(dev))
+    out["torch_copy"] = round(2 * nbytes * 20 / t / 1e9, 1)
+    for name in ("copy", "read", "write"):
+        out[f"best_{name}"] = max(v for k, v in out.items() if k.startswith(name + "_"))
+    print(f"[bench] streaming reference GB/s: copy {out['best_copy']}, read {out['best_read']}, "
+          f"write {out['best_write']}, torch copy {out['torch_copy']}", file=sys.stderr, flush=True)
+    return out
+
+
 def _cavity_leg(args, L, wl, dev, stream):
     """The 192^3 lid-driven cavity: walls on every face, the lid moving.  The
     masked one-step kernel moves 36 B per node: the state read and written
@@ -292,6 +329,10 @@ def main():
                     help="time only the 256^3 step with a temperature field")
     ap.add_argument("--cavity-only", action="store_true",
                     help="time only the 192^3 lid-driven cavity (walls, moving lid)")
+    ap.add_argument("--stream-reference", action="store_true",
+                    help="time the hand-written streaming kernels of bench_stream_ref.hip "
+                         "(16-byte buffer copy, read and write of 1 GiB under four cache "
+                         "policies): the HBM rate the HBM-bound steps are read against")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of 256 MiB (the reference kernel for "
                          "scaling HBM byte counters) and exit")
@@ -310,6 +351,9 @@ def main():
     L.load_library()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if args.stream_reference:
+        print(json.dumps({"stream_reference": _stream_reference(dev)}), flush=True)
+        return
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
