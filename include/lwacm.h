@@ -403,6 +403,41 @@ int lwacm_adjoint_step(lwacm_ctx *c, const void *d_state_t, const float *d_mu_in
 int lwacm_adjoint_step2(lwacm_ctx *c, const void *d_state_t, const void *d_state_tm1,
                         const float *d_mu_in, float *d_mu_out, double *d_dL_domega, int final_t0);
 
+/*
+ * The two halves of a checkpointed reverse sweep over one segment, each one
+ * call (the recompute-and-reverse scheme of the checkpointed gradient: a
+ * state every K steps, the segment's states recomputed from it, then K
+ * reverse steps).
+ *
+ * lwacm_forward_states: from d_state0 (storage format, the state at step
+ *   index t0) runs nsteps forward steps with the context's problem and
+ *   kernels and writes the state after step t0 + k (k = 0 .. nsteps - 1)
+ *   to d_states + k * lwacm_state_bytes(..): the same fields as nsteps
+ *   calls of lwacm_step from that state (bitwise; t0 selects the FP16
+ *   stochastic-rounding words), one launch per step (with walls on the
+ *   D3Q19 tile kernels, which do not rewrite solid nodes, d_state0 is first
+ *   copied into every slot).  The
+ *   context's own buffers, step count and diagnostics are untouched.
+ *   d_state0 must not overlap d_states.  LWACM_EUNSUPPORTED with a
+ *   temperature field.  Asynchronous.
+ * lwacm_adjoint_sweep: nsteps reverse steps t = t0 + nsteps - 1 down to t0,
+ *   d_states + (t - t0) * lwacm_state_bytes(..) holding state_t (the input
+ *   of forward step t).  d_mu holds mu_{t0 + nsteps - 1} on entry and on
+ *   return mu_{t0 - 1}, or, when t0 == 0, the gradient with respect to the
+ *   initial (rho - 1, u), field-major (as lwacm_adjoint_step with final_t0);
+ *   d_mu_tmp is scratch of the same size.  Pairs of steps run in one launch
+ *   where lwacm_adjoint_step2 applies.  The steps' dL/domega are added to
+ *   *d_dL_domega after the last step, in the order separate calls add them,
+ *   so d_mu and *d_dL_domega equal those of the separate calls bitwise.
+ *   The first call for a longer sweep allocates the library's per-step
+ *   partials (nsteps x blocks doubles).  Unsupported cases as
+ *   lwacm_adjoint_step.  Asynchronous.
+ */
+int lwacm_forward_states(lwacm_ctx *c, const void *d_state0, long long t0, int nsteps,
+                         void *d_states);
+int lwacm_adjoint_sweep(lwacm_ctx *c, const void *d_states, long long t0, int nsteps,
+                        float *d_mu, float *d_mu_tmp, double *d_dL_domega);
+
 /* Release the library's scratch.  Caller buffers are untouched. */
 void lwacm_destroy(lwacm_ctx *c);
 

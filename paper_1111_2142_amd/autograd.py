@@ -3,9 +3,10 @@ forward step and the hand-written reverse step of the library.
 
 Forward: run ``nsteps`` steps from (rho0 - 1, u0), saving the state (storage
 format) every ``K`` steps.  Backward: seed mu from the loss cotangent of the
-final state, then for each segment from last to first restore its
-checkpoint, recompute the segment's states into a K-slot buffer and apply
-the reverse step K times (two per launch where the library supports it).  The omega gradient is accumulated in FP64 on the
+final state, then for each segment from last to first recompute the
+segment's states from its checkpoint into a K-slot buffer (one library call)
+and apply the K reverse steps (one call; two per launch where the library
+supports it).  The omega gradient is accumulated in FP64 on the
 device.  Every arithmetic step runs in the library's kernels; this module
 only sequences the calls.
 """
@@ -56,25 +57,18 @@ class _Run(torch.autograd.Function):
         mu_next = torch.empty_like(lam)
         dw = torch.zeros(1, dtype=torch.float64, device=dev)
         L.lwacm_adjoint_seed(solver.ctx, ctx.final_state, lam, mu)
-        seg_buf = [solver.new_state_buffer() for _ in range(min(ctx.K, max(ctx.nsteps, 1)))]
+        # the segment's states, slot j = the state at step t0 + j: the
+        # checkpoint, then the recomputed ones (lwacm_forward_states), then the
+        # segment's reverse steps in one call (lwacm_adjoint_sweep, two per
+        # launch where the library can; bitwise the separate calls' result)
+        sb = solver.state_bytes
+        seg = torch.empty(min(ctx.K, max(ctx.nsteps, 1)) * sb, dtype=torch.uint8, device=dev)
         for (t0, ckpt) in reversed(ctx.checkpoints):
             nseg = min(ctx.K, ctx.nsteps - t0)
-            solver.load_state(ckpt, t0)
-            for j in range(nseg):
-                solver.save_state(seg_buf[j])
-                if j + 1 < nseg:
-                    solver.step(1)
-            # reverse steps two per launch where the library can (the same
-            # result as two single calls), single steps otherwise
-            j = nseg - 1
-            while j >= 0:
-                if j >= 1 and L.lwacm_adjoint_step2(solver.ctx, seg_buf[j], seg_buf[j - 1], mu,
-                                                    mu_next, dw, t0 + j - 1 == 0):
-                    j -= 2
-                else:
-                    L.lwacm_adjoint_step(solver.ctx, seg_buf[j], mu, mu_next, dw, t0 + j == 0)
-                    j -= 1
-                mu, mu_next = mu_next, mu
+            seg[:sb].copy_(ckpt)
+            if nseg > 1:
+                L.lwacm_forward_states(solver.ctx, ckpt, t0, nseg - 1, seg[sb:nseg * sb])
+            L.lwacm_adjoint_sweep(solver.ctx, seg, t0, nseg, mu, mu_next, dw)
         if ctx.nsteps == 0:
             mu = lam
         grad_drho0 = mu[0].clone()

@@ -220,7 +220,9 @@ hipError_t launch_adj_march(const ProblemArgs &p, int storage, const void *state
     const hipError_t e =
         storage ? dispatch<__half>(p, state, mu_in, mu_out, bits, wallg, final_t0, r, stream)
                 : dispatch<float>(p, state, mu_in, mu_out, bits, wallg, final_t0, r, stream);
-    return e != hipSuccess ? e : launch_reduce(r, 1, adj_march_num_blocks(p), stream);
+    // r.out null: the caller adds the block partials itself (lwacm_adjoint_sweep)
+    if (e != hipSuccess || !r.out) return e;
+    return launch_reduce(r, 1, adj_march_num_blocks(p), stream);
 }
 
 }  // namespace lwacm

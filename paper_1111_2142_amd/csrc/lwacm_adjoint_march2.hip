@@ -258,7 +258,9 @@ hipError_t launch_adj_march2(const ProblemArgs &p, int storage, const void *stat
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // the two steps' dL/domega, in the order two one-step calls add them
+    // the two steps' dL/domega, in the order two one-step calls add them (r.out
+    // null: the caller adds the block partials itself, lwacm_adjoint_sweep)
+    if (!r.out) return hipSuccess;
     e = launch_reduce(r, 1, nb, stream);
     if (e != hipSuccess) return e;
     ReduceArgs rb = r;

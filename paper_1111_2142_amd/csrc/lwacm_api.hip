@@ -53,6 +53,10 @@ struct lwacm_ctx {
     int tcur;
     lwacm::ThermalArgs targs;
     double *d_force;  // wall-force partials (allocated on first use)
+    // reverse sweeps (lwacm_adjoint_sweep): the steps' block partials and
+    // totals, allocated on first use and grown as needed (doubles)
+    double *d_sweep;
+    size_t sweep_cap;
     double *h_force;  // pinned host memory the wall-force sum kernel writes its six results to
     // fluid nodes next to a wall, in node order (built on first use)
     unsigned *d_wlist;
@@ -180,6 +184,9 @@ void free_scratch(lwacm_ctx *c)
     if (c->d_bits) (void)hipFree(c->d_bits);
     if (c->d_wallg) (void)hipFree(c->d_wallg);
     if (c->d_force) (void)hipFree(c->d_force);
+    if (c->d_sweep) (void)hipFree(c->d_sweep);
+    c->d_sweep = nullptr;
+    c->sweep_cap = 0;
     if (c->h_force) (void)hipHostFree(c->h_force);
     c->h_force = nullptr;
     if (c->d_wlist) (void)hipFree(c->d_wlist);
@@ -952,6 +959,127 @@ int lwacm_adjoint_step2(lwacm_ctx *c, const void *d_state_t, const void *d_state
     r.partials_b = c->d_partials + c->n_partial_blocks;
     return dev_err(lwacm::launch_adj_march2(c->p, c->storage, d_state_t, d_state_tm1, d_mu_in,
                                             d_mu_out, final_t0, r, c->stream));
+}
+
+int lwacm_forward_states(lwacm_ctx *c, const void *d_state0, long long t0, int nsteps,
+                         void *d_states)
+{
+    if (!c || !d_state0 || !d_states || nsteps < 0 || t0 < 0) return LWACM_EINVAL;
+    if (c->thermal) return LWACM_EUNSUPPORTED;
+    const size_t sb = state_bytes(c);
+    const char *lo = static_cast<const char *>(d_states);
+    const char *s0 = static_cast<const char *>(d_state0);
+    if (s0 + sb > lo && s0 < lo + (size_t)nsteps * sb) return LWACM_EINVAL;  // overlap
+    const bool march = use_march(c);
+    const bool multi = !march && use_multi(c);
+    const unsigned nb1 = march ? lwacm::march_num_blocks(c->p)
+                               : (multi ? lwacm::d2q9_multi_num_blocks(c->p)
+                                        : lwacm::generic_grid(c->p.n));
+    // The masked tile kernels leave solid nodes unwritten (the context's two
+    // buffers both hold them): the slots get them from d_state0 first.
+    if (march && c->p.mask)
+        for (int k = 0; k < nsteps; ++k)
+            if (hipMemcpyAsync(static_cast<char *>(d_states) + (size_t)k * sb, d_state0, sb,
+                               hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+                return LWACM_EDEVICE;
+    // block partials go to the scratch; no second pass (no diagnostics)
+    ReduceArgs r = reduce_args(c, nullptr, nullptr);
+    for (int k = 0; k < nsteps; ++k) {
+        const void *src = k == 0 ? d_state0 : static_cast<const void *>(lo + (size_t)(k - 1) * sb);
+        void *dst = static_cast<char *>(d_states) + (size_t)k * sb;
+        ProblemArgs pl = c->p;
+        pl.sr_word = (uint32_t)(t0 + k + 1) ^ c->sr_seed;  // as lwacm_step draws for step t0 + k
+        hipError_t e = hipSuccess;
+        if (march && pl.corr)
+            e = lwacm::launch_wall_correction(pl, c->storage, src, wall_links(c), c->d_corr,
+                                              c->stream);
+        if (e == hipSuccess) {
+            if (march)
+                e = lwacm::launch_fwd_march(pl, c->storage, src, dst, c->d_cls, c->d_bits,
+                                            c->d_wallg, r, c->stream);
+            else if (multi)
+                e = lwacm::launch_fwd_d2q9_multi(pl, static_cast<const float *>(src),
+                                                 static_cast<float *>(dst), 1, r, c->stream);
+            else
+                e = lwacm::launch_fwd_generic(pl, c->storage, pl.has_force != 0, src, dst, r, nb1,
+                                              c->stream);
+        }
+        if (e == hipSuccess && c->semi_implicit)
+            e = lwacm::launch_density_si(pl, static_cast<const float *>(src),
+                                         static_cast<float *>(dst), r, nb1, c->stream);
+        if (e != hipSuccess) return LWACM_EDEVICE;
+    }
+    return LWACM_OK;
+}
+
+int lwacm_adjoint_sweep(lwacm_ctx *c, const void *d_states, long long t0, int nsteps,
+                        float *d_mu, float *d_mu_tmp, double *d_dL_domega)
+{
+    if (!c || !d_states || !d_mu || !d_mu_tmp || !d_dL_domega || d_mu == d_mu_tmp ||
+        nsteps < 0 || t0 < 0)
+        return LWACM_EINVAL;
+    if (c->p.split || c->p.g_field || c->p.qd || c->p.uwl || c->semi_implicit)
+        return LWACM_EUNSUPPORTED;
+    if (nsteps == 0) return LWACM_OK;
+    const size_t sb = state_bytes(c);
+    const char *st = static_cast<const char *>(d_states);
+    const size_t stride = c->n_partial_blocks;  // doubles per slice
+    const size_t need = (size_t)nsteps * (stride + 1);
+    if (need > c->sweep_cap) {
+        if (c->d_sweep) (void)hipFree(c->d_sweep);
+        c->d_sweep = nullptr;
+        c->sweep_cap = 0;
+        if (hipMalloc(&c->d_sweep, need * sizeof(double)) != hipSuccess) return LWACM_ENOMEM;
+        c->sweep_cap = need;
+    }
+    // zero slices: each launch fills its own blocks' entries only
+    if (hipMemsetAsync(c->d_sweep, 0, (size_t)nsteps * stride * sizeof(double), c->stream) !=
+        hipSuccess)
+        return LWACM_EDEVICE;
+    const bool two_ok = (c->variant == LWACM_KERNEL_AUTO || c->variant == LWACM_KERNEL_MARCH2) &&
+                        lwacm::adj_march2_supported(c->p);
+    const bool tile = c->variant != LWACM_KERNEL_GENERIC && lwacm::adj_march_supported(c->p);
+    float *mu_in = d_mu, *mu_out = d_mu_tmp;
+    unsigned slice = 0;
+    long long t = t0 + nsteps - 1;
+    while (t >= t0) {
+        ReduceArgs r = reduce_args(c, nullptr, nullptr);  // partials only, added below
+        r.partials = c->d_sweep + (size_t)slice * stride;
+        hipError_t e;
+        if (two_ok && t - 1 >= t0) {
+            r.partials_b = r.partials + stride;
+            e = lwacm::launch_adj_march2(c->p, c->storage, st + (size_t)(t - t0) * sb,
+                                         st + (size_t)(t - 1 - t0) * sb, mu_in, mu_out,
+                                         t - 1 == 0, r, c->stream);
+            slice += 2;
+            t -= 2;
+        } else {
+            if (tile)
+                e = lwacm::launch_adj_march(c->p, c->storage, st + (size_t)(t - t0) * sb, mu_in,
+                                            mu_out, c->d_bits, c->d_wallg, t == 0, r, c->stream);
+            else
+                e = lwacm::launch_adj_generic(c->p, c->storage, st + (size_t)(t - t0) * sb,
+                                              mu_in, mu_out, t == 0, r,
+                                              lwacm::generic_grid(c->p.n), c->stream);
+            slice += 1;
+            t -= 1;
+        }
+        if (e != hipSuccess) return LWACM_EDEVICE;
+        float *tmp = mu_in;
+        mu_in = mu_out;
+        mu_out = tmp;
+    }
+    // the steps' dL/domega, added in the order separate calls add them
+    if (lwacm::launch_reduce_slices(c->d_sweep, stride, (unsigned)stride, slice,
+                                    c->d_sweep + (size_t)nsteps * stride,
+                                    2.0 / (c->omega * c->omega), d_dL_domega,
+                                    c->stream) != hipSuccess)
+        return LWACM_EDEVICE;
+    if (mu_in != d_mu &&
+        hipMemcpyAsync(d_mu, mu_in, (size_t)(c->p.D + 1) * (size_t)c->p.n * sizeof(float),
+                       hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return LWACM_EDEVICE;
+    return LWACM_OK;
 }
 
 void lwacm_destroy(lwacm_ctx *c)

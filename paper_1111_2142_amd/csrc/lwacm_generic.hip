@@ -454,7 +454,42 @@ __global__ __launch_bounds__(kGenericBlock) void k_reduce_partials(ReduceArgs r,
     }
 }
 
+// The per-step block partials of a reverse sweep (one slice of `stride`
+// doubles per reduction, zero past each launch's own blocks): block s adds
+// slice s in the order of k_reduce_partials (extra zeros change no sum).
+__global__ __launch_bounds__(kGenericBlock) void k_reduce_slices(const double *partials,
+                                                                 size_t stride, unsigned nblocks,
+                                                                 double *totals)
+{
+    const double *slice = partials + (size_t)blockIdx.x * stride;
+    double acc[1] = {0.0};
+    for (unsigned b = threadIdx.x; b < nblocks; b += kReduceThreads) acc[0] += slice[b];
+    block_sum<1>(acc);
+    if (threadIdx.x == 0) totals[blockIdx.x] = acc[0];
+}
+
+// out += total_s * scale for s = 0, 1, ... in turn: what the reductions of
+// separate reverse-step calls add, in the same order.
+__global__ void k_accumulate_totals(const double *totals, unsigned n, double scale, double *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double v = out[0];
+    for (unsigned s = 0; s < n; ++s) v += totals[s] * scale;
+    out[0] = v;
+}
+
 }  // namespace
+
+hipError_t launch_reduce_slices(const double *partials, size_t stride, unsigned nblocks,
+                                unsigned nslices, double *totals, double scale, double *out,
+                                hipStream_t s)
+{
+    if (nslices == 0) return hipSuccess;
+    // the thread count and tree of k_reduce_partials
+    k_reduce_slices<<<nslices, kReduceThreads, 0, s>>>(partials, stride, nblocks, totals);
+    k_accumulate_totals<<<1, 1, 0, s>>>(totals, nslices, scale, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_reduce(const ReduceArgs &r, int nv, unsigned nblocks, hipStream_t s)
 {
@@ -503,7 +538,9 @@ hipError_t launch_adj_generic(const ProblemArgs &p, int storage, const void *sta
     else
         e = storage ? adj_dispatch<19, __half>(p, state, mu_in, mu_out, final_t0, r, nb, s)
                     : adj_dispatch<19, float>(p, state, mu_in, mu_out, final_t0, r, nb, s);
-    return e != hipSuccess ? e : launch_reduce(r, 1, nb, s);
+    // r.out null: the caller adds the block partials itself (lwacm_adjoint_sweep)
+    if (e != hipSuccess || !r.out) return e;
+    return launch_reduce(r, 1, nb, s);
 }
 
 hipError_t launch_adj_seed(const ProblemArgs &p, int storage, const void *state,

@@ -80,6 +80,13 @@ struct ReduceArgs {
 
 // Second pass of a grid reduction over nblocks blocks of NV (1 or 2) values.
 hipError_t launch_reduce(const ReduceArgs &r, int nv, unsigned nblocks, hipStream_t stream);
+// The block partials of several reverse steps, one slice of `stride` doubles
+// each (zero-padded past the launch's own blocks, nblocks the largest count):
+// *out += total_s * scale for each slice s in order, as separate calls of the
+// reverse step add them.
+hipError_t launch_reduce_slices(const double *partials, size_t stride, unsigned nblocks,
+                                unsigned nslices, double *totals, double scale, double *out,
+                                hipStream_t stream);
 
 // The forward launchers store per-block partials only; the caller runs the
 // second pass (launch_reduce, or deferred into the next step's launch).

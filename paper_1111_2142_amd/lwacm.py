@@ -84,6 +84,8 @@ def load_library():
         "lwacm_adjoint_seed": (i, [_vp, _vp, _vp, _vp]),
         "lwacm_adjoint_step": (i, [_vp, _vp, _vp, _vp, _vp, i]),
         "lwacm_adjoint_step2": (i, [_vp, _vp, _vp, _vp, _vp, _vp, i]),
+        "lwacm_forward_states": (i, [_vp, _vp, ll, i, _vp]),
+        "lwacm_adjoint_sweep": (i, [_vp, _vp, ll, i, _vp, _vp, _vp]),
         "lwacm_destroy": (None, [_vp]),
         "lwacm_coefficients": (i, [d, ctypes.POINTER(ctypes.c_float),
                                    ctypes.POINTER(ctypes.c_float)]),
@@ -288,6 +290,24 @@ def lwacm_adjoint_step2(ctx, state_t: torch.Tensor, state_tm1: torch.Tensor, mu_
         return False
     _check(code, "lwacm_adjoint_step2")
     return True
+
+
+def lwacm_forward_states(ctx, state0: torch.Tensor, t0: int, nsteps: int,
+                         states: torch.Tensor):
+    """States after steps t0 .. t0 + nsteps - 1 from state0 (step index t0)
+    into consecutive slots of `states` (uint8, >= nsteps state sizes)."""
+    _check(load_library().lwacm_forward_states(ctx, _ptr(state0), int(t0), int(nsteps),
+                                               _ptr(states)), "lwacm_forward_states")
+
+
+def lwacm_adjoint_sweep(ctx, states: torch.Tensor, t0: int, nsteps: int, mu: torch.Tensor,
+                        mu_tmp: torch.Tensor, dL_domega: torch.Tensor):
+    """Reverse steps t0 + nsteps - 1 .. t0 over the states in `states` (slot
+    t - t0 = state_t); mu in place: mu_{t0+nsteps-1} in, mu_{t0-1} (or the
+    field-major gradient when t0 == 0) out."""
+    _check(load_library().lwacm_adjoint_sweep(ctx, _ptr(states), int(t0), int(nsteps), _ptr(mu),
+                                              _ptr(mu_tmp), _ptr(dL_domega)),
+           "lwacm_adjoint_sweep")
 
 
 def lwacm_destroy(ctx):
