@@ -426,9 +426,13 @@ int lwacm_adjoint_step2(lwacm_ctx *c, const void *d_state_t, const void *d_state
  *   return mu_{t0 - 1}, or, when t0 == 0, the gradient with respect to the
  *   initial (rho - 1, u), field-major (as lwacm_adjoint_step with final_t0);
  *   d_mu_tmp is scratch of the same size.  Pairs of steps run in one launch
- *   where lwacm_adjoint_step2 applies.  The steps' dL/domega are added to
- *   *d_dL_domega after the last step, in the order separate calls add them,
- *   so d_mu and *d_dL_domega equal those of the separate calls bitwise.
+ *   where lwacm_adjoint_step2 applies, and D2Q9 FP32 problems without
+ *   link-wall distances or link velocities run up to 8 steps per launch in
+ *   LDS.  The steps' dL/domega are added to *d_dL_domega after the last
+ *   step, in the order separate calls add them: d_mu equals that of the
+ *   separate calls bitwise, and so does *d_dL_domega except with 8 D2Q9
+ *   steps per launch, whose per-step sums run over 32 x 32 tiles instead
+ *   (equal to FP64 rounding).
  *   The first call for a longer sweep allocates the library's per-step
  *   partials (nsteps x blocks doubles).  Unsupported cases as
  *   lwacm_adjoint_step.  Asynchronous.

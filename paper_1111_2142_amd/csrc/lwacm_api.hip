@@ -984,6 +984,20 @@ int lwacm_forward_states(lwacm_ctx *c, const void *d_state0, long long t0, int n
                 return LWACM_EDEVICE;
     // block partials go to the scratch; no second pass (no diagnostics)
     ReduceArgs r = reduce_args(c, nullptr, nullptr);
+    if (multi) {  // D2Q9: up to kMultiSteps steps per launch, each step's state out
+        for (int k = 0; k < nsteps;) {
+            const int kk = nsteps - k < lwacm::kMultiSteps ? nsteps - k : lwacm::kMultiSteps;
+            const void *src = k == 0 ? d_state0 : static_cast<const void *>(lo + (size_t)(k - 1) * sb);
+            if (lwacm::launch_fwd_d2q9_multi(c->p, static_cast<const float *>(src), nullptr, kk, r,
+                                             c->stream,
+                                             reinterpret_cast<float *>(
+                                                 static_cast<char *>(d_states) + (size_t)k * sb),
+                                             sb / 4) != hipSuccess)
+                return LWACM_EDEVICE;
+            k += kk;
+        }
+        return LWACM_OK;
+    }
     for (int k = 0; k < nsteps; ++k) {
         const void *src = k == 0 ? d_state0 : static_cast<const void *>(lo + (size_t)(k - 1) * sb);
         void *dst = static_cast<char *>(d_states) + (size_t)k * sb;
@@ -1039,6 +1053,10 @@ int lwacm_adjoint_sweep(lwacm_ctx *c, const void *d_states, long long t0, int ns
     const bool two_ok = (c->variant == LWACM_KERNEL_AUTO || c->variant == LWACM_KERNEL_MARCH2) &&
                         lwacm::adj_march2_supported(c->p);
     const bool tile = c->variant != LWACM_KERNEL_GENERIC && lwacm::adj_march_supported(c->p);
+    // D2Q9: up to kMultiSteps reverse steps per launch in LDS
+    const bool multi = c->variant == LWACM_KERNEL_AUTO && c->storage == LWACM_FP32 &&
+                       lwacm::d2q9_multi_supported(c->p) &&
+                       lwacm::d2q9_multi_num_blocks(c->p) <= c->n_partial_blocks;
     float *mu_in = d_mu, *mu_out = d_mu_tmp;
     unsigned slice = 0;
     long long t = t0 + nsteps - 1;
@@ -1046,7 +1064,14 @@ int lwacm_adjoint_sweep(lwacm_ctx *c, const void *d_states, long long t0, int ns
         ReduceArgs r = reduce_args(c, nullptr, nullptr);  // partials only, added below
         r.partials = c->d_sweep + (size_t)slice * stride;
         hipError_t e;
-        if (two_ok && t - 1 >= t0) {
+        if (multi) {
+            const int k = (int)(t - t0 + 1 < lwacm::kMultiSteps ? t - t0 + 1 : lwacm::kMultiSteps);
+            e = lwacm::launch_adj_d2q9_multi(c->p, reinterpret_cast<const float *>(st), sb / 4,
+                                             (int)(t - t0), k, t - k + 1 == 0, mu_in, mu_out,
+                                             c->d_sweep, stride, slice, c->stream);
+            slice += (unsigned)k;
+            t -= k;
+        } else if (two_ok && t - 1 >= t0) {
             r.partials_b = r.partials + stride;
             e = lwacm::launch_adj_march2(c->p, c->storage, st + (size_t)(t - t0) * sb,
                                          st + (size_t)(t - 1 - t0) * sb, mu_in, mu_out,

@@ -42,7 +42,8 @@ constexpr int MR = 2;  // rows per thread: a strip of MR nodes shares its neighb
 template <bool MASK, bool FORCE>
 __global__ __launch_bounds__(MTHREADS) void k_fwd_d2q9_multi(ProblemArgs p, const float *__restrict__ src,
                                                              float *__restrict__ dst, int ksteps,
-                                                             ReduceArgs r)
+                                                             ReduceArgs r, float *__restrict__ slots,
+                                                             size_t slot_floats)
 {
     // per node of the region, two steps' buffers: (rho - 1, u_x, u_y, w) with
     // w = node_B(u) <= -0 at a fluid node (computed once where the node is
@@ -109,8 +110,20 @@ __global__ __launch_bounds__(MTHREADS) void k_fwd_d2q9_multi(ProblemArgs p, cons
                 const int ly = ly0 + rr;
                 const int l = ly * MW + lx;
                 const float4 own = w[rr + 1][1];
+                // slots: every step's state goes out, tile node by tile node
+                const int sgx = tile_x0 - MK + lx, sgy = tile_y0 - MK + ly;
+                const bool put = slots && lx >= MK && lx < MK + MT && ly >= MK && ly < MK + MT &&
+                                 sgx < p.nx && sgy < p.ny;
+                float *const so = put ? slots + (size_t)(s - 1) * slot_floats +
+                                            3 * ((size_t)sgy * p.nx + sgx)
+                                      : nullptr;
                 if (MASK && own.w > 0.0f) {  // solid: unchanged
                     buf[b1][l] = own;
+                    if (put) {
+                        so[0] = own.x;
+                        so[1] = own.y;
+                        so[2] = own.z;
+                    }
                     continue;
                 }
                 const float ux[3] = {own.y, own.z, 0.0f};
@@ -132,6 +145,11 @@ __global__ __launch_bounds__(MTHREADS) void k_fwd_d2q9_multi(ProblemArgs p, cons
                 link_update<9, MASK, FORCE, false>(p, gidx, own.x, ux, own.w, fmask, fstate, out, e);
                 const float un[3] = {out[1], out[2], 0.0f};
                 buf[b1][l] = make_float4(out[0], out[1], out[2], node_B(un));
+                if (put) {
+                    so[0] = out[0];
+                    so[1] = out[1];
+                    so[2] = out[2];
+                }
             }
         }
         __syncthreads();
@@ -146,9 +164,11 @@ __global__ __launch_bounds__(MTHREADS) void k_fwd_d2q9_multi(ProblemArgs p, cons
         if (gx >= p.nx || gy >= p.ny) continue;
         const float4 v = buf[bf][(oy + MK) * MW + (ox + MK)];
         const long long g = (long long)gy * p.nx + gx;
-        dst[3 * g] = v.x;
-        dst[3 * g + 1] = v.y;
-        dst[3 * g + 2] = v.z;
+        if (!slots) {  // with slots the last step's state is already out
+            dst[3 * g] = v.x;
+            dst[3 * g + 1] = v.y;
+            dst[3 * g + 2] = v.z;
+        }
         if (MASK && v.w > 0.0f) continue;
         float e = 0.0f;
         e = fmaf(v.y, v.y, e);
@@ -159,6 +179,138 @@ __global__ __launch_bounds__(MTHREADS) void k_fwd_d2q9_multi(ProblemArgs p, cons
     store_block_partials<2>(acc, r.partials, blockIdx.x);
     if (blockIdx.x == 0 && r.prev_nblocks)
         finish_previous_sums(r.prev_partials, r.prev_nblocks, r.prev_out, r.prev_out2);
+}
+
+// Several D2Q9 reverse steps per launch, the same temporal blocking: the
+// region's mu (with the mask id) is loaded into LDS once; reverse step s (the
+// forward step of slot slot_hi - s + 1 of the caller's state slots) is
+// computed on the region less s nodes on each side from the node's own state,
+// read from its slot, and the mu of its neighbours y + v_k in LDS.  Each node
+// goes through adj_node_update, as in the one-step reverse kernel, so mu is
+// bitwise that of ksteps single reverse steps.  Each step's dL/da of the
+// tile's nodes is summed per workgroup into slice slice0 + s - 1 of the
+// partials (a different order of addition than the one-step kernel's blocks).
+// final_last: the last step is step 0, its lambda goes out field-major.
+template <bool MASK>
+__global__ __launch_bounds__(MTHREADS) void k_adj_d2q9_multi(ProblemArgs p,
+                                                             const float *__restrict__ states,
+                                                             size_t slot_floats, int slot_hi,
+                                                             int ksteps, int final_last,
+                                                             const float *__restrict__ mu_in,
+                                                             float *__restrict__ mu_out,
+                                                             double *__restrict__ partials,
+                                                             size_t stride, unsigned slice0)
+{
+    // per node of the region, two steps' buffers: (mu_R, mu_Jx, mu_Jy, mask id)
+    __shared__ float4 buf[2][MW * MW];
+    const int ntx = (p.nx + MT - 1) / MT;
+    const int tile_x0 = (int)(blockIdx.x % ntx) * MT;
+    const int tile_y0 = (int)(blockIdx.x / ntx) * MT;
+    const int tid = threadIdx.x;
+
+    constexpr int NL = (MW * MW + MTHREADS - 1) / MTHREADS;
+    float4 v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int j = tid + k * MTHREADS;
+        if (j < MW * MW) {
+            const int ly = j / MW, lx = j - (j / MW) * MW;
+            const long long g = (long long)wrap_mod(tile_y0 - MK + ly, p.ny) * p.nx +
+                                wrap_mod(tile_x0 - MK + lx, p.nx);
+            v[k] = make_float4(mu_in[3 * g], mu_in[3 * g + 1], mu_in[3 * g + 2],
+                               MASK ? (float)p.mask[g] : 0.0f);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int j = tid + k * MTHREADS;
+        if (j < MW * MW) buf[0][j] = v[k];
+    }
+    __syncthreads();
+
+    static_assert(MR == 2 && MW % 2 == 0, "strips of two rows tile every step's square");
+    for (int s = 1; s <= ksteps; ++s) {
+        const int b0 = (s - 1) & 1, b1 = s & 1;
+        const bool fin = final_last && s == ksteps;
+        const float *st = states + (size_t)(slot_hi - s + 1) * slot_floats;
+        const int m = MW - 2 * s;
+        const int items = (m / MR) * m;
+        const float inv_m = 1.0f / (float)m;
+        double da_sum = 0.0;
+        for (int it = tid; it < items; it += MTHREADS) {
+            const int strip = (int)(((float)it + 0.5f) * inv_m);
+            const int lx = s + (it - strip * m);
+            const int ly0 = s + strip * MR;
+            float4 w[MR + 2][3];
+#pragma unroll
+            for (int rr = 0; rr < MR + 2; ++rr)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                    w[rr][cc] = buf[b0][(ly0 - 1 + rr) * MW + lx - 1 + cc];
+#pragma unroll
+            for (int rr = 0; rr < MR; ++rr) {
+                const int ly = ly0 + rr;
+                const int l = ly * MW + lx;
+                const float4 own = w[rr + 1][1];
+                const int gx = tile_x0 - MK + lx, gy = tile_y0 - MK + ly;
+                const bool tile = lx >= MK && lx < MK + MT && ly >= MK && ly < MK + MT &&
+                                  gx < p.nx && gy < p.ny;
+                const long long g = (long long)wrap_mod(gy, p.ny) * p.nx + wrap_mod(gx, p.nx);
+                if (MASK && own.w != 0.0f) {  // solid: mu (or lambda) zero
+                    if (fin) {
+                        if (tile) mu_out[g] = mu_out[p.n + g] = mu_out[2 * p.n + g] = 0.0f;
+                    } else {
+                        buf[b1][l] = make_float4(0.0f, 0.0f, 0.0f, own.w);
+                    }
+                    continue;
+                }
+                const float uy[3] = {st[3 * g + 1], st[3 * g + 2], 0.0f};
+                const float dry = st[3 * g];
+                const float muJ[3] = {own.y, own.z, 0.0f};
+                auto fmask = [&](int dx, int dy, int) -> uint8_t {
+                    return MASK ? (uint8_t)w[rr + 1 + dy][1 + dx].w : (uint8_t)0;
+                };
+                auto fmu = [&](int dx, int dy, int, float &mr, float (&mt)[3]) {
+                    const float4 q = w[rr + 1 + dy][1 + dx];
+                    mr = q.x;
+                    mt[0] = q.y;
+                    mt[1] = q.z;
+                    mt[2] = 0.0f;
+                };
+                float lr, lu[3], da;
+                adj_node_update<9, MASK>(p, dry, uy, own.x, muJ, fmask, fmu, lr, lu, da);
+                if (tile) da_sum += (double)da;
+                if (fin) {
+                    if (tile) {
+                        mu_out[g] = lr;
+                        mu_out[p.n + g] = lu[0];
+                        mu_out[2 * p.n + g] = lu[1];
+                    }
+                } else {
+                    float mR, mJ[3];
+                    adj_fold<2>(dry, uy, lr, lu, mR, mJ);
+                    buf[b1][l] = make_float4(mR, mJ[0], mJ[1], own.w);
+                }
+            }
+        }
+        double acc[1] = {da_sum};
+        block_sum<1>(acc);  // its barriers also end the step
+        if (tid == 0) partials[(size_t)(slice0 + s - 1) * stride + blockIdx.x] = acc[0];
+    }
+
+    if (!final_last) {
+        const int bf = ksteps & 1;
+        for (int j = tid; j < MT * MT; j += MTHREADS) {
+            const int oy = j / MT, ox = j - (j / MT) * MT;
+            const int gx = tile_x0 + ox, gy = tile_y0 + oy;
+            if (gx >= p.nx || gy >= p.ny) continue;
+            const float4 q = buf[bf][(oy + MK) * MW + (ox + MK)];
+            const long long g = (long long)gy * p.nx + gx;
+            mu_out[3 * g] = q.x;
+            mu_out[3 * g + 1] = q.y;
+            mu_out[3 * g + 2] = q.z;
+        }
+    }
 }
 
 }  // namespace
@@ -174,22 +326,46 @@ unsigned d2q9_multi_num_blocks(const ProblemArgs &p)
     return (unsigned)(((long long)(p.nx + MT - 1) / MT) * ((p.ny + MT - 1) / MT));
 }
 
+hipError_t launch_adj_d2q9_multi(const ProblemArgs &p, const float *states, size_t slot_floats,
+                                 int slot_hi, int ksteps, int final_last, const float *mu_in,
+                                 float *mu_out, double *partials, size_t stride, unsigned slice0,
+                                 hipStream_t s)
+{
+    if (!d2q9_multi_supported(p) || ksteps < 1 || ksteps > MK || slot_hi < ksteps - 1)
+        return hipErrorInvalidValue;
+    const unsigned nb = d2q9_multi_num_blocks(p);
+    if (p.mask)
+        k_adj_d2q9_multi<true><<<nb, MTHREADS, 0, s>>>(p, states, slot_floats, slot_hi, ksteps,
+                                                       final_last, mu_in, mu_out, partials, stride,
+                                                       slice0);
+    else
+        k_adj_d2q9_multi<false><<<nb, MTHREADS, 0, s>>>(p, states, slot_floats, slot_hi, ksteps,
+                                                        final_last, mu_in, mu_out, partials,
+                                                        stride, slice0);
+    return hipGetLastError();
+}
+
 hipError_t launch_fwd_d2q9_multi(const ProblemArgs &p, const float *src, float *dst, int ksteps,
-                                 const ReduceArgs &r, hipStream_t s)
+                                 const ReduceArgs &r, hipStream_t s, float *slots,
+                                 size_t slot_floats)
 {
     if (!d2q9_multi_supported(p) || ksteps < 1 || ksteps > MK) return hipErrorInvalidValue;
     const unsigned nb = d2q9_multi_num_blocks(p);
     const bool force = p.has_force != 0;
     if (p.mask) {
         if (force)
-            k_fwd_d2q9_multi<true, true><<<nb, MTHREADS, 0, s>>>(p, src, dst, ksteps, r);
+            k_fwd_d2q9_multi<true, true><<<nb, MTHREADS, 0, s>>>(p, src, dst, ksteps, r, slots,
+                                                             slot_floats);
         else
-            k_fwd_d2q9_multi<true, false><<<nb, MTHREADS, 0, s>>>(p, src, dst, ksteps, r);
+            k_fwd_d2q9_multi<true, false><<<nb, MTHREADS, 0, s>>>(p, src, dst, ksteps, r, slots,
+                                                             slot_floats);
     } else {
         if (force)
-            k_fwd_d2q9_multi<false, true><<<nb, MTHREADS, 0, s>>>(p, src, dst, ksteps, r);
+            k_fwd_d2q9_multi<false, true><<<nb, MTHREADS, 0, s>>>(p, src, dst, ksteps, r, slots,
+                                                             slot_floats);
         else
-            k_fwd_d2q9_multi<false, false><<<nb, MTHREADS, 0, s>>>(p, src, dst, ksteps, r);
+            k_fwd_d2q9_multi<false, false><<<nb, MTHREADS, 0, s>>>(p, src, dst, ksteps, r, slots,
+                                                             slot_floats);
     }
     return hipGetLastError();
 }

@@ -227,68 +227,28 @@ __global__ __launch_bounds__(kGenericBlock) void k_adj_generic(ProblemArgs p, co
         }
         float dry, uy[3];
         load_state<D, T>(state, idx, p, dry, uy);
-        const float ry = 1.0f + dry;
-        const float By = -1.5f * (uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2]);
         const Coord c = decompose(idx, p.nx, p.ny);
         float muR_y, muJ_y[3];
         load_mu<D>(mu_in, idx, muR_y, muJ_y);
-        float lr = 0.0f, lu[3] = {0.0f, 0.0f, 0.0f}, da = 0.0f;
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            const long long t = node_at(p, wrap_add(c.x, link_cx(k), p.nx),
-                                        wrap_add(c.y, link_cy(k), p.ny),
-                                        wrap_add(c.z, link_cz(k), p.nz));
-            float m;
-            uint8_t wm = 0;
-            if (MASK) wm = p.mask[t];
-            if (MASK && wm != 0) {
-                // the term bounces back into y itself along -v_k
-                m = muR_y - vdot<Q>(k, muJ_y);
-                const float wd[3] = {p.wall_da[wm][0], p.wall_da[wm][1], p.wall_da[wm][2]};
-                da = fmaf(L::w36(k) * (1.0f / 36.0f) * vdot<Q>(k, wd), m, da);
-            } else {
-                float mr, mt[3];
-                load_mu<D>(mu_in, t, mr, mt);
-                m = mr + vdot<Q>(k, mt);
-            }
-            const float cc = vdot<Q>(k, uy);
-            const float wm_ = L::w36(k) * (1.0f / 36.0f) * m;
-            // d s_k / d(rho-1) = w_k [1 + c (A + 9/2 c) - 3/2 |u|^2]
-            lr = fmaf(wm_, 1.0f + cc * fmaf(4.5f, cc, p.A) + By, lr);
-            // d s_k / d u = w_k rho [(A + 9 c) v_k - 3 u]
-            const float q = wm_ * ry * fmaf(9.0f, cc, p.A);
-            if (link_cx(k) != 0) lu[0] += link_cx(k) * q;
-            if (link_cy(k) != 0) lu[1] += link_cy(k) * q;
-            if (link_cz(k) != 0) lu[2] += link_cz(k) * q;
-#pragma unroll
-            for (int j = 0; j < D; ++j) lu[j] = fmaf(-3.0f * wm_ * ry, uy[j], lu[j]);
-            // d s_k / d a = -3 w_k rho c
-            da = fmaf(-3.0f * wm_ * ry, cc, da);
-        }
-        // post-combine a rho u and forcing rho g of the node's own momentum
-        float mJu = 0.0f;
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            lr = fmaf(muJ_y[j], fmaf(p.a, uy[j], p.g[j]), lr);
-            lu[j] = fmaf(p.a * ry, muJ_y[j], lu[j]);
-            mJu = fmaf(muJ_y[j], uy[j], mJu);
-        }
-        da = fmaf(ry, mJu, da);
+        auto at = [&](int dx, int dy, int dz) {
+            return node_at(p, wrap_add(c.x, dx, p.nx), wrap_add(c.y, dy, p.ny),
+                           wrap_add(c.z, dz, p.nz));
+        };
+        auto fmask = [&](int dx, int dy, int dz) -> uint8_t { return p.mask[at(dx, dy, dz)]; };
+        auto fmu = [&](int dx, int dy, int dz, float &mr, float (&mt)[3]) {
+            load_mu<D>(mu_in, at(dx, dy, dz), mr, mt);
+        };
+        float lr, lu[3], da;
+        adj_node_update<Q, MASK>(p, dry, uy, muR_y, muJ_y, fmask, fmu, lr, lu, da);
         if (final_t0) {
             // the gradient with respect to the initial state, field-major
             mu_out[idx] = lr;
 #pragma unroll
             for (int j = 0; j < D; ++j) mu_out[(j + 1) * n + idx] = lu[j];
         } else {
-            // fold the normalisation u = J / rho of the previous step
-            const float inv = 1.0f / ry;
-            float lu_u = 0.0f;
-#pragma unroll
-            for (int j = 0; j < D; ++j) lu_u = fmaf(lu[j], uy[j], lu_u);
-            float mj[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int j = 0; j < D; ++j) mj[j] = lu[j] * inv;
-            store_mu<D>(mu_out, idx, lr - lu_u * inv, mj);
+            float mR, mJ[3];
+            adj_fold<D>(dry, uy, lr, lu, mR, mJ);
+            store_mu<D>(mu_out, idx, mR, mJ);
         }
         acc[0] += (double)da;
     }

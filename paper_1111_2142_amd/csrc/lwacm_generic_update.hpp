@@ -165,6 +165,84 @@ __device__ __forceinline__ void link_update(const ProblemArgs &p, long long idx,
     }
 }
 
+// The reverse step at one fluid node y (the exact derivative of link_update,
+// in the gather form of its transpose): given y's state (dry, uy), its own
+// mu_t (muR_y, muJ_y) and two accessors of the nodes y + (dx, dy, dz) --
+// fmask returns the mask value, fmu(dx, dy, dz, mr, mt) their mu_t -- the
+// cotangents of y's state lambda_t = (lr, lu) and y's share da of dL/da.
+// Shared by the one-step reverse kernel (accessors read global memory) and
+// the multi-step D2Q9 reverse kernel (accessors read its LDS tile), so both
+// round every operation alike.
+template <int Q, bool MASK, class FMask, class FMu>
+__device__ __forceinline__ void adj_node_update(const ProblemArgs &p, float dry,
+                                                const float (&uy)[3], float muR_y,
+                                                const float (&muJ_y)[3], const FMask &fmask,
+                                                const FMu &fmu, float &lr, float (&lu)[3],
+                                                float &da)
+{
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    const float ry = 1.0f + dry;
+    const float By = -1.5f * (uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2]);
+    lr = 0.0f;
+    lu[0] = lu[1] = lu[2] = 0.0f;
+    da = 0.0f;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        float m;
+        uint8_t wm = 0;
+        if (MASK) wm = fmask(link_cx(k), link_cy(k), link_cz(k));
+        if (MASK && wm != 0) {
+            // the term bounces back into y itself along -v_k
+            m = muR_y - vdot<Q>(k, muJ_y);
+            const float wd[3] = {p.wall_da[wm][0], p.wall_da[wm][1], p.wall_da[wm][2]};
+            da = fmaf(L::w36(k) * (1.0f / 36.0f) * vdot<Q>(k, wd), m, da);
+        } else {
+            float mr, mt[3];
+            fmu(link_cx(k), link_cy(k), link_cz(k), mr, mt);
+            m = mr + vdot<Q>(k, mt);
+        }
+        const float cc = vdot<Q>(k, uy);
+        const float wm_ = L::w36(k) * (1.0f / 36.0f) * m;
+        // d s_k / d(rho-1) = w_k [1 + c (A + 9/2 c) - 3/2 |u|^2]
+        lr = fmaf(wm_, 1.0f + cc * fmaf(4.5f, cc, p.A) + By, lr);
+        // d s_k / d u = w_k rho [(A + 9 c) v_k - 3 u]
+        const float q = wm_ * ry * fmaf(9.0f, cc, p.A);
+        if (link_cx(k) != 0) lu[0] += link_cx(k) * q;
+        if (link_cy(k) != 0) lu[1] += link_cy(k) * q;
+        if (link_cz(k) != 0) lu[2] += link_cz(k) * q;
+#pragma unroll
+        for (int j = 0; j < D; ++j) lu[j] = fmaf(-3.0f * wm_ * ry, uy[j], lu[j]);
+        // d s_k / d a = -3 w_k rho c
+        da = fmaf(-3.0f * wm_ * ry, cc, da);
+    }
+    // post-combine a rho u and forcing rho g of the node's own momentum
+    float mJu = 0.0f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        lr = fmaf(muJ_y[j], fmaf(p.a, uy[j], p.g[j]), lr);
+        lu[j] = fmaf(p.a * ry, muJ_y[j], lu[j]);
+        mJu = fmaf(muJ_y[j], uy[j], mJu);
+    }
+    da = fmaf(ry, mJu, da);
+}
+
+// mu_{t-1} of the node from its lambda_t: the normalisation u = J / rho of
+// the previous step folded in
+template <int D>
+__device__ __forceinline__ void adj_fold(float dry, const float (&uy)[3], float lr,
+                                         const float (&lu)[3], float &muR, float (&muJ)[3])
+{
+    const float inv = 1.0f / (1.0f + dry);
+    float lu_u = 0.0f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) lu_u = fmaf(lu[j], uy[j], lu_u);
+    muJ[0] = muJ[1] = muJ[2] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) muJ[j] = lu[j] * inv;
+    muR = lr - lu_u * inv;
+}
+
 }  // namespace
 
 }  // namespace lwacm

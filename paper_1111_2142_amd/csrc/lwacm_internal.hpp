@@ -165,8 +165,21 @@ constexpr int kMultiTile = 32;
 constexpr int kMultiSteps = 8;
 bool d2q9_multi_supported(const ProblemArgs &p);
 unsigned d2q9_multi_num_blocks(const ProblemArgs &p);
+// Up to kMultiSteps D2Q9 reverse steps per launch (FP32, the forward
+// multi-step kernel's problems): forward-step states in caller slots of
+// slot_floats floats, slot slot_hi for the first (latest) step, the rest
+// below it; mu node-interleaved in and out (field-major lambda out when
+// final_last: the last step is step 0); each step's per-workgroup dL/da in
+// partials[(slice0 + s) * stride + block] (blocks: d2q9_multi_num_blocks).
+hipError_t launch_adj_d2q9_multi(const ProblemArgs &p, const float *states, size_t slot_floats,
+                                 int slot_hi, int ksteps, int final_last, const float *mu_in,
+                                 float *mu_out, double *partials, size_t stride, unsigned slice0,
+                                 hipStream_t s);
+// slots non-null: the state after each of the ksteps steps goes to slots +
+// s * slot_floats (s = 0 .. ksteps - 1) instead of the last one to dst.
 hipError_t launch_fwd_d2q9_multi(const ProblemArgs &p, const float *src, float *dst, int ksteps,
-                                 const ReduceArgs &r, hipStream_t stream);
+                                 const ReduceArgs &r, hipStream_t stream, float *slots = nullptr,
+                                 size_t slot_floats = 0);
 
 // Number of blocks the generic grid-stride kernels use for n nodes.
 unsigned generic_grid(long long n);
