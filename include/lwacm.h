@@ -75,10 +75,12 @@ enum {
     LWACM_KERNEL_GENERIC = 1, /* one thread per node, neighbours from global memory */
     LWACM_KERNEL_MARCH = 2,   /* D3Q19 z-marching tile kernels (nx % 32 == 0, ny % 16 == 0;
                                  the forward one without body force), one step per launch */
-    LWACM_KERNEL_MARCH2 = 3   /* as MARCH, and the forward steps of FP32 problems without
-                                 walls (nz >= 2) two per launch: the intermediate state stays
-                                 on chip, halving the HBM bytes per update; results are
-                                 bitwise those of single steps.  AUTO includes it. */
+    LWACM_KERNEL_MARCH2 = 3   /* as MARCH, and the forward steps of FP32 problems two per
+                                 launch (nz >= 8; no walls or halfway walls, moving or not; no
+                                 interpolated walls, link velocities, body force or separate
+                                 omega_p): the intermediate state stays on chip, halving the
+                                 HBM bytes per update; results are bitwise those of single
+                                 steps.  AUTO includes it. */
 };
 
 /* Bytes of one state buffer: (D+1) * nodes * (4 for FP32, 2 for FP16).

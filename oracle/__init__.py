@@ -254,19 +254,23 @@ def step_q(p: Problem, rho, u, qd, uwl=None):
     return r1, u1
 
 
-def thermal_step(p: Problem, T, u, omega_t: float, wall_T=None):
+def thermal_step(p: Problem, T, u, omega_t: float, wall_T=None, qt=None):
     """One step of the temperature lattice (Eq. ACM2.0t) on the problem's
-    lattice, grid and mask, advected by the flow velocity u (D, nz, ny, nx) at
-    the same time; wall_T[m] is the temperature of the walls with mask id m
-    (NaN or ids past the end: adiabatic; None: all adiabatic).  Returns T at
-    the next step."""
+    grid and mask, advected by the flow velocity u (D, nz, ny, nx) at the
+    same time; wall_T[m] is the temperature of the walls with mask id m
+    (NaN or ids past the end: adiabatic; None: all adiabatic).  qt: the
+    temperature lattice, None for the problem's own, 5 (D2Q5) under D2Q9 or
+    7 (D3Q7) under D3Q19.  Returns T at the next step."""
     lib = _load()
     T = _f64(T, p.shape)
     u = _f64(u, (p.d,) + p.shape)
     mask = None if p.mask is None else np.ascontiguousarray(p.mask, dtype=np.uint8)
     wt = None if wall_T is None else np.ascontiguousarray(wall_T, dtype=np.float64).reshape(-1)
     out = np.empty_like(T)
-    rc = lib.oracle_thermal_step(p.q, p.nx, p.ny, p.nz, float(omega_t), _ptr(mask, _u8p),
+    q = p.q if qt is None else int(qt)
+    if q not in (p.q, 5 if p.q == 9 else 7):
+        raise ValueError(f"temperature lattice Q={q} under a Q={p.q} flow")
+    rc = lib.oracle_thermal_step(q, p.nx, p.ny, p.nz, float(omega_t), _ptr(mask, _u8p),
                                  _ptr(wt), 0 if wt is None else len(wt), _ptr(T), _ptr(u),
                                  _ptr(out))
     if rc != 0:
@@ -295,7 +299,8 @@ def wall_force(p: Problem, rho, u, wall_id: int, center=(0.0, 0.0, 0.0), qd=None
 
 
 def thermal_equilibrium(q: int, T: float, u):
-    """(g^(e)_i, g^(e,e)_i), i = 0..q-1, of the temperature lattice at (T, u)."""
+    """(g^(e)_i, g^(e,e)_i), i = 0..q-1, of the temperature lattice q (5, 7,
+    9 or 19) at (T, u)."""
     lib = _load()
     uu = np.zeros(3)
     uu[:len(u)] = u

@@ -47,9 +47,11 @@
  *   - force and torque on a wall by momentum exchange (Eqs. MEA3, MEA4,
  *     MEA5), for halfway and interpolated walls at rest;
  *   - the thermal extension (Appendix "Asymptotic analysis for energy
- *     equation", Eqs. ACM2.0t and feqe): a temperature lattice on the
- *     flow's lattice, advected by the flow velocity, with an equilibrium
- *     whose moments are the ones the appendix states, its even part taken
+ *     equation", Eqs. ACM2.0t and feqe): a temperature lattice, the flow's
+ *     own or the smaller D2Q5 / D3Q7 (the appendix allows Q_t != Q),
+ *     advected by the flow velocity, with an equilibrium whose moments are
+ *     the ones the appendix states (on D2Q5 / D3Q7 all but the O(eps^2)
+ *     u u part, which those lattices cannot carry), its even part taken
  *     literally as the mean at +u and -u, and adiabatic or fixed-temperature
  *     halfway walls (the oracle's reading; the paper has no thermal wall rule);
  *   - the vector-Jacobian product of one step (reverse mode), obtained by
@@ -79,6 +81,7 @@ typedef struct {
     int v[MAXQ][3]; /* link velocities */
     double w[MAXQ]; /* weights */
     int opp[MAXQ];  /* BB(i): the link opposite to i */
+    int lin;        /* temperature lattices D2Q5, D3Q7: linear equilibrium */
 } lattice_t;
 
 /* D2Q9 in the order of Appendix A: rest, the four axis links, the four
@@ -298,10 +301,14 @@ void oracle_set_num_threads(int n)
 #endif
 }
 
+static int make_thermal_lattice(int qt, lattice_t *L);
+
+/* D, velocities, weights and opposite links of lattice q: the flow lattices
+ * 9 and 19, and the temperature-only lattices 5 and 7. */
 int oracle_lattice_info(int q, int *d, int *v_out, double *w_out, int *opp_out)
 {
     lattice_t L;
-    if (make_lattice(q, &L)) return -1;
+    if (make_thermal_lattice(q, &L)) return -1;
     *d = L.d;
     for (int i = 0; i < L.q; ++i) {
         for (int k = 0; k < 3; ++k) v_out[3 * i + k] = L.v[i][k];
@@ -828,18 +835,59 @@ int oracle_vjp(int q, int nx, int ny, int nz, double omega, const uint8_t *mask,
 /* ---- thermal LW-ACM: a temperature lattice advected by the flow ----
  *
  * Appendix "Asymptotic analysis for energy equation", Eqs. ACM2.0t and
- * feqe.  The temperature lattice uses the flow's lattice (Q_t = Q); its only
- * state is T at every node.  The velocity u in its equilibria is the flow
- * velocity at the same node and time (the flow is not influenced by T).
+ * feqe.  The temperature lattice is the flow's (Q_t = Q) or, as the appendix
+ * allows (Q_t != Q), the rest link and the axis links alone: D2Q5 under a
+ * D2Q9 flow, D3Q7 under a D3Q19 flow.  Its only state is T at every node.
+ * The velocity u in its equilibria is the flow velocity at the same node and
+ * time (the flow is not influenced by T).
  */
+
+/* Temperature lattices: D2Q9 and D3Q19 as the flow's; D2Q5 (rest and the
+ * four axis links of D2Q9, weights 1/3, 1/6) and D3Q7 (rest and the six
+ * axis links of D3Q19, weights 0, 1/6).  The second moment T/3 I that the
+ * appendix requires fixes the axis weight at 1/6 (sum_i w_i v_i v_i =
+ * 2 w_axis I), and the weights sum to one; D3Q7 then has no rest weight. */
+static int make_thermal_lattice(int qt, lattice_t *L)
+{
+    if (qt == 9 || qt == 19) return make_lattice(qt, L);
+    if (qt != 5 && qt != 7) return -1;
+    if (make_lattice(qt == 5 ? 9 : 19, L)) return -1;
+    lattice_t A = *L;
+    int k = 0;
+    for (int i = 0; i < A.q; ++i) {
+        int nz = (A.v[i][0] != 0) + (A.v[i][1] != 0) + (A.v[i][2] != 0);
+        if (nz > 1) continue; /* keep the rest and the axis links, in order */
+        for (int c = 0; c < 3; ++c) L->v[k][c] = A.v[i][c];
+        L->w[k] = (nz == 0) ? (qt == 5 ? 1.0 / 3.0 : 0.0) : 1.0 / 6.0;
+        ++k;
+    }
+    if (k != qt) return -1;
+    L->q = qt;
+    L->lin = 1;
+    for (int i = 0; i < L->q; ++i) {
+        L->opp[i] = -1;
+        for (int j = 0; j < L->q; ++j)
+            if (L->v[j][0] == -L->v[i][0] && L->v[j][1] == -L->v[i][1] &&
+                L->v[j][2] == -L->v[i][2])
+                L->opp[i] = j;
+        if (L->opp[i] < 0) return -1;
+    }
+    return 0;
+}
 
 /* g_i^(e)(T, u): the function of T and u whose moments are the ones the
  * appendix requires -- sum_i g = T, sum_i v_i g = T u and
  * sum_i v_i v_i g = u u + T/3 I -- written with the lattice's weights as
- * w_i [T (1 + 3 v_i.u) + 4.5 (v_i.u)^2 - 1.5 |u|^2]. */
+ * w_i [T (1 + 3 v_i.u) + 4.5 (v_i.u)^2 - 1.5 |u|^2] on D2Q9 and D3Q19.
+ * D2Q5 and D3Q7 cannot carry the u u part (their v_i v_i have no
+ * off-diagonal components, and no quadratic term has both the diagonal
+ * u_a^2 and a zero sum); under the appendix's diffusive scaling (Eq.
+ * scaling2t) that part is O(eps^2), so on those lattices the equilibrium is
+ * the linear one, w_i T (1 + 3 v_i.u), with the moments T, T u and T/3 I. */
 static double geq(const lattice_t *L, int i, double T, const double u[3])
 {
     double c = vdot(L, i, u);
+    if (L->lin) return L->w[i] * T * (1.0 + 3.0 * c);
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     return L->w[i] * (T * (1.0 + 3.0 * c) + 4.5 * c * c - 1.5 * uu);
 }
@@ -851,13 +899,14 @@ static double gee(const lattice_t *L, int i, double T, const double u[3])
     return 0.5 * (geq(L, i, T, u) + geq(L, i, T, mu));
 }
 
-/* g^(e)_i(T, u) and g^(e,e)_i(T, u) for i = 0..q-1 (pinned in the tests
- * against the moments the appendix requires). */
+/* g^(e)_i(T, u) and g^(e,e)_i(T, u) for i = 0..q-1 of the temperature
+ * lattice q (5, 7, 9 or 19; pinned in the tests against the moments the
+ * appendix requires). */
 int oracle_thermal_equilibrium(int q, double T, const double *u_in, double *g_out,
                                double *gee_out)
 {
     lattice_t L;
-    if (make_lattice(q, &L)) return -1;
+    if (make_thermal_lattice(q, &L)) return -1;
     double u[3] = {0, 0, 0};
     for (int k = 0; k < L.d; ++k) u[k] = u_in[k];
     for (int i = 0; i < L.q; ++i) {
@@ -871,6 +920,7 @@ int oracle_thermal_equilibrium(int q, double T, const double *u_in, double *g_ou
  * One step of the temperature lattice, Eq. ACM2.0t:
  *   g_i(x, t+1) = g^(e)_i(x - v_i) + (2 - 2/omega_t) (g^(e,e)_i(x) - g^(e,e)_i(x - v_i)),
  *   T(x, t+1)   = sum_i g_i(x, t+1),
+ * on the temperature lattice q (5, 7, 9 or 19; D2Q5 and D2Q9 need nz = 1),
  * with T(., t) from T_in and u(., t) the flow velocity (D fields, SoA).
  *
  * Walls (the paper gives no thermal wall rule; this is the oracle's reading,
@@ -890,7 +940,7 @@ int oracle_thermal_step(int q, int nx, int ny, int nz, double omega_t, const uin
                         double *T_out)
 {
     lattice_t L;
-    if (make_lattice(q, &L)) return -1;
+    if (make_thermal_lattice(q, &L)) return -1;
     if (nx <= 0 || ny <= 0 || nz <= 0 || (L.d == 2 && nz != 1)) return -1;
     if (!(omega_t > 0.0 && omega_t < 2.0)) return -1;
     long n = (long)nx * ny * nz;

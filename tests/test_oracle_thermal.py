@@ -17,6 +17,14 @@ energy equation", Eqs. ACM2.0t, feqe, AAT2 and diffusivity2).
   state is the exact linear profile, at rest and in plane Couette flow (the
   thermal Couette problem without viscous heating, Br = 0); a uniform
   initial state converges to it.
+- A temperature lattice smaller than the flow's (Q_t != Q, which the
+  appendix allows): D2Q5 under D2Q9, D3Q7 under D3Q19.  The lattice is the
+  rest link and the axis links with weights fixed by the required moments
+  (axis 1/6 from T/3 I, the rest the remainder: 1/3 and 0); its equilibrium
+  has the moments T, T u and T/3 I exactly and no u u part (those lattices
+  cannot carry it; it is O(eps^2) under the diffusive scaling).  The same
+  Fourier amplification factor with these weights, the paper's alpha, the
+  conservation and the linear-profile pins hold on them.
 """
 import numpy as np
 import pytest
@@ -165,3 +173,171 @@ def test_linear_profile_between_fixed_temperature_walls_is_steady(q, U, omega_t)
 @pytest.mark.parametrize("q", [9, 19])
 def test_thermal_couette_without_heating_converges_to_linear_profile(q):
     assert _channel(q, 10, 1.0, 0.2, 0.05, 1.5, 1500, False) < 1e-9
+
+
+# ---- temperature lattices smaller than the flow's (Q_t != Q)
+
+# The rest link and the axis links; axis weight 1/6 (second moment T/3 I),
+# rest weight 1 - 2 D / 6.
+def _axis_lattice(qt):
+    d = 2 if qt == 5 else 3
+    v = [np.zeros(3, int)]
+    for a in range(d):
+        for sgn in (1, -1):
+            e = np.zeros(3, int)
+            e[a] = sgn
+            v.append(e)
+    w = [1.0 - 2 * d / 6.0] + [1.0 / 6.0] * (2 * d)
+    return d, np.array(v), np.array(w)
+
+
+def _flow_q(qt):
+    return 9 if qt == 5 else 19
+
+
+@pytest.mark.parametrize("qt", [5, 7])
+def test_axis_lattice_is_rest_and_axis_links_with_moment_weights(qt):
+    d, v, w = _axis_lattice(qt)
+    do, vo, wo, opp = oracle.lattice_info(qt)
+    assert do == d
+    assert sorted(map(tuple, vo)) == sorted(map(tuple, v))
+    for i in range(qt):
+        j = [k for k in range(qt) if tuple(v[k]) == tuple(vo[i])][0]
+        assert abs(wo[i] - w[j]) < 1e-15
+        assert tuple(vo[opp[i]]) == tuple(-vo[i])
+
+
+@pytest.mark.parametrize("qt", [5, 7])
+def test_axis_lattice_equilibrium_moments(qt):
+    d, v, w, _ = oracle.lattice_info(qt)
+    rng = _rng(3)
+    eye = np.diag([1.0] * d + [0.0] * (3 - d))
+    vv = np.einsum("ia,ib->iab", v, v)
+    for _ in range(5):
+        T = rng.uniform(0.2, 1.0)
+        u = rng.uniform(-0.1, 0.1, d)
+        u3 = np.zeros(3)
+        u3[:d] = u
+        g, ge = oracle.thermal_equilibrium(qt, T, u)
+        assert abs(g.sum() - T) < 1e-15
+        assert np.abs(v.T @ g - T * u3).max() < 1e-15
+        assert np.abs(np.einsum("iab,i->ab", vv, g) - T / 3.0 * eye).max() < 1e-15
+        assert abs(ge.sum() - T) < 1e-15
+        assert np.abs(v.T @ ge).max() < 1e-15
+        assert np.abs(np.einsum("iab,i->ab", vv, ge) - T / 3.0 * eye).max() < 1e-15
+        assert np.abs(ge - 0.5 * (g + oracle.thermal_equilibrium(qt, T, -u)[0])).max() < 1e-16
+
+
+@pytest.mark.parametrize("qt,shape,kvec,u,omega_t", [
+    (5, (1, 16, 24), (2 * np.pi * 3 / 24, 2 * np.pi / 16, 0.0), (0.04, -0.03), 1.3),
+    (5, (1, 12, 12), (2 * np.pi * 2 / 12, 2 * np.pi * 5 / 12, 0.0), (0.0, 0.1), 0.7),
+    (7, (8, 12, 10), (2 * np.pi / 10, 2 * np.pi * 2 / 12, 2 * np.pi * 3 / 8), (0.03, 0.02, -0.05),
+     1.6),
+])
+def test_axis_lattice_fourier_mode_in_uniform_flow(qt, shape, kvec, u, omega_t):
+    d, v, w = _axis_lattice(qt)
+    kap = 2.0 - 2.0 / omega_t
+    k3 = np.array(kvec)
+    u3 = np.zeros(3)
+    u3[:d] = u
+    lam = kap + sum(w[i] * (1.0 + 3.0 * (v[i] @ u3) - kap) * np.exp(-1j * (k3 @ v[i]))
+                    for i in range(qt))
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phase = k3[0] * x + k3[1] * y + k3[2] * z
+    T = 0.5 + 0.1 * np.cos(phase)
+    uf = np.zeros((d,) + shape)
+    for a in range(d):
+        uf[a] = u[a]
+    p = Problem(_flow_q(qt), nx, ny, nz)
+    steps = 15
+    for _ in range(steps):
+        T = oracle.thermal_step(p, T, uf, omega_t, qt=qt)
+    exact = 0.5 + 0.1 * np.real(lam ** steps * np.exp(1j * phase))
+    assert np.abs(T - exact).max() < 1e-13
+
+
+@pytest.mark.parametrize("qt,shape", [(5, (1, 2, 128)), (7, (2, 2, 128))])
+def test_axis_lattice_long_wave_diffuses_with_alpha(qt, shape):
+    n, steps = shape[2], 400
+    kx = 2 * np.pi / n
+    x = np.arange(n)
+    for omega_t in (1.2, 1.8, 0.8):
+        T = 0.5 + 0.1 * np.cos(kx * x) * np.ones(shape)
+        u = np.zeros((2 if qt == 5 else 3,) + shape)
+        p = Problem(_flow_q(qt), shape[2], shape[1], shape[0])
+        for _ in range(steps):
+            T = oracle.thermal_step(p, T, u, omega_t, qt=qt)
+        amp = 2.0 / n * np.sum((T[0, 0] - 0.5) * np.exp(-1j * kx * x)) / 0.1
+        alpha = (1.0 / omega_t - 0.5) / 3.0
+        alpha_meas = -np.log(abs(amp)) / (kx * kx * steps)
+        assert abs(alpha_meas / alpha - 1.0) < 5e-3, (omega_t, alpha_meas, alpha)
+
+
+@pytest.mark.parametrize("qt,shape", [(5, (1, 18, 20)), (7, (8, 10, 12))])
+def test_axis_lattice_total_temperature_is_conserved(qt, shape):
+    d = 2 if qt == 5 else 3
+    nz, ny, nx = shape
+    rng = _rng(4)
+    T = rng.uniform(0.3, 1.0, shape)
+    u = 0.05 * rng.standard_normal((d,) + shape)
+    mask = (rng.random(shape) < 0.12).astype(np.uint8)
+    mask[mask == 1] = rng.integers(1, 4, int(mask.sum())).astype(np.uint8)
+    for m in (None, mask):
+        p = Problem(_flow_q(qt), nx, ny, nz, mask=m)
+        fl = np.ones(shape, bool) if m is None else (m == 0)
+        total0 = T[fl].sum()
+        t = T
+        for _ in range(20):
+            t = oracle.thermal_step(p, t, u, 1.4, qt=qt)
+        assert abs(t[fl].sum() / total0 - 1.0) < 1e-13
+        if m is not None:
+            assert np.array_equal(t[~fl], T[~fl])
+
+
+def _channel_qt(qt, h, Tb, Tt, U, omega_t, steps, start_exact):
+    q = _flow_q(qt)
+    d = 2 if q == 9 else 3
+    ax = 1 if q == 9 else 2
+    shape = (1, h, 4) if q == 9 else (h, 4, 4)
+    nz, ny, nx = shape
+    mask = np.zeros(shape, np.uint8)
+    sl = [slice(None)] * 3
+    sl[2 - ax] = 0
+    mask[tuple(sl)] = 1
+    sl[2 - ax] = h - 1
+    mask[tuple(sl)] = 2
+    coord = np.arange(h, dtype=float)
+    exact = Tb + (Tt - Tb) * (coord - 0.5) / (h - 2.0)
+    bshape = [1, 1, 1]
+    bshape[2 - ax] = h
+    prof = exact.reshape(bshape) * np.ones(shape)
+    u = np.zeros((d,) + shape)
+    u[0] = (U * (coord - 0.5) / (h - 2.0)).reshape(bshape)
+    T = prof.copy() if start_exact else np.full(shape, 0.5 * (Tb + Tt))
+    p = Problem(q, nx, ny, nz, mask=mask)
+    for _ in range(steps):
+        T = oracle.thermal_step(p, T, u, omega_t, wall_T=[np.nan, Tb, Tt], qt=qt)
+    fl = mask == 0
+    return float(np.abs(T[fl] - prof[fl]).max() / abs(Tt - Tb))
+
+
+@pytest.mark.parametrize("qt", [5, 7])
+@pytest.mark.parametrize("U", [0.0, 0.05])
+@pytest.mark.parametrize("omega_t", [0.9, 1.5])
+def test_axis_lattice_linear_profile_is_steady(qt, U, omega_t):
+    assert _channel_qt(qt, 10, 1.0, 0.2, U, omega_t, 40, True) < 1e-13
+
+
+@pytest.mark.parametrize("qt", [5, 7])
+def test_axis_lattice_converges_to_linear_profile(qt):
+    assert _channel_qt(qt, 10, 1.0, 0.2, 0.05, 1.5, 1500, False) < 1e-9
+
+
+def test_temperature_lattice_must_fit_the_flow():
+    p = Problem(9, 8, 8, 1)
+    T = np.ones((1, 8, 8))
+    u = np.zeros((2, 1, 8, 8))
+    for qt in (7, 19, 6):
+        with pytest.raises(ValueError):
+            oracle.thermal_step(p, T, u, 1.3, qt=qt)
