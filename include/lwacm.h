@@ -284,6 +284,21 @@ int lwacm_set_wall_velocity_links(lwacm_ctx *c, const float *d_uw);
 int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
                       const float *h_wall_T, int n_wall_T);
 
+/* The temperature lattice (Appendix "Asymptotic analysis for energy
+ * equation": the number of its links may differ from the flow's, Q_t != Q).
+ *   q_t  0 or the flow's Q: the flow's lattice (the default);
+ *        5 under a D2Q9 flow (D2Q5) or 7 under D3Q19 (D3Q7): the rest link
+ *        and the axis links, weights 1/3, 1/6 (D2Q5) and 0, 1/6 (D3Q7) -- the
+ *        axis weight 1/6 is what the required second moment T/3 I fixes.
+ *        These lattices cannot carry the u u part of the second moment
+ *        (O(eps^2) under the diffusive scaling), so their equilibrium is
+ *        w_i T (1 + 3 v_i.u), with moments T, T u and T/3 I; alpha is the
+ *        same (Eq. diffusivity2), and the wall rule of lwacm_set_thermal
+ *        applies link by link.  They run on the one-thread-per-node kernel.
+ * May be called before or after lwacm_set_thermal; it takes effect from the
+ * next step and stays until changed.  LWACM_EINVAL for any other q_t. */
+int lwacm_set_thermal_lattice(lwacm_ctx *c, int q_t);
+
 /* Force and torque that the fluid exerts on the walls with mask id wall_id,
  * by momentum exchange (Section "Moving complex boundaries", Eqs. MEA3, MEA4
  * and MEA5), from the current state.  Every link j from a fluid node x to a

@@ -49,6 +49,7 @@ struct lwacm_ctx {
     unsigned long long n_fluid;
     // temperature lattice (lwacm_set_thermal): two caller-owned buffers
     bool thermal;
+    int thermal_qt;  // temperature lattice (lwacm_set_thermal_lattice): 0 = the flow's
     float *T_buf[2];
     int tcur;
     lwacm::ThermalArgs targs;
@@ -614,6 +615,7 @@ int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
     if (c->storage != LWACM_FP32 || c->variant == LWACM_KERNEL_MARCH2) return LWACM_EUNSUPPORTED;
     lwacm::ThermalArgs &t = c->targs;
     t.Q = c->p.Q;
+    t.QT = c->thermal_qt ? c->thermal_qt : c->p.Q;
     t.nx = c->p.nx;
     t.ny = c->p.ny;
     t.nz = c->p.nz;
@@ -627,6 +629,16 @@ int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
     c->tcur = 0;
     c->thermal = true;
     return omega_t < 1.0 ? LWACM_WOMEGA : LWACM_OK;
+}
+
+int lwacm_set_thermal_lattice(lwacm_ctx *c, int q_t)
+{
+    if (!c) return LWACM_EINVAL;
+    const int axis = c->p.Q == 9 ? 5 : 7;
+    if (q_t != 0 && q_t != c->p.Q && q_t != axis) return LWACM_EINVAL;
+    c->thermal_qt = q_t == c->p.Q ? 0 : q_t;
+    c->targs.QT = q_t ? q_t : c->p.Q;
+    return LWACM_OK;
 }
 
 int lwacm_wall_force(lwacm_ctx *c, int wall_id, const double *h_center, double *h_out)
@@ -789,7 +801,7 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
         // state this step's flow kernel reads, before that kernel runs
         ProblemArgs pl = c->p;
         const bool tfuse = c->thermal && march && !two && c->storage == LWACM_FP32 &&
-                           lwacm::march_thermal_supported(c->p);
+                           c->targs.QT == c->p.Q && lwacm::march_thermal_supported(c->p);
         if (tfuse) {
             pl.T_in = c->T_buf[c->tcur];
             pl.T_out = c->T_buf[c->tcur ^ 1];

@@ -29,7 +29,6 @@ constexpr int MT = kMultiTile;       // output tile side
 constexpr int MK = kMultiSteps;      // halo width = most steps per launch
 constexpr int MW = MT + 2 * MK;      // region side
 constexpr int MTHREADS = 1024;       // 32 x 32 threads
-constexpr int MSIDE = 32;
 
 __device__ __forceinline__ int wrap_mod(int v, int n)
 {

@@ -1,7 +1,8 @@
 // lwacm_thermal.hip -- the temperature lattice of the thermal LW-ACM.
 //
 // Appendix "Asymptotic analysis for energy equation", Eq. ACM2.0t: a second
-// lattice (here the flow's own, Q_t = Q) whose only state is T.  With
+// lattice (the flow's own, Q_t = Q, or its rest and axis links alone, Q_t =
+// 5 or 7: see below) whose only state is T.  With
 // c = v_i . u and q = 9/2 c^2 - 3/2 |u|^2 its equilibrium is
 // g^(e)_i = w_i [T (1 + 3 c) + q] (moments T, T u and u u + T/3 I) and the
 // even part of Eq. feqe is w_i (T + q).  Eq. ACM2.0t then reads, with
@@ -16,6 +17,14 @@
 // unchanged (adiabatic wall) or with its sign reversed plus 2 h w_i T_w (wall
 // at temperature T_w, anti-bounce-back).  The paper states no thermal wall
 // rule; a linear profile between two such walls is an exact steady state.
+//
+// Q_t != Q (the appendix allows it): D2Q5 under a D2Q9 flow, D3Q7 under
+// D3Q19, the rest link and the axis links with 36 w = 6 on the axis links and
+// 36 - 12 D on the rest link (12 and 0): the second moment T/3 I fixes the
+// axis weight.  These lattices cannot carry the u u part of the second
+// moment (O(eps^2) under diffusive scaling), so their equilibrium is the
+// linear w_i T (1 + 3 c): the terms above with q = 0.  They run the gather
+// kernel.
 //
 // D3Q19 with nx % 32 == 0 and ny % 16 == 0 runs the tile kernel: a workgroup
 // owns a 32 x 16 column tile and marches up a chunk of z planes; each plane's
@@ -58,7 +67,19 @@ __device__ __forceinline__ void load_u(const float *state, long long idx, float 
     }
 }
 
-template <int Q, bool MASK>
+// links of the axis lattice (rest and axis links) and their 36 w
+__host__ __device__ constexpr bool axis_link(int i)
+{
+    return (link_cx(i) != 0) + (link_cy(i) != 0) + (link_cz(i) != 0) <= 1;
+}
+template <int Q>
+__host__ __device__ constexpr float axis_w36(int i)
+{
+    return i == 0 ? 36.0f - 12.0f * Lattice<Q>::D : 6.0f;
+}
+
+// AXIS: the temperature on the axis lattice of the flow's lattice Q
+template <int Q, bool MASK, bool AXIS>
 __global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_step(ThermalArgs t)
 {
     const int x = blockIdx.x * kThermalBX + threadIdx.x;
@@ -74,16 +95,17 @@ __global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_step(Thermal
     }
     float ux[3];
     load_u<Q>(t.state, idx, ux);
-    const float bx = -1.5f * (ux[0] * ux[0] + ux[1] * ux[1] + ux[2] * ux[2]);
+    const float bx = AXIS ? 0.0f : -1.5f * (ux[0] * ux[0] + ux[1] * ux[1] + ux[2] * ux[2]);
     float acc = 0.0f;  // sum of 36 w_i times the incoming terms
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
+        if (AXIS && (!axis_link(i) || axis_w36<Q>(i) == 0.0f)) continue;
         const int cx = link_cx(i), cy = link_cy(i), cz = link_cz(i);
         const int xs = wrap_step(x, cx, t.nx);
         const int ys = wrap_step(y, cy, t.ny);
         const int zs = wrap_step(z, cz, t.nz);
         const long long is = (long long)zs * plane + (long long)ys * t.nx + xs;
-        const float w36 = Lattice<Q>::w36(i);
+        const float w36 = AXIS ? axis_w36<Q>(i) : Lattice<Q>::w36(i);
         float term;
         bool fluid = true;
         uint8_t m = 0;
@@ -96,11 +118,13 @@ __global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_step(Thermal
             load_u<Q>(t.state, is, us);
             const float Ts = t.T_in[is];
             const float c = cx * us[0] + cy * us[1] + cz * us[2];
-            const float q = fmaf(4.5f * c, c, -1.5f * (us[0] * us[0] + us[1] * us[1] + us[2] * us[2]));
+            const float q =
+                AXIS ? 0.0f
+                     : fmaf(4.5f * c, c, -1.5f * (us[0] * us[0] + us[1] * us[1] + us[2] * us[2]));
             term = fmaf(t.h, Ts + q, 3.0f * Ts * c);
         } else {
             const float c = cx * ux[0] + cy * ux[1] + cz * ux[2];
-            const float q = fmaf(4.5f * c, c, bx);
+            const float q = AXIS ? 0.0f : fmaf(4.5f * c, c, bx);
             const float sent = fmaf(t.h, Tx + q, -3.0f * Tx * c);
             const float Tw = m < kMaxThermalWallIds ? t.wall_T[m] : __builtin_nanf("");
             term = (Tw != Tw) ? sent : fmaf(2.0f * t.h, Tw, -sent);
@@ -260,7 +284,7 @@ __global__ __launch_bounds__(kTX *kTY) void k_thermal_march(ThermalArgs t)
 
 bool march_shape(const ThermalArgs &t)
 {
-    return t.Q == 19 && t.nx % kTX == 0 && t.ny % kTY == 0;
+    return t.Q == 19 && t.QT == 19 && t.nx % kTX == 0 && t.ny % kTY == 0;
 }
 
 template <int Q>
@@ -281,10 +305,15 @@ hipError_t launch_q(const ThermalArgs &t, hipStream_t stream)
     const dim3 block(kThermalBX, kThermalBY, 1);
     const dim3 grid((t.nx + kThermalBX - 1) / kThermalBX, (t.ny + kThermalBY - 1) / kThermalBY,
                     t.nz);
-    if (t.mask)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, true>), grid, block, 0, stream, t);
+    const bool axis = t.QT != Q;
+    if (t.mask && axis)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, true, true>), grid, block, 0, stream, t);
+    else if (t.mask)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, true, false>), grid, block, 0, stream, t);
+    else if (axis)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, false, true>), grid, block, 0, stream, t);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, false>), grid, block, 0, stream, t);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, false, false>), grid, block, 0, stream, t);
     return hipGetLastError();
 }
 
@@ -295,6 +324,7 @@ hipError_t launch_thermal_step(const ThermalArgs &t, hipStream_t stream)
     if (t.nx <= 0 || t.ny <= 0 || t.nz <= 0 || t.nz > 65535 ||
         (t.ny + kThermalBY - 1) / kThermalBY > 65535)
         return hipErrorInvalidValue;
+    if (t.QT != t.Q && t.QT != (t.Q == 9 ? 5 : 7)) return hipErrorInvalidValue;
     if (t.Q == 9) return t.nz == 1 ? launch_q<9>(t, stream) : hipErrorInvalidValue;
     if (t.Q == 19) return launch_q<19>(t, stream);
     return hipErrorInvalidValue;

@@ -12,6 +12,8 @@ constexpr int kMaxThermalWallIds = 16;
 
 struct ThermalArgs {
     int Q, nx, ny, nz;
+    int QT;               // temperature lattice: Q, or 5 (D2Q5) / 7 (D3Q7), the rest
+                          // and axis links of the flow's lattice
     float kap;            // 2 - 2/omega_t: weight of the even-part difference
     float h;              // 1 - kap = 2/omega_t - 1
     const float *state;   // flow state at the step's time, FP32 (D + 1 floats per node)

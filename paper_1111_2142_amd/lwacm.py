@@ -68,6 +68,7 @@ def load_library():
         "lwacm_set_omega_p": (i, [_vp, ctypes.c_double]),
         "lwacm_set_force_field": (i, [_vp, _vp]),
         "lwacm_set_thermal": (i, [_vp, d, _vp, _vp, _vp, i]),
+        "lwacm_set_thermal_lattice": (i, [_vp, i]),
         "lwacm_set_wall_velocity_links": (i, [_vp, _vp]),
         "lwacm_set_semi_implicit": (i, [_vp, i]),
         "lwacm_temperature": (i, [_vp, ctypes.POINTER(_vp)]),
@@ -198,6 +199,12 @@ def lwacm_set_thermal(ctx, omega_t: float, T_a: Optional[torch.Tensor],
         arr = (ctypes.c_float * max(n, 1))(*[float(v) for v in wall_T])
     _check(load_library().lwacm_set_thermal(ctx, float(omega_t), _ptr(T_a), _ptr(T_b), arr, n),
            "lwacm_set_thermal")
+
+
+def lwacm_set_thermal_lattice(ctx, q_t: int):
+    """Temperature lattice: 0 or the flow's Q, 5 (D2Q5) under D2Q9, 7 (D3Q7)
+    under D3Q19."""
+    _check(load_library().lwacm_set_thermal_lattice(ctx, int(q_t)), "lwacm_set_thermal_lattice")
 
 
 def lwacm_temperature(ctx) -> int:
@@ -427,9 +434,10 @@ class Solver:
         lwacm_set_wall_velocity_links(self.ctx, uw)
 
     def set_thermal(self, omega_t: float, T: Optional[torch.Tensor],
-                    wall_T: Optional[Sequence[float]] = None):
+                    wall_T: Optional[Sequence[float]] = None, q_t: int = 0):
         """Advance a temperature field T (nz, ny, nx) with every following step
-        (thermal LW-ACM, relaxation omega_t); None switches it off.  The solver
+        (thermal LW-ACM, relaxation omega_t) on the temperature lattice q_t
+        (0: the flow's; 5 or 7: D2Q5 / D3Q7); None switches it off.  The solver
         owns the two FP32 buffers it passes to the library."""
         if T is None:
             lwacm_set_thermal(self.ctx, 1.0, None, None)
@@ -440,6 +448,7 @@ class Solver:
             raise LWACMError(LWACM_EINVAL, "set_thermal size")
         a = T.clone().reshape(self.shape)
         b = torch.empty_like(a)
+        lwacm_set_thermal_lattice(self.ctx, q_t)
         lwacm_set_thermal(self.ctx, omega_t, a, b, wall_T)
         self._T = (a, b)
 

@@ -16,6 +16,9 @@ thermal_step, run in lockstep with the flow.
 - Unmasked D3Q19 tile shapes run the temperature step inside the flow's
   single-step kernel: against the temperature kernel of its own (generic
   variant) and the oracle.
+- A temperature lattice smaller than the flow's (D2Q5 under D2Q9, D3Q7 under
+  D3Q19) against the oracle's, with and without walls; the lattice switched
+  back to the flow's mid-run; scope of lwacm_set_thermal_lattice.
 """
 import numpy as np
 import pytest
@@ -209,3 +212,92 @@ def test_temperature_leaves_the_flow_alone_and_scope():
         h.set_thermal(1.2, T0)
     assert ei.value.code == L.LWACM_EUNSUPPORTED
     h.close()
+
+
+@pytest.mark.parametrize("q,qt,masked,shape", [(9, 5, False, (1, 40, 48)), (9, 5, True, (1, 40, 48)),
+                                                (19, 7, False, (12, 32, 32)),
+                                                (19, 7, True, (40, 32, 64)),
+                                                (19, 7, True, (10, 20, 24))])
+def test_axis_temperature_lattice_matches_oracle(q, qt, masked, shape):
+    """A temperature lattice smaller than the flow's (lwacm_set_thermal_lattice:
+    D2Q5 under D2Q9, D3Q7 under D3Q19) on tile and other shapes, random flow,
+    T and walls of three kinds, 6 steps in lockstep with the flow: T on the
+    fluid nodes to the FP32 bar; solid nodes keep their T."""
+    L = need_gpu()
+    banner(f"thermal axis lattice q={q} qt={qt} masked={masked} shape={shape}")
+    nz, ny, nx = shape
+    d = 2 if q == 9 else 3
+    drho, u = wl.random_state(shape, d, seed=71, du=0.03, drho=0.01)
+    drho = drho.astype(np.float32).astype(np.float64)
+    u = u.astype(np.float32).astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(72))
+    T = rng.uniform(0.2, 1.0, shape).astype(np.float32).astype(np.float64)
+    mask = _walls(shape, 73) if masked else None
+    table = np.zeros((4, 3))
+    s = L.Solver(q, nx, ny, nz, 1.6, mask=None if mask is None else to_dev(mask, torch.uint8),
+                 wall_u=[list(r) for r in table])
+    s.set_state(to_dev(drho), to_dev(u))
+    s.set_thermal(1.3, to_dev(T), wall_T=WALL_T, q_t=qt)
+    steps = 6
+    s.step(steps)
+    Tg = s.temperature().double().cpu().numpy()
+    s.close()
+    rho0 = 1.0 + (drho if mask is None else drho[mask == 0]).astype(np.float32).mean()
+    p = oracle.Problem(q, nx, ny, nz, omega=1.6, mask=mask, wall_u=table, rho0=rho0)
+    r, ru, rT, rT_full = 1.0 + drho, u, T, T
+    for _ in range(steps):
+        rT = oracle.thermal_step(p, rT, ru, 1.3, wall_T=WALL_T, qt=qt)
+        rT_full = oracle.thermal_step(p, rT_full, ru, 1.3, wall_T=WALL_T)
+        r, ru = oracle.step(p, r, ru)
+    fl = fluid_of(mask, shape)
+    err_T = rel_l2(Tg[fl], rT[fl])
+    err_max = float(np.abs(Tg[fl] - rT[fl]).max())
+    diff_full = rel_l2(rT_full[fl], rT[fl])
+    banner(f"thermal axis lattice: rel-L2 T {err_T:.3e}, max |dT| {err_max:.3e} "
+           f"(the flow's lattice differs by {diff_full:.3e})")
+    assert err_T < 1e-6 and err_max < 1e-5
+    assert diff_full > 100 * err_T  # the test tells the two lattices apart
+    if mask is not None:
+        assert np.array_equal(Tg[~fl], T[~fl])
+
+
+def test_thermal_lattice_scope():
+    L = need_gpu()
+    for q, bad in ((9, (7, 19, 3, 6)), (19, (5, 9, 3, 8))):
+        shape = (1, 16, 32) if q == 9 else (8, 16, 32)
+        s = L.Solver(q, shape[2], shape[1], shape[0], 1.6)
+        for qt in bad:
+            with pytest.raises(L.LWACMError):
+                L.lwacm_set_thermal_lattice(s.ctx, qt)
+        for qt in (0, q, 5 if q == 9 else 7):
+            L.lwacm_set_thermal_lattice(s.ctx, qt)
+        s.close()
+
+
+def test_switching_the_temperature_lattice_back():
+    """D3Q7 for three steps, then the flow's D3Q19 (fused into the flow's
+    tile kernel) for three: the oracle run the same way."""
+    L = need_gpu()
+    shape = (16, 32, 64)
+    nz, ny, nx = shape
+    drho, u = wl.random_state(shape, 3, seed=75, du=0.03, drho=0.01)
+    drho = drho.astype(np.float32).astype(np.float64)
+    u = u.astype(np.float32).astype(np.float64)
+    T = np.random.Generator(np.random.PCG64(76)).uniform(0.2, 1.0, shape)
+    T = T.astype(np.float32).astype(np.float64)
+    s = L.Solver(19, nx, ny, nz, 1.6)
+    s.set_state(to_dev(drho), to_dev(u))
+    s.set_thermal(1.3, to_dev(T), q_t=7)
+    s.step(3)
+    L.lwacm_set_thermal_lattice(s.ctx, 0)
+    s.step(3)
+    Tg = s.temperature().double().cpu().numpy()
+    s.close()
+    p = oracle.Problem(19, nx, ny, nz, omega=1.6)
+    r, ru, rT = 1.0 + drho, u, T
+    for k in range(6):
+        rT = oracle.thermal_step(p, rT, ru, 1.3, qt=7 if k < 3 else None)
+        r, ru = oracle.step(p, r, ru)
+    err = rel_l2(Tg, rT)
+    banner(f"thermal lattice switched back: rel-L2 T {err:.3e}")
+    assert err < 1e-6
