@@ -156,9 +156,9 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_march(ProblemArgs p, const T *
                 reinterpret_cast<float4 *>(mu_out)[idx] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
         } else if (role == INTERIOR && k >= 2 && tz < z1) {
-            const float(*Wm)[NSLOT] = win[(k - 2) % NWIN];  // plane tz - 1
-            const float(*W0)[NSLOT] = win[(k - 1) % NWIN];  // plane tz
-            const float(*Wp)[NSLOT] = win[k % NWIN];        // plane tz + 1
+            const float(*Wm)[NSLOT] = win[(k + NWIN - 2) % NWIN];  // plane tz - 1
+            const float(*W0)[NSLOT] = win[(k + NWIN - 1) % NWIN];  // plane tz
+            const float(*Wp)[NSLOT] = win[k % NWIN];                // plane tz + 1
             const long long idx = (long long)tz * plane + col;
             unsigned bits = 0u;
             if (MASK) bits = bb_bits[idx];
