@@ -17,6 +17,7 @@ strings the per-step calls together:
                     steps and recomputation in between;
 * ``thermal_step`` -- one step of the temperature lattice (Eq. ACM2.0t)
                     advected by a given flow velocity;
+* ``thermal_vjp`` -- reverse mode of one temperature step;
 * ``step_q``     -- one step with link-wall distances (interpolated
                     bounce-back) and, optionally, wall velocities per link.
 
@@ -71,6 +72,9 @@ def _load():
     lib.oracle_thermal_step.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double, _u8p, _dp,
                                                             ctypes.c_int, _dp, _dp, _dp]
     lib.oracle_thermal_step.restype = ctypes.c_int
+    lib.oracle_thermal_vjp.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double, _u8p, _dp,
+                                                            ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
+    lib.oracle_thermal_vjp.restype = ctypes.c_int
     lib.oracle_thermal_equilibrium.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
     lib.oracle_thermal_equilibrium.restype = ctypes.c_int
     lib.oracle_wall_force.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double, _u8p, _dp, _dp, _dp,
@@ -276,6 +280,29 @@ def thermal_step(p: Problem, T, u, omega_t: float, wall_T=None, qt=None):
     if rc != 0:
         raise RuntimeError(f"oracle_thermal_step failed ({rc})")
     return out
+
+
+def thermal_vjp(p: Problem, T, u, lam, omega_t: float, wall_T=None, qt=None):
+    """Reverse mode of one temperature step (thermal_step's arguments) for the
+    cotangent lam = dL/dT(t+1): returns (dL/dT(t), dL/du(t)) through that
+    step, u's cotangent of shape (D, nz, ny, nx)."""
+    lib = _load()
+    T = _f64(T, p.shape)
+    u = _f64(u, (p.d,) + p.shape)
+    lam = _f64(lam, p.shape)
+    mask = None if p.mask is None else np.ascontiguousarray(p.mask, dtype=np.uint8)
+    wt = None if wall_T is None else np.ascontiguousarray(wall_T, dtype=np.float64).reshape(-1)
+    q = p.q if qt is None else int(qt)
+    if q not in (p.q, 5 if p.q == 9 else 7):
+        raise ValueError(f"temperature lattice Q={q} under a Q={p.q} flow")
+    lt = np.empty_like(T)
+    lu = np.empty_like(u)
+    rc = lib.oracle_thermal_vjp(q, p.nx, p.ny, p.nz, float(omega_t), _ptr(mask, _u8p), _ptr(wt),
+                                0 if wt is None else len(wt), _ptr(T), _ptr(u), _ptr(lam),
+                                _ptr(lt), _ptr(lu))
+    if rc != 0:
+        raise RuntimeError(f"oracle_thermal_vjp failed ({rc})")
+    return lt, lu
 
 
 def wall_force(p: Problem, rho, u, wall_id: int, center=(0.0, 0.0, 0.0), qd=None):

@@ -985,6 +985,88 @@ int oracle_thermal_step(int q, int nx, int ny, int nz, double omega_t, const uin
     return 0;
 }
 
+/* Derivatives of g^(e)_i and g^(e,e)_i with respect to T and to u
+ * (componentwise), term by term from geq and gee. */
+static void dgeq(const lattice_t *L, int i, double T, const double u[3], double *dT,
+                 double du[3], double *deT, double deu[3])
+{
+    double c = vdot(L, i, u);
+    *dT = L->w[i] * (1.0 + 3.0 * c);
+    *deT = L->w[i];
+    for (int k = 0; k < 3; ++k) {
+        /* d/du_k of 4.5 c^2 - 1.5 |u|^2 (zero on the linear lattices) */
+        double dq = L->lin ? 0.0 : 9.0 * c * L->v[i][k] - 3.0 * u[k];
+        du[k] = L->w[i] * (3.0 * T * L->v[i][k] + dq);
+        /* gee = (geq(u) + geq(-u)) / 2 keeps the even terms: T and the quadratic */
+        deu[k] = L->w[i] * dq;
+    }
+}
+
+/*
+ * Reverse mode of one temperature step (not in the paper: the exact
+ * derivative of oracle_thermal_step with respect to its inputs T and u, by
+ * the chain rule through the same terms).  lam holds dL/dT(., t+1); the
+ * outputs are lamT = dL/dT(., t) and lamU = dL/du(., t) (D fields, SoA)
+ * through this step alone.  A solid node's T is copied through, so its
+ * lamT is its lam; its u is never read (lamU = 0).
+ */
+int oracle_thermal_vjp(int q, int nx, int ny, int nz, double omega_t, const uint8_t *mask,
+                       const double *wall_T, int n_ids, const double *T_in, const double *u,
+                       const double *lam, double *lamT, double *lamU)
+{
+    lattice_t L;
+    if (make_thermal_lattice(q, &L)) return -1;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (L.d == 2 && nz != 1)) return -1;
+    if (!(omega_t > 0.0 && omega_t < 2.0)) return -1;
+    long n = (long)nx * ny * nz;
+    double k = 2.0 * (omega_t - 1.0) / omega_t;
+    for (long ix = 0; ix < n; ++ix) lamT[ix] = 0.0;
+    for (long j = 0; j < (long)L.d * n; ++j) lamU[j] = 0.0;
+
+    /* Serial scatter: every output T(x, t+1) adds its cotangent times the
+     * derivative of each of its link terms to the inputs that term reads. */
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long ix = node_index(nx, ny, x, y, z);
+                if (mask && mask[ix] != 0) {
+                    lamT[ix] += lam[ix];
+                    continue;
+                }
+                double ux[3];
+                load_u(&L, n, ix, u, ux);
+                double Tx = T_in[ix];
+                double lx = lam[ix];
+                for (int i = 0; i < L.q; ++i) {
+                    long iy = upstream(&L, nx, ny, nz, x, y, z, i);
+                    double dT, du[3], deT, deu[3];
+                    /* the own even part k g^(e,e)_i(x), in both branches */
+                    dgeq(&L, i, Tx, ux, &dT, du, &deT, deu);
+                    lamT[ix] += lx * k * deT;
+                    for (int c = 0; c < L.d; ++c) lamU[c * n + ix] += lx * k * deu[c];
+                    if (!mask || mask[iy] == 0) {
+                        /* g^(e)_i(y) - k g^(e,e)_i(y) */
+                        double uy[3];
+                        load_u(&L, n, iy, u, uy);
+                        dgeq(&L, i, T_in[iy], uy, &dT, du, &deT, deu);
+                        lamT[iy] += lx * (dT - k * deT);
+                        for (int c = 0; c < L.d; ++c) lamU[c * n + iy] += lx * (du[c] - k * deu[c]);
+                    } else {
+                        /* +- (g^(e)_ib(x) - k g^(e,e)_ib(x)): the term sent into the wall */
+                        int ib = L.opp[i];
+                        double Tw = NAN;
+                        if (wall_T && mask[iy] < n_ids) Tw = wall_T[mask[iy]];
+                        double sgn = isnan(Tw) ? 1.0 : -1.0;
+                        dgeq(&L, ib, Tx, ux, &dT, du, &deT, deu);
+                        lamT[ix] += lx * sgn * (dT - k * deT);
+                        for (int c = 0; c < L.d; ++c)
+                            lamU[c * n + ix] += lx * sgn * (du[c] - k * deu[c]);
+                    }
+                }
+            }
+    return 0;
+}
+
 /*
  * Force and torque on the walls with mask id wall_id by momentum exchange
  * (Section "Moving complex boundaries", Eqs. MEA3, MEA4 and MEA5), from the

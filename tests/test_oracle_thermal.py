@@ -25,6 +25,9 @@ energy equation", Eqs. ACM2.0t, feqe, AAT2 and diffusivity2).
   cannot carry it; it is O(eps^2) under the diffusive scaling).  The same
   Fourier amplification factor with these weights, the paper's alpha, the
   conservation and the linear-profile pins hold on them.
+- The reverse mode of the temperature step (not in the paper: its exact
+  derivative) against central differences of the step, on every input
+  component of small grids, with and without walls, on all four lattices.
 """
 import numpy as np
 import pytest
@@ -341,3 +344,51 @@ def test_temperature_lattice_must_fit_the_flow():
     for qt in (7, 19, 6):
         with pytest.raises(ValueError):
             oracle.thermal_step(p, T, u, 1.3, qt=qt)
+
+
+# ---- reverse mode of the temperature step (not in the paper: the exact
+# derivative of thermal_step), pinned by central differences of the step
+# itself.  The step is linear in T and a polynomial of degree two in u for
+# fixed T, so central differences are exact up to rounding.
+
+@pytest.mark.parametrize("q,qt,shape", [(9, None, (1, 5, 6)), (9, 5, (1, 5, 6)),
+                                        (19, None, (3, 4, 5)), (19, 7, (3, 4, 5))])
+@pytest.mark.parametrize("walls", [False, True])
+def test_thermal_vjp_matches_central_differences(q, qt, shape, walls):
+    d = 2 if q == 9 else 3
+    nz, ny, nx = shape
+    rng = _rng(11)
+    T = rng.uniform(0.3, 1.0, shape)
+    u = 0.08 * rng.standard_normal((d,) + shape)
+    lam = rng.standard_normal(shape)
+    mask = None
+    if walls:
+        mask = (rng.random(shape) < 0.2).astype(np.uint8)
+        mask[mask == 1] = rng.integers(1, 4, int(mask.sum())).astype(np.uint8)
+    wall_T = [np.nan, 0.25, np.nan, 0.8]
+    p = Problem(q, nx, ny, nz, mask=mask)
+    omega_t = 1.35
+
+    def loss(Tv, uv):
+        return float(np.sum(lam * oracle.thermal_step(p, Tv, uv, omega_t, wall_T=wall_T, qt=qt)))
+
+    lt, lu = oracle.thermal_vjp(p, T, u, lam, omega_t, wall_T=wall_T, qt=qt)
+    eps = 1e-3
+    fd_T = np.zeros(shape)
+    fd_u = np.zeros((d,) + shape)
+    for j in np.ndindex(shape):
+        Tp, Tm = T.copy(), T.copy()
+        Tp[j] += eps
+        Tm[j] -= eps
+        fd_T[j] = (loss(Tp, u) - loss(Tm, u)) / (2 * eps)
+        for c in range(d):
+            up, um = u.copy(), u.copy()
+            up[(c,) + j] += eps
+            um[(c,) + j] -= eps
+            fd_u[(c,) + j] = (loss(T, up) - loss(T, um)) / (2 * eps)
+    scale = np.abs(lam).max()
+    assert np.abs(lt - fd_T).max() < 1e-11 * scale
+    assert np.abs(lu - fd_u).max() < 1e-11 * scale
+    if mask is not None:
+        assert np.array_equal(lt[mask != 0], lam[mask != 0])
+        assert not lu[:, mask != 0].any()
