@@ -299,6 +299,30 @@ int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
  * next step and stays until changed.  LWACM_EINVAL for any other q_t. */
 int lwacm_set_thermal_lattice(lwacm_ctx *c, int q_t);
 
+/* Reverse mode of one temperature step (not in the paper: the exact
+ * derivative of the step of lwacm_set_thermal, on the lattice and walls set
+ * there).  Step t advances T_t to T_{t+1} with the flow velocity u_t of
+ * state_t, the input of the flow step of the same time.  Given
+ * lamT_{t+1} = dL/dT_{t+1}, this call writes lamT_t = dL/dT_t through the
+ * step to d_lamT_out and adds g = dL/du_t through the step to the flow's
+ * reverse sweep in d_mu, in the form lwacm_adjoint_step writes there:
+ *   final_t0 == 0: d_mu holds mu_{t-1} (node-interleaved); since mu_{t-1} is
+ *                  linear in lambda_u, mu_R -= g . u_t / rho_t, mu_J += g / rho_t;
+ *   final_t0 != 0: d_mu holds the gradient with respect to the initial
+ *                  (rho - 1, u), field-major; its u fields gain g.
+ * Call it after lwacm_adjoint_step for the same t (or with d_mu = the seed's
+ * output for the last step, final_t0 as that step's).  Solid nodes pass
+ * lamT through and add nothing.
+ *   d_state_t  state_t (FP32 storage format; FP16 returns LWACM_EUNSUPPORTED)
+ *   d_T_t      T_t, nx*ny*nz FP32 values
+ *   d_lamT_in, d_lamT_out  nx*ny*nz FP32 values each, distinct buffers
+ * LWACM_EINVAL for null pointers, aliased lam buffers, or when the
+ * temperature is off (lwacm_set_thermal gives omega_t and the walls'
+ * temperatures).  Asynchronous on the context's stream. */
+int lwacm_adjoint_thermal_step(lwacm_ctx *c, const void *d_state_t, const float *d_T_t,
+                               const float *d_lamT_in, float *d_lamT_out, float *d_mu,
+                               int final_t0);
+
 /* Force and torque that the fluid exerts on the walls with mask id wall_id,
  * by momentum exchange (Section "Moving complex boundaries", Eqs. MEA3, MEA4
  * and MEA5), from the current state.  Every link j from a fluid node x to a

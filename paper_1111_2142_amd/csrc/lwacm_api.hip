@@ -631,6 +631,25 @@ int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
     return omega_t < 1.0 ? LWACM_WOMEGA : LWACM_OK;
 }
 
+int lwacm_adjoint_thermal_step(lwacm_ctx *c, const void *d_state_t, const float *d_T_t,
+                               const float *d_lamT_in, float *d_lamT_out, float *d_mu,
+                               int final_t0)
+{
+    if (!c || !d_state_t || !d_T_t || !d_lamT_in || !d_lamT_out || !d_mu) return LWACM_EINVAL;
+    if (d_lamT_in == d_lamT_out || !c->thermal) return LWACM_EINVAL;
+    if (c->storage != LWACM_FP32) return LWACM_EUNSUPPORTED;
+    lwacm::ThermalAdjArgs a;
+    a.t = c->targs;
+    a.t.state = static_cast<const float *>(d_state_t);
+    a.t.T_in = d_T_t;
+    a.t.T_out = nullptr;
+    a.lam_in = d_lamT_in;
+    a.lam_out = d_lamT_out;
+    a.mu = d_mu;
+    a.final_t0 = final_t0 != 0;
+    return lwacm::launch_thermal_adjoint(a, c->stream) == hipSuccess ? LWACM_OK : LWACM_EDEVICE;
+}
+
 int lwacm_set_thermal_lattice(lwacm_ctx *c, int q_t)
 {
     if (!c) return LWACM_EINVAL;

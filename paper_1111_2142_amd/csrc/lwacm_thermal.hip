@@ -134,6 +134,95 @@ __global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_step(Thermal
     t.T_out[idx] = fmaf(t.kap, Tx, div36(acc));
 }
 
+// ---- reverse mode of one step (gather over the nodes a node's T and u reach)
+//
+// T(x, t+1) is linear in the T of its upstream nodes and quadratic in their u;
+// node z's cotangents collect, for every link i:
+//   x = z + v_i fluid: lam(x) d/d(T_z, u_z) of w_i [h (T_z + q) + 3 T_z c],
+//     c = v_i . u_z: (w_i (h + 3 c), w_i (3 T_z v_i + h dq)), dq = 9 c v_i - 3 u_z;
+//   z - v_i solid: lam(z) d/d(T_z, u_z) of the term z sent along -v_i into the
+//     wall, returned with sign s (+1 adiabatic, -1 fixed temperature):
+//     s (w_i (h - 3 c), w_i (-3 T_z v_i + h dq));
+// plus kap lam(z) from the own even parts (their u terms sum to zero on every
+// lattice here).  On the D2Q5/D3Q7 lattices q = 0 and dq = 0.  A solid node
+// passes lam through and gives no u cotangent.
+template <int Q, bool MASK, bool AXIS>
+__global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_adjoint(ThermalAdjArgs a)
+{
+    const ThermalArgs &t = a.t;
+    const int x = blockIdx.x * kThermalBX + threadIdx.x;
+    const int y = blockIdx.y * kThermalBY + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= t.nx || y >= t.ny) return;
+    const long long plane = (long long)t.nx * t.ny;
+    const long long n = plane * t.nz;
+    const long long idx = (long long)z * plane + (long long)y * t.nx + x;
+    const float lz = a.lam_in[idx];
+    if (MASK && t.mask[idx] != 0) {
+        a.lam_out[idx] = lz;
+        return;
+    }
+    constexpr int D = Lattice<Q>::D;
+    float u[3];
+    load_u<Q>(t.state, idx, u);
+    const float Tz = t.T_in[idx];
+    float lt = t.kap * lz;
+    float gu[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {  // the rest link too: its term is w_0 h (T_z + q)
+        if (AXIS && (!axis_link(i) || axis_w36<Q>(i) == 0.0f)) continue;
+        const int cx = link_cx(i), cy = link_cy(i), cz = link_cz(i);
+        const float w = (AXIS ? axis_w36<Q>(i) : Lattice<Q>::w36(i)) * (1.0f / 36.0f);
+        const float c = cx * u[0] + cy * u[1] + cz * u[2];
+        const float v[3] = {(float)cx, (float)cy, (float)cz};
+        float dq[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dq[k] = AXIS ? 0.0f : fmaf(9.0f * c, v[k], -3.0f * u[k]);
+        // downstream node x = z + v_i
+        const int xd = wrap_step(x, -cx, t.nx);
+        const int yd = wrap_step(y, -cy, t.ny);
+        const int zd = wrap_step(z, -cz, t.nz);
+        const long long id = (long long)zd * plane + (long long)yd * t.nx + xd;
+        if (!MASK || t.mask[id] == 0) {
+            const float lx = a.lam_in[id] * w;
+            lt = fmaf(lx, fmaf(3.0f, c, t.h), lt);
+#pragma unroll
+            for (int k = 0; k < D; ++k) gu[k] = fmaf(lx, fmaf(3.0f * Tz, v[k], t.h * dq[k]), gu[k]);
+        }
+        if (MASK && i != 0) {
+            // upstream node z - v_i solid: the wall returned z's own term
+            const int xs = wrap_step(x, cx, t.nx);
+            const int ys = wrap_step(y, cy, t.ny);
+            const int zs = wrap_step(z, cz, t.nz);
+            const uint8_t m = t.mask[(long long)zs * plane + (long long)ys * t.nx + xs];
+            if (m != 0) {
+                const float Tw = m < kMaxThermalWallIds ? t.wall_T[m] : __builtin_nanf("");
+                const float ls = ((Tw != Tw) ? lz : -lz) * w;
+                lt = fmaf(ls, fmaf(-3.0f, c, t.h), lt);
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    gu[k] = fmaf(ls, fmaf(-3.0f * Tz, v[k], t.h * dq[k]), gu[k]);
+            }
+        }
+    }
+    a.lam_out[idx] = lt;
+    if (a.final_t0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) a.mu[(1 + k) * n + idx] += gu[k];
+    } else {
+        // mu_{t-1} = (lambda_rho - lambda_u . u / rho, lambda_u / rho) is linear
+        // in lambda_u: the u cotangent enters both parts
+        const float rho = 1.0f + (Q == 19 ? t.state[4 * idx] : t.state[3 * idx]);
+        const float inv = 1.0f / rho;
+        float gdu = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) gdu = fmaf(gu[k], u[k], gdu);
+        a.mu[(D + 1) * idx] -= gdu * inv;
+#pragma unroll
+        for (int k = 0; k < D; ++k) a.mu[(D + 1) * idx + 1 + k] += gu[k] * inv;
+    }
+}
+
 // ---- tile kernel (D3Q19): LDS ring of three planes, one column per thread
 constexpr int kTX = 32, kTY = 16;            // tile of columns per workgroup
 constexpr int kHX = kTX + 2, kHY = kTY + 2;  // with the one-node halo
@@ -317,7 +406,38 @@ hipError_t launch_q(const ThermalArgs &t, hipStream_t stream)
     return hipGetLastError();
 }
 
+template <int Q>
+hipError_t launch_adj_q(const ThermalAdjArgs &a, hipStream_t stream)
+{
+    const ThermalArgs &t = a.t;
+    const dim3 block(kThermalBX, kThermalBY, 1);
+    const dim3 grid((t.nx + kThermalBX - 1) / kThermalBX, (t.ny + kThermalBY - 1) / kThermalBY,
+                    t.nz);
+    const bool axis = t.QT != Q;
+    if (t.mask && axis)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, true, true>), grid, block, 0, stream, a);
+    else if (t.mask)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, true, false>), grid, block, 0, stream, a);
+    else if (axis)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, false, true>), grid, block, 0, stream, a);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, false, false>), grid, block, 0, stream, a);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_thermal_adjoint(const ThermalAdjArgs &a, hipStream_t stream)
+{
+    const ThermalArgs &t = a.t;
+    if (t.nx <= 0 || t.ny <= 0 || t.nz <= 0 || t.nz > 65535 ||
+        (t.ny + kThermalBY - 1) / kThermalBY > 65535)
+        return hipErrorInvalidValue;
+    if (t.QT != t.Q && t.QT != (t.Q == 9 ? 5 : 7)) return hipErrorInvalidValue;
+    if (t.Q == 9) return t.nz == 1 ? launch_adj_q<9>(a, stream) : hipErrorInvalidValue;
+    if (t.Q == 19) return launch_adj_q<19>(a, stream);
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_thermal_step(const ThermalArgs &t, hipStream_t stream)
 {

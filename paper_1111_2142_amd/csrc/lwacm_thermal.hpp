@@ -25,4 +25,15 @@ struct ThermalArgs {
 
 hipError_t launch_thermal_step(const ThermalArgs &t, hipStream_t stream);
 
+// Reverse mode of one temperature step (lwacm_adjoint_thermal_step).
+struct ThermalAdjArgs {
+    ThermalArgs t;         // the step's arguments; t.state and t.T_in are its inputs
+    const float *lam_in;   // dL/dT(t + 1)
+    float *lam_out;        // dL/dT(t) through this step
+    float *mu;             // the flow cotangent dL/du(t) is added to (see the header)
+    int final_t0;          // mu field-major (the gradient of the initial state)
+};
+
+hipError_t launch_thermal_adjoint(const ThermalAdjArgs &a, hipStream_t stream);
+
 }  // namespace lwacm

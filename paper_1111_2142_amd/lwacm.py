@@ -69,6 +69,7 @@ def load_library():
         "lwacm_set_force_field": (i, [_vp, _vp]),
         "lwacm_set_thermal": (i, [_vp, d, _vp, _vp, _vp, i]),
         "lwacm_set_thermal_lattice": (i, [_vp, i]),
+        "lwacm_adjoint_thermal_step": (i, [_vp, _vp, _vp, _vp, _vp, _vp, i]),
         "lwacm_set_wall_velocity_links": (i, [_vp, _vp]),
         "lwacm_set_semi_implicit": (i, [_vp, i]),
         "lwacm_temperature": (i, [_vp, ctypes.POINTER(_vp)]),
@@ -205,6 +206,17 @@ def lwacm_set_thermal_lattice(ctx, q_t: int):
     """Temperature lattice: 0 or the flow's Q, 5 (D2Q5) under D2Q9, 7 (D3Q7)
     under D3Q19."""
     _check(load_library().lwacm_set_thermal_lattice(ctx, int(q_t)), "lwacm_set_thermal_lattice")
+
+
+def lwacm_adjoint_thermal_step(ctx, state_t: torch.Tensor, T_t: torch.Tensor,
+                               lamT_in: torch.Tensor, lamT_out: torch.Tensor, mu: torch.Tensor,
+                               final_t0: bool):
+    """Reverse mode of one temperature step: lamT_out = dL/dT_t; dL/du_t
+    added to mu (the flow sweep's mu_{t-1}, or the field-major initial-state
+    gradient when final_t0)."""
+    _check(load_library().lwacm_adjoint_thermal_step(ctx, _ptr(state_t), _ptr(T_t), _ptr(lamT_in),
+                                                     _ptr(lamT_out), _ptr(mu), int(bool(final_t0))),
+           "lwacm_adjoint_thermal_step")
 
 
 def lwacm_temperature(ctx) -> int:
