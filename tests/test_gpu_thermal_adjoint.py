@@ -9,6 +9,9 @@
   lwacm_adjoint_step): the gradient of L = sum a T_N + sum b . u_N with
   respect to the initial T, rho - 1 and u against the oracle's chain of
   vjp and thermal_vjp over the oracle's own forward run.
+- lwacm_run_thermal (torch.autograd over flow and temperature, checkpoints
+  and ragged segments): gradients of T0, rho0 - 1, u0 and omega against the
+  oracle's chain.
 - Argument checks.
 """
 import numpy as np
@@ -168,3 +171,60 @@ def test_reverse_temperature_step_rejects_bad_arguments():
     with pytest.raises(L.LWACMError):  # lam buffers alias
         L.lwacm_adjoint_thermal_step(s.ctx, st, s.temperature(), lam, lam, mu, True)
     s.close()
+
+
+@pytest.mark.parametrize("q,qt,masked,shape", [(9, None, True, (1, 24, 40)),
+                                                (19, 7, False, (8, 16, 32))])
+def test_differentiable_thermal_run_matches_oracle(q, qt, masked, shape):
+    """lwacm_run_thermal through torch.autograd: 9 steps with checkpoints every
+    4 (segments of 4, 4 and 1), L = sum a T_N + sum b . u_N + sum c (rho_N - 1);
+    gradients with respect to T0, rho0 - 1, u0 and omega against the oracle's
+    chain of vjp and thermal_vjp."""
+    L = need_gpu()
+    from paper_1111_2142_amd.autograd import lwacm_run_thermal
+    banner(f"thermal autograd q={q} qt={qt} masked={masked} shape={shape}")
+    N, K = 9, 4
+    nz, ny, nx = shape
+    d = 2 if q == 9 else 3
+    drho, u = wl.random_state(shape, d, seed=111, du=0.03, drho=0.01)
+    drho = drho.astype(np.float32).astype(np.float64)
+    u = u.astype(np.float32).astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(112))
+    T = rng.uniform(0.2, 1.0, shape).astype(np.float32).astype(np.float64)
+    mask = _walls(shape, 113) if masked else None
+    if mask is not None:
+        u[:, mask != 0] = 0.0
+    a = rng.standard_normal(shape)
+    b = rng.standard_normal((d,) + shape)
+    c = rng.standard_normal(shape)
+    table = [[0.0, 0.0, 0.0]] * 4
+    x_r = to_dev(drho).requires_grad_(True)
+    x_u = to_dev(u).requires_grad_(True)
+    x_T = to_dev(T).requires_grad_(True)
+    om = torch.tensor(OMEGA, dtype=torch.float64, requires_grad=True)
+    r_N, u_N, T_N = lwacm_run_thermal(x_r, x_u, x_T, om, OMEGA_T, N, q, K=K,
+                                      mask=None if mask is None else to_dev(mask, torch.uint8),
+                                      wall_u=table, wall_T=WALL_T, q_t=qt or 0)
+    loss = (to_dev(a) * T_N).sum() + (to_dev(b) * u_N).sum() + (to_dev(c) * r_N).sum()
+    loss.backward()
+    p = oracle.Problem(q, nx, ny, nz, omega=OMEGA, mask=mask, wall_u=np.zeros((4, 3)))
+    rhos, us, Ts = [1.0 + drho], [u], [T]
+    for _ in range(N):
+        Ts.append(oracle.thermal_step(p, Ts[-1], us[-1], OMEGA_T, wall_T=WALL_T, qt=qt))
+        r1, u1 = oracle.step(p, rhos[-1], us[-1])
+        rhos.append(r1)
+        us.append(u1)
+    lr, lu, lt, dw = c.copy(), b.copy(), a.copy(), 0.0
+    for t in range(N - 1, -1, -1):
+        lr, lu_f, dwt = oracle.vjp(p, rhos[t], us[t], lr, lu)
+        lt, gu = oracle.thermal_vjp(p, Ts[t], us[t], lt, OMEGA_T, wall_T=WALL_T, qt=qt)
+        lu = lu_f + gu
+        dw += dwt
+    fl = fluid_of(mask, shape)
+    e_T = rel_l2(x_T.grad.double().cpu().numpy(), lt)
+    e_r = rel_l2(x_r.grad.double().cpu().numpy()[fl], lr[fl])
+    e_u = rel_l2(x_u.grad.double().cpu().numpy()[:, fl], lu[:, fl])
+    e_w = abs(om.grad.item() - dw) / abs(dw)
+    banner(f"thermal autograd: rel-L2 dL/dT0 {e_T:.3e}, dL/drho0 {e_r:.3e}, dL/du0 {e_u:.3e}, "
+           f"dL/domega {e_w:.3e}")
+    assert e_T < 1e-5 and e_r < 1e-5 and e_u < 1e-5 and e_w < 1e-5
