@@ -602,8 +602,8 @@ def main():
                          "achieved_GBs": round(32.0 * nodes / (msa * 1e-3) / 1e9, 1),
                          "basis": "reverse steps two per launch (lwacm_adjoint_step2): state_t, "
                                   "state_t-1, mu in, mu out = 32 B per node and step",
-                         "kernel": "k_adj_march2<float,false,64>" if n == 256 else None,
-                         "traffic": _measured_traffic("k_adj_march2<float,false,64>")
+                         "kernel": "k_adj_march2<float,false,128>" if n == 256 else None,
+                         "traffic": _measured_traffic("k_adj_march2<float,false,128>")
                          if n == 256 else None,
                          "one_step_kernel": {
                              "ms_per_step": round(msa1, 5),

@@ -433,7 +433,9 @@ int lwacm_adjoint_step(lwacm_ctx *c, const void *d_state_t, const float *d_mu_in
  * grids without walls, nz >= 8; variant AUTO or MARCH2): the same result as
  *     lwacm_adjoint_step(c, d_state_t,   d_mu_in, tmp,      w, 0);
  *     lwacm_adjoint_step(c, d_state_tm1, tmp,     d_mu_out, w, final_t0);
- * (bitwise in d_mu_out; *d_dL_domega receives the same two additions) with
+ * (bitwise in d_mu_out; *d_dL_domega receives the same two additions where
+ * both kernels split the planes among workgroups alike, nz <= 64, else the
+ * same sums grouped by 128-plane chunks: equal to FP64 rounding) with
  * the intermediate mu kept on chip: 32 instead of 48 bytes of HBM per node
  * and step.  d_state_t and d_state_tm1 are the inputs of forward steps t and
  * t - 1 (storage format); d_mu_in = mu_t, node-interleaved.  final_t0: the

@@ -34,9 +34,13 @@ constexpr int HALO0 = NINT + 2 * kWave;              // first thread of the oute
 constexpr int NTHREADS = NINT + 4 * kWave;
 constexpr int SX1 = TX + 4, NS1 = SX1 * (TY + 4);    // mu_t window slots
 constexpr int SX2 = TX + 2, NS2 = SX2 * (TY + 2);    // mu_{t-1} window slots
-constexpr int kAdjChunk = 64;                        // the one-step reverse kernel's depth
-
-// Chunk depth: 64 planes, halved while deeper than nz.
+// Chunk depth: 128 planes, halved while deeper than nz.  At 256^3 that is one
+// workgroup per compute unit in a single round (the kernel's 136 VGPRs allow
+// one 768-thread workgroup per CU); 64-plane chunks, the one-step reverse
+// kernel's depth, take two rounds and measured 2.5 % slower.  Where the depths
+// differ, the dL/da block partials group the planes differently from the
+// one-step kernel's (equal to FP64 rounding of the per-thread partials).
+constexpr int kAdjChunk = 128;
 int adj2_nzc(const ProblemArgs &p)
 {
     int c = kAdjChunk;
@@ -225,7 +229,8 @@ void launch_t(const ProblemArgs &p, const void *sa, const void *sb, const float 
     case 8: k_adj_march2<T, FINAL, 8><<<nb, NTHREADS, 0, s>>>(p, a, b, mu_in, mu_out, r); break;
     case 16: k_adj_march2<T, FINAL, 16><<<nb, NTHREADS, 0, s>>>(p, a, b, mu_in, mu_out, r); break;
     case 32: k_adj_march2<T, FINAL, 32><<<nb, NTHREADS, 0, s>>>(p, a, b, mu_in, mu_out, r); break;
-    default: k_adj_march2<T, FINAL, 64><<<nb, NTHREADS, 0, s>>>(p, a, b, mu_in, mu_out, r); break;
+    case 64: k_adj_march2<T, FINAL, 64><<<nb, NTHREADS, 0, s>>>(p, a, b, mu_in, mu_out, r); break;
+    default: k_adj_march2<T, FINAL, 128><<<nb, NTHREADS, 0, s>>>(p, a, b, mu_in, mu_out, r); break;
     }
 }
 

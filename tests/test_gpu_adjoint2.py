@@ -1,7 +1,7 @@
 """Two reverse steps per launch (lwacm_adjoint_step2): bitwise the mu (or the
 final gradient) of two one-step reverse calls, on grids whose last z chunk
 is ragged, on thin grids (nz = 8, 20: chunk depths 8 and 16), with FP32 and
-FP16 states, for both output forms, and at 256^3; the omega-gradient sum
+FP16 states, for both output forms, and at 256^3 (128-plane chunks); the omega-gradient sum
 bitwise where both kernels split the planes among workgroups alike, else to
 the rounding of the per-thread FP32 partials.  Problems with walls are
 declined, and the checkpointed gradient, which now pairs its reverse steps,
@@ -117,4 +117,6 @@ def test_adjoint_step2_256_cubed_bitwise():
     (ra, wa), (rb, wb) = single(), fused()
     s.close()
     assert bool(torch.isfinite(ra).all())
-    assert torch.equal(ra, rb) and wa == wb
+    assert torch.equal(ra, rb)
+    # 128-plane chunks against the single step's 64: the block sums regroup
+    assert abs(wa - wb) <= 1e-6 * abs(wa)
