@@ -253,7 +253,8 @@ int lwacm_set_wall_velocity_links(lwacm_ctx *c, const float *d_uw);
 
 /* Temperature advected by the flow: the thermal LW-ACM (Appendix
  * "Asymptotic analysis for energy equation", Eq. ACM2.0t with the even part
- * of Eq. feqe) on the flow's lattice.  Its only state is T per node; its
+ * of Eq. feqe) on the flow's lattice (or a smaller one: see
+ * lwacm_set_thermal_lattice).  Its only state is T per node; its
  * equilibrium w_i [T (1 + 3 v_i.u) + 9/2 (v_i.u)^2 - 3/2 |u|^2] has the
  * moments the appendix requires (T, T u, u u + T/3 I), u being the flow
  * velocity at the same node and time; T diffuses with
@@ -280,7 +281,8 @@ int lwacm_set_wall_velocity_links(lwacm_ctx *c, const float *d_uw);
  *             Solid nodes keep their T.
  * LWACM_EINVAL for bad arguments, LWACM_EUNSUPPORTED with FP16 storage or
  * with the two-step kernel requested (the two-step kernel is not used while
- * the temperature is on).  The reverse steps cover the flow only. */
+ * the temperature is on).  The flow's reverse steps cover the flow only;
+ * lwacm_adjoint_thermal_step is the temperature's. */
 int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
                       const float *h_wall_T, int n_wall_T);
 
