@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # VALU issue: 256 CUs x 4 SIMDs, one wave64 FP32 instruction per 4 cycles, 2.4 GHz
 VALU_WAVE_INSTS_PER_S = 1024 * 2.4e9 / 4
 FP32_PEAK_TFLOPS = 157.3           # packed FP32 FMA (published vector peak)
-FP32_UNPACKED_TFLOPS = 78.6        # one FP32 FMA per lane per cycle (this build: no packing)
+FP32_UNPACKED_TFLOPS = 78.6        # one FP32 FMA per lane per cycle (the kernels use no packed FP32)
 # FP32 operations of one lattice update in the tile kernels (Eqs. ACM2.0b as
 # implemented, mass/energy sums included): 47 FMA, 40 add/sub, 22 mul, 1 rcp
 FLOPS_PER_UPDATE = 2 * 47 + 40 + 22 + 1
@@ -504,7 +504,7 @@ def main():
                      "launch_us": burst["launch_us"],
                      "peak_basis": "FP32 FMA on every lane of 256 CUs x 4 SIMDs x 16 lanes at "
                                    "2.4 GHz (78.6 TFLOP/s); the published 157.3 counts packed "
-                                   "FP32, which this build does not emit",
+                                   "FP32, which the kernels do not use",
                      "frac_of_packed_peak": burst["frac_of_packed_peak"],
                      "valu_issue_frac": burst["valu_issue_frac"],
                      "hbm_GBs_measured": burst["hbm_GBs_measured"],

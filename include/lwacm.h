@@ -57,7 +57,7 @@ enum {
     LWACM_ENOMEM = -2,      /* the library could not allocate its scratch */
     LWACM_EDEVICE = -3,     /* a HIP call or kernel launch failed */
     LWACM_ENONFINITE = -4,  /* mass or kinetic energy is not finite (blow-up) */
-    LWACM_EUNSUPPORTED = -5, /* valid request this build does not implement */
+    LWACM_EUNSUPPORTED = -5, /* valid request the library does not implement */
     LWACM_ESCRATCH = -6,     /* lwacm_step_static: problem beyond its fixed scratch */
     /* Success with a warning: a relaxation frequency (omega, omega_p or
      * omega_t) below 1.  The paper finds the method stable for 1 <= omega < 2

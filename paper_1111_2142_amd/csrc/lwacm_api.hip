@@ -358,7 +358,7 @@ const char *lwacm_strerror(int code)
     case LWACM_ENOMEM: return "out of device memory for library scratch";
     case LWACM_EDEVICE: return "HIP runtime or kernel launch error";
     case LWACM_ENONFINITE: return "non-finite mass or kinetic energy (unstable run)";
-    case LWACM_EUNSUPPORTED: return "not supported by this build";
+    case LWACM_EUNSUPPORTED: return "not supported by the library";
     case LWACM_ESCRATCH: return "problem too large for the fixed scratch of lwacm_step_static";
     case LWACM_WOMEGA:
         return "success, with a warning: relaxation frequency below 1 (the method is stable "

@@ -3,12 +3,12 @@ AddressSanitizer and UndefinedBehaviorSanitizer on the CPU.
 
 - The oracle (plain C, gcc) is rebuilt with -fsanitize=address,undefined and
   the oracle test modules run against it in a child process that preloads
-  gcc's sanitizer runtimes (LWACM_ORACLE_LIB selects the build).
+  gcc's sanitizer runtimes (LWACM_ORACLE_LIB selects the library file).
 - The library's host side (lwacm_api.hip: argument checks, omega
   coefficients, error strings, the no-context step's checks) is rebuilt with
   the host-only sanitizer flags of hipcc (the device code is untouched) and
   tests/test_abi.py runs against it with clang's ASan runtime preloaded
-  (LWACM_LIBRARY selects the build).  Device work needs a GPU and is not
+  (LWACM_LIBRARY selects the library file).  Device work needs a GPU and is not
   exercised here.
 - A control plants a heap overflow in a throwaway C library, built and loaded
   the same way, and requires the sanitizer to report it: the harness can see
