@@ -279,9 +279,12 @@ int lwacm_set_wall_velocity_links(lwacm_ctx *c, const float *d_uw);
  *             gives no thermal wall rule; this halfway reading keeps a linear
  *             profile between two such walls exactly steady.  n_wall_T <= 16.
  *             Solid nodes keep their T.
- * LWACM_EINVAL for bad arguments, LWACM_EUNSUPPORTED with FP16 storage or
- * with the two-step kernel requested (the two-step kernel is not used while
- * the temperature is on).  The flow's reverse steps cover the flow only;
+ * T stays FP32 with either flow storage; with FP16 flow storage the
+ * temperature step reads u from the FP16 state (its load scales) on the
+ * one-thread-per-node kernel.
+ * LWACM_EINVAL for bad arguments, LWACM_EUNSUPPORTED with the two-step
+ * kernel requested (the two-step kernel is not used while the temperature
+ * is on).  The flow's reverse steps cover the flow only;
  * lwacm_adjoint_thermal_step is the temperature's. */
 int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
                       const float *h_wall_T, int n_wall_T);
@@ -315,7 +318,7 @@ int lwacm_set_thermal_lattice(lwacm_ctx *c, int q_t);
  * Call it after lwacm_adjoint_step for the same t (or with d_mu = the seed's
  * output for the last step, final_t0 as that step's).  Solid nodes pass
  * lamT through and add nothing.
- *   d_state_t  state_t (FP32 storage format; FP16 returns LWACM_EUNSUPPORTED)
+ *   d_state_t  state_t (storage format, FP32 or FP16)
  *   d_T_t      T_t, nx*ny*nz FP32 values
  *   d_lamT_in, d_lamT_out  nx*ny*nz FP32 values each, distinct buffers
  * LWACM_EINVAL for null pointers, aliased lam buffers, or when the

@@ -612,8 +612,11 @@ int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
         return LWACM_EINVAL;
     if (n_wall_T < 0 || n_wall_T > lwacm::kMaxThermalWallIds || (n_wall_T > 0 && !h_wall_T))
         return LWACM_EINVAL;
-    if (c->storage != LWACM_FP32 || c->variant == LWACM_KERNEL_MARCH2) return LWACM_EUNSUPPORTED;
+    if (c->variant == LWACM_KERNEL_MARCH2) return LWACM_EUNSUPPORTED;
     lwacm::ThermalArgs &t = c->targs;
+    t.st_half = c->storage != LWACM_FP32;  // refreshed with the scales at every launch
+    t.ld_scale[0] = c->p.ld_scale[0];
+    t.ld_scale[1] = c->p.ld_scale[1];
     t.Q = c->p.Q;
     t.QT = c->thermal_qt ? c->thermal_qt : c->p.Q;
     t.nx = c->p.nx;
@@ -637,10 +640,12 @@ int lwacm_adjoint_thermal_step(lwacm_ctx *c, const void *d_state_t, const float 
 {
     if (!c || !d_state_t || !d_T_t || !d_lamT_in || !d_lamT_out || !d_mu) return LWACM_EINVAL;
     if (d_lamT_in == d_lamT_out || !c->thermal) return LWACM_EINVAL;
-    if (c->storage != LWACM_FP32) return LWACM_EUNSUPPORTED;
     lwacm::ThermalAdjArgs a;
     a.t = c->targs;
-    a.t.state = static_cast<const float *>(d_state_t);
+    a.t.state = d_state_t;
+    a.t.st_half = c->storage != LWACM_FP32;
+    a.t.ld_scale[0] = c->p.ld_scale[0];
+    a.t.ld_scale[1] = c->p.ld_scale[1];
     a.t.T_in = d_T_t;
     a.t.T_out = nullptr;
     a.lam_in = d_lamT_in;
@@ -829,7 +834,10 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
             c->tcur ^= 1;
         } else if (c->thermal) {
             lwacm::ThermalArgs t = c->targs;
-            t.state = static_cast<const float *>(src);
+            t.state = src;
+            t.st_half = c->storage != LWACM_FP32;
+            t.ld_scale[0] = c->p.ld_scale[0];
+            t.ld_scale[1] = c->p.ld_scale[1];
             t.T_in = c->T_buf[c->tcur];
             t.T_out = c->T_buf[c->tcur ^ 1];
             if (lwacm::launch_thermal_step(t, c->stream) != hipSuccess) return LWACM_EDEVICE;

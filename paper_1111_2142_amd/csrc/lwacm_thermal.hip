@@ -52,19 +52,18 @@ __device__ __forceinline__ int wrap_step(int a, int d, int n)
     return r;
 }
 
-template <int Q>
-__device__ __forceinline__ void load_u(const float *state, long long idx, float (&u)[3])
+// (rho - 1, u) of node idx from the flow state in storage format S (float or
+// FP16 deviations with the load scales)
+template <class S, int Q>
+__device__ __forceinline__ float load_u(const ThermalArgs &t, long long idx, float (&u)[3])
 {
-    if constexpr (Q == 19) {
-        const float4 s = reinterpret_cast<const float4 *>(state)[idx];
-        u[0] = s.y;
-        u[1] = s.z;
-        u[2] = s.w;
-    } else {
-        u[0] = state[3 * idx + 1];
-        u[1] = state[3 * idx + 2];
-        u[2] = 0.0f;
-    }
+    constexpr int NF = Lattice<Q>::D + 1;
+    float v[NF];
+    NodeState<S, NF>::load(static_cast<const S *>(t.state), idx, t.ld_scale, v);
+    u[0] = v[1];
+    u[1] = v[2];
+    u[2] = NF == 4 ? v[NF - 1] : 0.0f;
+    return v[0];
 }
 
 // links of the axis lattice (rest and axis links) and their 36 w
@@ -79,7 +78,7 @@ __host__ __device__ constexpr float axis_w36(int i)
 }
 
 // AXIS: the temperature on the axis lattice of the flow's lattice Q
-template <int Q, bool MASK, bool AXIS>
+template <int Q, bool MASK, bool AXIS, class S>
 __global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_step(ThermalArgs t)
 {
     const int x = blockIdx.x * kThermalBX + threadIdx.x;
@@ -94,7 +93,7 @@ __global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_step(Thermal
         return;
     }
     float ux[3];
-    load_u<Q>(t.state, idx, ux);
+    load_u<S, Q>(t, idx, ux);
     const float bx = AXIS ? 0.0f : -1.5f * (ux[0] * ux[0] + ux[1] * ux[1] + ux[2] * ux[2]);
     float acc = 0.0f;  // sum of 36 w_i times the incoming terms
 #pragma unroll
@@ -115,7 +114,7 @@ __global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_step(Thermal
         }
         if (fluid) {
             float us[3];
-            load_u<Q>(t.state, is, us);
+            load_u<S, Q>(t, is, us);
             const float Ts = t.T_in[is];
             const float c = cx * us[0] + cy * us[1] + cz * us[2];
             const float q =
@@ -146,7 +145,7 @@ __global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_step(Thermal
 // plus kap lam(z) from the own even parts (their u terms sum to zero on every
 // lattice here).  On the D2Q5/D3Q7 lattices q = 0 and dq = 0.  A solid node
 // passes lam through and gives no u cotangent.
-template <int Q, bool MASK, bool AXIS>
+template <int Q, bool MASK, bool AXIS, class S>
 __global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_adjoint(ThermalAdjArgs a)
 {
     const ThermalArgs &t = a.t;
@@ -164,7 +163,7 @@ __global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_adjoint(Ther
     }
     constexpr int D = Lattice<Q>::D;
     float u[3];
-    load_u<Q>(t.state, idx, u);
+    const float dr = load_u<S, Q>(t, idx, u);
     const float Tz = t.T_in[idx];
     float lt = t.kap * lz;
     float gu[3] = {0.0f, 0.0f, 0.0f};
@@ -212,8 +211,7 @@ __global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_adjoint(Ther
     } else {
         // mu_{t-1} = (lambda_rho - lambda_u . u / rho, lambda_u / rho) is linear
         // in lambda_u: the u cotangent enters both parts
-        const float rho = 1.0f + (Q == 19 ? t.state[4 * idx] : t.state[3 * idx]);
-        const float inv = 1.0f / rho;
+        const float inv = 1.0f / (1.0f + dr);
         float gdu = 0.0f;
 #pragma unroll
         for (int k = 0; k < D; ++k) gdu = fmaf(gu[k], u[k], gdu);
@@ -268,7 +266,7 @@ __device__ __forceinline__ void fetch_plane(const ThermalArgs &t, PlaneRegs<MASK
             gy += (gy < 0) ? t.ny : 0;
             gy -= (gy >= t.ny) ? t.ny : 0;
             const long long g = base + (long long)gy * t.nx + gx;
-            v.s[k] = reinterpret_cast<const float4 *>(t.state)[g];
+            v.s[k] = static_cast<const float4 *>(t.state)[g];
             v.T[k] = t.T_in[g];
             if constexpr (MASK) v.m[k] = t.mask[g];
         }
@@ -373,7 +371,21 @@ __global__ __launch_bounds__(kTX *kTY) void k_thermal_march(ThermalArgs t)
 
 bool march_shape(const ThermalArgs &t)
 {
-    return t.Q == 19 && t.QT == 19 && t.nx % kTX == 0 && t.ny % kTY == 0;
+    return t.Q == 19 && t.QT == 19 && !t.st_half && t.nx % kTX == 0 && t.ny % kTY == 0;
+}
+
+template <int Q, class S>
+void launch_gather(const ThermalArgs &t, dim3 grid, dim3 block, hipStream_t stream)
+{
+    const bool axis = t.QT != Q;
+    if (t.mask && axis)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, true, true, S>), grid, block, 0, stream, t);
+    else if (t.mask)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, true, false, S>), grid, block, 0, stream, t);
+    else if (axis)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, false, true, S>), grid, block, 0, stream, t);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, false, false, S>), grid, block, 0, stream, t);
 }
 
 template <int Q>
@@ -394,15 +406,10 @@ hipError_t launch_q(const ThermalArgs &t, hipStream_t stream)
     const dim3 block(kThermalBX, kThermalBY, 1);
     const dim3 grid((t.nx + kThermalBX - 1) / kThermalBX, (t.ny + kThermalBY - 1) / kThermalBY,
                     t.nz);
-    const bool axis = t.QT != Q;
-    if (t.mask && axis)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, true, true>), grid, block, 0, stream, t);
-    else if (t.mask)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, true, false>), grid, block, 0, stream, t);
-    else if (axis)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, false, true>), grid, block, 0, stream, t);
+    if (t.st_half)
+        launch_gather<Q, __half>(t, grid, block, stream);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_step<Q, false, false>), grid, block, 0, stream, t);
+        launch_gather<Q, float>(t, grid, block, stream);
     return hipGetLastError();
 }
 
@@ -414,14 +421,25 @@ hipError_t launch_adj_q(const ThermalAdjArgs &a, hipStream_t stream)
     const dim3 grid((t.nx + kThermalBX - 1) / kThermalBX, (t.ny + kThermalBY - 1) / kThermalBY,
                     t.nz);
     const bool axis = t.QT != Q;
-    if (t.mask && axis)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, true, true>), grid, block, 0, stream, a);
-    else if (t.mask)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, true, false>), grid, block, 0, stream, a);
-    else if (axis)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, false, true>), grid, block, 0, stream, a);
-    else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, false, false>), grid, block, 0, stream, a);
+    if (t.st_half) {
+        if (t.mask && axis)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, true, true, __half>), grid, block, 0, stream, a);
+        else if (t.mask)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, true, false, __half>), grid, block, 0, stream, a);
+        else if (axis)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, false, true, __half>), grid, block, 0, stream, a);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, false, false, __half>), grid, block, 0, stream, a);
+    } else {
+        if (t.mask && axis)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, true, true, float>), grid, block, 0, stream, a);
+        else if (t.mask)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, true, false, float>), grid, block, 0, stream, a);
+        else if (axis)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, false, true, float>), grid, block, 0, stream, a);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_thermal_adjoint<Q, false, false, float>), grid, block, 0, stream, a);
+    }
     return hipGetLastError();
 }
 

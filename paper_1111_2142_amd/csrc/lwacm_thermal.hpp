@@ -16,7 +16,9 @@ struct ThermalArgs {
                           // and axis links of the flow's lattice
     float kap;            // 2 - 2/omega_t: weight of the even-part difference
     float h;              // 1 - kap = 2/omega_t - 1
-    const float *state;   // flow state at the step's time, FP32 (D + 1 floats per node)
+    const void *state;    // flow state at the step's time (storage format: D + 1 values per node)
+    int st_half;          // state in FP16 deviations (lwacm storage LWACM_FP16_DEV)
+    float ld_scale[2];    // storage -> value factors of (rho - 1, u); 1 for FP32
     const float *T_in;    // T at the step's time
     float *T_out;         // T one step later
     const uint8_t *mask;  // 0 fluid, m >= 1 solid with wall id m; null: no walls

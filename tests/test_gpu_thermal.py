@@ -11,7 +11,8 @@ thermal_step, run in lockstep with the flow.
 - Thermal Couette flow without heating: the exact linear profile between the
   two fixed-temperature walls stays steady.
 - The temperature does not change the flow (bitwise equal to the same steps
-  without it); scope: FP16 storage and the two-step kernel decline it;
+  without it); scope: the two-step kernel declines it; with FP16 flow
+  storage (T in FP32) each step against the oracle from the same inputs;
   switching it off is allowed.
 - Unmasked D3Q19 tile shapes run the temperature step inside the flow's
   single-step kernel: against the temperature kernel of its own (generic
@@ -207,11 +208,42 @@ def test_temperature_leaves_the_flow_alone_and_scope():
         s.temperature()
     L.lwacm_set_variant(s.ctx, MARCH2)
     s.close()
-    h = L.Solver(19, nx, ny, nz, 1.7, storage=1)
-    with pytest.raises(L.LWACMError) as ei:
-        h.set_thermal(1.2, T0)
-    assert ei.value.code == L.LWACM_EUNSUPPORTED
-    h.close()
+
+
+@pytest.mark.parametrize("q,qt,masked,shape", [(9, None, True, (1, 40, 48)),
+                                                (19, None, False, (16, 32, 64)),
+                                                (19, 7, True, (10, 20, 24))])
+def test_fp16_flow_storage_temperature_matches_oracle(q, qt, masked, shape):
+    """FP16 flow storage with the temperature (T stays FP32): each of four
+    steps against the oracle's temperature step from the same T and the
+    flow velocity the GPU state holds (dequantized, as the kernel reads it)."""
+    L = need_gpu()
+    banner(f"thermal with FP16 flow storage q={q} qt={qt} masked={masked} shape={shape}")
+    nz, ny, nx = shape
+    d = 2 if q == 9 else 3
+    drho, u = wl.random_state(shape, d, seed=57, du=0.03, drho=0.01)
+    rng = np.random.Generator(np.random.PCG64(58))
+    T = rng.uniform(0.2, 1.0, shape).astype(np.float32)
+    mask = _walls(shape, 59) if masked else None
+    table = np.zeros((4, 3))
+    s = L.Solver(q, nx, ny, nz, 1.6, storage=1,
+                 mask=None if mask is None else to_dev(mask, torch.uint8),
+                 wall_u=[list(r) for r in table])
+    s.set_state(to_dev(drho), to_dev(u))
+    s.set_thermal(1.3, to_dev(T), wall_T=WALL_T, q_t=qt or 0)
+    p = oracle.Problem(q, nx, ny, nz, omega=1.6, mask=mask, wall_u=table)
+    worst = 0.0
+    for _ in range(4):
+        Tt = s.temperature().double().cpu().numpy()
+        ut = s.moments()[1].double().cpu().numpy()
+        s.step(1)
+        got = s.temperature().double().cpu().numpy()
+        ref = oracle.thermal_step(p, Tt, ut, 1.3, wall_T=WALL_T, qt=qt)
+        worst = max(worst, rel_l2(got, ref))
+        assert np.abs(got - ref).max() < 1e-5
+    s.close()
+    banner(f"thermal with FP16 flow storage: worst rel-L2 T {worst:.3e}")
+    assert worst < 1e-6
 
 
 @pytest.mark.parametrize("q,qt,masked,shape", [(9, 5, False, (1, 40, 48)), (9, 5, True, (1, 40, 48)),

@@ -12,6 +12,7 @@
 - lwacm_run_thermal (torch.autograd over flow and temperature, checkpoints
   and ragged segments): gradients of T0, rho0 - 1, u0 and omega against the
   oracle's chain.
+- FP16 flow states: the step reads u and rho through the FP16 load scales.
 - Argument checks.
 """
 import numpy as np
@@ -102,6 +103,49 @@ def test_one_reverse_temperature_step_matches_oracle(q, qt, masked, shape):
         assert not got_u[1:, sol].any()
         assert np.array_equal(got_i[:, sol], base[:, sol])
     s.close()
+
+
+@pytest.mark.parametrize("q,qt,masked", [(9, None, True), (19, 7, False), (19, None, True)])
+def test_reverse_temperature_step_on_fp16_states(q, qt, masked):
+    """FP16 flow storage: the reverse temperature step reads u and rho from
+    the FP16 state; against thermal_vjp at the dequantized state."""
+    L = need_gpu()
+    banner(f"thermal reverse step on an FP16 state q={q} qt={qt} masked={masked}")
+    shape = (1, 24, 40) if q == 9 else (6, 10, 12)
+    nz, ny, nx = shape
+    d = 2 if q == 9 else 3
+    n = nx * ny * nz
+    drho, u = wl.random_state(shape, d, seed=121, du=0.03, drho=0.01)
+    rng = np.random.Generator(np.random.PCG64(122))
+    T = rng.uniform(0.2, 1.0, shape).astype(np.float32)
+    mask = _walls(shape, 123) if masked else None
+    s = L.Solver(q, nx, ny, nz, OMEGA, storage=1,
+                 mask=None if mask is None else to_dev(mask, torch.uint8),
+                 wall_u=[[0.0, 0.0, 0.0]] * 4)
+    s.set_state(to_dev(drho), to_dev(u))
+    s.set_thermal(OMEGA_T, to_dev(T), wall_T=WALL_T, q_t=qt or 0)
+    st = s.save_state()
+    dr_t, u_t = (x.double().cpu().numpy() for x in s.moments())
+    lam = rng.standard_normal(shape).astype(np.float32)
+    lam_out = torch.empty(shape, dtype=torch.float32, device="cuda")
+    mu_f = torch.zeros((d + 1,) + shape, dtype=torch.float32, device="cuda")
+    L.lwacm_adjoint_thermal_step(s.ctx, st, to_dev(T), to_dev(lam), lam_out, mu_f, True)
+    mu_i = torch.zeros(n * (d + 1), dtype=torch.float32, device="cuda")
+    L.lwacm_adjoint_thermal_step(s.ctx, st, to_dev(T), to_dev(lam), torch.empty_like(lam_out),
+                                 mu_i, False)
+    torch.cuda.synchronize()
+    s.close()
+    p = oracle.Problem(q, nx, ny, nz, omega=OMEGA, mask=mask, wall_u=np.zeros((4, 3)))
+    lt, lu = oracle.thermal_vjp(p, T.astype(np.float64), u_t, lam.astype(np.float64), OMEGA_T,
+                                wall_T=WALL_T, qt=qt)
+    e_T = rel_l2(lam_out.double().cpu().numpy(), lt)
+    e_u = rel_l2(mu_f.double().cpu().numpy()[1:], lu)
+    got_i = mu_i.double().cpu().numpy().reshape(n, d + 1).T.reshape((d + 1,) + shape)
+    inv = 1.0 / (1.0 + dr_t)
+    e_r = rel_l2(got_i[0], -(lu * u_t).sum(0) * inv)
+    banner(f"thermal reverse step, FP16 state: rel-L2 dL/dT {e_T:.3e}, dL/du {e_u:.3e}, "
+           f"mu_R {e_r:.3e}")
+    assert e_T < 1e-6 and e_u < 1e-5 and e_r < 1e-5
 
 
 @pytest.mark.parametrize("q,qt,masked,shape", [(9, None, True, (1, 24, 40)), (9, 5, False, (1, 24, 40)),
