@@ -188,7 +188,9 @@ __global__ __launch_bounds__(MTHREADS) void k_fwd_d2q9_multi(ProblemArgs p, cons
 // goes through adj_node_update, as in the one-step reverse kernel, so mu is
 // bitwise that of ksteps single reverse steps.  Each step's dL/da of the
 // tile's nodes is summed per workgroup into slice slice0 + s - 1 of the
-// partials (a different order of addition than the one-step kernel's blocks).
+// partials (a different order of addition than the one-step kernel's blocks):
+// per wave during the step, over the waves after the last step, so a step
+// ends with a single barrier.
 // final_last: the last step is step 0, its lambda goes out field-major.
 template <bool MASK>
 __global__ __launch_bounds__(MTHREADS) void k_adj_d2q9_multi(ProblemArgs p,
@@ -202,6 +204,9 @@ __global__ __launch_bounds__(MTHREADS) void k_adj_d2q9_multi(ProblemArgs p,
 {
     // per node of the region, two steps' buffers: (mu_R, mu_Jx, mu_Jy, mask id)
     __shared__ float4 buf[2][MW * MW];
+    // each step's dL/da per wave, added up after the last step
+    constexpr int NWAVES = MTHREADS / kWave;
+    __shared__ double stepsum[MK][NWAVES];
     const int ntx = (p.nx + MT - 1) / MT;
     const int tile_x0 = (int)(blockIdx.x % ntx) * MT;
     const int tile_y0 = (int)(blockIdx.x / ntx) * MT;
@@ -292,9 +297,16 @@ __global__ __launch_bounds__(MTHREADS) void k_adj_d2q9_multi(ProblemArgs p,
                 }
             }
         }
-        double acc[1] = {da_sum};
-        block_sum<1>(acc);  // its barriers also end the step
-        if (tid == 0) partials[(size_t)(slice0 + s - 1) * stride + blockIdx.x] = acc[0];
+        // the wave's sum now; the sum over the waves, in wave order (the
+        // order of block_sum), after the last step, one thread per step
+        const double wsum = wave_sum(da_sum);
+        if ((tid & (kWave - 1)) == 0) stepsum[s - 1][tid / kWave] = wsum;
+        __syncthreads();  // ends the step
+    }
+    if (tid < ksteps) {
+        double sum = 0.0;
+        for (int w = 0; w < NWAVES; ++w) sum += stepsum[tid][w];
+        partials[(size_t)(slice0 + tid) * stride + blockIdx.x] = sum;
     }
 
     if (!final_last) {
