@@ -50,6 +50,7 @@ struct lwacm_ctx {
     // temperature lattice (lwacm_set_thermal): two caller-owned buffers
     bool thermal;
     int thermal_qt;  // temperature lattice (lwacm_set_thermal_lattice): 0 = the flow's
+    uint2 *d_twall;  // fixed-temperature wall links per node (fused step with walls)
     float *T_buf[2];
     int tcur;
     lwacm::ThermalArgs targs;
@@ -196,6 +197,9 @@ void free_scratch(lwacm_ctx *c)
     if (c->d_wsec) (void)hipFree(c->d_wsec);
     if (c->d_wbits) (void)hipFree(c->d_wbits);
     c->d_wbits = nullptr;
+    if (c->d_twall) (void)hipFree(c->d_twall);
+    c->d_twall = nullptr;
+    c->p.T_wall = nullptr;
     c->d_wqc = nullptr;
     c->d_wsec = nullptr;
     c->d_wlist = nullptr;
@@ -627,6 +631,18 @@ int lwacm_set_thermal(lwacm_ctx *c, double omega_t, float *d_T_a, float *d_T_b,
     t.mask = c->p.mask;
     for (int m = 0; m < lwacm::kMaxThermalWallIds; ++m)
         t.wall_T[m] = m < n_wall_T ? h_wall_T[m] : __builtin_nanf("");
+    // walls on a D3Q19 flow: the table of fixed-temperature wall links that
+    // the flow kernel's fused temperature step reads
+    if (c->p.mask && c->p.Q == 19) {
+        if (!c->d_twall &&
+            hipMalloc(&c->d_twall, sizeof(uint2) * (size_t)c->p.n) != hipSuccess) {
+            c->d_twall = nullptr;
+            return LWACM_ENOMEM;
+        }
+        if (lwacm::launch_thermal_wall_table(t, c->d_twall, c->stream) != hipSuccess)
+            return LWACM_EDEVICE;
+        c->p.T_wall = c->d_twall;
+    }
     c->T_buf[0] = d_T_a;
     c->T_buf[1] = d_T_b;
     c->tcur = 0;

@@ -51,6 +51,9 @@ struct ProblemArgs {
     const float *T_in;
     float *T_out;
     float t_h, t_kap;
+    // with walls: per node, the links into fixed-temperature walls (bit i) and
+    // the FP32 bits of the sum of 36 w_i T_w over them (lwacm_set_thermal)
+    const uint2 *T_wall;
 };
 
 // Scratch and destination of the fixed-order grid reductions: a kernel stores

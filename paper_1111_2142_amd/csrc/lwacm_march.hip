@@ -279,7 +279,8 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march(ProblemArgs p, const T *
 // THERM: the temperature lattice's step (Eq. ACM2.0t) in the same pass, from
 // the same step-t velocities: each column also loads its T (p.T_in) with the
 // state, pushes the temperature terms through the omega_p arrays and writes
-// the new T (p.T_out): 4 + 4 bytes more per node instead of a pass of its own.
+// the new T (p.T_out): 4 + 4 bytes more per node instead of a pass of its own
+// (with walls 8 more: the node's fixed-temperature wall links and their sum).
 template <class T, int NZC, bool SR, bool MASK, bool SPLIT, int FRC, bool CORR, bool THERM>
 __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
                                                                const T *__restrict__ src,
@@ -296,8 +297,8 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
     constexpr int QS = QX ? NSLOT + 1 : 1;       // q slots (one spare, as above)
     __shared__ float xq[QX ? 2 : 1][8][QS];
     static_assert(!(SPLIT && MASK), "the separate omega_p runs without walls");
-    static_assert(!THERM || (!MASK && !SPLIT && FRC == 0 && std::is_same<T, float>::value),
-                  "the fused temperature step: FP32 state, no walls, force or omega_p");
+    static_assert(!THERM || (!CORR && !SPLIT && FRC == 0 && std::is_same<T, float>::value),
+                  "the fused temperature step: FP32 state, halfway walls, no force or omega_p");
     const float dA = p.Ap - p.A;
 
     const int tid = threadIdx.x;
@@ -353,11 +354,20 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
     const Rsrc rTi = make_rsrc(THERM ? p.T_in : nullptr, THERM ? (unsigned long long)n * 4u : 0ull);
     const Rsrc rTo = make_rsrc(THERM ? p.T_out : nullptr, THERM ? (unsigned long long)n * 4u : 0ull);
     unsigned tw[3] = {0u, 0u, 0u};
+    // with walls, each node's links into fixed-temperature walls and the sum of
+    // 36 w T_w over them (a table lwacm_set_thermal builds)
+    constexpr bool TWALL = THERM && MASK;
+    const Rsrc rTw = make_rsrc(TWALL ? (const void *)p.T_wall : nullptr,
+                               TWALL ? (unsigned long long)n * 8u : 0ull);
+    uint2 twb[3] = {{0u, 0u}, {0u, 0u}, {0u, 0u}};
     auto issue = [&](int j, Ring<T> &rg, int pz) {
         const unsigned pw = (unsigned)wrap_index(pz, nz);
         rg.v = BufIO<T>::load(rs, voff, pw * plane_bytes);
         if (MASK) bw[j] = __builtin_amdgcn_raw_buffer_load_b32(rbits, col * 4u, pw * (unsigned)(plane * 4), 0);
         if (THERM) tw[j] = __builtin_amdgcn_raw_buffer_load_b32(rTi, col * 4u, pw * (unsigned)(plane * 4), 0);
+        if (TWALL)
+            twb[j] = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(
+                                                   rTw, col * 8u, pw * (unsigned)(plane * 8), 0));
     };
     // node-by-node acceleration (FRC 2): three FP32 fields, one resource each
     const unsigned long long gbytes = FRC == 2 ? (unsigned long long)n * 4u : 0ull;
@@ -418,8 +428,9 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
                               acc[j], Am, !corr);
             if (SPLIT) push_split_column(1.0f + dr, ux, uy, uz, dA, acc[(j + 1) % 3], acc[j], Am);
             if (THERM)
-                push_temp_column(__builtin_bit_cast(float, tw[j]), ux, uy, uz, p.t_h,
-                                 acc[(j + 1) % 3], acc[j], Am);
+                push_temp_column<MASK>(__builtin_bit_cast(float, tw[j]), ux, uy, uz, p.t_h,
+                                       acc[(j + 1) % 3], acc[j], Am, MASK ? class_of(b) : 0, b,
+                                       twb[j]);
             if (FRC) {  // post-combine a rho u plus the forcing rho g
                 const float rho = 1.0f + dr, arho = a * rho;
                 const float gx = FRC == 2 ? __builtin_bit_cast(float, gq[j][0]) : p.g[0];
@@ -478,9 +489,10 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
                 BufIO<T>::store_raw(rd, voff, so, out);
             }
             if constexpr (THERM) {
-                // T(x, t + 1) = (2 - 2/omega_t) T(x) + the incoming terms / 36
+                // T(x, t + 1) = (2 - 2/omega_t) T(x) + the incoming terms / 36;
+                // a solid node keeps its T (written, so both buffers hold it)
                 const float Tsum = Am.qd + gather_split<QS, SX>(XchgQ<QS>{xq[k & 1]}, slot);
-                const float Tn = fmaf(p.t_kap, Am.tx, div36(Tsum));
+                const float Tn = solid ? Am.tx : fmaf(p.t_kap, Am.tx, div36(Tsum));
                 __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, Tn), rTo,
                                                       col * 4u, (unsigned)tz * (unsigned)(plane * 4),
                                                       0);
@@ -508,7 +520,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
                                 hq[jm]);
             if (THERM)
                 push_temp_halo(__builtin_bit_cast(float, tw[j]), ux, uy, uz, p.t_h, isY, sgn, hq[j1],
-                               hq[j], hq1[j], hq2[j], hq[jm]);
+                               hq[j], hq1[j], hq2[j], hq[jm], MASK && class_of(bw[j]) >= 2);
             __builtin_amdgcn_sched_barrier(0);
             if (I::refill) issue(j, ring[j], z0 + 2 + k);
             if (I::phase < 2) return;
@@ -641,8 +653,12 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
     const bool sr = std::is_same<T, __half>::value && p.fp16_sr;
     if constexpr (std::is_same<T, float>::value) {
         if (p.T_in) {  // with the temperature step (march_thermal_supported)
-            launch_rolled<float, false, false, false, 0, false, true>(c, nb, s, p, a, b, bits, wallg,
-                                                                     r);
+            if (p.mask)
+                launch_rolled<float, false, true, false, 0, false, true>(c, nb, s, p, a, b, bits,
+                                                                        wallg, r);
+            else
+                launch_rolled<float, false, false, false, 0, false, true>(c, nb, s, p, a, b, bits,
+                                                                         wallg, r);
             return hipGetLastError();
         }
     }
@@ -725,8 +741,9 @@ hipError_t launch_classify(const ProblemArgs &p, uint8_t *cls, unsigned *bits, f
 
 bool march_thermal_supported(const ProblemArgs &p)
 {
-    return march_supported(p) && !p.mask && !p.split && !p.has_force && !p.corr && !p.qd &&
-           !p.uwl && rolled_nzc(p) > 0;
+    // halfway walls need the fixed-temperature wall table (p.T_wall)
+    return march_supported(p) && (!p.mask || p.T_wall) && !p.split && !p.has_force && !p.corr &&
+           !p.qd && !p.uwl && rolled_nzc(p) > 0;
 }
 
 hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, void *dst,

@@ -585,12 +585,28 @@ __device__ __forceinline__ void push_split_halo(float rho, float ux, float uy, f
 // the density partials, in the omega_p arrays (q fields, XchgQ), which a
 // problem with a temperature does not use.  Opposite links share the even
 // part, as in push_column.
+//
+// Walls (MASK): a solid node pushes nothing and keeps its T.  Where the
+// upstream node x - v_i of a fluid node is solid (bit i of its link set), the
+// node's own term for the opposite link comes back along i: with its sign kept
+// at an adiabatic wall, reversed at a wall held at T_w, which also adds
+// 2 h 36 w_i T_w.  tw.x holds the node's links into fixed-temperature walls
+// (bit i), tw.y the FP32 bits of the sum of 36 w_i T_w over them; the node's
+// returned terms are summed when it is pushed (one wave-level test), like the
+// flow's bounce-back.
+template <bool MASK>
 __device__ __forceinline__ void push_temp_column(float T, float ux, float uy, float uz, float h,
-                                                 Acc &A1, Acc &A0, Acc &Am)
+                                                 Acc &A1, Acc &A0, Acc &Am, int cls = 0,
+                                                 unsigned bits = 0u, uint2 tw = {0u, 0u})
 {
     const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
-    const float AT = h * fmaf(-1.5f, usq, T);
-    const float H = 4.5f * h, T3 = 3.0f * T;
+    float AT = h * fmaf(-1.5f, usq, T);
+    float H = 4.5f * h, T3 = 3.0f * T;
+    if (MASK && cls >= 2) {  // solid: push nothing
+        AT = 0.0f;
+        H = 0.0f;
+        T3 = 0.0f;
+    }
     auto pair = [&](float c, float &lp, float &lm) {
         const float m = fmaf(H * c, c, AT);
         lp = fmaf(T3, c, m);
@@ -624,6 +640,43 @@ __device__ __forceinline__ void push_temp_column(float T, float ux, float uy, fl
     A0.qsw = Tmm0;
     A0.qd = fmaf(12.0f, AT, A0.qd);
     A0.tx = T;
+    if (MASK && __builtin_amdgcn_ballot_w64(bits > 1u) != 0ull) {
+        // returned terms: all wall links, and again (twice, negated) the
+        // fixed-temperature ones
+        float sa = 0.0f, sf = 0.0f;
+        auto link = [&](auto cxc, auto cyc, auto czc, float lo) {
+            constexpr int i = link_index(decltype(cxc)::value, decltype(cyc)::value,
+                                         decltype(czc)::value);
+            constexpr float w = Lattice<19>::w36(i);
+            const unsigned m = (unsigned)((int)(bits << (31 - i)) >> 31);
+            const unsigned f = (unsigned)((int)(tw.x << (31 - i)) >> 31);
+            const unsigned lb = __builtin_bit_cast(unsigned, lo);
+            sa = fmaf(w, __builtin_bit_cast(float, lb & m), sa);
+            sf = fmaf(w, __builtin_bit_cast(float, lb & f), sf);
+        };
+        using P = std::integral_constant<int, 1>;
+        using Z = std::integral_constant<int, 0>;
+        using M = std::integral_constant<int, -1>;
+        link(P{}, Z{}, Z{}, Tmx);
+        link(M{}, Z{}, Z{}, Tpx);
+        link(Z{}, P{}, Z{}, Tmy);
+        link(Z{}, M{}, Z{}, Tpy);
+        link(Z{}, Z{}, P{}, Tmz);
+        link(Z{}, Z{}, M{}, Tpz);
+        link(P{}, P{}, Z{}, Tmm0);
+        link(M{}, M{}, Z{}, Tpp0);
+        link(P{}, M{}, Z{}, Tmp0);
+        link(M{}, P{}, Z{}, Tpm0);
+        link(P{}, Z{}, P{}, Tm0m);
+        link(M{}, Z{}, M{}, Tp0p);
+        link(P{}, Z{}, M{}, Tm0p);
+        link(M{}, Z{}, P{}, Tp0m);
+        link(Z{}, P{}, P{}, T0mm);
+        link(Z{}, M{}, M{}, T0pp);
+        link(Z{}, P{}, M{}, T0mp);
+        link(Z{}, M{}, P{}, T0pm);
+        A0.qd += fmaf(-2.0f, sf, sa) + 2.0f * h * __builtin_bit_cast(float, tw.y);
+    }
     // v_z = -1: plane pz - 1
     Am.qe += Tp0m;
     Am.qw += Tm0m;
@@ -636,11 +689,17 @@ __device__ __forceinline__ void push_temp_column(float T, float ux, float uy, fl
 // push_halo; the same operations as push_temp_column's pairs)
 __device__ __forceinline__ void push_temp_halo(float T, float ux, float uy, float uz, float h,
                                                bool isY, float sgn, float &q1, float &q0,
-                                               float &qd1, float &qd2, float &qm)
+                                               float &qd1, float &qd2, float &qm,
+                                               bool solid = false)
 {
     const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
-    const float AT = h * fmaf(-1.5f, usq, T);
-    const float H = 4.5f * h, T3 = 3.0f * T;
+    float AT = h * fmaf(-1.5f, usq, T);
+    float H = 4.5f * h, T3 = 3.0f * T;
+    if (solid) {  // a solid node pushes nothing
+        AT = 0.0f;
+        H = 0.0f;
+        T3 = 0.0f;
+    }
     auto lt = [&](float c) { return fmaf(T3, c, fmaf(H * c, c, AT)); };
     const float ua = isY ? uy : ux;
     const float ub = isY ? ux : uy;

@@ -133,6 +133,35 @@ __global__ __launch_bounds__(kThermalBX *kThermalBY) void k_thermal_step(Thermal
     t.T_out[idx] = fmaf(t.kap, Tx, div36(acc));
 }
 
+__global__ __launch_bounds__(256) void k_thermal_wall_table(ThermalArgs t, uint2 *out)
+{
+    const long long n = (long long)t.nx * t.ny * t.nz;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        unsigned fb = 0u;
+        float tw = 0.0f;
+        if (t.mask[idx] == 0) {
+            const long long r = idx / t.nx;
+            const int x = (int)(idx - r * t.nx);
+            const int z = (int)(r / t.ny);
+            const int y = (int)(r - (long long)z * t.ny);
+#pragma unroll
+            for (int i = 1; i < 19; ++i) {
+                const int xs = wrap_step(x, link_cx(i), t.nx);
+                const int ys = wrap_step(y, link_cy(i), t.ny);
+                const int zs = wrap_step(z, link_cz(i), t.nz);
+                const uint8_t m = t.mask[((long long)zs * t.ny + ys) * t.nx + xs];
+                const float Tw = m < kMaxThermalWallIds ? t.wall_T[m] : __builtin_nanf("");
+                if (m != 0 && Tw == Tw) {
+                    fb |= 1u << i;
+                    tw = fmaf(Lattice<19>::w36(i), Tw, tw);
+                }
+            }
+        }
+        out[idx] = make_uint2(fb, __builtin_bit_cast(unsigned, tw));
+    }
+}
+
 // ---- reverse mode of one step (gather over the nodes a node's T and u reach)
 //
 // T(x, t+1) is linear in the T of its upstream nodes and quadratic in their u;
@@ -444,6 +473,15 @@ hipError_t launch_adj_q(const ThermalAdjArgs &a, hipStream_t stream)
 }
 
 }  // namespace
+
+hipError_t launch_thermal_wall_table(const ThermalArgs &t, uint2 *out, hipStream_t stream)
+{
+    if (t.Q != 19 || !t.mask || !out) return hipErrorInvalidValue;
+    long long nb = ((long long)t.nx * t.ny * t.nz + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    k_thermal_wall_table<<<(unsigned)nb, 256, 0, stream>>>(t, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_thermal_adjoint(const ThermalAdjArgs &a, hipStream_t stream)
 {

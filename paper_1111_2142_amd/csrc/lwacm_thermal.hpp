@@ -27,6 +27,12 @@ struct ThermalArgs {
 
 hipError_t launch_thermal_step(const ThermalArgs &t, hipStream_t stream);
 
+// For the temperature step fused into the D3Q19 flow kernel with walls: per
+// node, the links i whose upstream node x - v_i is a wall held at a fixed
+// temperature (bit i, the flow kernels' link order) and the FP32 bits of the
+// sum of 36 w_i T_w over them; zero for solid nodes and away from such walls.
+hipError_t launch_thermal_wall_table(const ThermalArgs &t, uint2 *out, hipStream_t stream);
+
 // Reverse mode of one temperature step (lwacm_adjoint_thermal_step).
 struct ThermalAdjArgs {
     ThermalArgs t;         // the step's arguments; t.state and t.T_in are its inputs

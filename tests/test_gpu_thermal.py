@@ -14,9 +14,9 @@ thermal_step, run in lockstep with the flow.
   without it); scope: the two-step kernel declines it; with FP16 flow
   storage (T in FP32) each step against the oracle from the same inputs;
   switching it off is allowed.
-- Unmasked D3Q19 tile shapes run the temperature step inside the flow's
-  single-step kernel: against the temperature kernel of its own (generic
-  variant) and the oracle.
+- D3Q19 tile shapes run the temperature step inside the flow's single-step
+  kernel, with and without walls: against the temperature kernel of its own
+  (generic variant) and the oracle.
 - A temperature lattice smaller than the flow's (D2Q5 under D2Q9, D3Q7 under
   D3Q19) against the oracle's, with and without walls; the lattice switched
   back to the flow's mid-run; scope of lwacm_set_thermal_lattice.
@@ -118,6 +118,50 @@ def test_fused_temperature_step_matches_the_separate_kernel(shape):
     e_o = rel_l2(Tf, rT)
     banner(f"thermal fused vs separate: rel-L2 T {e_T:.3e}, u {e_u:.3e}; vs oracle T {e_o:.3e}")
     assert e_T < 1e-6 and e_u < 1e-6 and e_o < 1e-6
+
+
+@pytest.mark.parametrize("shape", [(40, 32, 64), (16, 32, 64)])
+def test_fused_temperature_with_walls_matches_the_separate_kernel(shape):
+    """D3Q19 tile shapes with walls of three kinds (two fixed temperatures,
+    one adiabatic) and a moving wall id: the temperature fused into the flow's
+    single-step kernel (bounced temperature terms summed at push time, the
+    fixed-temperature links from the table lwacm_set_thermal builds) against
+    the generic variant's separate kernels and the oracle, 10 steps."""
+    L = need_gpu()
+    banner(f"thermal fused with walls {shape}")
+    nz, ny, nx = shape
+    drho, u = wl.random_state(shape, 3, seed=63, du=0.03, drho=0.01)
+    drho = drho.astype(np.float32).astype(np.float64)
+    u = u.astype(np.float32).astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(64))
+    T = rng.uniform(0.2, 1.0, shape).astype(np.float32).astype(np.float64)
+    mask = _walls(shape, 65)
+    u[:, mask != 0] = 0.0
+    table = np.zeros((4, 3))
+    table[2] = (0.02, 0.0, -0.01)  # the adiabatic id moves
+    out = []
+    for variant in (0, 1):
+        s = L.Solver(19, nx, ny, nz, 1.6, mask=to_dev(mask, torch.uint8),
+                     wall_u=[list(r) for r in table], variant=variant)
+        s.set_state(to_dev(drho), to_dev(u))
+        s.set_thermal(1.3, to_dev(T), wall_T=WALL_T)
+        s.step(10)
+        out.append((s.temperature().double().cpu().numpy(), s.moments()[1].double().cpu().numpy()))
+        s.close()
+    (Tf, uf), (Ts, us) = out
+    fl = mask == 0
+    e_T, e_u = rel_l2(Tf[fl], Ts[fl]), rel_l2(uf[:, fl], us[:, fl])
+    rho0 = 1.0 + drho[fl].astype(np.float32).mean()
+    p = oracle.Problem(19, nx, ny, nz, omega=1.6, mask=mask, wall_u=table, rho0=rho0)
+    r, ru, rT = 1.0 + drho, u, T
+    for _ in range(10):
+        rT = oracle.thermal_step(p, rT, ru, 1.3, wall_T=WALL_T)
+        r, ru = oracle.step(p, r, ru)
+    e_o = rel_l2(Tf[fl], rT[fl])
+    banner(f"thermal fused with walls: rel-L2 T {e_T:.3e}, u {e_u:.3e}; vs oracle T {e_o:.3e}")
+    assert e_T < 1e-6 and e_u < 1e-6 and e_o < 1e-6
+    assert np.abs(Tf[fl] - rT[fl]).max() < 1e-5
+    assert np.array_equal(Tf[~fl], T[~fl])
 
 
 def test_full_size_step_matches_oracle_and_conserves_total():
