@@ -280,8 +280,7 @@ int lwacm_set_wall_velocity_links(lwacm_ctx *c, const float *d_uw);
  *             profile between two such walls exactly steady.  n_wall_T <= 16.
  *             Solid nodes keep their T.
  * T stays FP32 with either flow storage; with FP16 flow storage the
- * temperature step reads u from the FP16 state (its load scales) on the
- * one-thread-per-node kernel.  With walls on a D3Q19 flow the call allocates
+ * temperature step reads u from the FP16 state (its load scales).  With walls on a D3Q19 flow the call allocates
  * (once per context) and fills, on the context's stream, a table of 8 bytes
  * per node: each node's links into fixed-temperature walls and the sum of
  * 36 w_i T_w over them, which the flow kernel's fused temperature step

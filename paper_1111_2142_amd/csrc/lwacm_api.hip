@@ -840,8 +840,8 @@ int lwacm_step(lwacm_ctx *c, int nsteps)
         // tile kernel where it can, else by a kernel of its own that reads the
         // state this step's flow kernel reads, before that kernel runs
         ProblemArgs pl = c->p;
-        const bool tfuse = c->thermal && march && !two && c->storage == LWACM_FP32 &&
-                           c->targs.QT == c->p.Q && lwacm::march_thermal_supported(c->p);
+        const bool tfuse = c->thermal && march && !two && c->targs.QT == c->p.Q &&
+                           lwacm::march_thermal_supported(c->p);
         if (tfuse) {
             pl.T_in = c->T_buf[c->tcur];
             pl.T_out = c->T_buf[c->tcur ^ 1];

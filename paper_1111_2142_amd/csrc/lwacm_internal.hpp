@@ -134,7 +134,8 @@ hipError_t launch_adj_march(const ProblemArgs &p, int storage, const void *state
                             const float4 *wallg, int final_t0, const ReduceArgs &r,
                             hipStream_t stream);
 // D3Q19 single-step tile kernel with the temperature step in the same pass
-// (p.T_in, p.T_out): FP32 state, no walls, force, omega_p or wall correction.
+// (p.T_in, p.T_out): FP32 or FP16 state, no walls or halfway walls (with the
+// table p.T_wall), no force, omega_p or wall correction.
 bool march_thermal_supported(const ProblemArgs &p);
 hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, void *dst,
                             const uint8_t *cls, const unsigned *bits, const float4 *wallg,

@@ -297,8 +297,8 @@ __global__ __launch_bounds__(NTHREADS) void k_fwd_march_rolled(ProblemArgs p,
     constexpr int QS = QX ? NSLOT + 1 : 1;       // q slots (one spare, as above)
     __shared__ float xq[QX ? 2 : 1][8][QS];
     static_assert(!(SPLIT && MASK), "the separate omega_p runs without walls");
-    static_assert(!THERM || (!CORR && !SPLIT && FRC == 0 && std::is_same<T, float>::value),
-                  "the fused temperature step: FP32 state, halfway walls, no force or omega_p");
+    static_assert(!THERM || (!CORR && !SPLIT && FRC == 0),
+                  "the fused temperature step: halfway walls, no force or omega_p");
     const float dA = p.Ap - p.A;
 
     const int tid = threadIdx.x;
@@ -651,16 +651,17 @@ hipError_t dispatch(const ProblemArgs &p, const void *src, void *dst, const uint
     T *b = static_cast<T *>(dst);
     const int c = rolled_nzc(p);
     const bool sr = std::is_same<T, __half>::value && p.fp16_sr;
-    if constexpr (std::is_same<T, float>::value) {
-        if (p.T_in) {  // with the temperature step (march_thermal_supported)
-            if (p.mask)
-                launch_rolled<float, false, true, false, 0, false, true>(c, nb, s, p, a, b, bits,
-                                                                        wallg, r);
-            else
-                launch_rolled<float, false, false, false, 0, false, true>(c, nb, s, p, a, b, bits,
-                                                                         wallg, r);
-            return hipGetLastError();
+    if (p.T_in) {  // with the temperature step (march_thermal_supported)
+        if constexpr (std::is_same<T, __half>::value) {
+            if (sr) {
+                if (p.mask) launch_rolled<T, true, true, false, 0, false, true>(c, nb, s, p, a, b, bits, wallg, r);
+                else launch_rolled<T, true, false, false, 0, false, true>(c, nb, s, p, a, b, bits, wallg, r);
+                return hipGetLastError();
+            }
         }
+        if (p.mask) launch_rolled<T, false, true, false, 0, false, true>(c, nb, s, p, a, b, bits, wallg, r);
+        else launch_rolled<T, false, false, false, 0, false, true>(c, nb, s, p, a, b, bits, wallg, r);
+        return hipGetLastError();
     }
     if (c == 0) {  // nz < 8: the unrolled kernel with a 32-plane chunk
         if (p.mask)
@@ -751,8 +752,7 @@ hipError_t launch_fwd_march(const ProblemArgs &p, int storage, const void *src, 
                             const ReduceArgs &r, hipStream_t s)
 {
     if (!march_supported(p) || (p.mask && (!cls || !bits))) return hipErrorNotSupported;
-    if (p.T_in && (storage != 0 || !p.T_out || !march_thermal_supported(p)))
-        return hipErrorNotSupported;
+    if (p.T_in && (!p.T_out || !march_thermal_supported(p))) return hipErrorNotSupported;
     return storage ? dispatch<__half>(p, src, dst, cls, bits, wallg, r, s)
                    : dispatch<float>(p, src, dst, cls, bits, wallg, r, s);
 }

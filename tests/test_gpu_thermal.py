@@ -256,11 +256,14 @@ def test_temperature_leaves_the_flow_alone_and_scope():
 
 @pytest.mark.parametrize("q,qt,masked,shape", [(9, None, True, (1, 40, 48)),
                                                 (19, None, False, (16, 32, 64)),
+                                                (19, None, True, (16, 32, 64)),
                                                 (19, 7, True, (10, 20, 24))])
 def test_fp16_flow_storage_temperature_matches_oracle(q, qt, masked, shape):
     """FP16 flow storage with the temperature (T stays FP32): each of four
     steps against the oracle's temperature step from the same T and the
-    flow velocity the GPU state holds (dequantized, as the kernel reads it)."""
+    flow velocity the GPU state holds (dequantized, as the kernels read it);
+    the D3Q19 tile shapes run it fused into the FP16 flow kernel (stochastic
+    rounding of the state), with and without walls."""
     L = need_gpu()
     banner(f"thermal with FP16 flow storage q={q} qt={qt} masked={masked} shape={shape}")
     nz, ny, nx = shape
