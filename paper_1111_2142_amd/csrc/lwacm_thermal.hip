@@ -26,14 +26,18 @@
 // linear w_i T (1 + 3 c): the terms above with q = 0.  They run the gather
 // kernel.
 //
+// Where it can, the library runs the step inside the D3Q19 flow tile kernel
+// (lwacm_march.hip, THERM); the kernels here serve the other cases.
 // D3Q19 with nx % 32 == 0 and ny % 16 == 0 runs the tile kernel: a workgroup
 // owns a 32 x 16 column tile and marches up a chunk of z planes; each plane's
 // T, u (and mask) with a one-node halo are staged once through LDS into a ring
 // of three planes, and every thread reads its 19 upstream nodes from there.
 // HBM then sees each node's state and T about once (the halo columns are
 // mostly L2 hits), so the kernel is bound by HBM at 24 B per node.  Other
-// shapes and D2Q9 run the gather kernel: one thread per node, the upstream
-// nodes read through L1/L2.
+// shapes, D2Q9, FP16 flow states and the D2Q5/D3Q7 lattices run the gather
+// kernel: one thread per node, the upstream nodes read through L1/L2.  The
+// reverse mode and the fused kernel's fixed-temperature wall table are here
+// too.
 #include "lwacm_device.hpp"
 #include "lwacm_thermal.hpp"
 
