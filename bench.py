@@ -265,6 +265,43 @@ def _thermal_leg(args, L, wl, dev, stream, drho_t, u_t, n):
             "basis": "40 B per node: FP32 flow state and T read and written in one pass"}
 
 
+def _thermal_cavity_leg(args, L, wl, dev, stream):
+    """The 192^3 lid-driven cavity with a temperature field: the walls at rest
+    held at T = 0.2, the lid at T = 0.8 (omega_t = 1.4).  The temperature step
+    runs inside the masked single-step flow kernel: per node 52 B (the state
+    read and written, the link set, T read and written, the node's 8-byte entry
+    of the fixed-temperature wall table).  Timed beside the same steps
+    without T on the same kernel."""
+    import torch
+    c4 = wl.CAVITY_192
+    m4 = torch.as_tensor(wl.cavity_mask(c4.nx), device=dev)
+    shape = (c4.nz, c4.ny, c4.nx)
+    times = []
+    for thermal in (False, True):
+        s = L.Solver(L.LWACM_D3Q19, c4.nx, c4.ny, c4.nz, c4.omega, mask=m4,
+                     wall_u=[list(r) for r in wl.wall_table(c4.lid)], device=dev, variant=2)
+        s.set_state(torch.zeros(shape, device=dev), torch.zeros((3,) + shape, device=dev))
+        if thermal:
+            s.set_thermal(1.4, torch.full(shape, 0.5, device=dev),
+                          wall_T=[float("nan"), 0.2, 0.8])
+        s.step(args.warmup)
+        times.append(_events_time(s.step, args.steps, stream))
+        s.close()
+    torch.cuda.empty_cache()
+    ms_flow, ms_both = (t / args.steps * 1e3 for t in times)
+    fluid = (c4.nx - 2) * (c4.ny - 2) * (c4.nz - 2)
+    print(f"[bench] cavity 192^3 with T: {ms_both:.4f} ms/step, {ms_flow:.4f} without",
+          file=sys.stderr, flush=True)
+    return {"value": round(fluid * args.steps / times[1] / 1e6, 1),
+            "unit": "MLUPS (fluid nodes, flow and temperature)", "ms_per_step": round(ms_both, 5),
+            "ms_flow_only": round(ms_flow, 5),
+            "ms_added_by_temperature": round(ms_both - ms_flow, 5),
+            "achieved_GBs": round(52.0 * c4.nx * c4.ny * c4.nz / (ms_both * 1e-3) / 1e9, 1),
+            "kernel": "k_fwd_march_rolled<float,64,false,true,false,0,false,true>",
+            "basis": "52 B per node: state in and out, link set, T in and out, wall-table entry; "
+                     "one step per launch (the two-step kernel does not carry T)"}
+
+
 def _c5_leg(L, wl, dev):
     """End-to-end gradient of the D2Q9 512^2 workload (seeded k <= 8 fields,
     omega 1.6, loss sum |u_T - u*|^2): 2000 forward steps storing a checkpoint
@@ -325,6 +362,8 @@ def main():
                     help="time only the 192^3 cavity with interpolated bounce-back (q = 0.3)")
     ap.add_argument("--field-only", action="store_true",
                     help="time only the 256^3 step with a node-by-node acceleration field")
+    ap.add_argument("--thermal-cavity-only", action="store_true",
+                    help="time the 192^3 cavity with a temperature field and exit")
     ap.add_argument("--thermal-only", action="store_true",
                     help="time only the 256^3 step with a temperature field")
     ap.add_argument("--cavity-only", action="store_true",
@@ -371,6 +410,10 @@ def main():
         return
     if args.cavity_only:
         print(json.dumps({"cavity_192": _cavity_leg(args, L, wl, dev, stream)}), flush=True)
+        return
+    if args.thermal_cavity_only:
+        print(json.dumps({"thermal_cavity_192": _thermal_cavity_leg(args, L, wl, dev, stream)}),
+              flush=True)
         return
     n = args.n
     cfg = wl.TGV3D_256
@@ -629,6 +672,8 @@ def main():
 
     # ---- temperature advected by the flow: the same 256^3 step plus the temperature kernel
     result["thermal"] = _thermal_leg(args, L, wl, dev, stream, drho_t, u_t, n)
+    # ---- the same with walls: the 192^3 cavity with hot lid and cold walls
+    result["thermal_cavity_192"] = _thermal_cavity_leg(args, L, wl, dev, stream)
 
     # ---- interpolated bounce-back: the 192^3 cavity with walls at q = 0.3
     result["cavity_192_interpolated"] = _qbb_leg(args, L, wl, dev, stream)
